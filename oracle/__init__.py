@@ -1,0 +1,400 @@
+"""FP64 CPU oracle of the HEALPix Gaussian rasterizer -- TEST INFRASTRUCTURE.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package.  It shares no code with the HIP path
+(``paper_2606_29794_amd``); the two meet only through the seeded inputs of
+``paper_2606_29794_amd.scenes``.
+
+The arithmetic lives in ``hp_oracle.cpp`` (plain C++17, double precision,
+OpenMP loops); this module builds it with g++ and wraps it with ctypes.
+Each wrapper names the paper passage the underlying routine follows.
+
+Parity status of each function is stated in tests/test_oracle_*.py; all of
+them are pinned there (closed forms, invariants, finite differences).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "hp_oracle.cpp")
+_LIB = os.path.join(_HERE, "libhp_oracle.so")
+
+# constants of the method (readings of the paper; identical values are used
+# by the HIP path, which defines its own copy)
+EPS_T = 1e-4          # early-termination transmittance (Alg. 1)
+ALPHA_MAX = 0.99      # opacity clamp
+Q_CUT = 9.0           # 3-sigma Mahalanobis support
+R_MIN = 0.1           # near cull on radial depth
+RS_SIGMA = 3.0        # r_s = 3 sqrt(lambda_max)  (Sec. 3.2)
+BIN_GUARD = 1e-6      # radians added to the tile-overlap test
+SH_OFFSET = 0.5
+TILE_LOG2 = 4         # B = 16 (Table tab:resolution)
+SSIM_SIGMA = 1.5
+SSIM_C1 = 0.01 ** 2
+SSIM_C2 = 0.03 ** 2
+LAMBDA = 0.2
+
+
+def build(force: bool = False) -> str:
+    """Compile hp_oracle.cpp into libhp_oracle.so (g++, -O2, OpenMP)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        cmd = ["g++", "-O2", "-std=c++17", "-fopenmp", "-fPIC", "-shared", "-o", tmp, _SRC]
+        subprocess.check_call(cmd)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Scene(C.Structure):
+    _fields_ = [("P", C.c_int64), ("sh_degree", C.c_int),
+                ("mean", C.c_void_p), ("scale", C.c_void_p), ("rot", C.c_void_p),
+                ("opacity", C.c_void_p), ("sh", C.c_void_p)]
+
+
+class _View(C.Structure):
+    _fields_ = [("W", C.c_double * 9), ("b", C.c_double * 3), ("center", C.c_double * 3),
+                ("cam_type", C.c_int), ("fov_x", C.c_double), ("fov_y", C.c_double), ("order", C.c_int)]
+
+
+class _Params(C.Structure):
+    _fields_ = [("eps_T", C.c_double), ("alpha_max", C.c_double), ("q_cut", C.c_double),
+                ("r_min", C.c_double), ("rs_sigma", C.c_double), ("bin_guard", C.c_double),
+                ("sh_offset", C.c_double), ("tile_log2", C.c_int)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = C.CDLL(build())
+        _lib.or_mask.restype = C.c_int64
+        _lib.or_tile_sets.restype = C.c_int64
+        _lib.or_chart_pixel.restype = C.c_int64
+        _lib.or_hssim.restype = C.c_double
+        _lib.or_num_threads.restype = C.c_int
+    return _lib
+
+
+def _p(a):
+    return C.c_void_p(a.ctypes.data) if a is not None else None
+
+
+def num_threads() -> int:
+    return int(lib().or_num_threads())
+
+
+def set_threads(n: int) -> None:
+    lib().or_set_threads(int(n))
+
+
+def params(**kw) -> _Params:
+    d = dict(eps_T=EPS_T, alpha_max=ALPHA_MAX, q_cut=Q_CUT, r_min=R_MIN, rs_sigma=RS_SIGMA,
+             bin_guard=BIN_GUARD, sh_offset=SH_OFFSET, tile_log2=TILE_LOG2)
+    d.update(kw)
+    return _Params(**d)
+
+
+def view_struct(cam: dict) -> _View:
+    v = _View()
+    W = np.asarray(cam["W"], np.float32).astype(np.float64).reshape(-1)
+    for k in range(9):
+        v.W[k] = W[k]
+    for k in range(3):
+        v.b[k] = float(np.float32(cam["b"][k]))
+        v.center[k] = float(np.float32(cam["center"][k]))
+    v.cam_type = int(cam["cam_type"])
+    v.fov_x = float(cam["fov_x"])
+    v.fov_y = float(cam["fov_y"])
+    v.order = int(cam["order"])
+    return v
+
+
+class SceneRef:
+    """Keeps the float32 arrays alive while the C struct points at them."""
+
+    def __init__(self, scene):
+        self.arrs = [np.ascontiguousarray(a, dtype=np.float32) for a in
+                     (scene.mean, scene.scale, scene.rot, scene.opacity, scene.sh)]
+        self.s = _Scene(scene.P, scene.sh_degree, *[a.ctypes.data for a in self.arrs])
+        self.P = scene.P
+        self.K = (scene.sh_degree + 1) ** 2
+
+
+# ---------------------------------------------------------------------------
+# HEALPix geometry (Gorski et al. 2005; the grid of Sec. 3.1)
+# ---------------------------------------------------------------------------
+
+def npix(order: int) -> int:
+    return 12 * (1 << (2 * order))
+
+
+def nest2xyf(order, p):
+    p = np.ascontiguousarray(p, np.int64)
+    x = np.empty_like(p); y = np.empty_like(p); f = np.empty(p.shape, np.int32)
+    lib().or_nest2xyf(order, C.c_int64(p.size), _p(p), _p(x), _p(y), _p(f))
+    return x, y, f
+
+
+def xyf2nest(order, x, y, f):
+    x = np.ascontiguousarray(x, np.int64); y = np.ascontiguousarray(y, np.int64)
+    f = np.ascontiguousarray(f, np.int32); p = np.empty_like(x)
+    lib().or_xyf2nest(order, C.c_int64(x.size), _p(x), _p(y), _p(f), _p(p))
+    return p
+
+
+def nest2ring(order, p):
+    p = np.ascontiguousarray(p, np.int64); r = np.empty_like(p)
+    lib().or_nest2ring(order, C.c_int64(p.size), _p(p), _p(r))
+    return r
+
+
+def ring2nest_table(order):
+    """Inverse of nest2ring by inverting the full table (plain and exact)."""
+    p = np.arange(npix(order), dtype=np.int64)
+    r = nest2ring(order, p)
+    inv = np.full(p.size, -1, np.int64)
+    inv[r] = p
+    return inv
+
+
+def pix_ringinfo(order, p):
+    p = np.ascontiguousarray(p, np.int64)
+    jr = np.empty_like(p); jp = np.empty_like(p)
+    z = np.empty(p.shape, np.float64); phi = np.empty(p.shape, np.float64)
+    lib().or_pix_ringinfo(order, C.c_int64(p.size), _p(p), _p(jr), _p(jp), _p(z), _p(phi))
+    return jr, jp, z, phi
+
+
+def pix_vec(order, p):
+    """Camera-frame unit vectors [n][3] of nested pixel centres."""
+    p = np.ascontiguousarray(p, np.int64)
+    v = np.empty((p.size, 3), np.float64)
+    lib().or_pix_vec(order, C.c_int64(p.size), _p(p), _p(v))
+    return v
+
+
+def chart_pixel(order, f, x, y) -> int:
+    return int(lib().or_chart_pixel(order, int(f), C.c_int64(int(x)), C.c_int64(int(y))))
+
+
+def tile_order(order: int, tile_log2: int = TILE_LOG2) -> int:
+    return order - min(tile_log2, order)
+
+
+# ---------------------------------------------------------------------------
+# Camera mask (Sec. 3.1 M_C; supp. camera models)
+# ---------------------------------------------------------------------------
+
+def mask(cam: dict) -> np.ndarray:
+    v = view_struct(cam)
+    n = lib().or_mask(C.byref(v), None)
+    out = np.empty(n, np.int64)
+    lib().or_mask(C.byref(v), _p(out))
+    return out
+
+
+def nside_star(W: float, H: float, omega_in: float) -> float:
+    """Continuous matched resolution N* = sqrt(4 pi W H / (12 Omega_in)) (Sec. 3.1)."""
+    return math.sqrt(4 * math.pi * W * H / (12.0 * omega_in))
+
+
+def omega_in(kind: str, theta: float = 0.0, theta_x: float = 0.0, theta_y: float = 0.0) -> float:
+    """Visible solid angle: 4 pi (equirectangular), 2 pi (1 - cos theta)
+    (fisheye, half-FoV theta), 4 asin(sin theta_x sin theta_y) (perspective)."""
+    if kind == "erp":
+        return 4 * math.pi
+    if kind == "fisheye":
+        return 2 * math.pi * (1 - math.cos(theta))
+    if kind == "pinhole":
+        return 4 * math.asin(math.sin(theta_x) * math.sin(theta_y))
+    raise ValueError(kind)
+
+
+def orders_for(W, H, om):
+    """(k, k_L, k_H) = (round, floor, ceil) of log2 N* (Table tab:resolution)."""
+    l2 = math.log2(nside_star(W, H, om))
+    return int(round(l2)), int(math.floor(l2)), int(math.ceil(l2))
+
+
+# ---------------------------------------------------------------------------
+# SH, preprocessing, tiles, compositing, gradients, HSSIM
+# ---------------------------------------------------------------------------
+
+def sh_basis(deg: int, v: np.ndarray) -> np.ndarray:
+    v = np.ascontiguousarray(v, np.float64).reshape(-1, 3)
+    Y = np.zeros((v.shape[0], 16), np.float64)
+    lib().or_sh_basis(deg, C.c_int64(v.shape[0]), _p(v), _p(Y))
+    return Y[:, : (deg + 1) ** 2]
+
+
+@dataclass
+class Projected:
+    valid: np.ndarray
+    omega: np.ndarray
+    phi: np.ndarray
+    rho: np.ndarray
+    conic: np.ndarray   # [3][P]  (A, B, C)
+    sarc: np.ndarray    # [3][P]  Sigma_arc (omega-omega, omega-phi, phi-phi)
+    rs: np.ndarray
+    rgb: np.ndarray     # [3][P]
+
+    def dirs(self) -> np.ndarray:
+        """Camera-frame unit directions [3][P]."""
+        c = np.cos(self.phi)
+        return np.stack([c * np.sin(self.omega), np.sin(self.phi), c * np.cos(self.omega)])
+
+
+def preprocess(scene, cam, prm=None) -> Projected:
+    prm = prm or params()
+    S = SceneRef(scene)
+    v = view_struct(cam)
+    P = scene.P
+    valid = np.zeros(P, np.int32)
+    om = np.zeros(P); ph = np.zeros(P); rho = np.zeros(P); rs = np.zeros(P)
+    conic = np.zeros((3, P)); sarc = np.zeros((3, P)); rgb = np.zeros((3, P))
+    lib().or_preprocess(C.byref(S.s), C.byref(v), C.byref(prm), _p(valid), _p(om), _p(ph), _p(rho),
+                        _p(conic), _p(sarc), _p(rs), _p(rgb))
+    return Projected(valid, om, ph, rho, conic, sarc, rs, rgb)
+
+
+def tile_caps(order: int, tile_log2: int = TILE_LOG2):
+    kt = tile_order(order, tile_log2)
+    nt = 12 * (1 << (2 * kt))
+    c = np.zeros((nt, 3)); r = np.zeros(nt)
+    lib().or_tile_caps(order, tile_log2, _p(c), _p(r))
+    return c, r
+
+
+def tile_active(order: int, active: np.ndarray, tile_log2: int = TILE_LOG2) -> np.ndarray:
+    kt = tile_order(order, tile_log2)
+    nt = 12 * (1 << (2 * kt))
+    t = np.zeros(nt, np.uint8)
+    t[np.asarray(active) >> (2 * (order - kt))] = 1
+    return t
+
+
+def tile_sets(order, proj: Projected, active, gids=None, prm=None, caps=None, report_band=0.0):
+    """Binning definition: (gid, tile, margin, in) for every valid Gaussian in
+    gids and every active tile with distance(cap centre, Gaussian) within
+    r_s + R_t + guard (in = 1), plus near misses within report_band (in = 0)."""
+    prm = prm or params()
+    tc, tr = caps if caps is not None else tile_caps(order, prm.tile_log2)
+    ta = tile_active(order, active, prm.tile_log2)
+    P = proj.valid.size
+    gids = np.arange(P, dtype=np.int64) if gids is None else np.ascontiguousarray(gids, np.int64)
+    args = (order, C.byref(prm), _p(np.ascontiguousarray(tc)), _p(np.ascontiguousarray(tr)), _p(ta),
+            C.c_int64(gids.size), _p(gids), _p(proj.valid), _p(proj.omega), _p(proj.phi), _p(proj.rs),
+            C.c_double(report_band))
+    n = lib().or_tile_sets(*args, C.c_int64(0), None, None, None, None)
+    g = np.empty(n, np.int64); t = np.empty(n, np.int64); m = np.empty(n); i = np.empty(n, np.int32)
+    lib().or_tile_sets(*args, C.c_int64(n), _p(g), _p(t), _p(m), _p(i))
+    return g, t, m, i
+
+
+def sorted_tile_lists(order, proj: Projected, g, t, inn, prm=None):
+    """Per-tile lists ordered by (rho, gid) (Alg. 1 sort; ties by index).
+    Returns (list, ranges[ntile][2]) over the pairs with inn == 1."""
+    prm = prm or params()
+    kt = tile_order(order, prm.tile_log2)
+    nt = 12 * (1 << (2 * kt))
+    sel = inn.astype(bool)
+    g = g[sel]; t = t[sel]
+    order_idx = np.lexsort((g, proj.rho[g], t))
+    lst = g[order_idx]
+    ts = t[order_idx]
+    starts = np.searchsorted(ts, np.arange(nt), side="left")
+    ends = np.searchsorted(ts, np.arange(nt), side="right")
+    return lst, np.stack([starts, ends], axis=1).astype(np.int64)
+
+
+def render(scene, cam, proj: Projected, pix, prm=None, qtol=0.0, ttol=0.0):
+    """Brute-force compositing at nested pixels `pix` (Eq. unified_rendering).
+    Returns rgb [3][n], T [n], n_used [n], frag [n]."""
+    prm = prm or params()
+    S = SceneRef(scene)
+    v = view_struct(cam)
+    pix = np.ascontiguousarray(pix, np.int64)
+    n = pix.size
+    rgb = np.zeros((3, n)); T = np.zeros(n); nu = np.zeros(n, np.int64); fr = np.zeros(n)
+    lib().or_render(C.byref(S.s), C.byref(v), C.byref(prm), _p(proj.valid), _p(proj.omega), _p(proj.phi),
+                    _p(proj.rho), _p(np.ascontiguousarray(proj.conic)), _p(proj.rs),
+                    _p(np.ascontiguousarray(proj.rgb)), C.c_int64(n), _p(pix), C.c_double(qtol),
+                    C.c_double(ttol), _p(rgb), _p(T), _p(nu), _p(fr))
+    return rgb, T, nu, fr
+
+
+def n_contrib(scene, cam, proj: Projected, lst, ranges, pix, prm=None):
+    prm = prm or params()
+    S = SceneRef(scene)
+    v = view_struct(cam)
+    pix = np.ascontiguousarray(pix, np.int64)
+    out = np.zeros(pix.size, np.int64)
+    lst = np.ascontiguousarray(lst, np.int64)
+    ranges = np.ascontiguousarray(ranges, np.int64)
+    lib().or_n_contrib(C.byref(S.s), C.byref(v), C.byref(prm), _p(proj.omega), _p(proj.phi),
+                       _p(np.ascontiguousarray(proj.conic)), _p(lst), _p(ranges), C.c_int64(pix.size), _p(pix),
+                       _p(out))
+    return out
+
+
+@dataclass
+class Grads:
+    mean: np.ndarray
+    scale: np.ndarray
+    rot: np.ndarray
+    opacity: np.ndarray
+    sh: np.ndarray
+
+
+def render_bwd(scene, cam, proj: Projected, pix, dLdC, dLdT=None, prm=None) -> Grads:
+    """Exact gradients of L at pixels `pix` given dL/dC [3][n] and dL/dT [n]."""
+    prm = prm or params()
+    S = SceneRef(scene)
+    v = view_struct(cam)
+    pix = np.ascontiguousarray(pix, np.int64)
+    n = pix.size
+    P = scene.P
+    g = Grads(np.zeros((3, P)), np.zeros((3, P)), np.zeros((4, P)), np.zeros(P), np.zeros((S.K, 3, P)))
+    dLdC = np.ascontiguousarray(dLdC, np.float64)
+    dLdT = None if dLdT is None else np.ascontiguousarray(dLdT, np.float64)
+    lib().or_render_bwd(C.byref(S.s), C.byref(v), C.byref(prm), _p(proj.valid), _p(proj.omega), _p(proj.phi),
+                        _p(proj.rho), _p(np.ascontiguousarray(proj.conic)), _p(proj.rs),
+                        _p(np.ascontiguousarray(proj.rgb)), C.c_int64(n), _p(pix), _p(dLdC), _p(dLdT),
+                        _p(g.mean), _p(g.scale), _p(g.rot), _p(g.opacity), _p(g.sh))
+    return g
+
+
+def hssim(order, active, img, ref, sigma=SSIM_SIGMA, c1=SSIM_C1, c2=SSIM_C2, want_map=False, want_grad=False):
+    """Mean HEALPix-SSIM over active pixels and channels (Sec. 4.1, supp. eq.
+    for the masked average); optional map [3][n] and d mean / d img [3][n]."""
+    active = np.ascontiguousarray(active, np.int64)
+    img = np.ascontiguousarray(img, np.float64)
+    ref = np.ascontiguousarray(ref, np.float64)
+    n = active.size
+    m = np.zeros((3, n)) if want_map else None
+    g = np.zeros((3, n)) if want_grad else None
+    mean = lib().or_hssim(order, C.c_int64(n), _p(active), _p(img), _p(ref), C.c_double(sigma), C.c_double(c1),
+                          C.c_double(c2), _p(m), _p(g))
+    return mean, m, g
+
+
+def loss(order, active, img, ref, lam=LAMBDA, want_grad=False):
+    """L = (1 - lambda) L1 + lambda (1 - HSSIM) (Sec. 4.1); L1 = mean |img - ref|.
+    Returns (L, dL/dimg or None)."""
+    img = np.asarray(img, np.float64); ref = np.asarray(ref, np.float64)
+    l1 = float(np.mean(np.abs(img - ref)))
+    s, _, gs = hssim(order, active, img, ref, want_grad=want_grad)
+    L = (1 - lam) * l1 + lam * (1 - s)
+    if not want_grad:
+        return L, None
+    g = (1 - lam) * np.sign(img - ref) / img.size - lam * gs
+    return L, g

@@ -1,0 +1,258 @@
+"""Pins of the oracle's compositing (Eq. unified_rendering, Alg. 1 rendering
+loop), spherical offset (Sec. 3.4) and tile sets -- no GPU."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2606_29794_amd import scenes as SC
+
+
+def _scene(mean, scale, rot=None, opac=None, dc=None):
+    mean = np.asarray(mean, np.float32).reshape(3, -1)
+    P = mean.shape[1]
+    scale = np.asarray(scale, np.float32).reshape(3, P)
+    rot = np.tile(np.array([[1], [0], [0], [0]], np.float32), (1, P)) if rot is None else np.asarray(rot, np.float32)
+    opac = np.full(P, 0.5, np.float32) if opac is None else np.asarray(opac, np.float32)
+    dc = np.zeros((3, P)) if dc is None else np.asarray(dc, np.float64).reshape(3, P)
+    sh = (dc * math.sqrt(4 * math.pi))[None].astype(np.float32)
+    return SC.Scene(mean, scale, rot, opac, sh, 0)
+
+
+def _cam(order, W=None, c=None, cam_type=0, fx=2 * math.pi, fy=math.pi):
+    W = np.eye(3, dtype=np.float32) if W is None else np.asarray(W, np.float32)
+    c = np.zeros(3, np.float32) if c is None else np.asarray(c, np.float32)
+    b = (-(W.astype(np.float64) @ c.astype(np.float64))).astype(np.float32)
+    return dict(W=W, b=b, center=c, cam_type=cam_type, fov_x=fx, fov_y=fy, order=order)
+
+
+def _angles(v):
+    return np.arctan2(v[:, 0], v[:, 2]), np.arctan2(v[:, 1], np.hypot(v[:, 0], v[:, 2]))
+
+
+def test_single_isotropic_gaussian_analytic():
+    """One isotropic Gaussian: C(p) = c min(0.99, o exp(-d^2 r^2 / (2 s^2)))
+    where d = great-circle distance <= 3 s / r, and T = 1 - alpha."""
+    order = 6
+    d0 = np.array([0.3, 0.5, 0.8]); d0 /= np.linalg.norm(d0)
+    r, s, o = 4.0, 0.08, 0.7
+    sc = _scene((d0 * r)[:, None], [[s], [s], [s]], opac=[o], dc=[[0.2], [-0.1], [0.4]])
+    cam = _cam(order)
+    pr = O.preprocess(sc, cam)
+    pix = np.arange(O.npix(order))
+    rgb, T, nu, fr = O.render(sc, cam, pr, pix)
+    u = O.pix_vec(order, pix)
+    m = sc.mean[:, 0].astype(np.float64)
+    rr = np.linalg.norm(m)
+    g = m / rr
+    d = np.arctan2(np.linalg.norm(np.cross(u, g), axis=1), u @ g)
+    s32 = float(sc.scale[0, 0]); o32 = float(sc.opacity[0])
+    q = (d * rr / s32) ** 2
+    a = np.where(q <= 9, np.minimum(0.99, o32 * np.exp(-0.5 * q)), 0.0)
+    assert np.allclose(T, 1 - a, atol=1e-12)
+    for ch, c in enumerate([0.7, 0.4, 0.9]):
+        assert np.allclose(rgb[ch], c * a, atol=2e-7)   # colours are float32 SH inputs
+    assert (a > 0).sum() > 30
+
+
+def test_partition_of_unity_with_white_gaussians():
+    """With every colour 1 and background 0, C + T = 1 at every pixel
+    (front-to-back compositing telescopes), also where the loop stops early."""
+    sc = SC.make_scene(4000, 0, "volume", 2.0, 6.0, seed=5, log_scale_mu=-1.2, rgb_dc=True)
+    sc.opacity[:] = 0.9
+    sc.sh[:] = 0.5 * math.sqrt(4 * math.pi)
+    cam = _cam(5)
+    pr = O.preprocess(sc, cam)
+    pix = np.arange(O.npix(cam["order"]))
+    rgb, T, nu, fr = O.render(sc, cam, pr, pix)
+    for ch in range(3):
+        assert np.allclose(rgb[ch] + T, 1.0, atol=1e-12)
+    assert np.all((T >= 0) & (T <= 1))
+    assert (nu > 3).sum() > 100 and (T < 1e-4).sum() > 10
+
+
+def test_two_gaussians_ordered_by_radial_depth():
+    """Same direction, different depths: C = c1 a1 + c2 a2 (1 - a1) with 1 the
+    nearer (radial distance, not z-depth); the input order does not matter."""
+    order = 5
+    d0 = np.array([-0.2, 0.9, 0.1]); d0 /= np.linalg.norm(d0)
+    r1, r2 = 2.0, 5.0
+    s1, s2 = 0.2 * r1 / 4, 0.2 * r2 / 4     # the same angular size
+    cam = _cam(order)
+    pix = np.arange(O.npix(order))
+    outs = []
+    for order_in in [(0, 1), (1, 0)]:
+        rs = [r1, r2]; ss = [s1, s2]; cs = [[0.4, 0.1, 0.0], [-0.3, 0.2, 0.5]]
+        idx = list(order_in)
+        sc = _scene(np.stack([d0 * rs[i] for i in idx], 1), np.stack([[ss[i]] * 3 for i in idx], 1),
+                    opac=[0.6, 0.6], dc=np.stack([cs[i] for i in idx], 1))
+        pr = O.preprocess(sc, cam)
+        rgb, T, nu, fr = O.render(sc, cam, pr, pix)
+        outs.append(rgb)
+        near = idx.index(0); far = idx.index(1)
+        u = O.pix_vec(order, pix)
+        a = []
+        for k in (near, far):
+            m = sc.mean[:, k].astype(np.float64)
+            rr = np.linalg.norm(m)
+            d = np.arctan2(np.linalg.norm(np.cross(u, m / rr), axis=1), u @ (m / rr))
+            q = (d * rr / float(sc.scale[0, k])) ** 2
+            a.append(np.where(q <= 9, np.minimum(0.99, float(sc.opacity[k]) * np.exp(-0.5 * q)), 0.0))
+        c1 = np.array(cs[0]) + 0.5; c2 = np.array(cs[1]) + 0.5
+        for ch in range(3):
+            exp = c1[ch] * a[0] + c2[ch] * a[1] * (1 - a[0])
+            assert np.allclose(rgb[ch], exp, atol=1e-6)
+    assert np.allclose(outs[0], outs[1], atol=1e-15)
+
+
+def test_alpha_integral():
+    """sum_p alpha(p) Omega_pix -> 2 pi o sqrt(det Sigma_arc) (1 - e^-4.5) for a
+    footprint much larger than a pixel and much smaller than a radian."""
+    order = 8
+    rng = np.random.default_rng(4)
+    for _ in range(3):
+        d0 = rng.normal(size=3); d0 /= np.linalg.norm(d0)
+        r = 3.0
+        s = np.array([0.06, 0.1, 0.02])
+        q = rng.normal(size=4); q /= np.linalg.norm(q)
+        sc = _scene((d0 * r)[:, None], s[:, None], rot=q[:, None], opac=[0.4], dc=[[0.5], [0.5], [0.5]])
+        cam = _cam(order)
+        pr = O.preprocess(sc, cam)
+        pix = np.arange(O.npix(order))
+        rgb, T, nu, fr = O.render(sc, cam, pr, pix)
+        alpha = 1 - T
+        integral = alpha.sum() * 4 * math.pi / O.npix(order)
+        det = pr.sarc[0, 0] * pr.sarc[2, 0] - pr.sarc[1, 0] ** 2
+        expect = 2 * math.pi * float(sc.opacity[0]) * math.sqrt(det) * (1 - math.exp(-4.5))
+        assert abs(integral - expect) / expect < 1.5e-2
+
+
+def test_camera_yaw_by_90_degrees_permutes_pixels():
+    """The grid is fixed in the camera frame and maps onto itself under a
+    90-degree rotation about the pole (camera +y); yawing the camera by 90
+    degrees (same centre) therefore permutes the image exactly: ring position
+    j -> j - n_r / 4.  World view directions are unchanged, so SH colours are
+    too."""
+    wl = SC.config0(P=300)
+    sc = wl.scene
+    rng = np.random.default_rng(9)
+    sc.sh = rng.normal(0, 0.3, size=(16, 3, sc.P)).astype(np.float32)
+    sc.sh_degree = 3
+    order = 5
+    W = SC.random_rotation(rng).astype(np.float32)
+    c = np.array([0.1, -0.2, 0.05], np.float32)
+    cam = _cam(order, W, c)
+    Ry = np.array([[0, 0, 1], [0, 1, 0], [-1, 0, 0]], np.float32)   # exact in float32
+    cam2 = _cam(order, Ry @ W, c)
+    cam2["b"] = (Ry.astype(np.float64) @ cam["b"].astype(np.float64)).astype(np.float32)
+    pix = np.arange(O.npix(order))
+    img1 = O.render(sc, cam, O.preprocess(sc, cam), pix)[0]
+    img2 = O.render(sc, cam2, O.preprocess(sc, cam2), pix)[0]
+    jr, jp, z, phi = O.pix_ringinfo(order, pix)
+    N = 1 << order
+    lut = {(a, b): p for a, b, p in zip(jr, jp, pix)}
+    perm = np.empty_like(pix)
+    for p in pix:
+        a, b = jr[p], jp[p]
+        nr = 4 * min(a, N, 4 * N - a)
+        perm[p] = lut[(a, (b - 1 - nr // 4) % nr + 1)]
+    assert np.abs(img1).max() > 0.1
+    assert np.allclose(img2, img1[:, perm], atol=1e-9)
+
+
+def test_offset_matches_azimuthal_equidistant_vector_form():
+    """The haversine/bearing offset equals the vector form
+    d = atan2(|v|, u_p . u_g) (u_p . e_w, u_p . e_p) / |v| (tangent frame at the
+    Gaussian), which is how the GPU evaluates it; checked through q."""
+    order = 6
+    rng = np.random.default_rng(11)
+    for _ in range(5):
+        d0 = rng.normal(size=3); d0 /= np.linalg.norm(d0)
+        s = np.exp(rng.normal(-1.5, 0.3, size=3))
+        q = rng.normal(size=4); q /= np.linalg.norm(q)
+        sc = _scene((d0 * 2.5)[:, None], s[:, None], rot=q[:, None], opac=[0.9], dc=[[0.5], [0.5], [0.5]])
+        cam = _cam(order)
+        pr = O.preprocess(sc, cam)
+        pix = np.arange(O.npix(order))
+        _, T, _, _ = O.render(sc, cam, pr, pix)
+        w, p = pr.omega[0], pr.phi[0]
+        ug = np.array([math.cos(p) * math.sin(w), math.sin(p), math.cos(p) * math.cos(w)])
+        ew = np.array([math.cos(w), 0, -math.sin(w)])
+        ep = np.array([-math.sin(p) * math.sin(w), math.cos(p), -math.sin(p) * math.cos(w)])
+        u = O.pix_vec(order, pix)
+        a, b, c = u @ ew, u @ ep, u @ ug
+        sn = np.hypot(a, b)
+        k = np.arctan2(sn, c) / sn
+        A, B, Cc = pr.conic[:, 0]
+        qq = k * k * (A * a * a + 2 * B * a * b + Cc * b * b)
+        alpha = np.where(qq <= 9, np.minimum(0.99, float(sc.opacity[0]) * np.exp(-0.5 * qq)), 0)
+        ok = np.abs(qq - 9) > 1e-6
+        assert np.allclose((1 - T)[ok], alpha[ok], atol=1e-10)
+
+
+def test_early_termination():
+    """T < eps stops compositing right after the Gaussian that crossed it."""
+    order = 4
+    d0 = np.array([0.0, 0.0, 1.0])
+    P = 12
+    rs_ = np.linspace(2, 5, P)
+    sc = _scene(np.stack([d0 * r for r in rs_], 1), np.stack([[0.2 * r] * 3 for r in rs_], 1),
+                opac=np.full(P, 0.95), dc=np.zeros((3, P)))
+    cam = _cam(order)
+    pr = O.preprocess(sc, cam)
+    pix = O.mask(cam)
+    rgb, T, nu, fr = O.render(sc, cam, pr, pix)
+    centre = np.argmax(O.pix_vec(order, pix) @ d0)
+    # alpha clamps to 0.95 near the centre: T = 0.05^k < 1e-4 after k = 4
+    assert nu[centre] == 4 and T[centre] < 1e-4 and T[centre] > 1e-4 * 0.05 * 0.9
+
+
+def test_tile_caps_contain_their_pixels():
+    order = 6
+    tc, tr = O.tile_caps(order)
+    kt = O.tile_order(order)
+    per = 1 << (2 * (order - kt))
+    u = O.pix_vec(order, np.arange(O.npix(order)))
+    for t in range(0, tc.shape[0], 7):
+        ang = np.arctan2(np.linalg.norm(np.cross(u[t * per:(t + 1) * per], tc[t]), axis=1), u[t * per:(t + 1) * per] @ tc[t])
+        assert ang.max() <= tr[t] + 1e-15
+        assert abs(ang.max() - tr[t]) < 1e-15
+
+
+def test_tile_sets_are_conservative_and_lists_sorted():
+    """Every (pixel, Gaussian) with q <= 9 has the pixel's tile in T_i (so
+    rendering from the tile lists equals brute force), and the per-tile lists
+    are ordered by (rho, index)."""
+    wl = SC.config0(P=600)
+    sc, cam = wl.scene, wl.cameras[0]
+    order = cam["order"]
+    pr = O.preprocess(sc, cam)
+    act = O.mask(cam)
+    g, t, m, inn = O.tile_sets(order, pr, act)
+    assert np.all(inn == 1) and np.all(m >= 0)
+    lst, ranges = O.sorted_tile_lists(order, pr, g, t, inn)
+    kt = O.tile_order(order)
+    sets = {}
+    for gg, tt in zip(g, t):
+        sets.setdefault(int(gg), set()).add(int(tt))
+    u = O.pix_vec(order, act)
+    om, ph = _angles(u)
+    # brute-force q at every pixel for a sample of Gaussians
+    for i in range(0, sc.P, 5):
+        if not pr.valid[i]:
+            continue
+        ug = np.array([math.cos(pr.phi[i]) * math.sin(pr.omega[i]), math.sin(pr.phi[i]),
+                       math.cos(pr.phi[i]) * math.cos(pr.omega[i])])
+        ang = np.arctan2(np.linalg.norm(np.cross(u, ug), axis=1), u @ ug)
+        near = np.nonzero(ang <= pr.rs[i])[0]
+        tiles = set((act[near] >> (2 * (order - kt))).tolist())
+        assert tiles <= sets.get(i, set()), i
+    for tt in range(ranges.shape[0]):
+        ids = lst[ranges[tt, 0]:ranges[tt, 1]]
+        key = list(zip(pr.rho[ids], ids))
+        assert key == sorted(key)
+    # rendering from the lists (n_contrib walk) visits every contributor
+    nc = O.n_contrib(sc, cam, pr, lst, ranges, act)
+    rgb, T, nu, fr = O.render(sc, cam, pr, act)
+    assert np.all(nc >= nu)
