@@ -1,0 +1,270 @@
+/*
+ * hp.h -- C ABI of the HEALPix Gaussian rasterizer for AMD Instinct MI355X
+ * (gfx950).  Every operation runs in hand-written HIP kernels; this header
+ * only uses plain C types.
+ *
+ * Conventions (all calls):
+ *  - Device pointers point to device (HBM) memory owned by the caller.  The
+ *    library never allocates or frees memory; scratch space comes from a
+ *    caller buffer whose size the matching _bytes / _workspace_bytes
+ *    function returns.  Buffers must be 256-byte aligned (hipMalloc and
+ *    torch allocations are).
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    Every call only enqueues work and returns without waiting, except the
+ *    read-back helpers whose names end in _counts/_total, which wait for the
+ *    stream.
+ *  - Arrays are float32 structure-of-arrays [component][count].
+ *  - Argument checks happen on the host before anything is enqueued and
+ *    return HP_ERR_INVALID_ARG / HP_ERR_UNSUPPORTED without side effects.
+ *    A failed launch returns HP_ERR_DEVICE.  Calls keep no global state and
+ *    may run concurrently on different streams with different buffers.
+ *
+ * The method is the camera-agnostic 3D Gaussian rasterizer on the HEALPix
+ * equal-area sphere grid of arXiv 2606.29794 ("UniTriSplat"): Sec. 3.1
+ * (grid, NESTED (x, y, f) indexing, tiles of B x B samples, visibility
+ * mask), Sec. 3.2 (projection Pi, Eq. lonlat_projection; latitude scaling,
+ * Eq. arc_scaling; gradients, Eqs. backward_lat_scale and grad_via_J_S),
+ * Sec. 3.3 (tile query), Sec. 3.4 (spherical offset, Eq.
+ * unified_rendering), Sec. 4.1 (HEALPix-SSIM and the training loss) and
+ * supplementary Alg. 1 (the three-stage pipeline).
+ */
+#ifndef HP_H
+#define HP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t hp_status;
+#define HP_OK 0
+#define HP_ERR_INVALID_ARG 1 /* null pointer, bad size, order/degree out of range */
+#define HP_ERR_UNSUPPORTED 2 /* valid request this build does not handle */
+#define HP_ERR_CAPACITY 3    /* caller buffer too small (see the call) */
+#define HP_ERR_DEVICE 4      /* HIP launch/runtime error */
+
+#define HP_CAM_FULL 0    /* full sphere (omnidirectional / equirectangular) */
+#define HP_CAM_FISHEYE 1 /* anisotropic equidistant fisheye, FoV (fov_x, fov_y) */
+#define HP_CAM_PINHOLE 2 /* perspective, half-FoVs fov_x/2, fov_y/2 */
+
+#define HP_MAX_ORDER 12  /* Nside up to 4096 */
+#define HP_MAX_SH_DEGREE 3
+
+/* Constants of the method.  Defaults (hp_default_params):
+ *   eps_T = 1e-4     early termination once T < eps_T (Alg. 1 rendering loop)
+ *   alpha_max = 0.99 opacity clamp
+ *   q_cut = 9        a Gaussian reaches a pixel only where d^T Sigma^-1 d <= 9
+ *   r_min = 0.1      Gaussians with radial depth below r_min are culled
+ *   rs_sigma = 3     bounding radius r_s = 3 sqrt(lambda_max(Sigma_arc)) (Sec. 3.2)
+ *   bin_guard = 1e-6 radians added to the tile-overlap test
+ *   sh_offset = 0.5  colour = max(0, sh_offset + sum_lm sh_lm Y_lm(view dir))
+ *   tile_log2 = 4    tiles of B x B = 16 x 16 samples (Table tab:resolution);
+ *                    below order 4 the tile is the whole face (B = Nside). */
+typedef struct {
+  float eps_T, alpha_max, q_cut, r_min, rs_sigma, bin_guard, sh_offset;
+  int32_t tile_log2;
+} hp_params;
+
+/* One camera.  W: world->camera rotation, row-major; b = -W * center; the
+ * HEALPix grid is fixed in the camera frame with its pole on camera +y and
+ * longitude omega = atan2(t_x, t_z) (Eq. lonlat_projection).  order k gives
+ * Nside = 2^k, Npix = 12 * 4^k.  fov_x/fov_y in radians (ignored for FULL). */
+typedef struct {
+  float W[9], b[3], center[3];
+  int32_t cam_type;
+  float fov_x, fov_y;
+  int32_t order;
+} hp_view;
+
+/* Gaussians (Alg. 1 input {(mu, s, q, o, c)}), device pointers:
+ *   mean [3][P], scale [3][P] (> 0, already exponentiated),
+ *   rot [4][P] quaternion (w, x, y, z), normalised inside the library,
+ *   opacity [P] in (0, 1) (already through the sigmoid),
+ *   sh [(d+1)^2][3][P] real SH coefficients, d = sh_degree in 0..3. */
+typedef struct {
+  int64_t P;
+  int32_t sh_degree;
+  const float *mean, *scale, *rot, *opacity, *sh;
+} hp_gaussians;
+
+/* Gradients, same shapes as hp_gaussians; ACCUMULATED into (+=). */
+typedef struct {
+  float *mean, *scale, *rot, *opacity, *sh;
+} hp_gaussians_grad;
+
+/* HEALPix-SSIM constants (Sec. 4.1; window of Wang et al. 2004):
+ * 11 x 11 window on face-local (x, y), Gaussian sigma, C1 = (0.01)^2,
+ * C2 = (0.03)^2, loss weight lambda = 0.2. */
+typedef struct {
+  float sigma, C1, C2, lambda;
+} hp_ssim_params;
+
+void hp_default_params(hp_params* p);
+void hp_default_ssim_params(hp_ssim_params* p);
+const char* hp_status_string(hp_status s);
+
+/* ---- grid ------------------------------------------------------------
+ * hp_grid_init: geometry tables of one HEALPix order, independent of any
+ * camera (the grid is camera-fixed): for every node of the NESTED quadtree
+ * from the 12 base faces (level 0) down to the tiles (level k_t = k - b,
+ * b = min(tile_log2, k)), a bounding cap (unit centre, angular radius).  A
+ * tile's cap is centred on the normalised sum of its B x B pixel-centre
+ * directions with radius the largest angle to them; a parent's cap contains
+ * its children's caps.  Computed in FP64 on the device, stored as float.
+ * grid: device buffer of hp_grid_bytes(order, tile_log2) bytes. */
+size_t hp_grid_bytes(int32_t order, int32_t tile_log2);
+hp_status hp_grid_init(int32_t order, const hp_params* prm, void* grid, size_t grid_bytes, void* stream);
+
+/* ---- visibility mask (Sec. 3.1: M_C(p) = 1[(omega_p, phi_p) in R_C]) ----
+ * Marks the pixels whose centre lies in the camera's field of view, decided
+ * in FP64 on pixel-centre directions:
+ *   FULL: all;  FISHEYE: incident angle psi <= (pi/2) w_eff(gamma) with
+ *   w_eff = sqrt((w_x cos gamma)^2 + (w_y sin gamma)^2), w = FoV/pi (supp.
+ *   anisotropic equidistant model);  PINHOLE: t_z > 0, |t_x| <= tan(fov_x/2) t_z,
+ *   |t_y| <= tan(fov_y/2) t_z.
+ * The mask depends only on (order, cam_type, fov_x, fov_y), not on the pose.
+ * mask: device buffer of hp_mask_bytes(order, tile_log2) bytes receiving:
+ *   the sorted list of active NESTED pixels (int32), per tile the offset of
+ *   its first active pixel in that list, its active count and 256-bit
+ *   membership, the compact index of every active tile, and per quadtree node
+ *   whether any active pixel lies below it.
+ * hp_mask_counts waits for `stream` and returns n_active (active pixels) and
+ * n_tiles (active tiles); outputs of the other calls are indexed by these.
+ * hp_mask_active_pix returns the device pointer to the int32 active pixel
+ * list inside `mask`. */
+size_t hp_mask_bytes(int32_t order, int32_t tile_log2);
+hp_status hp_mask(const hp_view* view, const hp_params* prm, const void* grid, void* mask, size_t mask_bytes,
+                  void* stream);
+hp_status hp_mask_counts(const void* mask, int32_t order, int32_t tile_log2, int64_t* n_active,
+                         int32_t* n_tiles, void* stream);
+const int32_t* hp_mask_active_pix(const void* mask, int32_t order, int32_t tile_log2);
+
+/* ---- stage 1: preprocessing (Alg. 1; Eqs. lonlat_projection, arc_scaling) --
+ * Per Gaussian: t = W mu + b, r = |t|, (omega, phi) = Pi(t);
+ * Sigma_3D = R diag(s^2) R^T; Sigma_arc = S_phi J W Sigma_3D W^T J^T S_phi
+ * with S_phi = diag(cos phi, 1), evaluated as (1/r^2) E W Sigma_3D W^T E^T where
+ * E = [e_omega; e_phi] is the unit tangent frame (the same matrix: S_phi J =
+ * E / r); conic = Sigma_arc^-1; r_s = min(pi, 3 sqrt(lambda_max)); colour
+ * from SH at the world direction normalise(mu - center).  Culled (r < r_min
+ * or det Sigma_arc <= 0) Gaussians get radius 0 and depth +inf.
+ * projected: device buffer of hp_projected_bytes(P) bytes: a 64-byte record
+ * per Gaussian (unit direction, opacity, tangent frame, conic, colour) plus
+ * depth [P] and radius [P] float arrays. */
+size_t hp_projected_bytes(int64_t P);
+hp_status hp_preprocess(const hp_gaussians* g, const hp_view* view, const hp_params* prm, void* projected,
+                        size_t projected_bytes, void* stream);
+const float* hp_projected_depth(const void* projected, int64_t P);
+/* Serving form of hp_preprocess: n_views (1..8) cameras in one launch that
+ * reads every Gaussian once; projected[v] (host array of device pointers,
+ * each of hp_projected_bytes(P) bytes) receives view v. */
+hp_status hp_preprocess_batch(const hp_gaussians* g, int32_t n_views, const hp_view* views, const hp_params* prm,
+                              void* const* projected, size_t projected_bytes, void* stream);
+const float* hp_projected_radius(const void* projected, int64_t P);
+
+/* ---- stage 2a: tile assignment (Alg. 1 QueryDisc + pair emission) --------
+ * T_i = { active tiles t : angle(cap centre_t, dir_i) <= r_s,i + R_t + bin_guard }
+ * (the tile's bounding cap against the Gaussian's r_s disc), found by a
+ * pruned traversal of the NESTED quadtree: each Gaussian walks the tree down
+ * to three levels above the tiles and every passing node there becomes a task
+ * whose subtree (at most 64 tiles) is walked separately, so no walk is long.
+ * Pairs (key = compact active tile index, val = Gaussian index) are emitted
+ * in order of increasing radial depth (ties by index), so a stable sort on the
+ * tile key alone yields the per-tile front-to-back order of Alg. 1.
+ * phase: HP_BIN_COUNT counts pairs (writes *n_pairs, device int64),
+ *        HP_BIN_EMIT writes them (needs a previous COUNT on the same ws),
+ *        HP_BIN_ALL does both.  If *n_pairs > capacity, EMIT writes nothing;
+ *        the caller reads *n_pairs (hp_read_total) and calls EMIT again with
+ *        larger buffers.  COUNT and EMIT each wait once for `stream` to read
+ *        the task count; COUNT returns HP_ERR_CAPACITY if the tasks exceed the
+ *        workspace (16 P + 2^20 of them).
+ * keys/vals: device uint32 [capacity]; ws: hp_bin_workspace_bytes(P). */
+#define HP_BIN_COUNT 1
+#define HP_BIN_EMIT 2
+#define HP_BIN_ALL 3
+size_t hp_bin_workspace_bytes(int64_t P);
+hp_status hp_bin(int32_t phase, const void* projected, int64_t P, const hp_view* view, const hp_params* prm,
+                 const void* grid, const void* mask, uint32_t* keys, uint32_t* vals, int64_t capacity,
+                 int64_t* n_pairs, void* ws, size_t ws_bytes, void* stream);
+/* Waits for `stream` and copies one device int64 to the host. */
+hp_status hp_read_total(const int64_t* dev_value, int64_t* host_value, void* stream);
+
+/* ---- stage 2b: sort + tile ranges (Alg. 1: sort by tile then depth,
+ * identify [start_t, end_t)) -------------------------------------------------
+ * Stable LSD radix sort of (keys, vals) on the tile key; n_pairs is the host
+ * count.  The sorted values are written back to vals (keys too).  tile_ranges
+ * [n_tiles][2] receives (start, end) of each active tile's list in vals.
+ * ws: hp_sort_workspace_bytes(n_pairs, n_tiles). */
+size_t hp_sort_workspace_bytes(int64_t n_pairs, int32_t n_tiles);
+hp_status hp_sort(uint32_t* keys, uint32_t* vals, int64_t n_pairs, int32_t n_tiles, uint32_t* tile_ranges, void* ws,
+                  size_t ws_bytes, void* stream);
+
+/* ---- stage 3: rendering (Eq. unified_rendering; Alg. 1 rendering loop) ----
+ * For each active pixel p, in its tile's list order: d = spherical offset of
+ * p from the Gaussian centre (great-circle distance along the bearing, Sec.
+ * 3.4), q = d^T conic d; where q <= q_cut: alpha = min(alpha_max, o e^{-q/2}),
+ * C += T alpha c, T *= 1 - alpha, stop once T < eps_T.
+ * Outputs over the n_active active pixels (mask order): rgb [3][n_active],
+ * T [n_active] (final transmittance; background is left to the caller),
+ * n_contrib [n_active] (list entries consumed, skipped ones included). */
+hp_status hp_render_fwd(const void* projected, int64_t P, const uint32_t* vals, const uint32_t* tile_ranges,
+                        int32_t n_tiles, const hp_view* view, const hp_params* prm, const void* mask, int64_t n_active,
+                        float* rgb, float* T, int32_t* n_contrib, void* stream);
+
+/* Serving form of hp_render_fwd: up to 16 independent renders (different
+ * cameras, orders and scenes) in ONE launch whose workgroups cover the union
+ * of their active tiles; every output equals that of hp_render_fwd on the same
+ * request alone (bit for bit: no atomics in the forward). */
+typedef struct {
+  const void* projected;
+  int64_t P;
+  const uint32_t* vals;
+  const uint32_t* tile_ranges;
+  int32_t n_tiles;
+  int32_t order;
+  const void* mask;
+  int64_t n_active;
+  float* rgb;
+  float* T;
+  int32_t* n_contrib;
+} hp_render_req;
+hp_status hp_render_fwd_batch(int32_t n_req, const hp_render_req* reqs, const hp_params* prm, void* stream);
+
+/* ---- backward (Sec. 3.2 Eqs. backward_lat_scale, grad_via_J_S) ------------
+ * Reverse traversal per pixel from n_contrib with T recomputed as
+ * T_j = T_{j+1} / (1 - alpha_j) (no per-Gaussian forward state), gradients
+ * of alpha through q to the conic and the Gaussian direction, then per
+ * Gaussian through Sigma_arc, S_phi, J, W to scale and rotation and through
+ * t = W mu + b and the SH view direction to the mean; SH coefficients and
+ * opacities directly.  dL_drgb [3][n_active], dL_dT [n_active] (nullable).
+ * Gradients are accumulated into `grad`.  ws: hp_render_bwd_workspace_bytes(P). */
+size_t hp_render_bwd_workspace_bytes(int64_t P);
+hp_status hp_render_bwd(const hp_gaussians* g, const void* projected, const uint32_t* vals,
+                        const uint32_t* tile_ranges, int32_t n_tiles, const hp_view* view, const hp_params* prm,
+                        const void* mask, int64_t n_active, const float* T, const int32_t* n_contrib,
+                        const float* dL_drgb, const float* dL_dT, hp_gaussians_grad* grad, void* ws, size_t ws_bytes,
+                        void* stream);
+
+/* ---- HEALPix-SSIM and the training loss (Sec. 4.1) ------------------------
+ * Per active pixel and channel, Gaussian-weighted 11x11 statistics over
+ * face-local (x, y) offsets, neighbours across face edges taken in the
+ * neighbouring face with its axes rotated to line up; the missing quadrant at
+ * the eight three-face vertices and inactive pixels get weight 0 and the rest
+ * is renormalised.  SSIM = ((2 mx my + C1)(2 sxy + C2)) / ((mx^2 + my^2 + C1)
+ * (sx^2 + sy^2 + C2)).  out[0] = mean SSIM over active pixels and channels
+ * (the masked average of the supplementary HSSIM metric), out[1] = mean L1,
+ * out[2] = L = (1 - lambda) L1 + lambda (1 - mean SSIM).
+ * img, ref: [3][n_active] in mask order; ssim_map [3][n_active] nullable.
+ * If dL_dloss (device scalar) is non-null, dL_dimg [3][n_active] receives
+ * dL_dloss * dL/dimg.  Requires order >= 3.  ws: hp_ssim_workspace_bytes. */
+size_t hp_ssim_workspace_bytes(int32_t order, int32_t tile_log2, int64_t n_active);
+hp_status hp_ssim(const float* img, const float* ref, int64_t n_active, int32_t n_tiles, int32_t order,
+                  const hp_params* prm, const hp_ssim_params* sp, const void* mask, float* out, float* ssim_map,
+                  const float* dL_dloss, float* dL_dimg, void* ws, size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HP_H */

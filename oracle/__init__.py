@@ -112,8 +112,9 @@ def view_struct(cam: dict) -> _View:
         v.b[k] = float(np.float32(cam["b"][k]))
         v.center[k] = float(np.float32(cam["center"][k]))
     v.cam_type = int(cam["cam_type"])
-    v.fov_x = float(cam["fov_x"])
-    v.fov_y = float(cam["fov_y"])
+    # the C ABI carries the field of view as float32: use the same input value
+    v.fov_x = float(np.float32(cam["fov_x"]))
+    v.fov_y = float(np.float32(cam["fov_y"]))
     v.order = int(cam["order"])
     return v
 

@@ -1,0 +1,309 @@
+// k_render.hip -- stage 3 of Alg. 1 (front-to-back compositing on the
+// HEALPix grid, Eq. unified_rendering) and its per-pixel backward pass.
+//
+// One 256-thread workgroup per active tile; each of its four waves owns 64
+// consecutive active pixels of the tile and walks the tile's depth-sorted
+// Gaussian list on its own (no barriers): the list index is wave-uniform, so
+// the Gaussian id and its 64-byte record are scalar loads shared by all lanes,
+// and a wave leaves the list as soon as all its pixels are saturated.
+#include "hp_common.h"
+#include "hp_offset.h"
+
+struct RenderArgs {
+  int order;
+  const int32_t* active_tiles;
+  const int32_t* tile_start;
+  const int32_t* tile_count;
+  const int32_t* active_pix;
+  const float4* rec;
+  const uint32_t* vals;
+  const uint32_t* ranges;
+  float eps_T, alpha_max, q_cut;
+  int64_t n_active;
+};
+
+__device__ __forceinline__ void pixel_of_lane(const RenderArgs& A, int ct, bool* valid, int64_t* slot, float* p) {
+  const int t = A.active_tiles[ct];
+  const int cnt = A.tile_count[t];
+  const int local = threadIdx.x;
+  *valid = local < cnt;
+  *slot = (int64_t)A.tile_start[t] + local;
+  p[0] = p[1] = p[2] = 0.f;
+  if (*valid) {
+    double v[3];
+    hp_pix_dir(A.order, A.active_pix[*slot], v);
+    p[0] = (float)v[0]; p[1] = (float)v[1]; p[2] = (float)v[2];
+  }
+}
+
+static RenderArgs make_args(const HpGeom& g, const HpMaskView& mv, const HpProjView& pv, const uint32_t* vals,
+                            const uint32_t* ranges, const hp_params* prm, int64_t n_active) {
+  RenderArgs A;
+  A.order = g.order;
+  A.active_tiles = mv.active_tiles;
+  A.tile_start = mv.tile_start;
+  A.tile_count = mv.tile_count;
+  A.active_pix = mv.active_pix;
+  A.rec = pv.rec;
+  A.vals = vals;
+  A.ranges = ranges;
+  A.eps_T = prm->eps_T;
+  A.alpha_max = prm->alpha_max;
+  A.q_cut = prm->q_cut;
+  A.n_active = n_active;
+  return A;
+}
+
+struct RenderOut {
+  float* rgb;
+  float* T;
+  int32_t* ncon;
+};
+
+__device__ __forceinline__ void render_fwd_tile(const RenderArgs& A, const RenderOut& O, int ct) {
+  bool valid;
+  int64_t slot;
+  float p[3];
+  pixel_of_lane(A, ct, &valid, &slot, p);
+  const uint32_t j0 = hp_uniform(A.ranges[2 * ct]), j1 = hp_uniform(A.ranges[2 * ct + 1]);
+  float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
+  bool done = !valid;
+  uint32_t used = j1 - j0;
+  const hp_cu32p vals = (hp_cu32p)A.vals;
+  const hp_cfloatp rec = (hp_cfloatp)A.rec;
+  for (uint32_t j = j0; j < j1; ++j) {
+    if (__ballot(!done) == 0) break;
+    const uint32_t g = hp_uniform(vals[hp_uniform(j)]);
+    float4 r0, r1, r2, r3;
+    hp_load_rec(rec, g, r0, r1, r2, r3);
+    if (done) continue;
+    const float a = p[0] * r1.x + p[2] * r1.y;
+    const float b = p[0] * r1.z + p[1] * r1.w + p[2] * r2.x;
+    const float qt = a * (r2.y * a + 2.f * r2.z * b) + r2.w * b * b;
+    if (!(qt <= A.q_cut)) continue;  // q >= qt
+    const float c = p[0] * r0.x + p[1] * r0.y + p[2] * r0.z;
+    const float q = qt * hp_k2(a * a + b * b, c);
+    if (!(q <= A.q_cut)) continue;
+    const float alpha = fminf(A.alpha_max, r0.w * __expf(-0.5f * q));
+    const float w = alpha * T;
+    C0 += w * r3.x;
+    C1 += w * r3.y;
+    C2 += w * r3.z;
+    T -= w;
+    if (T < A.eps_T) {
+      done = true;
+      used = j + 1 - j0;
+    }
+  }
+  if (valid) {
+    O.rgb[slot] = C0;
+    O.rgb[A.n_active + slot] = C1;
+    O.rgb[2 * A.n_active + slot] = C2;
+    O.T[slot] = T;
+    O.ncon[slot] = (int32_t)used;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_render_fwd(RenderArgs A, RenderOut O) { render_fwd_tile(A, O, blockIdx.x); }
+
+// Several requests in one launch: block b renders tile b - first[r] of
+// request r, where first[] is the prefix of the requests' tile counts.
+#define HP_MAX_BATCH 16
+struct RenderBatch {
+  int n;
+  int first[HP_MAX_BATCH + 1];
+  RenderArgs A[HP_MAX_BATCH];
+  RenderOut O[HP_MAX_BATCH];
+};
+
+__global__ __launch_bounds__(256) void k_render_fwd_batch(RenderBatch B) {
+  const int b = blockIdx.x;
+  int r = 0;
+  while (r + 1 < B.n && b >= B.first[r + 1]) ++r;
+  render_fwd_tile(B.A[r], B.O[r], b - B.first[r]);
+}
+
+// Per-Gaussian gradient accumulators written by the pixel pass:
+// [0..2] colour, [3] opacity, [4..6] conic (A, B, C), [7] omega, [8] phi.
+#define HP_NACC 9
+
+__global__ __launch_bounds__(256) void k_render_bwd(RenderArgs A, int64_t P, const float* __restrict__ Tfin,
+                                                    const int32_t* __restrict__ ncon, const float* __restrict__ gC,
+                                                    const float* __restrict__ gTfin, float* __restrict__ acc) {
+  const int ct = blockIdx.x;
+  bool valid;
+  int64_t slot;
+  float p[3];
+  pixel_of_lane(A, ct, &valid, &slot, p);
+  const uint32_t j0 = hp_uniform(A.ranges[2 * ct]);
+  const hp_cu32p vals = (hp_cu32p)A.vals;
+  const hp_cfloatp rec = (hp_cfloatp)A.rec;
+  int nc = 0;
+  float Tf = 1.f, g0 = 0.f, g1 = 0.f, g2 = 0.f, gT = 0.f;
+  if (valid) {
+    nc = ncon[slot];
+    Tf = Tfin[slot];
+    g0 = gC[slot];
+    g1 = gC[A.n_active + slot];
+    g2 = gC[2 * A.n_active + slot];
+    gT = gTfin ? gTfin[slot] : 0.f;
+  }
+  // wave-uniform trip count: the largest n_contrib of the wave
+  int ncmax = nc;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) ncmax = max(ncmax, __shfl_xor(ncmax, off, 64));
+  float Tcur = Tf;                     // transmittance after the current entry
+  float S0 = 0.f, S1 = 0.f, S2 = 0.f;  // colour composited behind the current entry
+  const float gTT = gT * Tf;
+  ncmax = (int)hp_uniform((uint32_t)ncmax);
+  for (int k = ncmax - 1; k >= 0; --k) {
+    const uint32_t g = hp_uniform(vals[j0 + (uint32_t)k]);
+    float4 r0, r1, r2, r3;
+    hp_load_rec(rec, g, r0, r1, r2, r3);
+    float v[HP_NACC];
+#pragma unroll
+    for (int m = 0; m < HP_NACC; ++m) v[m] = 0.f;
+    bool hit = false;
+    if (k < nc) {
+      const float a = p[0] * r1.x + p[2] * r1.y;
+      const float b = p[0] * r1.z + p[1] * r1.w + p[2] * r2.x;
+      const float qt = a * (r2.y * a + 2.f * r2.z * b) + r2.w * b * b;
+      if (qt <= A.q_cut) {
+        const float c = p[0] * r0.x + p[1] * r0.y + p[2] * r0.z;
+        const float s2 = a * a + b * b;
+        float dk2_ds2, dk2_dc;
+        const float k2 = hp_k2_grad(s2, c, &dk2_ds2, &dk2_dc);
+        const float q = qt * k2;
+        if (q <= A.q_cut) {
+          hit = true;
+          const float G = __expf(-0.5f * q);
+          const float oG = r0.w * G;
+          const float alpha = fminf(A.alpha_max, oG);
+          const float om = 1.f - alpha;
+          const float iom = __builtin_amdgcn_rcpf(om);
+          const float Tb = Tcur * iom;  // transmittance before this entry
+          const float wgt = alpha * Tb;
+          v[0] = g0 * wgt;
+          v[1] = g1 * wgt;
+          v[2] = g2 * wgt;
+          const float dLda = g0 * (r3.x * Tb - S0 * iom) + g1 * (r3.y * Tb - S1 * iom) + g2 * (r3.z * Tb - S2 * iom) -
+                             gTT * iom;
+          S0 += wgt * r3.x;
+          S1 += wgt * r3.y;
+          S2 += wgt * r3.z;
+          Tcur = Tb;
+          if (oG < A.alpha_max) {
+            v[3] = dLda * G;
+            const float dLdq = -0.5f * alpha * dLda;
+            v[4] = dLdq * k2 * a * a;
+            v[5] = dLdq * k2 * 2.f * a * b;
+            v[6] = dLdq * k2 * b * b;
+            // dq/d(a, b, c) with k2 = k2(s2, c)
+            const float dqa = k2 * 2.f * (r2.y * a + r2.z * b) + qt * dk2_ds2 * 2.f * a;
+            const float dqb = k2 * 2.f * (r2.z * a + r2.w * b) + qt * dk2_ds2 * 2.f * b;
+            const float dqc = qt * dk2_dc;
+            // motion of (a, b, c) with the Gaussian's longitude / latitude:
+            // da/dw = -cos(phi) c + sin(phi) b, db/dw = -sin(phi) a, dc/dw = cos(phi) a
+            // da/dp = 0, db/dp = -c, dc/dp = b
+            const float cph = r1.w, sph = r0.y;
+            v[7] = dLdq * (dqa * (sph * b - cph * c) - dqb * sph * a + dqc * cph * a);
+            v[8] = dLdq * (-dqb * c + dqc * b);
+          }
+        }
+      }
+    }
+    if (__ballot(hit) == 0) continue;
+    hp_wave_totals<HP_NACC>(v);
+    if (hp_lane() == 0) {
+#pragma unroll
+      for (int m = 0; m < HP_NACC; ++m) unsafeAtomicAdd(&acc[(int64_t)m * P + g], v[m]);
+    }
+  }
+}
+
+extern "C" hp_status hp_render_fwd(const void* projected, int64_t P, const uint32_t* vals, const uint32_t* tile_ranges,
+                                   int32_t n_tiles, const hp_view* view, const hp_params* prm, const void* mask,
+                                   int64_t n_active, float* rgb, float* T, int32_t* n_contrib, void* stream) {
+  HP_TRY(hp_check_view(view, prm));
+  if (P < 0 || n_tiles < 0 || n_active < 0) return HP_ERR_INVALID_ARG;
+  if (!projected || !mask || (n_tiles > 0 && !tile_ranges)) return HP_ERR_INVALID_ARG;
+  if (n_active > 0 && (!rgb || !T || !n_contrib)) return HP_ERR_INVALID_ARG;
+  if (n_tiles == 0) return HP_OK;
+  const HpGeom g = hp_geom(view->order, prm->tile_log2);
+  if (n_tiles > g.ntile || n_active > g.npix) return HP_ERR_INVALID_ARG;
+  RenderArgs A = make_args(g, hp_mask_view((const char*)mask, g), hp_proj_view((const char*)projected, P), vals,
+                           tile_ranges, prm, n_active);
+  RenderOut O{rgb, T, n_contrib};
+  hipLaunchKernelGGL(k_render_fwd, dim3((unsigned)n_tiles), dim3(256), 0, (hipStream_t)stream, A, O);
+  HP_CHECK_LAUNCH();
+  return HP_OK;
+}
+
+extern "C" hp_status hp_render_fwd_batch(int32_t n_req, const hp_render_req* reqs, const hp_params* prm,
+                                         void* stream) {
+  if (n_req < 1 || n_req > HP_MAX_BATCH || !reqs) return HP_ERR_INVALID_ARG;
+  HP_TRY(hp_check_params(prm));
+  RenderBatch B;
+  B.n = n_req;
+  int64_t total = 0;
+  for (int r = 0; r < n_req; ++r) {
+    const hp_render_req& q = reqs[r];
+    if (q.order < 0 || q.order > HP_MAX_ORDER || q.P < 0 || q.n_tiles < 0 || q.n_active < 0 || !q.projected ||
+        !q.mask)
+      return HP_ERR_INVALID_ARG;
+    if (q.n_tiles > 0 && (!q.tile_ranges || !q.vals || !q.rgb || !q.T || !q.n_contrib)) return HP_ERR_INVALID_ARG;
+    const HpGeom g = hp_geom(q.order, prm->tile_log2);
+    if (q.n_tiles > g.ntile || q.n_active > g.npix) return HP_ERR_INVALID_ARG;
+    B.first[r] = (int)total;
+    B.A[r] = make_args(g, hp_mask_view((const char*)q.mask, g), hp_proj_view((const char*)q.projected, q.P), q.vals,
+                       q.tile_ranges, prm, q.n_active);
+    B.O[r] = RenderOut{q.rgb, q.T, q.n_contrib};
+    total += q.n_tiles;
+  }
+  B.first[n_req] = (int)total;
+  if (total == 0) return HP_OK;
+  if (total > 0x7fffffff) return HP_ERR_UNSUPPORTED;
+  hipLaunchKernelGGL(k_render_fwd_batch, dim3((unsigned)total), dim3(256), 0, (hipStream_t)stream, B);
+  HP_CHECK_LAUNCH();
+  return HP_OK;
+}
+
+// the backward of stage 1 lives with the forward in k_preprocess.hip
+hp_status hp_preprocess_bwd_launch(const hp_gaussians* g, const hp_view* view, const hp_params* prm, const float* acc,
+                                   hp_gaussians_grad* grad, hipStream_t s);
+
+__global__ void k_zero_f32(float* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.f;
+}
+
+extern "C" size_t hp_render_bwd_workspace_bytes(int64_t P) { return P < 0 ? 0 : hp_align256((size_t)P * HP_NACC * 4); }
+
+extern "C" hp_status hp_render_bwd(const hp_gaussians* gs, const void* projected, const uint32_t* vals,
+                                   const uint32_t* tile_ranges, int32_t n_tiles, const hp_view* view,
+                                   const hp_params* prm, const void* mask, int64_t n_active, const float* T,
+                                   const int32_t* n_contrib, const float* dL_drgb, const float* dL_dT,
+                                   hp_gaussians_grad* grad, void* ws, size_t ws_bytes, void* stream) {
+  HP_TRY(hp_check_gaussians(gs));
+  HP_TRY(hp_check_view(view, prm));
+  if (!projected || !mask || !grad || n_tiles < 0 || n_active < 0) return HP_ERR_INVALID_ARG;
+  if (gs->P > 0 && (!grad->mean || !grad->scale || !grad->rot || !grad->opacity || !grad->sh || !ws))
+    return HP_ERR_INVALID_ARG;
+  if (n_active > 0 && n_tiles > 0 && (!T || !n_contrib || !dL_drgb || !tile_ranges || !vals)) return HP_ERR_INVALID_ARG;
+  if (ws_bytes < hp_render_bwd_workspace_bytes(gs->P)) return HP_ERR_CAPACITY;
+  if (gs->P == 0) return HP_OK;
+  const HpGeom g = hp_geom(view->order, prm->tile_log2);
+  if (n_tiles > g.ntile || n_active > g.npix) return HP_ERR_INVALID_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  float* acc = (float*)ws;
+  hipLaunchKernelGGL(k_zero_f32, dim3(hp_blocks(gs->P * HP_NACC, 256)), dim3(256), 0, s, acc, gs->P * HP_NACC);
+  HP_CHECK_LAUNCH();
+  if (n_tiles > 0 && n_active > 0) {
+    RenderArgs A = make_args(g, hp_mask_view((const char*)mask, g), hp_proj_view((const char*)projected, gs->P), vals,
+                             tile_ranges, prm, n_active);
+    hipLaunchKernelGGL(k_render_bwd, dim3((unsigned)n_tiles), dim3(256), 0, s, A, gs->P, T, n_contrib, dL_drgb, dL_dT,
+                       acc);
+    HP_CHECK_LAUNCH();
+  }
+  return hp_preprocess_bwd_launch(gs, view, prm, acc, grad, s);
+}

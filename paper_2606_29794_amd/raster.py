@@ -1,0 +1,238 @@
+"""Host-side driver of the HEALPix rasterizer: device buffers come from
+PyTorch's caching allocator, every computation is a call into libhp.so on the
+current HIP stream (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes as C
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import _abi as A
+
+
+def _p(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _bytes(n, device):
+    return torch.empty(max(int(n), 1), dtype=torch.uint8, device=device)
+
+
+@dataclass
+class Camera:
+    """World->camera rotation W (row-major 3x3), translation b = -W center,
+    camera type (A.HP_CAM_*), field of view (radians) and HEALPix order."""
+    W: np.ndarray
+    b: np.ndarray
+    center: np.ndarray
+    cam_type: int = A.HP_CAM_FULL
+    fov_x: float = 2 * math.pi
+    fov_y: float = math.pi
+    order: int = 9
+
+    @staticmethod
+    def from_dict(d: dict) -> "Camera":
+        return Camera(np.asarray(d["W"], np.float32), np.asarray(d["b"], np.float32),
+                      np.asarray(d["center"], np.float32), int(d["cam_type"]), float(d["fov_x"]),
+                      float(d["fov_y"]), int(d["order"]))
+
+    def view(self) -> A.hp_view:
+        return A.make_view(self.W, self.b, self.center, self.cam_type, self.fov_x, self.fov_y, self.order)
+
+    def mask_key(self, tile_log2: int):
+        if self.cam_type == A.HP_CAM_FULL:
+            return (self.order, 0, 0.0, 0.0, tile_log2)
+        return (self.order, self.cam_type, float(np.float32(self.fov_x)), float(np.float32(self.fov_y)), tile_log2)
+
+
+@dataclass
+class Gaussians:
+    """Device tensors, float32, contiguous: mean [3,P], scale [3,P] (>0),
+    rot [4,P] (w,x,y,z), opacity [P] in (0,1), sh [K,3,P]."""
+    mean: torch.Tensor
+    scale: torch.Tensor
+    rot: torch.Tensor
+    opacity: torch.Tensor
+    sh: torch.Tensor
+
+    @property
+    def P(self) -> int:
+        return int(self.mean.shape[1])
+
+    @property
+    def sh_degree(self) -> int:
+        return int(round(math.sqrt(self.sh.shape[0]))) - 1
+
+    @staticmethod
+    def from_scene(scene, device="cuda") -> "Gaussians":
+        t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float32, device=device)
+        return Gaussians(t(scene.mean), t(scene.scale), t(scene.rot), t(scene.opacity), t(scene.sh))
+
+    def struct(self) -> A.hp_gaussians:
+        for x in (self.mean, self.scale, self.rot, self.opacity, self.sh):
+            if not (x.is_cuda and x.dtype == torch.float32 and x.is_contiguous()):
+                raise ValueError("Gaussian tensors must be contiguous float32 device tensors")
+        return A.hp_gaussians(self.P, self.sh_degree, self.mean.data_ptr(), self.scale.data_ptr(),
+                              self.rot.data_ptr(), self.opacity.data_ptr(), self.sh.data_ptr())
+
+
+@dataclass
+class MaskInfo:
+    buf: torch.Tensor
+    n_active: int
+    n_tiles: int
+    active_pix: torch.Tensor   # int32 [n_active], sorted nested ids
+
+
+@dataclass
+class FwdState:
+    """What the backward pass needs from a forward render: no per-Gaussian
+    forward state beyond the projected records."""
+    camera: Camera
+    mask: MaskInfo
+    projected: torch.Tensor
+    vals: torch.Tensor
+    ranges: torch.Tensor
+    n_pairs: int
+    rgb: torch.Tensor
+    T: torch.Tensor
+    n_contrib: torch.Tensor
+    P: int
+
+
+class Rasterizer:
+    """Grid tables per HEALPix order and masks per camera model are built once
+    and cached; everything else is per call."""
+
+    def __init__(self, device="cuda", **params):
+        self.device = torch.device(device)
+        self.prm = A.default_params(**params)
+        self._grids = {}
+        self._masks = {}
+
+    # ---- camera-independent tables ------------------------------------
+    def grid(self, order: int) -> torch.Tensor:
+        key = (order, self.prm.tile_log2)
+        g = self._grids.get(key)
+        if g is None:
+            n = A.lib().hp_grid_bytes(order, self.prm.tile_log2)
+            if n == 0:
+                raise ValueError(f"unsupported order {order}")
+            g = _bytes(n, self.device)
+            A.call("hp_grid_init", order, C.byref(self.prm), _p(g), n, _stream())
+            self._grids[key] = g
+        return g
+
+    def mask(self, cam: Camera) -> MaskInfo:
+        key = cam.mask_key(self.prm.tile_log2)
+        m = self._masks.get(key)
+        if m is None:
+            n = A.lib().hp_mask_bytes(cam.order, self.prm.tile_log2)
+            buf = _bytes(n, self.device)
+            v = cam.view()
+            A.call("hp_mask", C.byref(v), C.byref(self.prm), _p(self.grid(cam.order)), _p(buf), n, _stream())
+            na, nt = C.c_int64(0), C.c_int32(0)
+            A.call("hp_mask_counts", _p(buf), cam.order, self.prm.tile_log2, C.byref(na), C.byref(nt), _stream())
+            ptr = A.lib().hp_mask_active_pix(_p(buf), cam.order, self.prm.tile_log2)
+            off = ptr - buf.data_ptr()
+            ap = buf[off: off + 4 * na.value].view(torch.int32)
+            m = MaskInfo(buf, int(na.value), int(nt.value), ap)
+            self._masks[key] = m
+        return m
+
+    # ---- stage 1 ---------------------------------------------------------
+    def preprocess(self, g: Gaussians, cam: Camera) -> torch.Tensor:
+        n = A.lib().hp_projected_bytes(g.P)
+        proj = _bytes(n, self.device)
+        gs = g.struct()
+        v = cam.view()
+        A.call("hp_preprocess", C.byref(gs), C.byref(v), C.byref(self.prm), _p(proj), n, _stream())
+        return proj
+
+    def projected_arrays(self, proj: torch.Tensor, P: int):
+        """Views of a projected buffer: rec [P,16], depth [P], radius [P]."""
+        rec = proj[: P * 64].view(torch.float32).view(P, 16)
+        dptr = A.lib().hp_projected_depth(_p(proj), P) - proj.data_ptr()
+        rptr = A.lib().hp_projected_radius(_p(proj), P) - proj.data_ptr()
+        depth = proj[dptr: dptr + 4 * P].view(torch.float32)
+        radius = proj[rptr: rptr + 4 * P].view(torch.float32)
+        return rec, depth, radius
+
+    # ---- stage 2 ---------------------------------------------------------
+    def bin(self, proj: torch.Tensor, P: int, cam: Camera):
+        m = self.mask(cam)
+        v = cam.view()
+        ws_n = A.lib().hp_bin_workspace_bytes(P)
+        ws = _bytes(ws_n, self.device)
+        npairs = torch.zeros(1, dtype=torch.int64, device=self.device)
+        A.call("hp_bin", A.HP_BIN_COUNT, _p(proj), P, C.byref(v), C.byref(self.prm), _p(self.grid(cam.order)),
+               _p(m.buf), None, None, 0, _p(npairs), _p(ws), ws_n, _stream())
+        total = C.c_int64(0)
+        A.call("hp_read_total", _p(npairs), C.byref(total), _stream())
+        n = int(total.value)
+        keys = torch.empty(max(n, 1), dtype=torch.int32, device=self.device)
+        vals = torch.empty(max(n, 1), dtype=torch.int32, device=self.device)
+        A.call("hp_bin", A.HP_BIN_EMIT, _p(proj), P, C.byref(v), C.byref(self.prm), _p(self.grid(cam.order)),
+               _p(m.buf), _p(keys), _p(vals), n, _p(npairs), _p(ws), ws_n, _stream())
+        return keys, vals, n
+
+    def sort(self, keys, vals, n: int, n_tiles: int):
+        ranges = torch.zeros((max(n_tiles, 1), 2), dtype=torch.int32, device=self.device)
+        ws_n = A.lib().hp_sort_workspace_bytes(n, n_tiles)
+        ws = _bytes(ws_n, self.device)
+        A.call("hp_sort", _p(keys), _p(vals), n, n_tiles, _p(ranges), _p(ws), ws_n, _stream())
+        return ranges
+
+    # ---- stage 3 ---------------------------------------------------------
+    def render_fwd(self, proj, P, vals, ranges, cam: Camera):
+        m = self.mask(cam)
+        v = cam.view()
+        rgb = torch.empty((3, max(m.n_active, 1)), dtype=torch.float32, device=self.device)
+        T = torch.empty(max(m.n_active, 1), dtype=torch.float32, device=self.device)
+        nc = torch.empty(max(m.n_active, 1), dtype=torch.int32, device=self.device)
+        A.call("hp_render_fwd", _p(proj), P, _p(vals), _p(ranges), m.n_tiles, C.byref(v), C.byref(self.prm),
+               _p(m.buf), m.n_active, _p(rgb), _p(T), _p(nc), _stream())
+        return rgb, T, nc
+
+    def forward(self, g: Gaussians, cam: Camera) -> FwdState:
+        m = self.mask(cam)
+        proj = self.preprocess(g, cam)
+        keys, vals, n = self.bin(proj, g.P, cam)
+        ranges = self.sort(keys, vals, n, m.n_tiles)
+        rgb, T, nc = self.render_fwd(proj, g.P, vals, ranges, cam)
+        return FwdState(cam, m, proj, vals, ranges, n, rgb, T, nc, g.P)
+
+    def backward(self, g: Gaussians, st: FwdState, dL_drgb, dL_dT, grads: Gaussians) -> None:
+        """Accumulates gradients into the tensors of `grads`."""
+        v = st.camera.view()
+        gs = g.struct()
+        gg = A.hp_gaussians_grad(grads.mean.data_ptr(), grads.scale.data_ptr(), grads.rot.data_ptr(),
+                                 grads.opacity.data_ptr(), grads.sh.data_ptr())
+        ws_n = A.lib().hp_render_bwd_workspace_bytes(g.P)
+        ws = _bytes(ws_n, self.device)
+        A.call("hp_render_bwd", C.byref(gs), _p(st.projected), _p(st.vals), _p(st.ranges), st.mask.n_tiles,
+               C.byref(v), C.byref(self.prm), _p(st.mask.buf), st.mask.n_active, _p(st.T), _p(st.n_contrib),
+               _p(dL_drgb.contiguous()), _p(None if dL_dT is None else dL_dT.contiguous()), C.byref(gg), _p(ws),
+               ws_n, _stream())
+
+    # ---- loss ----------------------------------------------------------------
+    def ssim_loss(self, img, ref, cam: Camera, sp: A.hp_ssim_params | None = None, dL_dloss=None, want_map=False):
+        """Returns (out[3] = (mean SSIM, L1, loss), ssim_map or None, dL/dimg or None)."""
+        m = self.mask(cam)
+        sp = sp or A.default_ssim_params()
+        out = torch.zeros(3, dtype=torch.float32, device=self.device)
+        smap = torch.empty_like(img) if want_map else None
+        dimg = torch.empty_like(img) if dL_dloss is not None else None
+        ws_n = A.lib().hp_ssim_workspace_bytes(cam.order, self.prm.tile_log2, m.n_active)
+        ws = _bytes(ws_n, self.device)
+        A.call("hp_ssim", _p(img.contiguous()), _p(ref.contiguous()), m.n_active, m.n_tiles, cam.order,
+               C.byref(self.prm), C.byref(sp), _p(m.buf), _p(out), _p(smap), _p(dL_dloss), _p(dimg), _p(ws), ws_n,
+               _stream())
+        return out, smap, dimg

@@ -1,0 +1,82 @@
+"""torch.autograd wrappers of the HIP rasterizer and the HEALPix-SSIM loss.
+
+``render`` runs preprocess -> bin -> sort -> render in libhp.so and returns
+the colour [3, n_active] and final transmittance [n_active] of the camera's
+active HEALPix pixels; its backward recomputes per-pixel transmittance in a
+reverse traversal (no per-Gaussian forward state is kept) and returns
+gradients for means, scales, rotations, opacities and SH coefficients.
+``hssim_loss`` returns (1 - lambda) L1 + lambda (1 - HSSIM) (Sec. 4.1) and its
+backward is the transposed HEALPix convolution.
+
+Parameters enter already activated (positive scales, opacities in (0, 1));
+apply exp / sigmoid in torch before calling.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import _abi as A
+from .raster import Camera, Gaussians, Rasterizer
+
+_default = {}
+
+
+def default_rasterizer(device="cuda") -> Rasterizer:
+    r = _default.get(str(device))
+    if r is None:
+        r = _default[str(device)] = Rasterizer(device)
+    return r
+
+
+class _Render(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, mean, scale, rot, opacity, sh, rasterizer, camera):
+        g = Gaussians(mean.detach().contiguous(), scale.detach().contiguous(), rot.detach().contiguous(),
+                      opacity.detach().contiguous(), sh.detach().contiguous())
+        st = rasterizer.forward(g, camera)
+        ctx.g, ctx.st, ctx.R = g, st, rasterizer
+        ctx.mark_non_differentiable(st.n_contrib)
+        return st.rgb, st.T
+
+    @staticmethod
+    def backward(ctx, grad_rgb, grad_T):
+        g, st, R = ctx.g, ctx.st, ctx.R
+        z = torch.zeros_like
+        gr = Gaussians(z(g.mean), z(g.scale), z(g.rot), z(g.opacity), z(g.sh))
+        if grad_rgb is None:
+            grad_rgb = torch.zeros_like(st.rgb)
+        R.backward(g, st, grad_rgb, grad_T, gr)
+        ctx.g = ctx.st = None
+        return gr.mean, gr.scale, gr.rot, gr.opacity, gr.sh, None, None
+
+
+def render(mean, scale, rot, opacity, sh, camera: Camera, rasterizer: Rasterizer | None = None):
+    """Differentiable HEALPix render of one camera.  Returns (rgb [3, n], T [n])
+    over the camera's active pixels (see ``rasterizer.mask(camera)``)."""
+    R = rasterizer or default_rasterizer(mean.device)
+    return _Render.apply(mean, scale, rot, opacity, sh, R, camera)
+
+
+class _HSSIMLoss(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, img, ref, rasterizer, camera, lam):
+        sp = A.default_ssim_params(lam=float(lam))
+        out, _, _ = rasterizer.ssim_loss(img.detach(), ref.detach(), camera, sp)
+        ctx.save_for_backward(img.detach(), ref.detach())
+        ctx.R, ctx.cam, ctx.sp = rasterizer, camera, sp
+        ctx.mark_non_differentiable(out)
+        return out[2], out
+
+    @staticmethod
+    def backward(ctx, grad_loss, grad_out):
+        img, ref = ctx.saved_tensors
+        up = grad_loss.reshape(1).to(torch.float32).contiguous()
+        _, _, dimg = ctx.R.ssim_loss(img, ref, ctx.cam, ctx.sp, dL_dloss=up)
+        return dimg, None, None, None, None
+
+
+def hssim_loss(img, ref, camera: Camera, lam: float = 0.2, rasterizer: Rasterizer | None = None):
+    """L = (1 - lam) mean|img - ref| + lam (1 - mean HSSIM); img, ref [3, n_active].
+    Returns (L, stats) with stats = (mean HSSIM, L1, L) (no gradient)."""
+    R = rasterizer or default_rasterizer(img.device)
+    return _HSSIMLoss.apply(img, ref, R, camera, lam)

@@ -1,0 +1,283 @@
+"""Continuous-batching render server over a device-resident Gaussian scene.
+
+Requests (camera pose, camera model, field of view, HEALPix order) arrive
+over time.  A dispatcher admits the requests that have arrived whenever a
+stream slot is free and the HBM budget allows, and launches them as one
+batch on that slot's stream:
+
+  masks of the batch's cameras -> one preprocessing launch that reads every
+  Gaussian once for all views -> per-request tile counts -> (one read-back of
+  all counts) -> pair emission and tile sorts -> ONE render launch whose
+  workgroups cover the active tiles of every request in the batch.
+
+Batches on different streams overlap on the device, so requests that arrive
+while others are on the GPU start as soon as a slot and memory free up.
+Latency is completion time minus arrival time; the forward pass has no
+atomics, so a request renders bit-identically alone or inside a batch.
+"""
+from __future__ import annotations
+
+import collections
+import ctypes as C
+import math
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import _abi as A
+from .raster import Camera, Gaussians, MaskInfo, Rasterizer, _bytes, _p
+
+MAX_VIEWS_PER_PREPROCESS = 8
+MAX_REQ_PER_RENDER = 16
+
+
+@dataclass
+class Request:
+    rid: int
+    arrival: float          # seconds from the start of the trace
+    camera: Camera
+
+
+@dataclass
+class Result:
+    rid: int
+    arrival: float
+    done: float
+    rgb: torch.Tensor | None = None
+    T: torch.Tensor | None = None
+
+    @property
+    def latency(self) -> float:
+        return self.done - self.arrival
+
+
+@dataclass
+class _Batch:
+    reqs: list
+    stream: torch.cuda.Stream
+    event: torch.cuda.Event
+    nbytes: int
+    outs: list = field(default_factory=list)
+    keep: list = field(default_factory=list)
+
+
+def select_batch(pending, estimate, mem_in_use: int, budget: int, max_batch: int, gpu_busy: bool) -> list:
+    """Admission policy: take requests from the front of `pending` (FIFO)
+    while the batch has room and their estimated bytes fit the HBM budget.
+    A request larger than the whole budget is admitted only when the GPU is
+    otherwise idle (alone), so it cannot starve.  Removes the taken requests
+    from `pending` and returns them."""
+    batch = []
+    est = 0
+    while pending and len(batch) < max_batch:
+        e = estimate(pending[0])
+        if mem_in_use + est + e > budget:
+            if batch or gpu_busy:
+                break
+        batch.append(pending.popleft())
+        est += e
+        if mem_in_use + est > budget:
+            break
+    return batch
+
+
+def _percentile(x, q):
+    return float(np.percentile(np.asarray(x), q)) if len(x) else float("nan")
+
+
+class Server:
+    def __init__(self, gaussians: Gaussians, rasterizer: Rasterizer | None = None, max_batch: int = 8,
+                 n_streams: int = 3, hbm_budget_bytes: int = 48 << 30):
+        self.g = gaussians
+        self.R = rasterizer or Rasterizer(gaussians.mean.device)
+        self.max_batch = min(max_batch, MAX_REQ_PER_RENDER)
+        self.streams = [torch.cuda.Stream(device=self.g.mean.device) for _ in range(n_streams)]
+        self.budget = hbm_budget_bytes
+        self._pairs_per_order = {}
+        self._mask_cache = {}
+
+    # ---- memory accounting ---------------------------------------------------
+    def _estimate(self, cam: Camera) -> int:
+        P = self.g.P
+        npix = 12 << (2 * cam.order)
+        pairs = self._pairs_per_order.get(cam.order, 8 * P)
+        return P * 72 + 24 * pairs + 24 * npix + A.lib().hp_mask_bytes(cam.order, self.R.prm.tile_log2)
+
+    # ---- one batch ------------------------------------------------------------
+    def _mask_async(self, cam: Camera):
+        """Mask buffer for the camera model (cached; computed on the current
+        stream, counts read back later together with the pair counts)."""
+        key = cam.mask_key(self.R.prm.tile_log2)
+        buf = self._mask_cache.get(key)
+        if buf is None:
+            n = A.lib().hp_mask_bytes(cam.order, self.R.prm.tile_log2)
+            buf = _bytes(n, self.g.mean.device)
+            v = cam.view()
+            A.call("hp_mask", C.byref(v), C.byref(self.R.prm), _p(self.R.grid(cam.order)), _p(buf), n,
+                   C.c_void_p(torch.cuda.current_stream().cuda_stream))
+            if len(self._mask_cache) > 64:
+                self._mask_cache.pop(next(iter(self._mask_cache)))
+            self._mask_cache[key] = buf
+        return buf
+
+    def _launch(self, reqs: list, stream: torch.cuda.Stream, keep: bool) -> _Batch:
+        R, g = self.R, self.g
+        P = g.P
+        dev = g.mean.device
+        prm = R.prm
+        with torch.cuda.stream(stream):
+            sptr = C.c_void_p(stream.cuda_stream)
+            for r in reqs:
+                R.grid(r.camera.order)
+            masks = [self._mask_async(r.camera) for r in reqs]
+            nproj = A.lib().hp_projected_bytes(P)
+            projs = [_bytes(nproj, dev) for _ in reqs]
+            gs = g.struct()
+            for s0 in range(0, len(reqs), MAX_VIEWS_PER_PREPROCESS):
+                chunk = reqs[s0:s0 + MAX_VIEWS_PER_PREPROCESS]
+                views = (A.hp_view * len(chunk))(*[r.camera.view() for r in chunk])
+                ptrs = (C.c_void_p * len(chunk))(*[projs[s0 + k].data_ptr() for k in range(len(chunk))])
+                A.call("hp_preprocess_batch", C.byref(gs), len(chunk), views, C.byref(prm), ptrs, nproj, sptr)
+            ws_n = A.lib().hp_bin_workspace_bytes(P)
+            wss = [_bytes(ws_n, dev) for _ in reqs]
+            npairs = torch.zeros(len(reqs), dtype=torch.int64, device=dev)
+            for k, r in enumerate(reqs):
+                v = r.camera.view()
+                A.call("hp_bin", A.HP_BIN_COUNT, _p(projs[k]), P, C.byref(v), C.byref(prm),
+                       _p(R.grid(r.camera.order)), _p(masks[k]), None, None, 0,
+                       C.c_void_p(npairs.data_ptr() + 8 * k), _p(wss[k]), ws_n, sptr)
+            # one read-back for the whole batch: pair counts and mask sizes
+            heads = torch.stack([m[:16] for m in masks]).view(torch.int64)
+            counts = torch.cat([npairs, heads.reshape(-1)]).cpu()
+            n_pairs = counts[: len(reqs)].tolist()
+            heads = counts[len(reqs):].view(len(reqs), 2).numpy()
+            reqd = []
+            outs = []
+            nbytes = 0
+            for k, r in enumerate(reqs):
+                n_active = int(heads[k, 0])
+                n_tiles = int(heads[k, 1] & 0xFFFFFFFF)   # int32 count in the low half (little-endian)
+                n = int(n_pairs[k])
+                self._pairs_per_order[r.camera.order] = max(n, self._pairs_per_order.get(r.camera.order, 0) // 2)
+                keys = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+                vals = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+                v = r.camera.view()
+                A.call("hp_bin", A.HP_BIN_EMIT, _p(projs[k]), P, C.byref(v), C.byref(prm), _p(R.grid(r.camera.order)),
+                       _p(masks[k]), _p(keys), _p(vals), n, C.c_void_p(npairs.data_ptr() + 8 * k), _p(wss[k]), ws_n,
+                       sptr)
+                ranges = torch.zeros((max(n_tiles, 1), 2), dtype=torch.int32, device=dev)
+                sws_n = A.lib().hp_sort_workspace_bytes(n, n_tiles)
+                sws = _bytes(sws_n, dev)
+                A.call("hp_sort", _p(keys), _p(vals), n, n_tiles, _p(ranges), _p(sws), sws_n, sptr)
+                rgb = torch.empty((3, max(n_active, 1)), dtype=torch.float32, device=dev)
+                T = torch.empty(max(n_active, 1), dtype=torch.float32, device=dev)
+                nc = torch.empty(max(n_active, 1), dtype=torch.int32, device=dev)
+                reqd.append(A.hp_render_req(projs[k].data_ptr(), P, vals.data_ptr(), ranges.data_ptr(), n_tiles,
+                                            r.camera.order, masks[k].data_ptr(), n_active, rgb.data_ptr(),
+                                            T.data_ptr(), nc.data_ptr()))
+                outs.append((rgb[:, :n_active], T[:n_active], keys, vals, ranges, sws))
+                nbytes += nproj + 8 * n + sws_n + 24 * n_active
+            for s0 in range(0, len(reqd), MAX_REQ_PER_RENDER):
+                chunk = reqd[s0:s0 + MAX_REQ_PER_RENDER]
+                arr = (A.hp_render_req * len(chunk))(*chunk)
+                A.call("hp_render_fwd_batch", len(chunk), arr, C.byref(prm), sptr)
+            ev = torch.cuda.Event()
+            ev.record(stream)
+        b = _Batch(reqs, stream, ev, nbytes, outs=outs)
+        b.keep = [projs, wss, masks]   # keep buffers alive until the batch completes
+        return b
+
+    # ---- the request loop -----------------------------------------------------
+    def serve(self, requests: list, realtime: bool = True, keep_outputs: bool = False, poll_s: float = 2e-5):
+        reqs = sorted(requests, key=lambda r: r.arrival)
+        pending = collections.deque()
+        inflight = []
+        results = {}
+        mem = 0
+        nxt = 0
+        free = list(range(len(self.streams)))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        clock = lambda: time.perf_counter() - t0
+        while len(results) < len(reqs):
+            now = clock()
+            while nxt < len(reqs) and (not realtime or reqs[nxt].arrival <= now):
+                pending.append(reqs[nxt])
+                nxt += 1
+            progressed = False
+            for b in list(inflight):
+                if b.event.query():
+                    t = clock()
+                    for k, r in enumerate(b.reqs):
+                        rgb, T = b.outs[k][0], b.outs[k][1]
+                        results[r.rid] = Result(r.rid, r.arrival, t, rgb if keep_outputs else None,
+                                                T if keep_outputs else None)
+                    inflight.remove(b)
+                    mem -= b.nbytes
+                    free.append(b._slot)
+                    progressed = True
+            if pending and free:
+                batch = select_batch(pending, lambda r: self._estimate(r.camera), mem, self.budget, self.max_batch,
+                                     bool(inflight))
+                if batch:
+                    slot = free.pop(0)
+                    b = self._launch(batch, self.streams[slot], keep_outputs)
+                    b._slot = slot
+                    inflight.append(b)
+                    mem += b.nbytes
+                    progressed = True
+            if not progressed:
+                if inflight and not pending:
+                    time.sleep(poll_s)
+                elif not inflight and not pending and nxt < len(reqs):
+                    time.sleep(max(0.0, min(reqs[nxt].arrival - clock(), 1e-3)))
+        makespan = max(r.done for r in results.values())
+        return ServeStats.of([results[r.rid] for r in reqs], makespan)
+
+    def serve_sequential(self, requests: list, realtime: bool = True, keep_outputs: bool = False):
+        """Baseline: one request at a time, FIFO, the plain per-request
+        pipeline (hp_preprocess, hp_bin, hp_sort, hp_render_fwd)."""
+        reqs = sorted(requests, key=lambda r: r.arrival)
+        results = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for r in reqs:
+            if realtime:
+                while time.perf_counter() - t0 < r.arrival:
+                    time.sleep(min(1e-3, max(0.0, r.arrival - (time.perf_counter() - t0))))
+            st = self.R.forward(self.g, r.camera)
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+            results.append(Result(r.rid, r.arrival, t, st.rgb if keep_outputs else None,
+                                  st.T if keep_outputs else None))
+        makespan = max(x.done for x in results)
+        return ServeStats.of(results, makespan)
+
+
+@dataclass
+class ServeStats:
+    n: int
+    makespan_s: float
+    renders_per_s: float
+    p50_ms: float
+    p99_ms: float
+    mean_ms: float
+    results: list
+
+    @staticmethod
+    def of(results, makespan):
+        lat = [r.latency * 1e3 for r in results]
+        return ServeStats(len(results), makespan, len(results) / makespan, _percentile(lat, 50), _percentile(lat, 99),
+                          float(np.mean(lat)), results)
+
+    def summary(self) -> dict:
+        return dict(n=self.n, makespan_s=self.makespan_s, renders_per_s=self.renders_per_s, p50_ms=self.p50_ms,
+                    p99_ms=self.p99_ms, mean_ms=self.mean_ms)
+
+
+def requests_from_workload(wl, limit: int | None = None) -> list:
+    cams = wl.cameras if limit is None else wl.cameras[:limit]
+    arr = wl.extra["arrivals"]
+    return [Request(k, float(arr[k]), Camera.from_dict(c)) for k, c in enumerate(cams)]

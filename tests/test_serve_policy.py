@@ -1,0 +1,42 @@
+"""Host-side tests of the serving admission policy (no GPU)."""
+import collections
+
+from paper_2606_29794_amd.serve import select_batch
+
+
+def _q(*sizes):
+    return collections.deque(sizes)
+
+
+def test_fifo_and_batch_limit():
+    q = _q(1, 2, 3, 4, 5)
+    b = select_batch(q, lambda r: 10, 0, 1000, 3, False)
+    assert b == [1, 2, 3] and list(q) == [4, 5]
+
+
+def test_budget_stops_admission_and_keeps_order():
+    q = _q("a", "b", "c")
+    est = {"a": 40, "b": 70, "c": 5}.get
+    b = select_batch(q, est, 0, 100, 8, True)
+    assert b == ["a"] and list(q) == ["b", "c"]       # c would fit but waits its turn (FIFO)
+    b = select_batch(q, est, 30, 100, 8, True)
+    assert b == ["b"] and list(q) == ["c"]
+
+
+def test_budget_exhausted_waits_while_busy():
+    q = _q("big")
+    b = select_batch(q, lambda r: 80, 50, 100, 8, True)
+    assert b == [] and list(q) == ["big"]
+
+
+def test_oversize_request_runs_alone_when_idle():
+    q = _q("huge", "small")
+    b = select_batch(q, {"huge": 500, "small": 1}.get, 0, 100, 8, False)
+    assert b == ["huge"] and list(q) == ["small"]
+    # while something is on the GPU it is not admitted
+    q = _q("huge")
+    assert select_batch(q, lambda r: 500, 0, 100, 8, True) == []
+
+
+def test_empty_queue():
+    assert select_batch(_q(), lambda r: 1, 0, 10, 4, False) == []
