@@ -41,13 +41,30 @@ def parse():
     ap.add_argument("--order", type=int, default=9)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-pixels", type=int, default=64)
-    ap.add_argument("--serve", action="store_true")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--profile-only", action="store_true", help="run warmup+steps without the extra passes")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy 1 GiB device-to-device (known bytes for scaling FETCH_SIZE / WRITE_SIZE)")
     return ap.parse_args()
+
+
+def copy_calibration():
+    import torch
+    n = (1 << 30) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_each_way": 1 << 30, "copies": 3}))
 
 
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
@@ -101,7 +118,37 @@ def main():
         out.update(kernel_breakdown(R, params, cams, targets, torch, A))
         if not args.no_cpu_baseline:
             out["cpu_baseline"] = cpu_baseline(wl, args.cpu_pixels)
+        if not args.no_serve:
+            del params, g0, targets
+            torch.cuda.empty_cache()
+            out["serve"] = serve_bench(args.serve_requests)
     print(json.dumps(out), flush=True)
+
+
+def serve_bench(n_requests):
+    """Config-4 serving trace: resident 2M SH-3 scene, Poisson arrivals at
+    200 req/s, random pose / camera model / FoV / Nside per request.  The
+    same trace runs through the continuous-batching server and through the
+    sequential one-request-at-a-time pipeline; both replay arrivals in real
+    time.  Latency = completion - arrival."""
+    import torch
+    from paper_2606_29794_amd import scenes as SC
+    from paper_2606_29794_amd.raster import Gaussians, Rasterizer
+    from paper_2606_29794_amd.serve import Server, requests_from_workload
+    wl = SC.config4(n_requests=n_requests)
+    g = Gaussians.from_scene(wl.scene)
+    R = Rasterizer()
+    reqs = requests_from_workload(wl)
+    srv = Server(g, R, max_batch=8, n_streams=3, hbm_budget_bytes=64 << 30)
+    # warm the grid tables of the four orders and the allocator
+    srv.serve(reqs[:16], realtime=False)
+    srv.serve_sequential(reqs[:8], realtime=False)
+    torch.cuda.synchronize()
+    batched = srv.serve(reqs, realtime=True)
+    seq = srv.serve_sequential(reqs, realtime=True)
+    return {"workload": f"cfg4: 2M SH-3 Gaussians resident, {n_requests} requests, Poisson 200 req/s, "
+                        "pinhole 60-90 / fisheye 180-220 / full sphere, Nside 128-1024",
+            "batched": batched.summary(), "sequential": seq.summary()}
 
 
 def kernel_breakdown(R, params, cams, targets, torch, A):
@@ -119,12 +166,11 @@ def kernel_breakdown(R, params, cams, targets, torch, A):
         e[0].record()
         proj = R.preprocess(g, cam)
         e[1].record()
-        keys, vals, n = R.bin(proj, g.P, cam)
-        e[2].record()
         m = R.mask(cam)
-        ranges = R.sort(keys, vals, n, m.n_tiles)
+        vals, ranges, n = R.bin_sorted(proj, g.P, cam)
+        e[2].record()
         e[3].record()
-        rgb, T, nc = R.render_fwd(proj, g.P, vals, ranges, cam)
+        rgb, T, nc, nu = R.render_fwd(proj, g.P, vals, ranges, cam, want_used=True)
         e[4].record()
         up = torch.ones(1, device=rgb.device)
         _, _, dimg = R.ssim_loss(rgb, targets[0], cam, dL_dloss=up)
@@ -137,36 +183,40 @@ def kernel_breakdown(R, params, cams, targets, torch, A):
         R.backward(g, st, dimg, None, gr)
         e[7].record()
         torch.cuda.synchronize()
-        for k, (a, b) in enumerate([(0, 1), (1, 2), (2, 3), (3, 4), (4, 5), (6, 7)]):
-            name = ["preprocess", "bin", "sort", "render_fwd", "ssim_fwd_bwd", "render_bwd"][k]
+        for k, (a, b) in enumerate([(0, 1), (1, 2), (3, 4), (4, 5), (6, 7)]):
+            name = ["preprocess", "bin_and_sort", "render_fwd", "ssim_fwd_bwd", "render_bwd"][k]
             times.setdefault(name, []).append(e[a].elapsed_time(e[b]))
     med = {k: float(np.median(v)) for k, v in times.items()}
     evals = int(nc.to(torch.int64).sum().item())
+    used = int(nu.to(torch.int64).sum().item())
     P = g.P
     K = g.sh.shape[0]
     # algorithmic bytes: preprocess reads the Gaussian SoA (mean 3, scale 3,
     # rot 4, opacity 1, SH 3K floats) and writes a 64 B record + depth + radius
     pre_bytes = P * (4 * (11 + 3 * K) + 72)
-    sort_bytes = n * 16
     res = {
         "stage_ms": med,
         "pairs": n,
         "evaluated_pixel_pairs": evals,
+        "composited_pixel_pairs": used,
         "roofline": {
             "bound": "alu", "kernel": "k_render_bwd",
             "achieved": None, "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s", "frac": None, "traffic": None,
         },
         "stage_roofline": {
             "preprocess_GBs": pre_bytes / (med["preprocess"] * 1e-3) / 1e9,
-            "sort_GBs_algorithmic": sort_bytes / (med["sort"] * 1e-3) / 1e9,
         },
     }
-    # render backward: per evaluated pixel-pair ~ BWD_FLOPS algorithmic flops
-    BWD_FLOPS = 2 * 60
-    FWD_FLOPS = 2 * 20
-    res["roofline"]["achieved"] = evals * BWD_FLOPS / (med["render_bwd"] * 1e-3) / 1e12
+    # algorithmic flops (FMA = 2) per pixel-Gaussian pair, see the design doc:
+    # every evaluated pair: offset projections a, b and the Mahalanobis bound
+    # qt (21 flop); every composited pair in addition: c, the distance factor,
+    # q, alpha and the compositing update (33 flop) in the forward, and the
+    # recomputation plus gradient terms (93 flop) in the backward
+    fwd_flops = 21 * evals + 33 * used
+    bwd_flops = 21 * evals + 93 * used
+    res["roofline"]["achieved"] = bwd_flops / (med["render_bwd"] * 1e-3) / 1e12
     res["roofline"]["frac"] = res["roofline"]["achieved"] / PEAK_VALU_TFLOPS
-    res["stage_roofline"]["render_fwd_TFLOPs"] = evals * FWD_FLOPS / (med["render_fwd"] * 1e-3) / 1e12
+    res["stage_roofline"]["render_fwd_TFLOPs"] = fwd_flops / (med["render_fwd"] * 1e-3) / 1e12
     return res
 
 

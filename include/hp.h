@@ -187,6 +187,21 @@ size_t hp_bin_workspace_bytes(int64_t P);
 hp_status hp_bin(int32_t phase, const void* projected, int64_t P, const hp_view* view, const hp_params* prm,
                  const void* grid, const void* mask, uint32_t* keys, uint32_t* vals, int64_t capacity,
                  int64_t* n_pairs, void* ws, size_t ws_bytes, void* stream);
+/* hp_bin_sorted: the same tile sets, emitted directly in the per-tile
+ * front-to-back order that hp_bin + hp_sort produce (Alg. 1 stage 2 as one
+ * step), without a sort of the pairs.  The tasks are sorted by their node
+ * (stable, so each node keeps depth order); every node's tasks are cut into
+ * chunks of 64; per chunk and tile the hits are counted, the counts are
+ * scanned in (tile, chunk) order and each hit is written at its slot.
+ * phase as for hp_bin (COUNT writes *n_pairs; EMIT fills vals [capacity] with
+ * Gaussian ids grouped by tile and tile_ranges [n_tiles][2] with each active
+ * tile's (start, end) in vals, n_tiles from hp_mask_counts).  If *n_pairs >
+ * capacity, EMIT writes no vals.  COUNT and EMIT each wait once for `stream`.
+ * ws: hp_bin_sorted_workspace_bytes(P, order, tile_log2) bytes. */
+size_t hp_bin_sorted_workspace_bytes(int64_t P, int32_t order, int32_t tile_log2);
+hp_status hp_bin_sorted(int32_t phase, const void* projected, int64_t P, const hp_view* view, const hp_params* prm,
+                        const void* grid, const void* mask, uint32_t* vals, uint32_t* tile_ranges, int32_t n_tiles,
+                        int64_t capacity, int64_t* n_pairs, void* ws, size_t ws_bytes, void* stream);
 /* Waits for `stream` and copies one device int64 to the host. */
 hp_status hp_read_total(const int64_t* dev_value, int64_t* host_value, void* stream);
 
@@ -207,10 +222,11 @@ hp_status hp_sort(uint32_t* keys, uint32_t* vals, int64_t n_pairs, int32_t n_til
  * C += T alpha c, T *= 1 - alpha, stop once T < eps_T.
  * Outputs over the n_active active pixels (mask order): rgb [3][n_active],
  * T [n_active] (final transmittance; background is left to the caller),
- * n_contrib [n_active] (list entries consumed, skipped ones included). */
+ * n_contrib [n_active] (list entries consumed, skipped ones included), and
+ * n_used [n_active] (nullable: Gaussians actually composited). */
 hp_status hp_render_fwd(const void* projected, int64_t P, const uint32_t* vals, const uint32_t* tile_ranges,
                         int32_t n_tiles, const hp_view* view, const hp_params* prm, const void* mask, int64_t n_active,
-                        float* rgb, float* T, int32_t* n_contrib, void* stream);
+                        float* rgb, float* T, int32_t* n_contrib, int32_t* n_used, void* stream);
 
 /* Serving form of hp_render_fwd: up to 16 independent renders (different
  * cameras, orders and scenes) in ONE launch whose workgroups cover the union
@@ -262,6 +278,21 @@ size_t hp_ssim_workspace_bytes(int32_t order, int32_t tile_log2, int64_t n_activ
 hp_status hp_ssim(const float* img, const float* ref, int64_t n_active, int32_t n_tiles, int32_t order,
                   const hp_params* prm, const hp_ssim_params* sp, const void* mask, float* out, float* ssim_map,
                   const float* dL_dloss, float* dL_dimg, void* ws, size_t ws_bytes, void* stream);
+
+/* The same loss split at the point where the upstream gradient becomes known
+ * (an autograd forward and its later backward).  hp_ssim_forward_saved does
+ * what hp_ssim does without dL_dloss and also leaves the per-pixel SSIM
+ * partials of the backward (9 floats per active pixel) in ws;
+ * hp_ssim_backward_saved then computes dL_dimg = dL_dloss * dL/dimg from them
+ * with the gather pass alone.  Between the two calls the caller keeps ws, img
+ * and ref unchanged; both calls take the same sizes, mask and parameters.
+ * Errors as hp_ssim; the backward's dL_dloss and dL_dimg are required. */
+hp_status hp_ssim_forward_saved(const float* img, const float* ref, int64_t n_active, int32_t n_tiles, int32_t order,
+                                const hp_params* prm, const hp_ssim_params* sp, const void* mask, float* out,
+                                float* ssim_map, void* ws, size_t ws_bytes, void* stream);
+hp_status hp_ssim_backward_saved(const float* img, const float* ref, int64_t n_active, int32_t n_tiles, int32_t order,
+                                 const hp_params* prm, const hp_ssim_params* sp, const void* mask, const void* ws,
+                                 size_t ws_bytes, const float* dL_dloss, float* dL_dimg, void* stream);
 
 #ifdef __cplusplus
 }

@@ -72,17 +72,24 @@ _PROTOS = {
     "hp_projected_radius": (P_, [P_, I64]),
     "hp_bin_workspace_bytes": (SZ, [I64]),
     "hp_bin": (I32, [I32, P_, I64, C.POINTER(hp_view), C.POINTER(hp_params), P_, P_, P_, P_, I64, P_, P_, SZ, P_]),
+    "hp_bin_sorted_workspace_bytes": (SZ, [I64, I32, I32]),
+    "hp_bin_sorted": (I32, [I32, P_, I64, C.POINTER(hp_view), C.POINTER(hp_params), P_, P_, P_, P_, I32, I64, P_, P_,
+                            SZ, P_]),
     "hp_read_total": (I32, [P_, C.POINTER(I64), P_]),
     "hp_sort_workspace_bytes": (SZ, [I64, I32]),
     "hp_sort": (I32, [P_, P_, I64, I32, P_, P_, SZ, P_]),
     "hp_render_fwd": (I32, [P_, I64, P_, P_, I32, C.POINTER(hp_view), C.POINTER(hp_params), P_, I64, P_, P_, P_,
-                            P_]),
+                            P_, P_]),
     "hp_render_bwd_workspace_bytes": (SZ, [I64]),
     "hp_render_bwd": (I32, [C.POINTER(hp_gaussians), P_, P_, P_, I32, C.POINTER(hp_view), C.POINTER(hp_params), P_,
                             I64, P_, P_, P_, P_, C.POINTER(hp_gaussians_grad), P_, SZ, P_]),
     "hp_ssim_workspace_bytes": (SZ, [I32, I32, I64]),
     "hp_ssim": (I32, [P_, P_, I64, I32, I32, C.POINTER(hp_params), C.POINTER(hp_ssim_params), P_, P_, P_, P_, P_, P_,
                       SZ, P_]),
+    "hp_ssim_forward_saved": (I32, [P_, P_, I64, I32, I32, C.POINTER(hp_params), C.POINTER(hp_ssim_params), P_, P_,
+                                    P_, P_, SZ, P_]),
+    "hp_ssim_backward_saved": (I32, [P_, P_, I64, I32, I32, C.POINTER(hp_params), C.POINTER(hp_ssim_params), P_,
+                                     P_, SZ, P_, P_, P_]),
 }
 
 # every symbol the header declares

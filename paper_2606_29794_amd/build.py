@@ -23,6 +23,8 @@ FLAGS = [
     # keep packed FP32 instructions out of the generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-result", "-Wno-unknown-warning-option",
+    # atomics here are issued by one lane with a wave-reduced value already
+    "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
 ]
 
 

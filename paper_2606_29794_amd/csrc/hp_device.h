@@ -92,7 +92,7 @@ HP_HD HpMaskView hp_mask_view(P* base, const HpGeom& g) {
 //   r0 = (u_x, u_y, u_z, opacity)    unit camera-frame direction
 //   r1 = (eo_x, eo_z, ep_x, ep_y)    tangent frame: e_omega = (eo_x, 0, eo_z)
 //   r2 = (ep_z, A, B, C)             e_phi = (ep_x, ep_y, ep_z); q = A a^2 + 2 B a b + C b^2
-//   r3 = (red, green, blue, 0)
+//   r3 = (red, green, blue, sin((r_s + bin_guard) / 2))   the last entry drives the binning
 struct HpProjView {
   float4* rec;
   float* depth;
@@ -261,6 +261,15 @@ __device__ __forceinline__ void hp_load_rec(hp_cfloatp rec, uint32_t g, float4& 
 }
 __device__ __forceinline__ uint32_t hp_uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Workgroups go to the 8 XCDs round-robin by index.  Giving each XCD a
+// contiguous range of tiles keeps neighbouring tiles, which share most of
+// their data, in the same L2.  A bijection of [0, nb).
+__device__ __forceinline__ int hp_xcd_tile(int b, int nb) {
+  const int per = nb >> 3, rem = nb & 7;
+  const int x = b & 7, k = b >> 3;
+  return x * per + (x < rem ? x : rem) + k;
+}
+
 template <int CTRL>
 __device__ __forceinline__ float hp_dpp(float v) {
   // every source lane of the patterns used here is inside the row, so the
@@ -287,6 +296,61 @@ __device__ __forceinline__ void hp_wave_totals(float* v) {
     v[m] = (__int_as_float(__builtin_amdgcn_readlane(x, 0)) + __int_as_float(__builtin_amdgcn_readlane(x, 16))) +
            (__int_as_float(__builtin_amdgcn_readlane(x, 32)) + __int_as_float(__builtin_amdgcn_readlane(x, 48)));
   }
+}
+
+// Same sums, left in lane 63 only: after the row sums, row_bcast:15 adds
+// row r-1's sum into rows 1 and 3, and row_bcast:31 adds lane 31 (rows 0+1)
+// into rows 2 and 3, so lane 63 ends with the total of the wave.
+template <int N>
+__device__ __forceinline__ void hp_wave_totals_lane63(float* v) {
+#pragma unroll
+  for (int m = 0; m < N; ++m) v[m] += hp_dpp<0xB1>(v[m]);
+#pragma unroll
+  for (int m = 0; m < N; ++m) v[m] += hp_dpp<0x4E>(v[m]);
+#pragma unroll
+  for (int m = 0; m < N; ++m) v[m] += hp_dpp<0x141>(v[m]);
+#pragma unroll
+  for (int m = 0; m < N; ++m) v[m] += hp_dpp<0x140>(v[m]);
+#pragma unroll
+  for (int m = 0; m < N; ++m)
+    v[m] += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v[m]), 0x142, 0xa, 0xf, false));
+#pragma unroll
+  for (int m = 0; m < N; ++m)
+    v[m] += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v[m]), 0x143, 0xc, 0xf, false));
+}
+
+// Eight sums over the 64 lanes at once by recursive halving: every exchange
+// step moves half of the remaining values to the partner lane group, so the
+// 8 x 64 inputs need 4 + 2 + 1 cross-lane moves plus three butterfly adds
+// instead of 8 x 6.  gfx950's permlane32 swap pairs lane L with L ^ 32 and
+// permlane16 swap pairs L with L ^ 16; a row rotation by 8 pairs L with L ^ 8.
+// On return, lane L holds the total of value L >> 3 in all eight lanes of its
+// group (L & ~7 .. L | 7).
+__device__ __forceinline__ float hp_wave_totals8_spread(const float* v) {
+  float w[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    // low half keeps value m, high half keeps value m + 4
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[m]), __float_as_uint(v[m + 4]), false, false);
+    w[m] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
+  float x[2];
+#pragma unroll
+  for (int m = 0; m < 2; ++m) {
+    // even rows keep w[m], odd rows keep w[m + 2]
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(w[m]), __float_as_uint(w[m + 2]), false, false);
+    x[m] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
+  // lanes with bit 3 clear keep x[0] and take x[0] of lane L ^ 8; the others
+  // keep x[1] and take x[1] of lane L ^ 8
+  const bool hi = (hp_lane() & 8) != 0;
+  const float send = hi ? x[0] : x[1];
+  const float keep = hi ? x[1] : x[0];
+  float y = keep + hp_dpp<0x128>(send);  // row_ror:8
+  y += hp_dpp<0xB1>(y);
+  y += hp_dpp<0x4E>(y);
+  y += hp_dpp<0x141>(y);
+  return y;
 }
 
 __device__ __forceinline__ float hp_wave_sum(float v) {

@@ -144,32 +144,41 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t* __r
   for (int d = threadIdx.x; d < radix; d += kSortThreads) hist[(int64_t)d * nblocks + blockIdx.x] = s_h[d];
 }
 
-// Stable scatter.  Items are visited in rounds of 256 (thread t takes item
-// round*256 + t), so the visit order equals the input order; equal digits
-// within a wave are ranked by a ballot match on the digit bits, across the
-// block's four waves by per-wave counts, across rounds by running counts.
+// Stable scatter.  Wave w of a block owns the contiguous items
+// [w*1024, (w+1)*1024) of the block's 4096 and ranks them in 16 rounds of 64:
+// equal digits inside a round are matched by ballots on the digit bits, and a
+// running count per digit, private to the wave, carries the rank across
+// rounds.  After one barrier the per-wave counts become per-wave offsets and
+// the block's items are placed in LDS sorted by digit, so that the final
+// writes go out as contiguous runs per digit.
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t* __restrict__ keys,
                                                                 const uint32_t* __restrict__ vals, int64_t n,
                                                                 int shift, int bits, const uint32_t* __restrict__ offs,
                                                                 int64_t nblocks, uint32_t* __restrict__ okeys,
                                                                 uint32_t* __restrict__ ovals) {
-  __shared__ uint32_t s_off[256];
-  __shared__ uint32_t s_run[256];
-  __shared__ uint32_t s_w[4][256];
+  constexpr int kWaveItems = kSortTile / 4;  // 1024
+  constexpr int kRounds = kWaveItems / 64;   // 16
+  __shared__ uint32_t s_cnt[4][256];
+  __shared__ uint32_t s_loc[256];
+  __shared__ uint32_t s_goff[256];
+  __shared__ uint32_t s_key[kSortTile];
+  __shared__ uint32_t s_val[kSortTile];
   const int radix = 1 << bits;
   const uint32_t mask = (uint32_t)radix - 1;
   const int tid = threadIdx.x, lane = hp_lane(), w = tid >> 6;
-  for (int d = tid; d < radix; d += kSortThreads) {
-    s_off[d] = offs[(int64_t)d * nblocks + blockIdx.x];
-    s_run[d] = 0;
-  }
+  for (int k = tid; k < 4 * 256; k += kSortThreads) (&s_cnt[0][0])[k] = 0;
+  for (int d = tid; d < radix; d += kSortThreads) s_goff[d] = offs[(int64_t)d * nblocks + blockIdx.x];
+  __syncthreads();
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const int64_t base = (int64_t)blockIdx.x * kSortTile;
-  for (int r = 0; r < kSortItems; ++r) {
-    const int64_t i = base + (int64_t)r * kSortThreads + tid;
+  uint32_t rk[kRounds], kk[kRounds], vv[kRounds];
+#pragma unroll
+  for (int r = 0; r < kRounds; ++r) {
+    const int64_t i = base + (int64_t)w * kWaveItems + r * 64 + lane;
     const bool valid = i < n;
     const uint32_t key = valid ? keys[i] : 0u;
-    const uint32_t val = valid ? vals[i] : 0u;
+    kk[r] = key;
+    vv[r] = valid ? vals[i] : 0u;
     const uint32_t d = (key >> shift) & mask;
     uint64_t peers = __ballot(valid);
     for (int b = 0; b < bits; ++b) {
@@ -177,20 +186,57 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t* 
       const uint64_t m = __ballot(bit);
       peers &= bit ? m : ~m;
     }
-    for (int k = tid; k < 4 * 256; k += kSortThreads) (&s_w[0][0])[k] = 0;
-    __syncthreads();
+    uint32_t before = 0;
+    if (valid) before = s_cnt[w][d];
+    rk[r] = before + (uint32_t)__popcll(peers & lt);
     const int leader = __ffsll((unsigned long long)peers) - 1;
-    if (valid && lane == leader) s_w[w][d] = (uint32_t)__popcll(peers);
-    __syncthreads();
-    if (valid) {
-      uint32_t pos = s_off[d] + s_run[d] + (uint32_t)__popcll(peers & lt);
-      for (int k = 0; k < w; ++k) pos += s_w[k][d];
-      okeys[pos] = key;
-      ovals[pos] = val;
+    if (valid && lane == leader) s_cnt[w][d] = before + (uint32_t)__popcll(peers);
+  }
+  __syncthreads();
+  // per digit: per-wave exclusive offsets and the block-local start of the digit
+  uint32_t tot = 0;
+  if (tid < radix) {
+    const uint32_t c0 = s_cnt[0][tid], c1 = s_cnt[1][tid], c2 = s_cnt[2][tid], c3 = s_cnt[3][tid];
+    s_cnt[0][tid] = 0;
+    s_cnt[1][tid] = c0;
+    s_cnt[2][tid] = c0 + c1;
+    s_cnt[3][tid] = c0 + c1 + c2;
+    tot = c0 + c1 + c2 + c3;
+  }
+  // exclusive scan of the digit totals over the (<= 256) digits
+  {
+    uint32_t x = tot;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const uint32_t y = __shfl_up(x, off, 64);
+      if (lane >= off) x += y;
     }
+    __shared__ uint32_t s_wsum[4];
+    if (lane == 63) s_wsum[w] = x;
     __syncthreads();
-    for (int dd = tid; dd < radix; dd += kSortThreads) s_run[dd] += s_w[0][dd] + s_w[1][dd] + s_w[2][dd] + s_w[3][dd];
-    __syncthreads();
+    uint32_t add = 0;
+    for (int k = 0; k < w; ++k) add += s_wsum[k];
+    if (tid < radix) s_loc[tid] = add + x - tot;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kRounds; ++r) {
+    const int64_t i = base + (int64_t)w * kWaveItems + r * 64 + lane;
+    if (i < n) {
+      const uint32_t d = (kk[r] >> shift) & mask;
+      const uint32_t lp = s_loc[d] + s_cnt[w][d] + rk[r];
+      s_key[lp] = kk[r];
+      s_val[lp] = vv[r];
+    }
+  }
+  __syncthreads();
+  const int64_t nloc = n - base < kSortTile ? n - base : kSortTile;
+  for (int lp = tid; lp < nloc; lp += kSortThreads) {
+    const uint32_t key = s_key[lp];
+    const uint32_t d = (key >> shift) & mask;
+    const uint32_t g = s_goff[d] + ((uint32_t)lp - s_loc[d]);
+    okeys[g] = key;
+    ovals[g] = s_val[lp];
   }
 }
 

@@ -10,7 +10,7 @@
 // Work is split in two so that no lane walks a large Gaussian alone:
 //  coarse: each Gaussian walks the quadtree from the 12 faces down to the
 //          split level Ls = kt - 3 and lists the nodes that pass ("tasks");
-//  fine:   each task walks its subtree (at most 64 tiles) down to the tiles.
+//  fine:   one wave per task tests the (at most 64) tiles below its node.
 // Both walks run twice (count, then write at scanned offsets) so that tasks
 // and pairs stay in depth order.
 constexpr int kSplitDepth = 3;
@@ -23,6 +23,7 @@ struct BinWs {
   uint32_t* task_g;  // [cap_t] Gaussian of each task
   uint32_t* task_n;  // [cap_t] node index at the split level
   uint32_t* pcount;  // [cap_t] pairs per task
+  uint64_t* pmask;   // [cap_t] tiles hit below the task's node (bit per leaf)
   uint64_t* poff;    // [cap_t] exclusive scan of pcount
   uint32_t* t_total; // device scalars: task total (u32), pair total (u64)
   uint64_t* p_total;
@@ -35,7 +36,7 @@ static int64_t task_capacity(int64_t P) { return 16 * P + (1 << 20); }
 
 static size_t bin_ws_size(int64_t P) {
   const int64_t ct = task_capacity(P);
-  return 4 * hp_align256(P * 4) + 3 * hp_align256(ct * 4) + hp_align256(ct * 8) + 256 +
+  return 4 * hp_align256(P * 4) + 3 * hp_align256(ct * 4) + 2 * hp_align256(ct * 8) + 256 +
          hpsort::radix_ws_bytes(P) + hpsort::scan_ws_bytes<uint64_t>(ct > P ? ct : P);
 }
 
@@ -50,6 +51,7 @@ static BinWs bin_ws(void* base, int64_t P) {
   w.task_g = (uint32_t*)p; p += hp_align256(ct * 4);
   w.task_n = (uint32_t*)p; p += hp_align256(ct * 4);
   w.pcount = (uint32_t*)p; p += hp_align256(ct * 4);
+  w.pmask = (uint64_t*)p; p += hp_align256(ct * 8);
   w.poff = (uint64_t*)p; p += hp_align256(ct * 8);
   w.t_total = (uint32_t*)p;
   w.p_total = (uint64_t*)(p + 128);
@@ -72,6 +74,7 @@ struct BinTables {
   const float4* cap;
   const float2* sc;
   const uint8_t* node_active;  // null: every node holds active pixels (full sphere)
+  const uint8_t* leaf_active;  // never null: active flags of every node (all set for the full sphere)
   const int32_t* tile_compact;
   int kt, ls;
 };
@@ -129,14 +132,19 @@ __device__ __forceinline__ void quad_walk(const BinTables& T, int l0, int64_t i0
   }
 }
 
+// direction and (sin, cos) of half the test angle r_s + guard (the sine is
+// precomputed in the record; the half angle is at most pi/2, so the cosine is
+// the non-negative root)
 __device__ __forceinline__ void gauss_dir(const float4* rec, const float* radius, uint32_t gid, float guard, float* u,
                                           float* sg, float* cg, bool* ok) {
+  (void)guard;
   const float rs = radius[gid];
   *ok = rs > 0.f;
   if (!*ok) return;
-  const float4 r0 = rec[4 * (int64_t)gid];
-  u[0] = r0.x; u[1] = r0.y; u[2] = r0.z;
-  sincosf(0.5f * (rs + guard), sg, cg);
+  const hp_cfloatp r = (hp_cfloatp)rec + 16 * (int64_t)gid;
+  u[0] = r[0]; u[1] = r[1]; u[2] = r[2];
+  *sg = r[15];
+  *cg = sqrtf(fmaxf(0.f, 1.f - *sg * *sg));
 }
 
 // coarse walk: tasks of Gaussian order[k]
@@ -158,8 +166,10 @@ __global__ __launch_bounds__(256) void k_bin_coarse(int64_t P, const uint32_t* _
   }
   uint32_t cnt = 0;
   const uint32_t base = EMIT ? toff[k] : 0;
+  // the emit walk writes no more tasks than the count walk reserved
+  const uint32_t room = EMIT ? tcount[k] : 0;
   quad_walk(T, -1, 0, T.ls, u[0], u[1], u[2], sg, cg, [&](int64_t i) {
-    if (EMIT) {
+    if (EMIT && cnt < room) {
       task_g[base + cnt] = gid;
       task_n[base + cnt] = (uint32_t)i;
     }
@@ -168,37 +178,295 @@ __global__ __launch_bounds__(256) void k_bin_coarse(int64_t P, const uint32_t* _
   if (!EMIT) tcount[k] = cnt;
 }
 
-// fine walk: pairs of task t
-template <bool EMIT>
-__global__ __launch_bounds__(256) void k_bin_fine(const uint32_t* __restrict__ n_tasks, int64_t cap_t,
-                                                  const uint32_t* __restrict__ task_g,
-                                                  const uint32_t* __restrict__ task_n, const float4* __restrict__ rec,
-                                                  const float* __restrict__ radius, BinTables T, float guard,
-                                                  uint32_t* __restrict__ pcount, const uint64_t* __restrict__ poff,
-                                                  const int64_t* __restrict__ n_pairs, int64_t capacity,
-                                                  uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t nt = (int64_t)*n_tasks;
-  if (t >= nt || t >= cap_t) return;
-  if (EMIT && *n_pairs > capacity) return;
-  const uint32_t gid = task_g[t];
-  float u[3], sg, cg;
-  bool ok;
-  gauss_dir(rec, radius, gid, guard, u, &sg, &cg, &ok);
-  uint32_t cnt = 0;
-  const uint64_t base = EMIT ? poff[t] : 0;
-  quad_walk(T, T.ls, task_n[t], T.kt, u[0], u[1], u[2], sg, cg, [&](int64_t i) {
-    if (EMIT) {
-      keys[base + cnt] = (uint32_t)T.tile_compact[i];
-      vals[base + cnt] = gid;
+// fine stage: one lane per tile below a task's node (64 tiles three levels
+// down).  A wave takes 64 consecutive tasks at a time (their Gaussian and
+// node ids in one coalesced load, then read out lane by lane) and issues the
+// loads of kFineGroup tasks before testing any of them, so that many memory
+// requests are in flight per wave.  The count pass keeps each task's 64-bit
+// hit mask; the emit pass only turns masks into pairs, each hit written at
+// its rank among the task's hits so that the pairs of a task are contiguous
+// and tasks stay in depth order.
+constexpr int kFineGroup = 8;
+
+__device__ __forceinline__ uint64_t hp_readlane64(uint64_t v, int i) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, i);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), i);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+__global__ __launch_bounds__(256) void k_bin_fine_count(const uint32_t* __restrict__ n_tasks, int64_t cap_t,
+                                                        const uint32_t* __restrict__ task_g,
+                                                        const uint32_t* __restrict__ task_n,
+                                                        const float4* __restrict__ rec, BinTables T,
+                                                        uint64_t* __restrict__ pmask, uint32_t* __restrict__ pcount) {
+  int64_t nt = (int64_t)*n_tasks;
+  if (nt > cap_t) nt = cap_t;
+  const int lane = hp_lane();
+  const int depth = T.kt - T.ls;  // 0..3 levels below the task node
+  const bool leaf_lane = lane < (1 << (2 * depth));
+  const int leaf_mask = (1 << (2 * depth)) - 1;
+  const int64_t leaf_off = hp_level_offset(T.kt);
+  const int64_t nch = (nt + 63) >> 6;
+  const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+  const hp_cfloatp rp = (hp_cfloatp)rec;
+  for (int64_t c = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); c < nch; c += waves) {
+    const int64_t t0 = c << 6;
+    const int nin = nt - t0 < 64 ? (int)(nt - t0) : 64;
+    const uint32_t tg = lane < nin ? task_g[t0 + lane] : 0u;
+    const uint32_t tn = lane < nin ? task_n[t0 + lane] : 0u;
+    uint64_t mine = 0;
+    for (int i0 = 0; i0 < nin; i0 += kFineGroup) {
+      float3 cap[kFineGroup];  // cap centre (the radius enters through sc)
+      float2 sc[kFineGroup];
+      uint32_t act[kFineGroup];
+      float ux[kFineGroup], uy[kFineGroup], uz[kFineGroup], sg[kFineGroup];
+#pragma unroll
+      for (int q = 0; q < kFineGroup; ++q) {
+        // past the chunk's end the last task is loaded again; its result is dropped
+        const int i = i0 + q < nin ? i0 + q : nin - 1;
+        const uint32_t gid = (uint32_t)__builtin_amdgcn_readlane((int)tg, i);
+        // lanes past the node's leaves (depth < 3) load a valid leaf and drop it
+        const int64_t node = leaf_off + ((int64_t)(uint32_t)__builtin_amdgcn_readlane((int)tn, i) << (2 * depth)) +
+                             (lane & leaf_mask);
+        const hp_cfloatp r = rp + 16 * (int64_t)gid;
+        ux[q] = r[0]; uy[q] = r[1]; uz[q] = r[2]; sg[q] = r[15];
+        const float* cp = (const float*)(T.cap + node);
+        cap[q] = make_float3(cp[0], cp[1], cp[2]);
+        sc[q] = T.sc[node];
+        act[q] = (uint32_t)T.leaf_active[node];
+      }
+#pragma unroll
+      for (int q = 0; q < kFineGroup; ++q) {
+        const float cg = sqrtf(fmaxf(0.f, 1.f - sg[q] * sg[q]));
+        const float dx = cap[q].x - ux[q], dy = cap[q].y - uy[q], dz = cap[q].z - uz[q];
+        const float chord2 = dx * dx + dy * dy + dz * dz;
+        const float sh = sc[q].x * cg + sc[q].y * sg[q];  // sin((R + theta) / 2)
+        const float ch = sc[q].y * cg - sc[q].x * sg[q];  // cos((R + theta) / 2)
+        const bool hit = leaf_lane && (act[q] != 0u) && ((ch <= 0.f) || (chord2 <= 4.f * sh * sh));
+        const uint64_t m = __ballot(hit);
+        if (lane == i0 + q) mine = m;
+      }
     }
-    ++cnt;
-  });
-  if (!EMIT) pcount[t] = cnt;
+    if (lane < nin) {
+      pmask[t0 + lane] = mine;
+      pcount[t0 + lane] = (uint32_t)__popcll(mine);
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_bin_fine_emit(const uint32_t* __restrict__ n_tasks, int64_t cap_t,
+                                                       const uint32_t* __restrict__ task_g,
+                                                       const uint32_t* __restrict__ task_n, BinTables T,
+                                                       const uint64_t* __restrict__ pmask,
+                                                       const uint64_t* __restrict__ poff,
+                                                       const int64_t* __restrict__ n_pairs, int64_t capacity,
+                                                       uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+  int64_t nt = (int64_t)*n_tasks;
+  if (nt > cap_t) nt = cap_t;
+  if (*n_pairs > capacity) return;
+  const int lane = hp_lane();
+  const int depth = T.kt - T.ls;
+  const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  const int64_t nch = (nt + 63) >> 6;
+  const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+  for (int64_t c = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); c < nch; c += waves) {
+    const int64_t t0 = c << 6;
+    const int nin = nt - t0 < 64 ? (int)(nt - t0) : 64;
+    const uint32_t tg = lane < nin ? task_g[t0 + lane] : 0u;
+    const uint32_t tn = lane < nin ? task_n[t0 + lane] : 0u;
+    const uint64_t mk = lane < nin ? pmask[t0 + lane] : 0ull;
+    const uint64_t of = lane < nin ? poff[t0 + lane] : 0ull;
+    for (int i0 = 0; i0 < nin; i0 += kFineGroup) {
+      // all addresses and values of the group first, then only stores: no
+      // register that an in-flight store reads is written before it drains
+      int32_t comp[kFineGroup];
+      uint32_t gv[kFineGroup];
+      uint32_t* kp[kFineGroup];
+      uint32_t* vp[kFineGroup];
+      bool hit[kFineGroup];
+#pragma unroll
+      for (int q = 0; q < kFineGroup; ++q) {
+        const int i = i0 + q < nin ? i0 + q : nin - 1;
+        const uint64_t m = i0 + q < nin ? hp_readlane64(mk, i) : 0ull;
+        const int64_t leaf = ((int64_t)(uint32_t)__builtin_amdgcn_readlane((int)tn, i) << (2 * depth)) + lane;
+        hit[q] = ((m >> lane) & 1ull) != 0;
+        comp[q] = hit[q] ? T.tile_compact[leaf] : 0;
+        const uint64_t at = hp_readlane64(of, i) + (uint64_t)__popcll(m & below);
+        kp[q] = keys + at;
+        vp[q] = vals + at;
+        gv[q] = (uint32_t)__builtin_amdgcn_readlane((int)tg, i);
+      }
+      // wait once for the group's gathers (vmcnt 0; expcnt and lgkmcnt left
+      // at their maxima), so that the masked stores below need no waits
+      __builtin_amdgcn_s_waitcnt(0x0F70);
+#pragma unroll
+      for (int q = 0; q < kFineGroup; ++q) {
+        if (hit[q]) {
+          *kp[q] = (uint32_t)comp[q];
+          *vp[q] = gv[q];
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Pairs straight into per-tile depth order (no sort of the pairs).  Every
+// task names one node at the split level and one Gaussian.  After a stable
+// sort of the tasks by node, the pairs of tile t = (node n, leaf b) are the
+// tasks of n's segment whose test on leaf b passes, in depth order.  Each
+// segment is cut into chunks of 64 tasks; a wave per chunk keeps one leaf per
+// lane and tests the chunk's tasks one after the other, collecting for leaf b
+// the 64-bit column W_b of hits.  popcount(W_b) per (chunk, leaf), laid out
+// tile-major -- for each node, for each leaf, its chunks in order -- and
+// scanned, gives every (chunk, leaf) its first output slot; inside a chunk
+// the task at bit j writes at popcount(W_b below j).
+// ---------------------------------------------------------------------------
+__global__ void k_seg_ranges(const uint32_t* __restrict__ keys, int64_t n, uint32_t nn, uint32_t* __restrict__ seg) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t k = keys[i];
+  if (k >= nn) return;
+  if (i == 0 || keys[i - 1] != k) seg[2 * (int64_t)k] = (uint32_t)i;
+  if (i == n - 1 || keys[i + 1] != k) seg[2 * (int64_t)k + 1] = (uint32_t)(i + 1);
+}
+
+__global__ void k_seg_chunks(const uint32_t* __restrict__ seg, uint32_t nn, uint32_t* __restrict__ nch) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nn) nch[i] = (seg[2 * i + 1] - seg[2 * i] + 63) / 64;
+}
+
+__global__ void k_fill_zero_u32(uint32_t* __restrict__ p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+// chunk c -> its node: the last n with choff[n] <= c (choff non-decreasing,
+// choff[0] = 0, c < choff[nn]); wave-uniform
+__device__ __forceinline__ uint32_t chunk_node(const uint32_t* __restrict__ choff, uint32_t nn, uint32_t c) {
+  uint32_t lo = 0, hi = nn;  // choff[lo] <= c < choff[hi]
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (hp_uniform(((hp_cu32p)choff)[mid]) <= c) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+struct ChunkInfo {
+  uint32_t node, local, nchn, t0, ntask;
+};
+__device__ __forceinline__ ChunkInfo chunk_info(const uint32_t* choff, uint32_t nn, const uint32_t* seg, uint32_t c) {
+  ChunkInfo ci;
+  ci.node = chunk_node(choff, nn, c);
+  const uint32_t c0 = hp_uniform(((hp_cu32p)choff)[ci.node]);
+  ci.nchn = hp_uniform(((hp_cu32p)choff)[ci.node + 1]) - c0;
+  ci.local = c - c0;
+  const uint32_t s0 = hp_uniform(((hp_cu32p)seg)[2 * ci.node]), s1 = hp_uniform(((hp_cu32p)seg)[2 * ci.node + 1]);
+  ci.t0 = s0 + 64 * ci.local;
+  ci.ntask = s1 - ci.t0 < 64 ? s1 - ci.t0 : 64;
+  return ci;
+}
+
+// per chunk: the hit columns W_b (kept) and their popcounts, tile-major
+__global__ __launch_bounds__(256) void k_bin_cols(const uint32_t* __restrict__ choff, uint32_t nn,
+                                                  const uint32_t* __restrict__ seg, const uint32_t* __restrict__ tgid,
+                                                  const float4* __restrict__ rec, BinTables T,
+                                                  uint64_t* __restrict__ wcol, uint32_t* __restrict__ cnt) {
+  const uint32_t nchunks = hp_uniform(((hp_cu32p)choff)[nn]);
+  const int lane = hp_lane();
+  const int depth = T.kt - T.ls;
+  const int nleaf = 1 << (2 * depth);
+  const bool leaf_lane = lane < nleaf;
+  const int64_t leaf_off = hp_level_offset(T.kt);
+  const hp_cfloatp rp = (hp_cfloatp)rec;
+  const uint32_t waves = gridDim.x * (blockDim.x >> 6);
+  for (uint32_t c = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); c < nchunks; c += waves) {
+    const ChunkInfo ci = chunk_info(choff, nn, seg, c);
+    // this lane's leaf below the chunk's node (lanes past the leaves test a
+    // valid leaf and drop the result)
+    const int64_t leaf = leaf_off + ((int64_t)ci.node << (2 * depth)) + (lane & (nleaf - 1));
+    const float* cp = (const float*)(T.cap + leaf);
+    const float cx = cp[0], cy = cp[1], cz = cp[2];
+    const float2 h = T.sc[leaf];
+    const bool act = leaf_lane && T.leaf_active[leaf] != 0;
+    const uint32_t tg = (uint32_t)lane < ci.ntask ? tgid[ci.t0 + lane] : 0u;
+    uint64_t W = 0;
+    for (uint32_t j0 = 0; j0 < ci.ntask; j0 += kFineGroup) {
+      float ux[kFineGroup], uy[kFineGroup], uz[kFineGroup], sg[kFineGroup];
+#pragma unroll
+      for (int q = 0; q < kFineGroup; ++q) {
+        const uint32_t j = j0 + q < ci.ntask ? j0 + q : ci.ntask - 1;
+        const hp_cfloatp r = rp + 16 * (int64_t)(uint32_t)__builtin_amdgcn_readlane((int)tg, (int)j);
+        ux[q] = r[0]; uy[q] = r[1]; uz[q] = r[2]; sg[q] = r[15];
+      }
+#pragma unroll
+      for (int q = 0; q < kFineGroup; ++q) {
+        const float cg = sqrtf(fmaxf(0.f, 1.f - sg[q] * sg[q]));
+        const float dx = cx - ux[q], dy = cy - uy[q], dz = cz - uz[q];
+        const float chord2 = dx * dx + dy * dy + dz * dz;
+        const float sh = h.x * cg + h.y * sg[q];  // sin((R + theta) / 2)
+        const float chh = h.y * cg - h.x * sg[q]; // cos((R + theta) / 2)
+        const bool hit = act && j0 + q < ci.ntask && ((chh <= 0.f) || (chord2 <= 4.f * sh * sh));
+        W |= hit ? (1ull << ((j0 + q) & 63u)) : 0ull;
+      }
+    }
+    if (leaf_lane) {
+      wcol[(int64_t)c * 64 + lane] = W;
+      const int64_t flat = (int64_t)(c - ci.local) * nleaf + (int64_t)lane * ci.nchn + ci.local;
+      cnt[flat] = (uint32_t)__popcll(W);
+    }
+  }
+}
+
+// per chunk: every hit of leaf b's column goes to its slot in tile (node, b)
+__global__ __launch_bounds__(256) void k_bin_emit_sorted(const uint32_t* __restrict__ choff, uint32_t nn,
+                                                         const uint32_t* __restrict__ seg,
+                                                         const uint32_t* __restrict__ tgid, int depth,
+                                                         const uint64_t* __restrict__ wcol,
+                                                         const uint64_t* __restrict__ start,
+                                                         const int64_t* __restrict__ n_pairs, int64_t capacity,
+                                                         uint32_t* __restrict__ vals) {
+  if (*n_pairs > capacity) return;
+  const uint32_t nchunks = hp_uniform(((hp_cu32p)choff)[nn]);
+  const int lane = hp_lane();
+  const int nleaf = 1 << (2 * depth);
+  const bool leaf_lane = lane < nleaf;
+  const uint32_t waves = gridDim.x * (blockDim.x >> 6);
+  for (uint32_t c = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); c < nchunks; c += waves) {
+    const ChunkInfo ci = chunk_info(choff, nn, seg, c);
+    const uint64_t W = leaf_lane ? wcol[(int64_t)c * 64 + lane] : 0ull;
+    const uint64_t base =
+        leaf_lane ? start[(int64_t)(c - ci.local) * nleaf + (int64_t)lane * ci.nchn + ci.local] : 0ull;
+    const uint32_t tg = (uint32_t)lane < ci.ntask ? tgid[ci.t0 + lane] : 0u;
+    for (uint32_t j = 0; j < ci.ntask; ++j) {
+      const uint32_t g = (uint32_t)__builtin_amdgcn_readlane((int)tg, (int)j);
+      if ((W >> j) & 1ull) vals[base + (uint64_t)__popcll(W & ((1ull << j) - 1ull))] = g;
+    }
+  }
+}
+
+// (start, end) of every active tile from the scanned column counts
+__global__ void k_bin_ranges(int32_t n_tiles, const int32_t* __restrict__ active_tiles, int depth,
+                             const uint32_t* __restrict__ choff, const uint64_t* __restrict__ start,
+                             uint32_t* __restrict__ ranges) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n_tiles) return;
+  const int t = active_tiles[k];
+  const int nleaf = 1 << (2 * depth);
+  const uint32_t n = (uint32_t)t >> (2 * depth), b = (uint32_t)t & (uint32_t)(nleaf - 1);
+  const int64_t c0 = choff[n], nchn = (int64_t)choff[n + 1] - c0;
+  ranges[2 * k] = (uint32_t)start[c0 * nleaf + b * nchn];
+  ranges[2 * k + 1] = (uint32_t)start[c0 * nleaf + (b + 1) * nchn];
 }
 
 __global__ void k_store_total(const uint64_t* grand, int64_t* n_pairs) { *n_pairs = (int64_t)*grand; }
 __global__ void k_store_zero(int64_t* n_pairs) { *n_pairs = 0; }
+
+// one wave per 64 tasks, at most 8192 blocks of 4 waves that loop over them
+static unsigned fine_grid(int64_t nt) {
+  const int64_t blocks = ((nt + 63) / 64 + 3) / 4;
+  return (unsigned)(blocks < 8192 ? (blocks > 0 ? blocks : 1) : 8192);
+}
 
 extern "C" size_t hp_bin_workspace_bytes(int64_t P) { return P < 0 ? 0 : bin_ws_size(P) + 256; }
 
@@ -218,8 +486,8 @@ extern "C" hp_status hp_bin(int32_t phase, const void* projected, int64_t P, con
   const HpMaskView mv = hp_mask_view((const char*)mask, g);
   BinWs w = bin_ws(ws, P);
   const int ls = g.kt > kSplitDepth ? g.kt - kSplitDepth : 0;
-  BinTables T{gv.cap, gv.sc, view->cam_type == HP_CAM_FULL ? nullptr : mv.node_active, mv.tile_compact, g.kt, ls};
-  const unsigned fine_blocks = hp_blocks(w.cap_t, 256);
+  BinTables T{gv.cap, gv.sc, view->cam_type == HP_CAM_FULL ? nullptr : mv.node_active, mv.node_active,
+              mv.tile_compact, g.kt, ls};
   if (phase & HP_BIN_COUNT) {
     if (P == 0) {
       hipLaunchKernelGGL(k_store_zero, dim3(1), dim3(1), 0, s, n_pairs);
@@ -242,10 +510,8 @@ extern "C" hp_status hp_bin(int32_t phase, const void* projected, int64_t P, con
                        T, prm->bin_guard, w.tcount, w.toff, w.task_g, w.task_n);
     HP_CHECK_LAUNCH();
     if (nt > 0) {
-      hipLaunchKernelGGL((k_bin_fine<false>), dim3(hp_blocks(nt, 256)), dim3(256), 0, s, (const uint32_t*)w.t_total,
-                         w.cap_t, w.task_g, w.task_n, pv.rec, pv.radius, T, prm->bin_guard, w.pcount,
-                         (const uint64_t*)nullptr, (const int64_t*)nullptr, (int64_t)0, (uint32_t*)nullptr,
-                         (uint32_t*)nullptr);
+      hipLaunchKernelGGL(k_bin_fine_count, dim3(fine_grid(nt)), dim3(256), 0, s, (const uint32_t*)w.t_total, w.cap_t,
+                         w.task_g, w.task_n, pv.rec, T, w.pmask, w.pcount);
       HP_CHECK_LAUNCH();
       HP_TRY((hpsort::scan_exclusive<uint64_t, uint32_t>(w.pcount, w.poff, nt, w.p_total, w.scan_ws, s)));
       hipLaunchKernelGGL(k_store_total, dim3(1), dim3(1), 0, s, (const uint64_t*)w.p_total, n_pairs);
@@ -255,18 +521,168 @@ extern "C" hp_status hp_bin(int32_t phase, const void* projected, int64_t P, con
     HP_CHECK_LAUNCH();
   }
   if ((phase & HP_BIN_EMIT) && P > 0) {
-    (void)fine_blocks;
     // the task count is read on the device; the grid covers the capacity bound
     // only up to the tasks present when the count phase ran on this stream
     uint32_t nt = 0;
     if (hipMemcpyAsync(&nt, w.t_total, 4, hipMemcpyDeviceToHost, s) != hipSuccess) return HP_ERR_DEVICE;
     if (hipStreamSynchronize(s) != hipSuccess) return HP_ERR_DEVICE;
     if (nt > 0) {
-      hipLaunchKernelGGL((k_bin_fine<true>), dim3(hp_blocks(nt, 256)), dim3(256), 0, s, (const uint32_t*)w.t_total,
-                         w.cap_t, w.task_g, w.task_n, pv.rec, pv.radius, T, prm->bin_guard, w.pcount, w.poff, n_pairs,
-                         capacity, keys, vals);
+      hipLaunchKernelGGL(k_bin_fine_emit, dim3(fine_grid(nt)), dim3(256), 0, s, (const uint32_t*)w.t_total, w.cap_t,
+                         w.task_g, w.task_n, T, (const uint64_t*)w.pmask, (const uint64_t*)w.poff, n_pairs, capacity,
+                         keys, vals);
       HP_CHECK_LAUNCH();
     }
+  }
+  return HP_OK;
+}
+
+// ---- sorted emission: workspace and entry point -----------------------------
+struct SortedWs {
+  void* tsort_ws;    // radix sort of the tasks by node
+  uint32_t* seg;     // [nn][2] task segment of every node
+  uint32_t* nch;     // [nn] chunks per node
+  uint32_t* choff;   // [nn + 1] first chunk of every node, total last
+  uint32_t* cnt;     // [L] hits per (chunk, leaf), tile-major, zero tail
+  uint64_t* start;   // [L] exclusive scan of cnt: first output slot
+  uint64_t* wcol;    // [nchunk_max][64] hit columns
+  void* scan_ws;
+  int64_t nn, nchunk_max, L;
+};
+
+static void sorted_dims(int64_t P, const HpGeom& g, int64_t* nn, int64_t* nchunk_max, int64_t* L) {
+  const int ls = g.kt > kSplitDepth ? g.kt - kSplitDepth : 0;
+  const int depth = g.kt - ls;
+  *nn = 12ll << (2 * ls);
+  *nchunk_max = task_capacity(P) / 64 + *nn + 1;
+  *L = *nchunk_max * (1ll << (2 * depth)) + 1;
+}
+
+static size_t sorted_ws_size(int64_t P, const HpGeom& g) {
+  int64_t nn, ncm, L;
+  sorted_dims(P, g, &nn, &ncm, &L);
+  return hpsort::radix_ws_bytes(task_capacity(P)) + hp_align256(nn * 8) + hp_align256(nn * 4) +
+         hp_align256((nn + 1) * 4) + hp_align256(L * 4) + hp_align256(L * 8) + hp_align256(ncm * 64 * 8) +
+         hpsort::scan_ws_bytes<uint64_t>(L > nn ? L : nn);
+}
+
+static SortedWs sorted_ws(void* base, int64_t P, const HpGeom& g) {
+  SortedWs w;
+  sorted_dims(P, g, &w.nn, &w.nchunk_max, &w.L);
+  char* p = (char*)base;
+  w.tsort_ws = p; p += hpsort::radix_ws_bytes(task_capacity(P));
+  w.seg = (uint32_t*)p; p += hp_align256(w.nn * 8);
+  w.nch = (uint32_t*)p; p += hp_align256(w.nn * 4);
+  w.choff = (uint32_t*)p; p += hp_align256((w.nn + 1) * 4);
+  w.cnt = (uint32_t*)p; p += hp_align256(w.L * 4);
+  w.start = (uint64_t*)p; p += hp_align256(w.L * 8);
+  w.wcol = (uint64_t*)p; p += hp_align256(w.nchunk_max * 64 * 8);
+  w.scan_ws = p;
+  return w;
+}
+
+extern "C" size_t hp_bin_sorted_workspace_bytes(int64_t P, int32_t order, int32_t tile_log2) {
+  if (P < 0 || order < 0 || order > HP_MAX_ORDER || tile_log2 < 0 || tile_log2 > 4) return 0;
+  const HpGeom g = hp_geom(order, tile_log2);
+  return bin_ws_size(P) + sorted_ws_size(P, g) + 512;
+}
+
+// one wave per chunk, at most 8192 blocks of 4 waves looping over the chunks
+static unsigned chunk_grid(int64_t nchunks) {
+  const int64_t blocks = (nchunks + 3) / 4;
+  return (unsigned)(blocks < 8192 ? (blocks > 0 ? blocks : 1) : 8192);
+}
+
+extern "C" hp_status hp_bin_sorted(int32_t phase, const void* projected, int64_t P, const hp_view* view,
+                                   const hp_params* prm, const void* grid, const void* mask, uint32_t* vals,
+                                   uint32_t* tile_ranges, int32_t n_tiles, int64_t capacity, int64_t* n_pairs,
+                                   void* ws, size_t ws_bytes, void* stream) {
+  if (phase < HP_BIN_COUNT || phase > HP_BIN_ALL) return HP_ERR_INVALID_ARG;
+  HP_TRY(hp_check_view(view, prm));
+  if (P < 0 || P > ((int64_t)1 << 31) - 1 || capacity < 0 || capacity > ((int64_t)1 << 32) - 1 || n_tiles < 0)
+    return HP_ERR_INVALID_ARG;
+  if (!projected || !grid || !mask || !n_pairs || !ws) return HP_ERR_INVALID_ARG;
+  if ((phase & HP_BIN_EMIT) && ((capacity > 0 && !vals) || (n_tiles > 0 && !tile_ranges))) return HP_ERR_INVALID_ARG;
+  const HpGeom g = hp_geom(view->order, prm->tile_log2);
+  if (n_tiles > g.ntile) return HP_ERR_INVALID_ARG;
+  if (ws_bytes < hp_bin_sorted_workspace_bytes(P, view->order, prm->tile_log2)) return HP_ERR_CAPACITY;
+  hipStream_t s = (hipStream_t)stream;
+  const HpProjView pv = hp_proj_view((const char*)projected, P);
+  const HpGridView gv = hp_grid_view((void*)grid, g);
+  const HpMaskView mv = hp_mask_view((const char*)mask, g);
+  BinWs w = bin_ws(ws, P);
+  SortedWs sw = sorted_ws((char*)ws + hp_align256(bin_ws_size(P)), P, g);
+  const int ls = g.kt > kSplitDepth ? g.kt - kSplitDepth : 0;
+  const int depth = g.kt - ls;
+  BinTables T{gv.cap, gv.sc, view->cam_type == HP_CAM_FULL ? nullptr : mv.node_active, mv.node_active,
+              mv.tile_compact, g.kt, ls};
+  const uint32_t nn = (uint32_t)sw.nn;
+  if (phase & HP_BIN_COUNT) {
+    if (P == 0) {
+      hipLaunchKernelGGL(k_store_zero, dim3(1), dim3(1), 0, s, n_pairs);
+      HP_CHECK_LAUNCH();
+      return HP_OK;
+    }
+    // tasks (Gaussian, node at the split level) in depth order
+    hipLaunchKernelGGL(k_depth_keys, dim3(hp_blocks(P, 256)), dim3(256), 0, s, P, pv.depth, w.dkey, w.order);
+    HP_CHECK_LAUNCH();
+    HP_TRY(hpsort::radix_sort(w.dkey, w.order, P, 32, w.sort_ws, s));
+    hipLaunchKernelGGL((k_bin_coarse<false>), dim3(hp_blocks(P, 256)), dim3(256), 0, s, P, w.order, pv.rec, pv.radius,
+                       T, prm->bin_guard, w.tcount, (const uint32_t*)nullptr, (uint32_t*)nullptr, (uint32_t*)nullptr);
+    HP_CHECK_LAUNCH();
+    HP_TRY((hpsort::scan_exclusive<uint32_t, uint32_t>(w.tcount, w.toff, P, w.t_total, w.scan_ws, s)));
+    uint32_t nt = 0;
+    if (hipMemcpyAsync(&nt, w.t_total, 4, hipMemcpyDeviceToHost, s) != hipSuccess) return HP_ERR_DEVICE;
+    if (hipStreamSynchronize(s) != hipSuccess) return HP_ERR_DEVICE;
+    if ((int64_t)nt > w.cap_t) return HP_ERR_CAPACITY;
+    hipLaunchKernelGGL((k_bin_coarse<true>), dim3(hp_blocks(P, 256)), dim3(256), 0, s, P, w.order, pv.rec, pv.radius,
+                       T, prm->bin_guard, w.tcount, w.toff, w.task_g, w.task_n);
+    HP_CHECK_LAUNCH();
+    // stable sort of the tasks by node; segments and chunk offsets per node
+    int nbits = 0;
+    while (((int64_t)1 << nbits) < sw.nn) ++nbits;
+    HP_TRY(hpsort::radix_sort(w.task_n, w.task_g, nt, nbits, sw.tsort_ws, s));
+    hipLaunchKernelGGL(k_fill_zero_u32, dim3(hp_blocks(2 * sw.nn, 256)), dim3(256), 0, s, sw.seg, 2 * sw.nn);
+    HP_CHECK_LAUNCH();
+    if (nt > 0) {
+      hipLaunchKernelGGL(k_seg_ranges, dim3(hp_blocks(nt, 256)), dim3(256), 0, s, w.task_n, (int64_t)nt, nn, sw.seg);
+      HP_CHECK_LAUNCH();
+    }
+    hipLaunchKernelGGL(k_seg_chunks, dim3(hp_blocks(sw.nn, 256)), dim3(256), 0, s, sw.seg, nn, sw.nch);
+    HP_CHECK_LAUNCH();
+    HP_TRY((hpsort::scan_exclusive<uint32_t, uint32_t>(sw.nch, sw.choff, sw.nn, sw.choff + sw.nn, sw.scan_ws, s)));
+    // hit columns and their counts.  The chunks number at most nt/64 + nn;
+    // the counts beyond the last chunk stay zero, so the scan entry at the
+    // end of the last tile is the total.
+    const int64_t nchunk_bound = (int64_t)nt / 64 + sw.nn + 1;
+    const int64_t La = nchunk_bound * (1ll << (2 * depth)) + 1;
+    hipLaunchKernelGGL(k_fill_zero_u32, dim3(hp_blocks(La, 256)), dim3(256), 0, s, sw.cnt, La);
+    HP_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_bin_cols, dim3(chunk_grid(nchunk_bound)), dim3(256), 0, s, (const uint32_t*)sw.choff, nn,
+                       (const uint32_t*)sw.seg, (const uint32_t*)w.task_g, pv.rec, T, sw.wcol, sw.cnt);
+    HP_CHECK_LAUNCH();
+    HP_TRY((hpsort::scan_exclusive<uint64_t, uint32_t>(sw.cnt, sw.start, La, w.p_total, sw.scan_ws, s)));
+    hipLaunchKernelGGL(k_store_total, dim3(1), dim3(1), 0, s, (const uint64_t*)w.p_total, n_pairs);
+    HP_CHECK_LAUNCH();
+  }
+  if ((phase & HP_BIN_EMIT) && P > 0) {
+    uint32_t nt = 0;
+    if (hipMemcpyAsync(&nt, w.t_total, 4, hipMemcpyDeviceToHost, s) != hipSuccess) return HP_ERR_DEVICE;
+    if (hipStreamSynchronize(s) != hipSuccess) return HP_ERR_DEVICE;
+    if ((int64_t)nt > w.cap_t) return HP_ERR_CAPACITY;
+    const int64_t nchunk_bound = (int64_t)nt / 64 + sw.nn + 1;
+    hipLaunchKernelGGL(k_bin_emit_sorted, dim3(chunk_grid(nchunk_bound)), dim3(256), 0, s, (const uint32_t*)sw.choff,
+                       nn, (const uint32_t*)sw.seg, (const uint32_t*)w.task_g, depth, (const uint64_t*)sw.wcol,
+                       (const uint64_t*)sw.start, (const int64_t*)n_pairs, capacity, vals);
+    HP_CHECK_LAUNCH();
+    if (n_tiles > 0) {
+      hipLaunchKernelGGL(k_bin_ranges, dim3(hp_blocks(n_tiles, 256)), dim3(256), 0, s, n_tiles, mv.active_tiles, depth,
+                         (const uint32_t*)sw.choff, (const uint64_t*)sw.start, tile_ranges);
+      HP_CHECK_LAUNCH();
+    }
+  } else if ((phase & HP_BIN_EMIT) && n_tiles > 0) {
+    hipLaunchKernelGGL(k_fill_zero_u32, dim3(hp_blocks(2 * (int64_t)n_tiles, 256)), dim3(256), 0, s, tile_ranges,
+                       2 * (int64_t)n_tiles);
+    HP_CHECK_LAUNCH();
   }
   return HP_OK;
 }

@@ -7,9 +7,8 @@
 // Projection of one Gaussian (inputs already in registers) for one view.
 __device__ __forceinline__ void project_one(int deg, float mx, float my, float mz, const float s_in[3],
                                             const float qin[4], float op, const float* shc /*[16][3]*/,
-                                            const HpViewK& V, float r_min, float rs_sigma, float sh_off,
-                                            float4* __restrict__ rec, float* __restrict__ depth,
-                                            float* __restrict__ radius, int64_t i) {
+                                            const HpViewK& V, float r_min, float rs_sigma, float sh_off, float guard,
+                                            float4 out[4], float* depth, float* radius) {
   const float tx = V.W[0] * mx + V.W[1] * my + V.W[2] * mz + V.b[0];
   const float ty = V.W[3] * mx + V.W[4] * my + V.W[5] * mz + V.b[1];
   const float tz = V.W[6] * mx + V.W[7] * my + V.W[8] * mz + V.b[2];
@@ -74,15 +73,16 @@ __device__ __forceinline__ void project_one(int deg, float mx, float my, float m
       r0 = make_float4(ux, uy, uz, op);
       r1 = make_float4(eo0, eo2, ep0, ep1);
       r2 = make_float4(ep2, sc * idet, -sb * idet, sa * idet);
-      r3 = make_float4(col[0], col[1], col[2], 0.f);
+      // sin of half the tile-test angle r_s + guard, used by the binning
+      r3 = make_float4(col[0], col[1], col[2], sinf(0.5f * fminf(rad + guard, (float)M_PI)));
     }
   }
-  rec[4 * i] = r0;
-  rec[4 * i + 1] = r1;
-  rec[4 * i + 2] = r2;
-  rec[4 * i + 3] = r3;
-  depth[i] = dep;
-  radius[i] = rad;
+  out[0] = r0;
+  out[1] = r1;
+  out[2] = r2;
+  out[3] = r3;
+  *depth = dep;
+  *radius = rad;
 }
 
 #define HP_MAX_VIEWS 8
@@ -95,24 +95,47 @@ struct PreBatch {
 };
 
 // One thread per Gaussian; SoA inputs give coalesced loads and are read once
-// for all the views of the batch; each view's 64-byte record is written as
-// four float4 stores.
+// for all the views of the batch.  The 64-byte records of a block's 256
+// Gaussians are contiguous in memory: they go through LDS so that every
+// store instruction writes 4 KB of whole lines (a thread storing its own
+// record would leave every store a quarter-line write).
 __global__ __launch_bounds__(256) void k_preprocess(int64_t P, int deg, const float* __restrict__ mean,
                                                     const float* __restrict__ scale, const float* __restrict__ rot,
                                                     const float* __restrict__ opac, const float* __restrict__ sh,
-                                                    PreBatch B, float r_min, float rs_sigma, float sh_off) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= P) return;
-  const float mx = mean[i], my = mean[P + i], mz = mean[2 * P + i];
-  const float s[3] = {scale[i], scale[P + i], scale[2 * P + i]};
-  const float q[4] = {rot[i], rot[P + i], rot[2 * P + i], rot[3 * P + i]};
-  const float op = opac[i];
+                                                    PreBatch B, float r_min, float rs_sigma, float sh_off,
+                                                    float guard) {
+  __shared__ float4 s_rec[4 * 256];
+  const int tid = threadIdx.x;
+  const int64_t i0 = (int64_t)blockIdx.x * 256;
+  const int64_t i = i0 + tid;
+  const bool ok = i < P;
+  const int64_t ii = ok ? i : P - 1;  // past the end: a valid Gaussian, result dropped
+  const float mx = mean[ii], my = mean[P + ii], mz = mean[2 * P + ii];
+  const float s[3] = {scale[ii], scale[P + ii], scale[2 * P + ii]};
+  const float q[4] = {rot[ii], rot[P + ii], rot[2 * P + ii], rot[3 * P + ii]};
+  const float op = opac[ii];
   const int K = (deg + 1) * (deg + 1);
   float shc[48];
 #pragma unroll
-  for (int k = 0; k < 48; ++k) shc[k] = k < 3 * K ? sh[(int64_t)k * P + i] : 0.f;
-  for (int v = 0; v < B.n; ++v)
-    project_one(deg, mx, my, mz, s, q, op, shc, B.V[v], r_min, rs_sigma, sh_off, B.rec[v], B.depth[v], B.radius[v], i);
+  for (int k = 0; k < 48; ++k) shc[k] = k < 3 * K ? sh[(int64_t)k * P + ii] : 0.f;
+  const int64_t nq = 4 * (P - i0 < 256 ? P - i0 : 256);  // float4 of this block's records
+  for (int v = 0; v < B.n; ++v) {
+    float4 r[4];
+    float dep, rad;
+    project_one(deg, mx, my, mz, s, q, op, shc, B.V[v], r_min, rs_sigma, sh_off, guard, r, &dep, &rad);
+    if (ok) {
+      B.depth[v][i] = dep;
+      B.radius[v][i] = rad;
+    }
+    __syncthreads();  // the previous view's records have left LDS
+#pragma unroll
+    for (int k = 0; k < 4; ++k) s_rec[4 * tid + k] = r[k];
+    __syncthreads();
+    float4* dst = B.rec[v] + 4 * i0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (k * 256 + tid < nq) dst[k * 256 + tid] = s_rec[k * 256 + tid];
+  }
 }
 
 extern "C" size_t hp_projected_bytes(int64_t P) { return P < 0 ? 0 : hp_proj_size(P); }
@@ -153,7 +176,8 @@ extern "C" hp_status hp_preprocess_batch(const hp_gaussians* g, int32_t n_views,
   if (projected_bytes < hp_proj_size(g->P)) return HP_ERR_CAPACITY;
   if (g->P == 0) return HP_OK;
   hipLaunchKernelGGL(k_preprocess, dim3(hp_blocks(g->P, 256)), dim3(256), 0, (hipStream_t)stream, g->P, g->sh_degree,
-                     g->mean, g->scale, g->rot, g->opacity, g->sh, B, prm->r_min, prm->rs_sigma, prm->sh_offset);
+                     g->mean, g->scale, g->rot, g->opacity, g->sh, B, prm->r_min, prm->rs_sigma, prm->sh_offset,
+                     prm->bin_guard);
   HP_CHECK_LAUNCH();
   return HP_OK;
 }

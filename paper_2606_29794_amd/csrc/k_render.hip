@@ -26,8 +26,9 @@ __device__ __forceinline__ void pixel_of_lane(const RenderArgs& A, int ct, bool*
   const int t = A.active_tiles[ct];
   const int cnt = A.tile_count[t];
   const int local = threadIdx.x;
-  *valid = local < cnt;
   *slot = (int64_t)A.tile_start[t] + local;
+  // the output arrays hold n_active pixels: a pixel past them is never written
+  *valid = local < cnt && *slot < A.n_active;
   p[0] = p[1] = p[2] = 0.f;
   if (*valid) {
     double v[3];
@@ -58,42 +59,95 @@ struct RenderOut {
   float* rgb;
   float* T;
   int32_t* ncon;
+  int32_t* nused;  // nullable: Gaussians composited per pixel
 };
 
-__device__ __forceinline__ void render_fwd_tile(const RenderArgs& A, const RenderOut& O, int ct) {
+// A tile's list is walked in chunks of HP_CHUNK entries staged in LDS: each of
+// the block's 256 threads fetches one 16-byte quarter of one record, so a
+// chunk costs one round of loads for the whole block.  The records of chunk
+// c + 1 (whose ids arrived a chunk earlier) and the ids of chunk c + 2 are
+// requested before chunk c is evaluated, so their latency overlaps the
+// evaluation; the waves then read each record as an LDS broadcast.
+#define HP_CHUNK 64
+#define HP_STAGE (4 * HP_CHUNK)  // float4 per chunk buffer = threads per block
+
+// quarter `q` of the record of Gaussian `g`, as written to LDS: quarter 3
+// carries the id in its last word (the render does not use that word).  The
+// id goes in only when the quarter is stored, so that a load still in flight
+// is never waited for early.
+__device__ __forceinline__ float4 stage_load(const float4* __restrict__ rec, uint32_t g, int q) {
+  return rec[4 * (size_t)g + q];
+}
+__device__ __forceinline__ void stage_store(float4* dst, float4 v, uint32_t g, int q) {
+  if (q == 3) v.w = __uint_as_float(g);
+  *dst = v;
+}
+
+__device__ __forceinline__ void render_fwd_tile(const RenderArgs& A, const RenderOut& O, int ct, float4* s_rec) {
   bool valid;
   int64_t slot;
   float p[3];
   pixel_of_lane(A, ct, &valid, &slot, p);
   const uint32_t j0 = hp_uniform(A.ranges[2 * ct]), j1 = hp_uniform(A.ranges[2 * ct + 1]);
+  const uint32_t n = j1 - j0;
   float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
   bool done = !valid;
-  uint32_t used = j1 - j0;
-  const hp_cu32p vals = (hp_cu32p)A.vals;
-  const hp_cfloatp rec = (hp_cfloatp)A.rec;
-  for (uint32_t j = j0; j < j1; ++j) {
-    if (__ballot(!done) == 0) break;
-    const uint32_t g = hp_uniform(vals[hp_uniform(j)]);
-    float4 r0, r1, r2, r3;
-    hp_load_rec(rec, g, r0, r1, r2, r3);
-    if (done) continue;
-    const float a = p[0] * r1.x + p[2] * r1.y;
-    const float b = p[0] * r1.z + p[1] * r1.w + p[2] * r2.x;
-    const float qt = a * (r2.y * a + 2.f * r2.z * b) + r2.w * b * b;
-    if (!(qt <= A.q_cut)) continue;  // q >= qt
-    const float c = p[0] * r0.x + p[1] * r0.y + p[2] * r0.z;
-    const float q = qt * hp_k2(a * a + b * b, c);
-    if (!(q <= A.q_cut)) continue;
-    const float alpha = fminf(A.alpha_max, r0.w * __expf(-0.5f * q));
-    const float w = alpha * T;
-    C0 += w * r3.x;
-    C1 += w * r3.y;
-    C2 += w * r3.z;
-    T -= w;
-    if (T < A.eps_T) {
-      done = true;
-      used = j + 1 - j0;
+  uint32_t used = n;
+  int nu = 0;
+  const int tid = threadIdx.x;
+  const uint32_t e = (uint32_t)tid >> 2;  // entry of a chunk this thread stages
+  const int q = tid & 3;                  // and which quarter of its record
+  const uint32_t* vals = A.vals + j0;
+  // per wave: does any pixel still composite; two sets by chunk parity, so
+  // that a wave already writing the next chunk's flag never overwrites one
+  // that a slower wave has yet to read
+  __shared__ int s_live[2][4];
+  {
+    const uint32_t g = e < n ? vals[e] : 0u;
+    stage_store(&s_rec[tid], e < n ? stage_load(A.rec, g, q) : make_float4(0.f, 0.f, 0.f, 0.f), g, q);
+  }
+  uint32_t gnext = HP_CHUNK + e < n ? vals[HP_CHUNK + e] : 0u;
+  __syncthreads();
+  const uint32_t nch = (n + HP_CHUNK - 1) / HP_CHUNK;
+  for (uint32_t c = 0; c < nch; ++c) {
+    const uint32_t base = c * HP_CHUNK;
+    float4 stage = make_float4(0.f, 0.f, 0.f, 0.f);
+    const uint32_t gstage = gnext;
+    if (base + HP_CHUNK + e < n) stage = stage_load(A.rec, gstage, q);
+    gnext = base + 2 * HP_CHUNK + e < n ? vals[base + 2 * HP_CHUNK + e] : 0u;
+    const float4* cur = s_rec + (c & 1) * HP_STAGE;
+    const uint32_t cnt = n - base < HP_CHUNK ? n - base : HP_CHUNK;
+    for (uint32_t i = 0; i < cnt; ++i) {
+      if (__ballot(!done) == 0) break;
+      const float4 r1 = cur[4 * i + 1], r2 = cur[4 * i + 2];
+      if (done) continue;
+      const float a = p[0] * r1.x + p[2] * r1.y;
+      const float b = p[0] * r1.z + p[1] * r1.w + p[2] * r2.x;
+      const float qt = a * (r2.y * a + 2.f * r2.z * b) + r2.w * b * b;
+      if (!(qt <= A.q_cut)) continue;  // q >= qt
+      const float4 r0 = cur[4 * i], r3 = cur[4 * i + 3];
+      const float cc = p[0] * r0.x + p[1] * r0.y + p[2] * r0.z;
+      const float qq = qt * hp_k2(a * a + b * b, cc);
+      if (!(qq <= A.q_cut)) continue;
+      const float alpha = fminf(A.alpha_max, r0.w * __expf(-0.5f * qq));
+      const float w = alpha * T;
+      C0 += w * r3.x;
+      C1 += w * r3.y;
+      C2 += w * r3.z;
+      T -= w;
+      ++nu;
+      if (T < A.eps_T) {
+        done = true;
+        used = base + i + 1;
+      }
     }
+    // one barrier both publishes the next chunk and tells whether any pixel
+    // of the block still composites
+    stage_store(&s_rec[((c + 1) & 1) * HP_STAGE + tid], stage, gstage, q);
+    const int par = c & 1;
+    if (hp_lane() == 0) s_live[par][tid >> 6] = __ballot(!done) != 0;
+    __syncthreads();
+    if (!(s_live[par][0] | s_live[par][1] | s_live[par][2] | s_live[par][3])) break;
   }
   if (valid) {
     O.rgb[slot] = C0;
@@ -101,10 +155,14 @@ __device__ __forceinline__ void render_fwd_tile(const RenderArgs& A, const Rende
     O.rgb[2 * A.n_active + slot] = C2;
     O.T[slot] = T;
     O.ncon[slot] = (int32_t)used;
+    if (O.nused) O.nused[slot] = nu;
   }
 }
 
-__global__ __launch_bounds__(256) void k_render_fwd(RenderArgs A, RenderOut O) { render_fwd_tile(A, O, blockIdx.x); }
+__global__ __launch_bounds__(256) void k_render_fwd(RenderArgs A, RenderOut O) {
+  __shared__ float4 s_rec[2 * HP_STAGE];
+  render_fwd_tile(A, O, hp_xcd_tile(blockIdx.x, gridDim.x), s_rec);
+}
 
 // Several requests in one launch: block b renders tile b - first[r] of
 // request r, where first[] is the prefix of the requests' tile counts.
@@ -117,10 +175,11 @@ struct RenderBatch {
 };
 
 __global__ __launch_bounds__(256) void k_render_fwd_batch(RenderBatch B) {
-  const int b = blockIdx.x;
+  __shared__ float4 s_rec[2 * HP_STAGE];
+  const int b = hp_xcd_tile(blockIdx.x, gridDim.x);
   int r = 0;
   while (r + 1 < B.n && b >= B.first[r + 1]) ++r;
-  render_fwd_tile(B.A[r], B.O[r], b - B.first[r]);
+  render_fwd_tile(B.A[r], B.O[r], b - B.first[r], s_rec);
 }
 
 // Per-Gaussian gradient accumulators written by the pixel pass:
@@ -130,14 +189,17 @@ __global__ __launch_bounds__(256) void k_render_fwd_batch(RenderBatch B) {
 __global__ __launch_bounds__(256) void k_render_bwd(RenderArgs A, int64_t P, const float* __restrict__ Tfin,
                                                     const int32_t* __restrict__ ncon, const float* __restrict__ gC,
                                                     const float* __restrict__ gTfin, float* __restrict__ acc) {
-  const int ct = blockIdx.x;
+  __shared__ float4 s_rec[2 * HP_STAGE];
+  __shared__ int s_nc[4];
+  // per chunk entry: the block's gradient totals (the 4 waves' sums), sent to
+  // memory with one atomic per non-zero value once the chunk is done
+  __shared__ float s_acc[HP_CHUNK * HP_NACC];
+  const int ct = hp_xcd_tile(blockIdx.x, gridDim.x);
   bool valid;
   int64_t slot;
   float p[3];
   pixel_of_lane(A, ct, &valid, &slot, p);
   const uint32_t j0 = hp_uniform(A.ranges[2 * ct]);
-  const hp_cu32p vals = (hp_cu32p)A.vals;
-  const hp_cfloatp rec = (hp_cfloatp)A.rec;
   int nc = 0;
   float Tf = 1.f, g0 = 0.f, g1 = 0.f, g2 = 0.f, gT = 0.f;
   if (valid) {
@@ -148,82 +210,122 @@ __global__ __launch_bounds__(256) void k_render_bwd(RenderArgs A, int64_t P, con
     g2 = gC[2 * A.n_active + slot];
     gT = gTfin ? gTfin[slot] : 0.f;
   }
-  // wave-uniform trip count: the largest n_contrib of the wave
+  // trip counts: the largest n_contrib of the wave and of the block
   int ncmax = nc;
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) ncmax = max(ncmax, __shfl_xor(ncmax, off, 64));
+  ncmax = (int)hp_uniform((uint32_t)ncmax);
+  const int tid = threadIdx.x, lane = hp_lane();
+  if (lane == 0) s_nc[tid >> 6] = ncmax;
+  for (int t = tid; t < HP_CHUNK * HP_NACC; t += 256) s_acc[t] = 0.f;
+  __syncthreads();
+  const int nb = max(max(s_nc[0], s_nc[1]), max(s_nc[2], s_nc[3]));
   float Tcur = Tf;                     // transmittance after the current entry
   float S0 = 0.f, S1 = 0.f, S2 = 0.f;  // colour composited behind the current entry
   const float gTT = gT * Tf;
-  ncmax = (int)hp_uniform((uint32_t)ncmax);
-  for (int k = ncmax - 1; k >= 0; --k) {
-    const uint32_t g = hp_uniform(vals[j0 + (uint32_t)k]);
-    float4 r0, r1, r2, r3;
-    hp_load_rec(rec, g, r0, r1, r2, r3);
-    float v[HP_NACC];
+  // entries nb-1 .. 0 in chunks of HP_CHUNK aligned at j0, last chunk first;
+  // the staging runs a chunk ahead as in the forward pass
+  const uint32_t e = (uint32_t)tid >> 2;
+  const int qs = tid & 3;
+  const uint32_t* vals = A.vals + j0;
+  const int ctop = nb > 0 ? (nb - 1) / HP_CHUNK : -1;
+  uint32_t gnext = 0u;
+  if (ctop >= 0) {
+    const uint32_t k0 = (uint32_t)ctop * HP_CHUNK + e;
+    const uint32_t g = k0 < (uint32_t)nb ? vals[k0] : 0u;
+    stage_store(&s_rec[tid], k0 < (uint32_t)nb ? stage_load(A.rec, g, qs) : make_float4(0.f, 0.f, 0.f, 0.f), g, qs);
+    if (ctop >= 1) gnext = vals[(uint32_t)(ctop - 1) * HP_CHUNK + e];
+  }
+  __syncthreads();
+  for (int ch = ctop; ch >= 0; --ch) {
+    float4 stage = make_float4(0.f, 0.f, 0.f, 0.f);
+    const uint32_t gstage = gnext;
+    if (ch >= 1) stage = stage_load(A.rec, gstage, qs);  // chunk ch - 1 is full
+    if (ch >= 2) gnext = vals[(uint32_t)(ch - 2) * HP_CHUNK + e];
+    const float4* cur = s_rec + ((ctop - ch) & 1) * HP_STAGE;
+    const int kbase = ch * HP_CHUNK;
+    const int ktop = min(kbase + HP_CHUNK, ncmax) - 1;  // this wave's last entry in the chunk
+    for (int k = ktop; k >= kbase; --k) {
+      const int i = k - kbase;
+      const float4 r0 = cur[4 * i], r1 = cur[4 * i + 1], r2 = cur[4 * i + 2], r3 = cur[4 * i + 3];
+      float v[HP_NACC];
 #pragma unroll
-    for (int m = 0; m < HP_NACC; ++m) v[m] = 0.f;
-    bool hit = false;
-    if (k < nc) {
-      const float a = p[0] * r1.x + p[2] * r1.y;
-      const float b = p[0] * r1.z + p[1] * r1.w + p[2] * r2.x;
-      const float qt = a * (r2.y * a + 2.f * r2.z * b) + r2.w * b * b;
-      if (qt <= A.q_cut) {
-        const float c = p[0] * r0.x + p[1] * r0.y + p[2] * r0.z;
-        const float s2 = a * a + b * b;
-        float dk2_ds2, dk2_dc;
-        const float k2 = hp_k2_grad(s2, c, &dk2_ds2, &dk2_dc);
-        const float q = qt * k2;
-        if (q <= A.q_cut) {
-          hit = true;
-          const float G = __expf(-0.5f * q);
-          const float oG = r0.w * G;
-          const float alpha = fminf(A.alpha_max, oG);
-          const float om = 1.f - alpha;
-          const float iom = __builtin_amdgcn_rcpf(om);
-          const float Tb = Tcur * iom;  // transmittance before this entry
-          const float wgt = alpha * Tb;
-          v[0] = g0 * wgt;
-          v[1] = g1 * wgt;
-          v[2] = g2 * wgt;
-          const float dLda = g0 * (r3.x * Tb - S0 * iom) + g1 * (r3.y * Tb - S1 * iom) + g2 * (r3.z * Tb - S2 * iom) -
-                             gTT * iom;
-          S0 += wgt * r3.x;
-          S1 += wgt * r3.y;
-          S2 += wgt * r3.z;
-          Tcur = Tb;
-          if (oG < A.alpha_max) {
-            v[3] = dLda * G;
-            const float dLdq = -0.5f * alpha * dLda;
-            v[4] = dLdq * k2 * a * a;
-            v[5] = dLdq * k2 * 2.f * a * b;
-            v[6] = dLdq * k2 * b * b;
-            // dq/d(a, b, c) with k2 = k2(s2, c)
-            const float dqa = k2 * 2.f * (r2.y * a + r2.z * b) + qt * dk2_ds2 * 2.f * a;
-            const float dqb = k2 * 2.f * (r2.z * a + r2.w * b) + qt * dk2_ds2 * 2.f * b;
-            const float dqc = qt * dk2_dc;
-            // motion of (a, b, c) with the Gaussian's longitude / latitude:
-            // da/dw = -cos(phi) c + sin(phi) b, db/dw = -sin(phi) a, dc/dw = cos(phi) a
-            // da/dp = 0, db/dp = -c, dc/dp = b
-            const float cph = r1.w, sph = r0.y;
-            v[7] = dLdq * (dqa * (sph * b - cph * c) - dqb * sph * a + dqc * cph * a);
-            v[8] = dLdq * (-dqb * c + dqc * b);
+      for (int m = 0; m < HP_NACC; ++m) v[m] = 0.f;
+      bool hit = false;
+      if (k < nc) {
+        const float a = p[0] * r1.x + p[2] * r1.y;
+        const float b = p[0] * r1.z + p[1] * r1.w + p[2] * r2.x;
+        const float qt = a * (r2.y * a + 2.f * r2.z * b) + r2.w * b * b;
+        if (qt <= A.q_cut) {
+          const float c = p[0] * r0.x + p[1] * r0.y + p[2] * r0.z;
+          const float s2 = a * a + b * b;
+          float dk2_ds2, dk2_dc;
+          const float k2 = hp_k2_grad(s2, c, &dk2_ds2, &dk2_dc);
+          const float q = qt * k2;
+          if (q <= A.q_cut) {
+            hit = true;
+            const float G = __expf(-0.5f * q);
+            const float oG = r0.w * G;
+            const float alpha = fminf(A.alpha_max, oG);
+            const float om = 1.f - alpha;
+            const float iom = __builtin_amdgcn_rcpf(om);
+            const float Tb = Tcur * iom;  // transmittance before this entry
+            const float wgt = alpha * Tb;
+            v[0] = g0 * wgt;
+            v[1] = g1 * wgt;
+            v[2] = g2 * wgt;
+            const float dLda = g0 * (r3.x * Tb - S0 * iom) + g1 * (r3.y * Tb - S1 * iom) +
+                               g2 * (r3.z * Tb - S2 * iom) - gTT * iom;
+            S0 += wgt * r3.x;
+            S1 += wgt * r3.y;
+            S2 += wgt * r3.z;
+            Tcur = Tb;
+            if (oG < A.alpha_max) {
+              v[3] = dLda * G;
+              const float dLdq = -0.5f * alpha * dLda;
+              v[4] = dLdq * k2 * a * a;
+              v[5] = dLdq * k2 * 2.f * a * b;
+              v[6] = dLdq * k2 * b * b;
+              // dq/d(a, b, c) with k2 = k2(s2, c)
+              const float dqa = k2 * 2.f * (r2.y * a + r2.z * b) + qt * dk2_ds2 * 2.f * a;
+              const float dqb = k2 * 2.f * (r2.z * a + r2.w * b) + qt * dk2_ds2 * 2.f * b;
+              const float dqc = qt * dk2_dc;
+              // motion of (a, b, c) with the Gaussian's longitude / latitude:
+              // da/dw = -cos(phi) c + sin(phi) b, db/dw = -sin(phi) a, dc/dw = cos(phi) a
+              // da/dp = 0, db/dp = -c, dc/dp = b
+              const float cph = r1.w, sph = r0.y;
+              v[7] = dLdq * (dqa * (sph * b - cph * c) - dqb * sph * a + dqc * cph * a);
+              v[8] = dLdq * (-dqb * c + dqc * b);
+            }
           }
         }
       }
+      if (__ballot(hit) == 0) continue;
+      // values 0..7: lane 8m holds the wave's total of value m; value 8: lane 63
+      const float t8 = hp_wave_totals8_spread(v);
+      hp_wave_totals_lane63<1>(&v[8]);
+      if ((lane & 7) == 0) atomicAdd(&s_acc[i * HP_NACC + (lane >> 3)], t8);
+      if (lane == 63) atomicAdd(&s_acc[i * HP_NACC + 8], v[8]);
     }
-    if (__ballot(hit) == 0) continue;
-    hp_wave_totals<HP_NACC>(v);
-    if (hp_lane() == 0) {
-#pragma unroll
-      for (int m = 0; m < HP_NACC; ++m) unsafeAtomicAdd(&acc[(int64_t)m * P + g], v[m]);
+    stage_store(&s_rec[((ctop - ch + 1) & 1) * HP_STAGE + tid], stage, gstage, qs);
+    __syncthreads();  // the chunk's totals are complete and the next chunk is staged
+    for (int t = tid; t < HP_CHUNK * HP_NACC; t += 256) {
+      const float x = s_acc[t];
+      if (x != 0.f) {
+        const int i = t / HP_NACC, m = t - i * HP_NACC;
+        const uint32_t g = __float_as_uint(cur[4 * i + 3].w);
+        unsafeAtomicAdd(&acc[(int64_t)m * P + g], x);
+        s_acc[t] = 0.f;
+      }
     }
+    __syncthreads();  // totals sent and cleared before the next chunk adds to them
   }
 }
 
 extern "C" hp_status hp_render_fwd(const void* projected, int64_t P, const uint32_t* vals, const uint32_t* tile_ranges,
                                    int32_t n_tiles, const hp_view* view, const hp_params* prm, const void* mask,
-                                   int64_t n_active, float* rgb, float* T, int32_t* n_contrib, void* stream) {
+                                   int64_t n_active, float* rgb, float* T, int32_t* n_contrib, int32_t* n_used,
+                                   void* stream) {
   HP_TRY(hp_check_view(view, prm));
   if (P < 0 || n_tiles < 0 || n_active < 0) return HP_ERR_INVALID_ARG;
   if (!projected || !mask || (n_tiles > 0 && !tile_ranges)) return HP_ERR_INVALID_ARG;
@@ -233,7 +335,7 @@ extern "C" hp_status hp_render_fwd(const void* projected, int64_t P, const uint3
   if (n_tiles > g.ntile || n_active > g.npix) return HP_ERR_INVALID_ARG;
   RenderArgs A = make_args(g, hp_mask_view((const char*)mask, g), hp_proj_view((const char*)projected, P), vals,
                            tile_ranges, prm, n_active);
-  RenderOut O{rgb, T, n_contrib};
+  RenderOut O{rgb, T, n_contrib, n_used};
   hipLaunchKernelGGL(k_render_fwd, dim3((unsigned)n_tiles), dim3(256), 0, (hipStream_t)stream, A, O);
   HP_CHECK_LAUNCH();
   return HP_OK;
@@ -257,7 +359,7 @@ extern "C" hp_status hp_render_fwd_batch(int32_t n_req, const hp_render_req* req
     B.first[r] = (int)total;
     B.A[r] = make_args(g, hp_mask_view((const char*)q.mask, g), hp_proj_view((const char*)q.projected, q.P), q.vals,
                        q.tile_ranges, prm, q.n_active);
-    B.O[r] = RenderOut{q.rgb, q.T, q.n_contrib};
+    B.O[r] = RenderOut{q.rgb, q.T, q.n_contrib, nullptr};
     total += q.n_tiles;
   }
   B.first[n_req] = (int)total;

@@ -8,10 +8,12 @@ __global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
   if (i < n) p[i] = v;
 }
 
-__global__ void k_tile_ranges(const uint32_t* __restrict__ keys, int64_t n, uint32_t* __restrict__ ranges) {
+__global__ void k_tile_ranges(const uint32_t* __restrict__ keys, int64_t n, uint32_t n_tiles,
+                              uint32_t* __restrict__ ranges) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const uint32_t k = keys[i];
+  if (k >= n_tiles) return;  // a key past the caller's tile count has no range slot
   if (i == 0 || keys[i - 1] != k) ranges[2 * (int64_t)k] = (uint32_t)i;
   if (i == n - 1 || keys[i + 1] != k) ranges[2 * (int64_t)k + 1] = (uint32_t)(i + 1);
 }
@@ -42,7 +44,8 @@ extern "C" hp_status hp_sort(uint32_t* keys, uint32_t* vals, int64_t n_pairs, in
   }
   if (n_pairs == 0) return HP_OK;
   HP_TRY(hpsort::radix_sort(keys, vals, n_pairs, bits_for(n_tiles), ws, s));
-  hipLaunchKernelGGL(k_tile_ranges, dim3(hp_blocks(n_pairs, 256)), dim3(256), 0, s, keys, n_pairs, tile_ranges);
+  hipLaunchKernelGGL(k_tile_ranges, dim3(hp_blocks(n_pairs, 256)), dim3(256), 0, s, keys, n_pairs, (uint32_t)n_tiles,
+                     tile_ranges);
   HP_CHECK_LAUNCH();
   return HP_OK;
 }

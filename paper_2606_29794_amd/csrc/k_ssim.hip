@@ -55,10 +55,13 @@ __device__ __forceinline__ void ss_tile_origin(const SsimArgs& A, int ct, int* f
 __global__ __launch_bounds__(256) void k_ssim_fwd(SsimArgs A, const float* __restrict__ img,
                                                   const float* __restrict__ ref, float* __restrict__ smap,
                                                   float* __restrict__ G, float2* __restrict__ part) {
-  __shared__ float s_in[7][SS_MAXH * SS_MAXH];
-  __shared__ float s_h[16][SS_MAXB * SS_MAXH];
+  // one LDS buffer serves first as the gathered patch [7][H*H] and then, once
+  // every thread holds its horizontal-pass sums in registers, as the pass
+  // output [16][B*H]: 26.6 KB instead of 45.5 KB, so twice the workgroups fit
+  constexpr int kIn = SS_MAXH * SS_MAXH, kH = SS_MAXB * SS_MAXH;
+  __shared__ float s_buf[16 * kH];
   __shared__ float s_red[2][4];
-  const int ct = blockIdx.x, tid = threadIdx.x;
+  const int ct = hp_xcd_tile(blockIdx.x, gridDim.x), tid = threadIdx.x;
   const int B = 1 << A.b, H = B + 2 * SS_R;
   int f, x0, y0;
   ss_tile_origin(A, ct, &f, &x0, &y0);
@@ -74,47 +77,70 @@ __global__ __launch_bounds__(256) void k_ssim_fwd(SsimArgs A, const float* __res
         v[3 + ch] = ref[ch * A.n_active + slot];
       }
     }
-    s_in[0][cell] = m;
+    s_buf[cell] = m;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) s_in[1 + k][cell] = v[k];
+    for (int k = 0; k < 6; ++k) s_buf[(1 + k) * kIn + cell] = v[k];
   }
   __syncthreads();
-  // pass 1 along x: rows 0..H-1 of the patch, output columns 0..B-1
-  for (int pos = tid; pos < B * H; pos += 256) {
-    const int ox = pos % B, row = pos / B;
-    float acc[16];
+  // the centre values of this thread's pixel, for the L1 term
+  float xc[3] = {0.f, 0.f, 0.f}, yc[3] = {0.f, 0.f, 0.f};
+  const int px = tid % B, py = tid / B;
+  if (tid < B * B) {
+    const int cc = (py + SS_R) * H + px + SS_R;
 #pragma unroll
-    for (int k = 0; k < 16; ++k) acc[k] = 0.f;
+    for (int ch = 0; ch < 3; ++ch) {
+      xc[ch] = s_buf[(1 + ch) * kIn + cc];
+      yc[ch] = s_buf[(4 + ch) * kIn + cc];
+    }
+  }
+  // pass 1 along x: rows 0..H-1 of the patch, output columns 0..B-1; at most
+  // two outputs per thread (B * H <= 416)
+  float acc[2][16];
 #pragma unroll
-    for (int a = 0; a < SS_W; ++a) {
-      const int cell = row * H + ox + a;
-      const float w = A.g[a] * s_in[0][cell];
-      acc[0] += w;
+  for (int j = 0; j < 2; ++j) {
 #pragma unroll
-      for (int ch = 0; ch < 3; ++ch) {
-        const float x = s_in[1 + ch][cell], y = s_in[4 + ch][cell];
-        acc[1 + ch] += w * x;
-        acc[4 + ch] += w * y;
-        acc[7 + ch] += w * x * x;
-        acc[10 + ch] += w * y * y;
-        acc[13 + ch] += w * x * y;
+    for (int k = 0; k < 16; ++k) acc[j][k] = 0.f;
+    const int pos = tid + 256 * j;
+    if (pos < B * H) {
+      const int ox = pos % B, row = pos / B;
+      // partial unroll: a full one keeps every tap's loads live at once
+#pragma unroll 3
+      for (int a = 0; a < SS_W; ++a) {
+        const int cell = row * H + ox + a;
+        const float w = A.g[a] * s_buf[cell];
+        acc[j][0] += w;
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+          const float x = s_buf[(1 + ch) * kIn + cell], y = s_buf[(4 + ch) * kIn + cell];
+          acc[j][1 + ch] += w * x;
+          acc[j][4 + ch] += w * y;
+          acc[j][7 + ch] += w * x * x;
+          acc[j][10 + ch] += w * y * y;
+          acc[j][13 + ch] += w * x * y;
+        }
       }
     }
+  }
+  __syncthreads();
 #pragma unroll
-    for (int k = 0; k < 16; ++k) s_h[k][row * B + ox] = acc[k];
+  for (int j = 0; j < 2; ++j) {
+    const int pos = tid + 256 * j;
+    if (pos < B * H) {
+#pragma unroll
+      for (int k = 0; k < 16; ++k) s_buf[k * kH + pos] = acc[j][k];  // pos = row * B + ox
+    }
   }
   __syncthreads();
   float ssum = 0.f, lsum = 0.f;
   if (tid < B * B) {
-    const int px = tid % B, py = tid / B;
     float S[16];
 #pragma unroll
     for (int k = 0; k < 16; ++k) S[k] = 0.f;
-#pragma unroll
+#pragma unroll 3
     for (int bb = 0; bb < SS_W; ++bb) {
       const int idx = (py + bb) * B + px;
 #pragma unroll
-      for (int k = 0; k < 16; ++k) S[k] += A.g[bb] * s_h[k][idx];
+      for (int k = 0; k < 16; ++k) S[k] += A.g[bb] * s_buf[k * kH + idx];
     }
     const int64_t slot = ss_slot(A, hp_xyf_nest(A.order, x0 + px, y0 + py, f));
     if (slot >= 0) {
@@ -129,8 +155,7 @@ __global__ __launch_bounds__(256) void k_ssim_fwd(SsimArgs A, const float* __res
         const float iden = 1.f / (Ad * Bd);
         const float s = An * Bn * iden;
         ssum += s;
-        const float xc = s_in[1 + ch][(py + SS_R) * H + px + SS_R], yc = s_in[4 + ch][(py + SS_R) * H + px + SS_R];
-        lsum += fabsf(xc - yc);
+        lsum += fabsf(xc[ch] - yc[ch]);
         if (smap) smap[ch * A.n_active + slot] = s;
         if (G) {
           // s(sx, sxx, sxy) with the y sums fixed; sx = mx etc. (normalised)
@@ -186,9 +211,11 @@ __global__ __launch_bounds__(1024) void k_ssim_reduce(const float2* __restrict__
 __global__ __launch_bounds__(256) void k_ssim_bwd(SsimArgs A, const float* __restrict__ img,
                                                   const float* __restrict__ ref, const float* __restrict__ G,
                                                   const float* __restrict__ dL_dloss, float* __restrict__ dimg) {
-  __shared__ float s_in[9][SS_MAXH * SS_MAXH];
-  __shared__ float s_h[9][SS_MAXB * SS_MAXH];
-  const int ct = blockIdx.x, tid = threadIdx.x;
+  // the gathered patch [9][H*H] and the horizontal-pass output [9][B*H]
+  // share one buffer (pass-1 sums wait in registers across a barrier)
+  constexpr int kIn = SS_MAXH * SS_MAXH, kH = SS_MAXB * SS_MAXH;
+  __shared__ float s_buf[9 * kIn];
+  const int ct = hp_xcd_tile(blockIdx.x, gridDim.x), tid = threadIdx.x;
   const int B = 1 << A.b, H = B + 2 * SS_R;
   int f, x0, y0;
   ss_tile_origin(A, ct, &f, &x0, &y0);
@@ -196,22 +223,33 @@ __global__ __launch_bounds__(256) void k_ssim_bwd(SsimArgs A, const float* __res
     const int cx = cell % H, cy = cell / H;
     const int64_t slot = ss_slot(A, hp_chart_pixel(A.order, f, x0 + cx - SS_R, y0 + cy - SS_R));
 #pragma unroll
-    for (int k = 0; k < 9; ++k) s_in[k][cell] = slot >= 0 ? G[k * A.n_active + slot] : 0.f;
+    for (int k = 0; k < 9; ++k) s_buf[k * kIn + cell] = slot >= 0 ? G[k * A.n_active + slot] : 0.f;
   }
   __syncthreads();
-  for (int pos = tid; pos < B * H; pos += 256) {
-    const int ox = pos % B, row = pos / B;
-    float acc[9];
+  float acc[2][9];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) acc[k] = 0.f;
+  for (int j = 0; j < 2; ++j) {
 #pragma unroll
-    for (int a = 0; a < SS_W; ++a) {
-      const int cell = row * H + ox + a;
+    for (int k = 0; k < 9; ++k) acc[j][k] = 0.f;
+    const int pos = tid + 256 * j;
+    if (pos < B * H) {
+      const int ox = pos % B, row = pos / B;
 #pragma unroll
-      for (int k = 0; k < 9; ++k) acc[k] += A.g[a] * s_in[k][cell];
+      for (int a = 0; a < SS_W; ++a) {
+        const int cell = row * H + ox + a;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) acc[j][k] += A.g[a] * s_buf[k * kIn + cell];
+      }
     }
+  }
+  __syncthreads();
 #pragma unroll
-    for (int k = 0; k < 9; ++k) s_h[k][row * B + ox] = acc[k];
+  for (int j = 0; j < 2; ++j) {
+    const int pos = tid + 256 * j;
+    if (pos < B * H) {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) s_buf[k * kH + pos] = acc[j][k];
+    }
   }
   __syncthreads();
   if (tid >= B * B) return;
@@ -225,7 +263,7 @@ __global__ __launch_bounds__(256) void k_ssim_bwd(SsimArgs A, const float* __res
   for (int bb = 0; bb < SS_W; ++bb) {
     const int idx = (py + bb) * B + px;
 #pragma unroll
-    for (int k = 0; k < 9; ++k) S[k] += A.g[bb] * s_h[k][idx];
+    for (int k = 0; k < 9; ++k) S[k] += A.g[bb] * s_buf[k * kH + idx];
   }
   const float up = *dL_dloss;
   const float inv3n = 1.f / (3.f * (float)A.n_active);
@@ -247,43 +285,84 @@ extern "C" size_t hp_ssim_workspace_bytes(int32_t order, int32_t tile_log2, int6
   return ssim_ws_size(n_active, hp_geom(order, tile_log2).ntile);
 }
 
-extern "C" hp_status hp_ssim(const float* img, const float* ref, int64_t n_active, int32_t n_tiles, int32_t order,
-                             const hp_params* prm, const hp_ssim_params* sp, const void* mask, float* out,
-                             float* ssim_map, const float* dL_dloss, float* dL_dimg, void* ws, size_t ws_bytes,
-                             void* stream) {
+// shared argument checks and set-up of the three entry points
+static hp_status ssim_setup(const float* img, const float* ref, int64_t n_active, int32_t n_tiles, int32_t order,
+                            const hp_params* prm, const hp_ssim_params* sp, const void* mask, const void* ws,
+                            size_t ws_bytes, SsimArgs* A, float** Gm, float2** part) {
   HP_TRY(hp_check_params(prm));
-  if (!sp || !mask || !out || !ws) return HP_ERR_INVALID_ARG;
+  if (!sp || !mask || !ws) return HP_ERR_INVALID_ARG;
   if (order < 3 || order > HP_MAX_ORDER) return order < 0 || order > HP_MAX_ORDER ? HP_ERR_INVALID_ARG : HP_ERR_UNSUPPORTED;
   if (n_active <= 0 || n_tiles <= 0 || !img || !ref) return HP_ERR_INVALID_ARG;
-  if (dL_dloss && !dL_dimg) return HP_ERR_INVALID_ARG;
   if (!(sp->sigma > 0) || !(sp->C1 > 0) || !(sp->C2 > 0) || !(sp->lambda >= 0 && sp->lambda <= 1))
     return HP_ERR_INVALID_ARG;
   const HpGeom g = hp_geom(order, prm->tile_log2);
   if (n_tiles > g.ntile || n_active > g.npix) return HP_ERR_INVALID_ARG;
   if (ws_bytes < ssim_ws_size(n_active, g.ntile)) return HP_ERR_CAPACITY;
   const HpMaskView mv = hp_mask_view((const char*)mask, g);
-  SsimArgs A;
-  A.order = order; A.b = g.b; A.kt = g.kt;
-  A.active_tiles = mv.active_tiles; A.tile_start = mv.tile_start; A.tile_count = mv.tile_count;
-  A.tile_bits = mv.tile_bits; A.n_active = n_active;
-  A.C1 = sp->C1; A.C2 = sp->C2; A.lam = sp->lambda;
+  A->order = order; A->b = g.b; A->kt = g.kt;
+  A->active_tiles = mv.active_tiles; A->tile_start = mv.tile_start; A->tile_count = mv.tile_count;
+  A->tile_bits = mv.tile_bits; A->n_active = n_active;
+  A->C1 = sp->C1; A->C2 = sp->C2; A->lam = sp->lambda;
   for (int a = 0; a < SS_W; ++a) {
     const double d = a - SS_R;
-    A.g[a] = (float)exp(-d * d / (2.0 * (double)sp->sigma * (double)sp->sigma));
+    A->g[a] = (float)exp(-d * d / (2.0 * (double)sp->sigma * (double)sp->sigma));
   }
-  float* Gm = (float*)ws;
-  float2* part = (float2*)((char*)ws + hp_align256((size_t)9 * n_active * 4));
+  *Gm = (float*)ws;
+  *part = (float2*)((char*)ws + hp_align256((size_t)9 * n_active * 4));
+  return HP_OK;
+}
+
+static hp_status ssim_fwd_launch(const SsimArgs& A, const float* img, const float* ref, int32_t n_tiles, float lam,
+                                 float* out, float* ssim_map, float* Gm, float2* part, hipStream_t s) {
+  hipLaunchKernelGGL(k_ssim_fwd, dim3((unsigned)n_tiles), dim3(256), 0, s, A, img, ref, ssim_map, Gm, part);
+  HP_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_ssim_reduce, dim3(1), dim3(1024), 0, s, (const float2*)part, (int)n_tiles, A.n_active, lam, out);
+  HP_CHECK_LAUNCH();
+  return HP_OK;
+}
+
+extern "C" hp_status hp_ssim(const float* img, const float* ref, int64_t n_active, int32_t n_tiles, int32_t order,
+                             const hp_params* prm, const hp_ssim_params* sp, const void* mask, float* out,
+                             float* ssim_map, const float* dL_dloss, float* dL_dimg, void* ws, size_t ws_bytes,
+                             void* stream) {
+  SsimArgs A;
+  float* Gm;
+  float2* part;
+  HP_TRY(ssim_setup(img, ref, n_active, n_tiles, order, prm, sp, mask, ws, ws_bytes, &A, &Gm, &part));
+  if (!out || (dL_dloss && !dL_dimg)) return HP_ERR_INVALID_ARG;
   hipStream_t s = (hipStream_t)stream;
-  hipLaunchKernelGGL(k_ssim_fwd, dim3((unsigned)n_tiles), dim3(256), 0, s, A, img, ref, ssim_map,
-                     dL_dloss ? Gm : (float*)nullptr, part);
-  HP_CHECK_LAUNCH();
-  hipLaunchKernelGGL(k_ssim_reduce, dim3(1), dim3(1024), 0, s, (const float2*)part, (int)n_tiles, n_active, sp->lambda,
-                     out);
-  HP_CHECK_LAUNCH();
+  HP_TRY(ssim_fwd_launch(A, img, ref, n_tiles, sp->lambda, out, ssim_map, dL_dloss ? Gm : nullptr, part, s));
   if (dL_dloss) {
     hipLaunchKernelGGL(k_ssim_bwd, dim3((unsigned)n_tiles), dim3(256), 0, s, A, img, ref, (const float*)Gm, dL_dloss,
                        dL_dimg);
     HP_CHECK_LAUNCH();
   }
+  return HP_OK;
+}
+
+extern "C" hp_status hp_ssim_forward_saved(const float* img, const float* ref, int64_t n_active, int32_t n_tiles,
+                                           int32_t order, const hp_params* prm, const hp_ssim_params* sp,
+                                           const void* mask, float* out, float* ssim_map, void* ws, size_t ws_bytes,
+                                           void* stream) {
+  SsimArgs A;
+  float* Gm;
+  float2* part;
+  HP_TRY(ssim_setup(img, ref, n_active, n_tiles, order, prm, sp, mask, ws, ws_bytes, &A, &Gm, &part));
+  if (!out) return HP_ERR_INVALID_ARG;
+  return ssim_fwd_launch(A, img, ref, n_tiles, sp->lambda, out, ssim_map, Gm, part, (hipStream_t)stream);
+}
+
+extern "C" hp_status hp_ssim_backward_saved(const float* img, const float* ref, int64_t n_active, int32_t n_tiles,
+                                            int32_t order, const hp_params* prm, const hp_ssim_params* sp,
+                                            const void* mask, const void* ws, size_t ws_bytes,
+                                            const float* dL_dloss, float* dL_dimg, void* stream) {
+  SsimArgs A;
+  float* Gm;
+  float2* part;
+  HP_TRY(ssim_setup(img, ref, n_active, n_tiles, order, prm, sp, mask, ws, ws_bytes, &A, &Gm, &part));
+  if (!dL_dloss || !dL_dimg) return HP_ERR_INVALID_ARG;
+  hipLaunchKernelGGL(k_ssim_bwd, dim3((unsigned)n_tiles), dim3(256), 0, (hipStream_t)stream, A, img, ref,
+                     (const float*)Gm, dL_dloss, dL_dimg);
+  HP_CHECK_LAUNCH();
   return HP_OK;
 }

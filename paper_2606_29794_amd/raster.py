@@ -116,6 +116,20 @@ class Rasterizer:
         self.prm = A.default_params(**params)
         self._grids = {}
         self._masks = {}
+        # cached tables are written on the stream current at creation; a
+        # later user on another stream waits for this event first
+        self._ready = {}
+
+    def _created(self, key):
+        ev = torch.cuda.Event()
+        ev.record(torch.cuda.current_stream(self.device))
+        self._ready[key] = (ev, torch.cuda.current_stream(self.device).cuda_stream)
+
+    def _await(self, key):
+        ev, sid = self._ready[key]
+        cur = torch.cuda.current_stream(self.device)
+        if cur.cuda_stream != sid:
+            cur.wait_event(ev)
 
     # ---- camera-independent tables ------------------------------------
     def grid(self, order: int) -> torch.Tensor:
@@ -128,6 +142,9 @@ class Rasterizer:
             g = _bytes(n, self.device)
             A.call("hp_grid_init", order, C.byref(self.prm), _p(g), n, _stream())
             self._grids[key] = g
+            self._created(("grid",) + key)
+        else:
+            self._await(("grid",) + key)
         return g
 
     def mask(self, cam: Camera) -> MaskInfo:
@@ -145,6 +162,9 @@ class Rasterizer:
             ap = buf[off: off + 4 * na.value].view(torch.int32)
             m = MaskInfo(buf, int(na.value), int(nt.value), ap)
             self._masks[key] = m
+            self._created(("mask",) + key)
+        else:
+            self._await(("mask",) + key)
         return m
 
     # ---- stage 1 ---------------------------------------------------------
@@ -183,6 +203,25 @@ class Rasterizer:
                _p(m.buf), _p(keys), _p(vals), n, _p(npairs), _p(ws), ws_n, _stream())
         return keys, vals, n
 
+    def bin_sorted(self, proj: torch.Tensor, P: int, cam: Camera):
+        """Pairs emitted directly in per-tile depth order: (vals, ranges, n)."""
+        m = self.mask(cam)
+        v = cam.view()
+        ws_n = A.lib().hp_bin_sorted_workspace_bytes(P, cam.order, self.prm.tile_log2)
+        ws = _bytes(ws_n, self.device)
+        npairs = torch.zeros(1, dtype=torch.int64, device=self.device)
+        grid = self.grid(cam.order)
+        A.call("hp_bin_sorted", A.HP_BIN_COUNT, _p(proj), P, C.byref(v), C.byref(self.prm), _p(grid), _p(m.buf), None,
+               None, m.n_tiles, 0, _p(npairs), _p(ws), ws_n, _stream())
+        total = C.c_int64(0)
+        A.call("hp_read_total", _p(npairs), C.byref(total), _stream())
+        n = int(total.value)
+        vals = torch.empty(max(n, 1), dtype=torch.int32, device=self.device)
+        ranges = torch.empty((max(m.n_tiles, 1), 2), dtype=torch.int32, device=self.device)
+        A.call("hp_bin_sorted", A.HP_BIN_EMIT, _p(proj), P, C.byref(v), C.byref(self.prm), _p(grid), _p(m.buf),
+               _p(vals), _p(ranges), m.n_tiles, n, _p(npairs), _p(ws), ws_n, _stream())
+        return vals, ranges, n
+
     def sort(self, keys, vals, n: int, n_tiles: int):
         ranges = torch.zeros((max(n_tiles, 1), 2), dtype=torch.int32, device=self.device)
         ws_n = A.lib().hp_sort_workspace_bytes(n, n_tiles)
@@ -191,21 +230,24 @@ class Rasterizer:
         return ranges
 
     # ---- stage 3 ---------------------------------------------------------
-    def render_fwd(self, proj, P, vals, ranges, cam: Camera):
+    def render_fwd(self, proj, P, vals, ranges, cam: Camera, want_used: bool = False):
+        """rgb [3, n], T [n], n_contrib [n] (and n_used [n] if want_used)."""
         m = self.mask(cam)
         v = cam.view()
         rgb = torch.empty((3, max(m.n_active, 1)), dtype=torch.float32, device=self.device)
         T = torch.empty(max(m.n_active, 1), dtype=torch.float32, device=self.device)
         nc = torch.empty(max(m.n_active, 1), dtype=torch.int32, device=self.device)
+        nu = torch.empty(max(m.n_active, 1), dtype=torch.int32, device=self.device) if want_used else None
         A.call("hp_render_fwd", _p(proj), P, _p(vals), _p(ranges), m.n_tiles, C.byref(v), C.byref(self.prm),
-               _p(m.buf), m.n_active, _p(rgb), _p(T), _p(nc), _stream())
+               _p(m.buf), m.n_active, _p(rgb), _p(T), _p(nc), _p(nu), _stream())
+        if want_used:
+            return rgb, T, nc, nu
         return rgb, T, nc
 
     def forward(self, g: Gaussians, cam: Camera) -> FwdState:
         m = self.mask(cam)
         proj = self.preprocess(g, cam)
-        keys, vals, n = self.bin(proj, g.P, cam)
-        ranges = self.sort(keys, vals, n, m.n_tiles)
+        vals, ranges, n = self.bin_sorted(proj, g.P, cam)
         rgb, T, nc = self.render_fwd(proj, g.P, vals, ranges, cam)
         return FwdState(cam, m, proj, vals, ranges, n, rgb, T, nc, g.P)
 
@@ -236,3 +278,24 @@ class Rasterizer:
                C.byref(self.prm), C.byref(sp), _p(m.buf), _p(out), _p(smap), _p(dL_dloss), _p(dimg), _p(ws), ws_n,
                _stream())
         return out, smap, dimg
+
+    def ssim_forward_saved(self, img, ref, cam: Camera, sp: A.hp_ssim_params | None = None, want_map=False):
+        """Loss forward that keeps the backward's per-pixel partials: returns
+        (out[3], ssim_map or None, saved workspace for ssim_backward_saved)."""
+        m = self.mask(cam)
+        sp = sp or A.default_ssim_params()
+        out = torch.zeros(3, dtype=torch.float32, device=self.device)
+        smap = torch.empty_like(img) if want_map else None
+        ws_n = A.lib().hp_ssim_workspace_bytes(cam.order, self.prm.tile_log2, m.n_active)
+        ws = _bytes(ws_n, self.device)
+        A.call("hp_ssim_forward_saved", _p(img), _p(ref), m.n_active, m.n_tiles, cam.order, C.byref(self.prm),
+               C.byref(sp), _p(m.buf), _p(out), _p(smap), _p(ws), ws_n, _stream())
+        return out, smap, ws
+
+    def ssim_backward_saved(self, img, ref, cam: Camera, sp: A.hp_ssim_params, ws, dL_dloss):
+        """dL/dimg from the partials a previous ssim_forward_saved left in ws."""
+        m = self.mask(cam)
+        dimg = torch.empty_like(img)
+        A.call("hp_ssim_backward_saved", _p(img), _p(ref), m.n_active, m.n_tiles, cam.order, C.byref(self.prm),
+               C.byref(sp), _p(m.buf), _p(ws), ws.numel(), _p(dL_dloss), _p(dimg), _stream())
+        return dimg

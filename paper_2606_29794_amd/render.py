@@ -61,8 +61,15 @@ class _HSSIMLoss(torch.autograd.Function):
     @staticmethod
     def forward(ctx, img, ref, rasterizer, camera, lam):
         sp = A.default_ssim_params(lam=float(lam))
-        out, _, _ = rasterizer.ssim_loss(img.detach(), ref.detach(), camera, sp)
-        ctx.save_for_backward(img.detach(), ref.detach())
+        img_d, ref_d = img.detach().contiguous(), ref.detach().contiguous()
+        if ctx.needs_input_grad[0]:
+            # keep the backward's per-pixel partials: the backward is then one gather pass
+            out, _, ws = rasterizer.ssim_forward_saved(img_d, ref_d, camera, sp)
+            ctx.ws = ws
+        else:
+            out, _, _ = rasterizer.ssim_loss(img_d, ref_d, camera, sp)
+            ctx.ws = None
+        ctx.save_for_backward(img_d, ref_d)
         ctx.R, ctx.cam, ctx.sp = rasterizer, camera, sp
         ctx.mark_non_differentiable(out)
         return out[2], out
@@ -71,7 +78,11 @@ class _HSSIMLoss(torch.autograd.Function):
     def backward(ctx, grad_loss, grad_out):
         img, ref = ctx.saved_tensors
         up = grad_loss.reshape(1).to(torch.float32).contiguous()
-        _, _, dimg = ctx.R.ssim_loss(img, ref, ctx.cam, ctx.sp, dL_dloss=up)
+        if ctx.ws is not None:
+            dimg = ctx.R.ssim_backward_saved(img, ref, ctx.cam, ctx.sp, ctx.ws, up)
+            ctx.ws = None
+        else:
+            _, _, dimg = ctx.R.ssim_loss(img, ref, ctx.cam, ctx.sp, dL_dloss=up)
         return dimg, None, None, None, None
 
 

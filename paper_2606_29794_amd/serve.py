@@ -6,8 +6,8 @@ stream slot is free and the HBM budget allows, and launches them as one
 batch on that slot's stream:
 
   masks of the batch's cameras -> one preprocessing launch that reads every
-  Gaussian once for all views -> per-request tile counts -> (one read-back of
-  all counts) -> pair emission and tile sorts -> ONE render launch whose
+  Gaussian once for all views -> per request: pair count, read-back of its
+  sizes, pairs emitted in per-tile depth order -> ONE render launch whose
   workgroups cover the active tiles of every request in the batch.
 
 Batches on different streams overlap on the device, so requests that arrive
@@ -96,7 +96,7 @@ class Server:
         self.streams = [torch.cuda.Stream(device=self.g.mean.device) for _ in range(n_streams)]
         self.budget = hbm_budget_bytes
         self._pairs_per_order = {}
-        self._mask_cache = {}
+        self._mask_cache = collections.OrderedDict()
 
     # ---- memory accounting ---------------------------------------------------
     def _estimate(self, cam: Camera) -> int:
@@ -110,16 +110,27 @@ class Server:
         """Mask buffer for the camera model (cached; computed on the current
         stream, counts read back later together with the pair counts)."""
         key = cam.mask_key(self.R.prm.tile_log2)
-        buf = self._mask_cache.get(key)
-        if buf is None:
+        cur = torch.cuda.current_stream()
+        ent = self._mask_cache.get(key)
+        if ent is None:
             n = A.lib().hp_mask_bytes(cam.order, self.R.prm.tile_log2)
             buf = _bytes(n, self.g.mean.device)
             v = cam.view()
             A.call("hp_mask", C.byref(v), C.byref(self.R.prm), _p(self.R.grid(cam.order)), _p(buf), n,
-                   C.c_void_p(torch.cuda.current_stream().cuda_stream))
+                   C.c_void_p(cur.cuda_stream))
+            ev = torch.cuda.Event()
+            ev.record(cur)
             if len(self._mask_cache) > 64:
-                self._mask_cache.pop(next(iter(self._mask_cache)))
-            self._mask_cache[key] = buf
+                # in-flight batches keep their own references to the masks they
+                # read (released only after their completion event), so the
+                # cache can drop the oldest entry at once
+                self._mask_cache.popitem(last=False)
+            self._mask_cache[key] = (buf, ev, cur.cuda_stream)
+            return buf
+        buf, ev, sid = ent
+        if sid != cur.cuda_stream:
+            # written on another stream: order this stream after it
+            cur.wait_event(ev)
         return buf
 
     def _launch(self, reqs: list, stream: torch.cuda.Stream, keep: bool) -> _Batch:
@@ -140,45 +151,41 @@ class Server:
                 views = (A.hp_view * len(chunk))(*[r.camera.view() for r in chunk])
                 ptrs = (C.c_void_p * len(chunk))(*[projs[s0 + k].data_ptr() for k in range(len(chunk))])
                 A.call("hp_preprocess_batch", C.byref(gs), len(chunk), views, C.byref(prm), ptrs, nproj, sptr)
-            ws_n = A.lib().hp_bin_workspace_bytes(P)
-            wss = [_bytes(ws_n, dev) for _ in reqs]
+            # one binning workspace for the batch: each request counts, reads
+            # its sizes back and emits before the next one reuses it (stream order)
+            ws_n = max(A.lib().hp_bin_sorted_workspace_bytes(P, r.camera.order, prm.tile_log2) for r in reqs)
+            ws = _bytes(ws_n, dev)
             npairs = torch.zeros(len(reqs), dtype=torch.int64, device=dev)
-            for k, r in enumerate(reqs):
-                v = r.camera.view()
-                A.call("hp_bin", A.HP_BIN_COUNT, _p(projs[k]), P, C.byref(v), C.byref(prm),
-                       _p(R.grid(r.camera.order)), _p(masks[k]), None, None, 0,
-                       C.c_void_p(npairs.data_ptr() + 8 * k), _p(wss[k]), ws_n, sptr)
-            # one read-back for the whole batch: pair counts and mask sizes
-            heads = torch.stack([m[:16] for m in masks]).view(torch.int64)
-            counts = torch.cat([npairs, heads.reshape(-1)]).cpu()
-            n_pairs = counts[: len(reqs)].tolist()
-            heads = counts[len(reqs):].view(len(reqs), 2).numpy()
             reqd = []
             outs = []
-            nbytes = 0
+            keep = []
+            nbytes = ws_n
             for k, r in enumerate(reqs):
-                n_active = int(heads[k, 0])
-                n_tiles = int(heads[k, 1] & 0xFFFFFFFF)   # int32 count in the low half (little-endian)
-                n = int(n_pairs[k])
-                self._pairs_per_order[r.camera.order] = max(n, self._pairs_per_order.get(r.camera.order, 0) // 2)
-                keys = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
-                vals = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
                 v = r.camera.view()
-                A.call("hp_bin", A.HP_BIN_EMIT, _p(projs[k]), P, C.byref(v), C.byref(prm), _p(R.grid(r.camera.order)),
-                       _p(masks[k]), _p(keys), _p(vals), n, C.c_void_p(npairs.data_ptr() + 8 * k), _p(wss[k]), ws_n,
-                       sptr)
+                grid = R.grid(r.camera.order)
+                A.call("hp_bin_sorted", A.HP_BIN_COUNT, _p(projs[k]), P, C.byref(v), C.byref(prm), _p(grid),
+                       _p(masks[k]), None, None, 0, 0, C.c_void_p(npairs.data_ptr() + 8 * k), _p(ws), ws_n, sptr)
+                # pair count and mask sizes (n_active int64, n_tiles int32) in one read-back
+                head = torch.cat([npairs[k:k + 1], masks[k][:16].view(torch.int64)]).cpu().numpy()
+                n, n_active, n_tiles = int(head[0]), int(head[1]), int(head[2] & 0xFFFFFFFF)
+                npix = 12 << (2 * r.camera.order)
+                if not (0 <= n_active <= npix and 0 <= n_tiles <= npix and n >= 0):
+                    raise RuntimeError(f"request {r.rid}: inconsistent mask header ({n_active}, {n_tiles}) or pair count {n}")
+                self._pairs_per_order[r.camera.order] = max(n, self._pairs_per_order.get(r.camera.order, 0) // 2)
+                vals = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
                 ranges = torch.zeros((max(n_tiles, 1), 2), dtype=torch.int32, device=dev)
-                sws_n = A.lib().hp_sort_workspace_bytes(n, n_tiles)
-                sws = _bytes(sws_n, dev)
-                A.call("hp_sort", _p(keys), _p(vals), n, n_tiles, _p(ranges), _p(sws), sws_n, sptr)
+                A.call("hp_bin_sorted", A.HP_BIN_EMIT, _p(projs[k]), P, C.byref(v), C.byref(prm), _p(grid),
+                       _p(masks[k]), _p(vals), _p(ranges), n_tiles, n, C.c_void_p(npairs.data_ptr() + 8 * k), _p(ws),
+                       ws_n, sptr)
                 rgb = torch.empty((3, max(n_active, 1)), dtype=torch.float32, device=dev)
                 T = torch.empty(max(n_active, 1), dtype=torch.float32, device=dev)
                 nc = torch.empty(max(n_active, 1), dtype=torch.int32, device=dev)
                 reqd.append(A.hp_render_req(projs[k].data_ptr(), P, vals.data_ptr(), ranges.data_ptr(), n_tiles,
                                             r.camera.order, masks[k].data_ptr(), n_active, rgb.data_ptr(),
                                             T.data_ptr(), nc.data_ptr()))
-                outs.append((rgb[:, :n_active], T[:n_active], keys, vals, ranges, sws))
-                nbytes += nproj + 8 * n + sws_n + 24 * n_active
+                outs.append((rgb[:, :n_active], T[:n_active]))
+                keep.append((vals, ranges, nc))
+                nbytes += nproj + 4 * n + 8 * n_tiles + 24 * n_active
             for s0 in range(0, len(reqd), MAX_REQ_PER_RENDER):
                 chunk = reqd[s0:s0 + MAX_REQ_PER_RENDER]
                 arr = (A.hp_render_req * len(chunk))(*chunk)
@@ -186,7 +193,7 @@ class Server:
             ev = torch.cuda.Event()
             ev.record(stream)
         b = _Batch(reqs, stream, ev, nbytes, outs=outs)
-        b.keep = [projs, wss, masks]   # keep buffers alive until the batch completes
+        b.keep = [projs, ws, masks, npairs, keep]   # alive until the batch completes
         return b
 
     # ---- the request loop -----------------------------------------------------
@@ -238,7 +245,7 @@ class Server:
 
     def serve_sequential(self, requests: list, realtime: bool = True, keep_outputs: bool = False):
         """Baseline: one request at a time, FIFO, the plain per-request
-        pipeline (hp_preprocess, hp_bin, hp_sort, hp_render_fwd)."""
+        pipeline (hp_preprocess, hp_bin_sorted, hp_render_fwd)."""
         reqs = sorted(requests, key=lambda r: r.arrival)
         results = []
         torch.cuda.synchronize()

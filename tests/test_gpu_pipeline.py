@@ -42,6 +42,33 @@ def test_tile_lists_and_order(R, case):
     assert stats["pairs"] > 0
 
 
+@pytest.mark.parametrize("case", list(CASES) + ["cfg1_fisheye", "cfg3_small"])
+def test_sorted_bin_equals_bin_then_sort(R, case):
+    """hp_bin_sorted emits exactly what hp_bin followed by the stable tile
+    sort hp_sort gives: the same ids in the same order, the same ranges."""
+    import torch
+    from paper_2606_29794_amd.raster import Camera, Gaussians
+    if case == "cfg1_fisheye":
+        wl = SC.config1(P=20000, order=8)
+        sc, camd = wl.scene, wl.cameras[0]
+    elif case == "cfg3_small":
+        wl = SC.config3(P=50000, order=9)
+        sc, camd = wl.scene, wl.cameras[0]
+    else:
+        sc, camd = CASES[case]()
+    g = Gaussians.from_scene(sc)
+    cam = Camera.from_dict(camd)
+    proj = R.preprocess(g, cam)
+    m = R.mask(cam)
+    keys, vals, n = R.bin(proj, g.P, cam)
+    ranges = R.sort(keys, vals, n, m.n_tiles)
+    vals2, ranges2, n2 = R.bin_sorted(proj, g.P, cam)
+    torch.cuda.synchronize()
+    assert n2 == n
+    assert torch.equal(vals[:n], vals2[:n])
+    assert torch.equal(ranges, ranges2)
+
+
 @pytest.mark.parametrize("case", list(CASES))
 def test_render_forward_full_image(R, case):
     sc, cam = CASES[case]()
@@ -64,6 +91,10 @@ def test_render_forward_full_image(R, case):
     ok = (frag == 0) & np.array([t not in fr_tiles for t in ptile])
     nc_g = st.n_contrib.cpu().numpy()
     assert np.array_equal(nc_g[ok], nc_o[ok]), np.count_nonzero(nc_g[ok] != nc_o[ok])
+    # Gaussians composited per pixel: exact on pixels without fragile decisions
+    _, _, _, nu_g = R.render_fwd(st.projected, g.P, st.vals, st.ranges, c, want_used=True)
+    nu_g = nu_g.cpu().numpy()
+    assert np.array_equal(nu_g[frag == 0], nu[frag == 0])
 
 
 def test_render_forward_sampled_config1(R):
@@ -140,3 +171,15 @@ def test_hssim_and_loss(R, order, masked):
     assert abs(out[1] - np.mean(np.abs(img.astype(np.float64) - ref))) < 1e-6
     assert np.abs(smap.cpu().numpy() - map_o).max() < 2e-5
     PT.grad_compare("hssim-loss grad", dimg.cpu().numpy(), 1.7 * gL_o)
+    # the split entry points (partials kept between forward and backward)
+    # run the same kernels: identical results
+    out2, smap2, ws = R.ssim_forward_saved(ti, tr_, Camera.from_dict(cam), want_map=True)
+    dimg2 = R.ssim_backward_saved(ti, tr_, Camera.from_dict(cam), A_default_ssim(), ws, up)
+    torch.cuda.synchronize()
+    assert np.array_equal(out2.cpu().numpy(), out)
+    assert torch.equal(smap2, smap) and torch.equal(dimg2, dimg)
+
+
+def A_default_ssim():
+    from paper_2606_29794_amd import _abi as A
+    return A.default_ssim_params()

@@ -50,7 +50,9 @@ def test_batched_preprocess_equals_single():
            C.c_void_p(torch.cuda.current_stream().cuda_stream))
     torch.cuda.synchronize()
     for a, b in zip(singles, outs):
-        assert torch.equal(a, b)
+        # compare the records, depths and radii (not the alignment padding)
+        for x, y in zip(R.projected_arrays(a, g.P), R.projected_arrays(b, g.P)):
+            assert torch.equal(x, y)
 
 
 def test_served_results_equal_solo_renders():
