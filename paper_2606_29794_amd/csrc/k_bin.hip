@@ -147,16 +147,31 @@ __device__ __forceinline__ void gauss_dir(const float4* rec, const float* radius
   *cg = sqrtf(fmaxf(0.f, 1.f - *sg * *sg));
 }
 
-// coarse walk: tasks of Gaussian order[k]
+// coarse walk: tasks of Gaussian order[k].  With `slots` (slot-major
+// [kSlots][P]) the count walk also keeps the first kSlots task nodes, and the
+// emit pass copies them instead of walking again when they are all there.
+constexpr int kSlots = 16;
+
 template <bool EMIT>
 __global__ __launch_bounds__(256) void k_bin_coarse(int64_t P, const uint32_t* __restrict__ order,
                                                     const float4* __restrict__ rec, const float* __restrict__ radius,
                                                     BinTables T, float guard, uint32_t* __restrict__ tcount,
                                                     const uint32_t* __restrict__ toff, uint32_t* __restrict__ task_g,
-                                                    uint32_t* __restrict__ task_n) {
+                                                    uint32_t* __restrict__ task_n, uint32_t* __restrict__ slots) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= P) return;
   const uint32_t gid = order[k];
+  if (EMIT && slots) {
+    const uint32_t cnt = tcount[k];
+    if (cnt <= (uint32_t)kSlots) {
+      const uint32_t base = toff[k];
+      for (uint32_t j = 0; j < cnt; ++j) {
+        task_g[base + j] = gid;
+        task_n[base + j] = slots[(int64_t)j * P + k];
+      }
+      return;
+    }
+  }
   float u[3], sg, cg;
   bool ok;
   gauss_dir(rec, radius, gid, guard, u, &sg, &cg, &ok);
@@ -173,6 +188,7 @@ __global__ __launch_bounds__(256) void k_bin_coarse(int64_t P, const uint32_t* _
       task_g[base + cnt] = gid;
       task_n[base + cnt] = (uint32_t)i;
     }
+    if (!EMIT && slots && cnt < (uint32_t)kSlots) slots[(int64_t)cnt * P + k] = (uint32_t)i;
     ++cnt;
   });
   if (!EMIT) tcount[k] = cnt;
@@ -418,7 +434,10 @@ __global__ __launch_bounds__(256) void k_bin_cols(const uint32_t* __restrict__ c
   }
 }
 
-// per chunk: every hit of leaf b's column goes to its slot in tile (node, b)
+// per chunk: every hit of leaf b's column goes to its slot in tile (node, b).
+// Lane b holds column W_b and its first slot; the wave walks the leaves, and
+// for leaf b the lanes j of the tasks with bit j set write consecutive slots,
+// so each store instruction covers one contiguous run.
 __global__ __launch_bounds__(256) void k_bin_emit_sorted(const uint32_t* __restrict__ choff, uint32_t nn,
                                                          const uint32_t* __restrict__ seg,
                                                          const uint32_t* __restrict__ tgid, int depth,
@@ -431,16 +450,18 @@ __global__ __launch_bounds__(256) void k_bin_emit_sorted(const uint32_t* __restr
   const int lane = hp_lane();
   const int nleaf = 1 << (2 * depth);
   const bool leaf_lane = lane < nleaf;
+  const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   const uint32_t waves = gridDim.x * (blockDim.x >> 6);
   for (uint32_t c = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); c < nchunks; c += waves) {
     const ChunkInfo ci = chunk_info(choff, nn, seg, c);
     const uint64_t W = leaf_lane ? wcol[(int64_t)c * 64 + lane] : 0ull;
     const uint64_t base =
         leaf_lane ? start[(int64_t)(c - ci.local) * nleaf + (int64_t)lane * ci.nchn + ci.local] : 0ull;
-    const uint32_t tg = (uint32_t)lane < ci.ntask ? tgid[ci.t0 + lane] : 0u;
-    for (uint32_t j = 0; j < ci.ntask; ++j) {
-      const uint32_t g = (uint32_t)__builtin_amdgcn_readlane((int)tg, (int)j);
-      if ((W >> j) & 1ull) vals[base + (uint64_t)__popcll(W & ((1ull << j) - 1ull))] = g;
+    const uint32_t g = (uint32_t)lane < ci.ntask ? tgid[ci.t0 + lane] : 0u;
+    for (int b = 0; b < nleaf; ++b) {
+      const uint64_t Wb = hp_readlane64(W, b);
+      if (Wb == 0) continue;
+      if ((Wb >> lane) & 1ull) vals[hp_readlane64(base, b) + (uint64_t)__popcll(Wb & below)] = g;
     }
   }
 }
@@ -498,7 +519,8 @@ extern "C" hp_status hp_bin(int32_t phase, const void* projected, int64_t P, con
     HP_CHECK_LAUNCH();
     HP_TRY(hpsort::radix_sort(w.dkey, w.order, P, 32, w.sort_ws, s));
     hipLaunchKernelGGL((k_bin_coarse<false>), dim3(hp_blocks(P, 256)), dim3(256), 0, s, P, w.order, pv.rec, pv.radius,
-                       T, prm->bin_guard, w.tcount, (const uint32_t*)nullptr, (uint32_t*)nullptr, (uint32_t*)nullptr);
+                       T, prm->bin_guard, w.tcount, (const uint32_t*)nullptr, (uint32_t*)nullptr, (uint32_t*)nullptr,
+                       (uint32_t*)nullptr);
     HP_CHECK_LAUNCH();
     HP_TRY((hpsort::scan_exclusive<uint32_t, uint32_t>(w.tcount, w.toff, P, w.t_total, w.scan_ws, s)));
     // the number of tasks must fit the workspace: read it back once
@@ -507,7 +529,7 @@ extern "C" hp_status hp_bin(int32_t phase, const void* projected, int64_t P, con
     if (hipStreamSynchronize(s) != hipSuccess) return HP_ERR_DEVICE;
     if ((int64_t)nt > w.cap_t) return HP_ERR_CAPACITY;
     hipLaunchKernelGGL((k_bin_coarse<true>), dim3(hp_blocks(P, 256)), dim3(256), 0, s, P, w.order, pv.rec, pv.radius,
-                       T, prm->bin_guard, w.tcount, w.toff, w.task_g, w.task_n);
+                       T, prm->bin_guard, w.tcount, w.toff, w.task_g, w.task_n, (uint32_t*)nullptr);
     HP_CHECK_LAUNCH();
     if (nt > 0) {
       hipLaunchKernelGGL(k_bin_fine_count, dim3(fine_grid(nt)), dim3(256), 0, s, (const uint32_t*)w.t_total, w.cap_t,
@@ -545,6 +567,7 @@ struct SortedWs {
   uint32_t* cnt;     // [L] hits per (chunk, leaf), tile-major, zero tail
   uint64_t* start;   // [L] exclusive scan of cnt: first output slot
   uint64_t* wcol;    // [nchunk_max][64] hit columns
+  uint32_t* slots;   // [kSlots][P] first task nodes of every Gaussian (coarse walk)
   void* scan_ws;
   int64_t nn, nchunk_max, L;
 };
@@ -562,7 +585,7 @@ static size_t sorted_ws_size(int64_t P, const HpGeom& g) {
   sorted_dims(P, g, &nn, &ncm, &L);
   return hpsort::radix_ws_bytes(task_capacity(P)) + hp_align256(nn * 8) + hp_align256(nn * 4) +
          hp_align256((nn + 1) * 4) + hp_align256(L * 4) + hp_align256(L * 8) + hp_align256(ncm * 64 * 8) +
-         hpsort::scan_ws_bytes<uint64_t>(L > nn ? L : nn);
+         hp_align256((size_t)kSlots * P * 4) + hpsort::scan_ws_bytes<uint64_t>(L > nn ? L : nn);
 }
 
 static SortedWs sorted_ws(void* base, int64_t P, const HpGeom& g) {
@@ -576,6 +599,7 @@ static SortedWs sorted_ws(void* base, int64_t P, const HpGeom& g) {
   w.cnt = (uint32_t*)p; p += hp_align256(w.L * 4);
   w.start = (uint64_t*)p; p += hp_align256(w.L * 8);
   w.wcol = (uint64_t*)p; p += hp_align256(w.nchunk_max * 64 * 8);
+  w.slots = (uint32_t*)p; p += hp_align256((size_t)kSlots * P * 4);
   w.scan_ws = p;
   return w;
 }
@@ -627,7 +651,8 @@ extern "C" hp_status hp_bin_sorted(int32_t phase, const void* projected, int64_t
     HP_CHECK_LAUNCH();
     HP_TRY(hpsort::radix_sort(w.dkey, w.order, P, 32, w.sort_ws, s));
     hipLaunchKernelGGL((k_bin_coarse<false>), dim3(hp_blocks(P, 256)), dim3(256), 0, s, P, w.order, pv.rec, pv.radius,
-                       T, prm->bin_guard, w.tcount, (const uint32_t*)nullptr, (uint32_t*)nullptr, (uint32_t*)nullptr);
+                       T, prm->bin_guard, w.tcount, (const uint32_t*)nullptr, (uint32_t*)nullptr, (uint32_t*)nullptr,
+                       sw.slots);
     HP_CHECK_LAUNCH();
     HP_TRY((hpsort::scan_exclusive<uint32_t, uint32_t>(w.tcount, w.toff, P, w.t_total, w.scan_ws, s)));
     uint32_t nt = 0;
@@ -635,7 +660,7 @@ extern "C" hp_status hp_bin_sorted(int32_t phase, const void* projected, int64_t
     if (hipStreamSynchronize(s) != hipSuccess) return HP_ERR_DEVICE;
     if ((int64_t)nt > w.cap_t) return HP_ERR_CAPACITY;
     hipLaunchKernelGGL((k_bin_coarse<true>), dim3(hp_blocks(P, 256)), dim3(256), 0, s, P, w.order, pv.rec, pv.radius,
-                       T, prm->bin_guard, w.tcount, w.toff, w.task_g, w.task_n);
+                       T, prm->bin_guard, w.tcount, w.toff, w.task_g, w.task_n, sw.slots);
     HP_CHECK_LAUNCH();
     // stable sort of the tasks by node; segments and chunk offsets per node
     int nbits = 0;

@@ -315,21 +315,28 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(int64_t P, int deg, cons
   const float ivn = rsqrtf(vx * vx + vy * vy + vz * vz);
   const float dx = vx * ivn, dy = vy * ivn, dz = vz * ivn;
   float Y[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) Y[k] = 0.f;  // basis functions above the degree stay 0
   hp_sh_eval(deg, dx, dy, dz, Y);
   const int K = (deg + 1) * (deg + 1);
-  float wk[16];
+  // all coefficients first (independent loads, all in flight at once)
+  float shc[48];
 #pragma unroll
-  for (int k = 0; k < 16; ++k) wk[k] = 0.f;
+  for (int k = 0; k < 48; ++k) shc[k] = k < 3 * K ? sh[(int64_t)k * P + i] : 0.f;
+  float gcol[3];
+#pragma unroll
   for (int ch = 0; ch < 3; ++ch) {
     float colour = sh_off;
-    for (int k = 0; k < K; ++k) colour += sh[(int64_t)(k * 3 + ch) * P + i] * Y[k];
-    if (colour < 0.f) continue;  // clamped channel
-    const float gcol = gy[ch];
-    for (int k = 0; k < K; ++k) {
-      gsh[(int64_t)(k * 3 + ch) * P + i] += gcol * Y[k];
-      wk[k] += gcol * sh[(int64_t)(k * 3 + ch) * P + i];
-    }
+#pragma unroll
+    for (int k = 0; k < 16; ++k) colour += shc[k * 3 + ch] * Y[k];
+    gcol[ch] = colour < 0.f ? 0.f : gy[ch];  // a clamped channel passes no gradient
   }
+  float wk[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) wk[k] = gcol[0] * shc[3 * k] + gcol[1] * shc[3 * k + 1] + gcol[2] * shc[3 * k + 2];
+#pragma unroll
+  for (int k = 0; k < 48; ++k)
+    if (k < 3 * K) gsh[(int64_t)k * P + i] += gcol[k % 3] * Y[k / 3];
   if (deg > 0) {
     float ddx, ddy, ddz;
     hp_sh_grad(deg, dx, dy, dz, wk, &ddx, &ddy, &ddz);

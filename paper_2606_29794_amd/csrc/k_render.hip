@@ -145,7 +145,8 @@ __device__ __forceinline__ void render_fwd_tile(const RenderArgs& A, const Rende
     // of the block still composites
     stage_store(&s_rec[((c + 1) & 1) * HP_STAGE + tid], stage, gstage, q);
     const int par = c & 1;
-    if (hp_lane() == 0) s_live[par][tid >> 6] = __ballot(!done) != 0;
+    const uint64_t live = __ballot(!done);  // all lanes vote, before one lane writes
+    if (hp_lane() == 0) s_live[par][tid >> 6] = live != 0;
     __syncthreads();
     if (!(s_live[par][0] | s_live[par][1] | s_live[par][2] | s_live[par][3])) break;
   }
