@@ -116,6 +116,8 @@ def main():
     }
     if not args.profile_only:
         out.update(kernel_breakdown(R, params, cams, targets, torch, A))
+        # Gaussian-pixel evaluations per second over the whole fwd+bwd step (view 0's counts)
+        out["gaussian_pixel_evaluations_per_s"] = out["evaluated_pixel_pairs"] * renders_per_s
         if not args.no_cpu_baseline:
             out["cpu_baseline"] = cpu_baseline(wl, args.cpu_pixels)
         if not args.no_serve:

@@ -97,16 +97,15 @@ __device__ __forceinline__ bool node_pass(const BinTables& T, int64_t node, floa
 // children 4i..4i+3 at level l+1; level 0 holds the 12 faces) from root
 // (l0, i0) -- or from all 12 faces when l0 < 0 -- down to level `stop`; calls
 // f(i) for every passing node at `stop`.
-template <class F>
-__device__ __forceinline__ void quad_walk(const BinTables& T, int l0, int64_t i0, int stop, float ux, float uy, float uz,
-                                          float sg, float cg, F&& f) {
+template <class Pass, class F>
+__device__ __forceinline__ void quad_walk(int l0, int64_t i0, int stop, Pass&& pass, F&& f) {
   const bool forest = l0 < 0;
   const int lroot = forest ? 0 : l0;
   int l = lroot;
   int64_t i = forest ? 0 : i0;
   int64_t loff = hp_level_offset(l);
   while (true) {
-    if (node_pass(T, loff + i, ux, uy, uz, sg, cg)) {
+    if (pass(loff + i)) {
       if (l == stop) {
         f(i);
       } else {
@@ -151,6 +150,7 @@ __device__ __forceinline__ void gauss_dir(const float4* rec, const float* radius
 // [kSlots][P]) the count walk also keeps the first kSlots task nodes, and the
 // emit pass copies them instead of walking again when they are all there.
 constexpr int kSlots = 16;
+constexpr int kTopNodes = 252;  // quadtree levels 0..2
 
 template <bool EMIT>
 __global__ __launch_bounds__(256) void k_bin_coarse(int64_t P, const uint32_t* __restrict__ order,
@@ -158,6 +158,19 @@ __global__ __launch_bounds__(256) void k_bin_coarse(int64_t P, const uint32_t* _
                                                     BinTables T, float guard, uint32_t* __restrict__ tcount,
                                                     const uint32_t* __restrict__ toff, uint32_t* __restrict__ task_g,
                                                     uint32_t* __restrict__ task_n, uint32_t* __restrict__ slots) {
+  // the quadtree's top levels (faces and two more: 252 nodes) in LDS; every
+  // walk starts there
+  __shared__ float4 s_cap[kTopNodes];
+  __shared__ float2 s_sc[kTopNodes];
+  __shared__ uint8_t s_act[kTopNodes];
+  const int64_t nlev = hp_level_offset(T.ls + 1);  // nodes of levels 0..ls
+  const int ntop = (int)(nlev < kTopNodes ? nlev : kTopNodes);
+  for (int t = threadIdx.x; t < ntop; t += blockDim.x) {
+    s_cap[t] = T.cap[t];
+    s_sc[t] = T.sc[t];
+    s_act[t] = T.node_active ? T.node_active[t] : (uint8_t)1;
+  }
+  __syncthreads();
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= P) return;
   const uint32_t gid = order[k];
@@ -183,7 +196,19 @@ __global__ __launch_bounds__(256) void k_bin_coarse(int64_t P, const uint32_t* _
   const uint32_t base = EMIT ? toff[k] : 0;
   // the emit walk writes no more tasks than the count walk reserved
   const uint32_t room = EMIT ? tcount[k] : 0;
-  quad_walk(T, -1, 0, T.ls, u[0], u[1], u[2], sg, cg, [&](int64_t i) {
+  // node test: the top levels from the LDS copy, deeper ones from memory
+  auto pass = [&](int64_t node) -> bool {
+    if (node < ntop) {
+      if (!s_act[node]) return false;
+      const float4 c = s_cap[node];
+      const float2 h = s_sc[node];
+      const float dx = c.x - u[0], dy = c.y - u[1], dz = c.z - u[2];
+      const float sh = h.x * cg + h.y * sg, ch = h.y * cg - h.x * sg;
+      return (ch <= 0.f) || (dx * dx + dy * dy + dz * dz <= 4.f * sh * sh);
+    }
+    return node_pass(T, node, u[0], u[1], u[2], sg, cg);
+  };
+  quad_walk(-1, 0, T.ls, pass, [&](int64_t i) {
     if (EMIT && cnt < room) {
       task_g[base + cnt] = gid;
       task_n[base + cnt] = (uint32_t)i;

@@ -99,7 +99,10 @@ struct PreBatch {
 // Gaussians are contiguous in memory: they go through LDS so that every
 // store instruction writes 4 KB of whole lines (a thread storing its own
 // record would leave every store a quarter-line write).
-__global__ __launch_bounds__(256) void k_preprocess(int64_t P, int deg, const float* __restrict__ mean,
+// DEG: SH degree as a compile-time constant, so that the coefficient loads
+// are unconditional and all in flight together
+template <int DEG>
+__global__ __launch_bounds__(256) void k_preprocess(int64_t P, const float* __restrict__ mean,
                                                     const float* __restrict__ scale, const float* __restrict__ rot,
                                                     const float* __restrict__ opac, const float* __restrict__ sh,
                                                     PreBatch B, float r_min, float rs_sigma, float sh_off,
@@ -114,7 +117,7 @@ __global__ __launch_bounds__(256) void k_preprocess(int64_t P, int deg, const fl
   const float s[3] = {scale[ii], scale[P + ii], scale[2 * P + ii]};
   const float q[4] = {rot[ii], rot[P + ii], rot[2 * P + ii], rot[3 * P + ii]};
   const float op = opac[ii];
-  const int K = (deg + 1) * (deg + 1);
+  constexpr int K = (DEG + 1) * (DEG + 1);
   float shc[48];
 #pragma unroll
   for (int k = 0; k < 48; ++k) shc[k] = k < 3 * K ? sh[(int64_t)k * P + ii] : 0.f;
@@ -122,7 +125,7 @@ __global__ __launch_bounds__(256) void k_preprocess(int64_t P, int deg, const fl
   for (int v = 0; v < B.n; ++v) {
     float4 r[4];
     float dep, rad;
-    project_one(deg, mx, my, mz, s, q, op, shc, B.V[v], r_min, rs_sigma, sh_off, guard, r, &dep, &rad);
+    project_one(DEG, mx, my, mz, s, q, op, shc, B.V[v], r_min, rs_sigma, sh_off, guard, r, &dep, &rad);
     if (ok) {
       B.depth[v][i] = dep;
       B.radius[v][i] = rad;
@@ -175,9 +178,18 @@ extern "C" hp_status hp_preprocess_batch(const hp_gaussians* g, int32_t n_views,
   }
   if (projected_bytes < hp_proj_size(g->P)) return HP_ERR_CAPACITY;
   if (g->P == 0) return HP_OK;
-  hipLaunchKernelGGL(k_preprocess, dim3(hp_blocks(g->P, 256)), dim3(256), 0, (hipStream_t)stream, g->P, g->sh_degree,
-                     g->mean, g->scale, g->rot, g->opacity, g->sh, B, prm->r_min, prm->rs_sigma, prm->sh_offset,
-                     prm->bin_guard);
+  const dim3 grid(hp_blocks(g->P, 256)), block(256);
+  hipStream_t st = (hipStream_t)stream;
+  switch (g->sh_degree) {
+    case 0: hipLaunchKernelGGL(k_preprocess<0>, grid, block, 0, st, g->P, g->mean, g->scale, g->rot, g->opacity, g->sh, B,
+                               prm->r_min, prm->rs_sigma, prm->sh_offset, prm->bin_guard); break;
+    case 1: hipLaunchKernelGGL(k_preprocess<1>, grid, block, 0, st, g->P, g->mean, g->scale, g->rot, g->opacity, g->sh, B,
+                               prm->r_min, prm->rs_sigma, prm->sh_offset, prm->bin_guard); break;
+    case 2: hipLaunchKernelGGL(k_preprocess<2>, grid, block, 0, st, g->P, g->mean, g->scale, g->rot, g->opacity, g->sh, B,
+                               prm->r_min, prm->rs_sigma, prm->sh_offset, prm->bin_guard); break;
+    default: hipLaunchKernelGGL(k_preprocess<3>, grid, block, 0, st, g->P, g->mean, g->scale, g->rot, g->opacity, g->sh, B,
+                                prm->r_min, prm->rs_sigma, prm->sh_offset, prm->bin_guard); break;
+  }
   HP_CHECK_LAUNCH();
   return HP_OK;
 }
@@ -190,7 +202,8 @@ extern "C" hp_status hp_preprocess_batch(const hp_gaussians* g, int32_t n_views,
 // backward_lat_scale and the J term of Eq. grad_via_J_S both arrive through
 // the dependence of E and r on the camera-space centre t.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_preprocess_bwd(int64_t P, int deg, const float* __restrict__ mean,
+template <int DEG>
+__global__ __launch_bounds__(256) void k_preprocess_bwd(int64_t P, const float* __restrict__ mean,
                                                         const float* __restrict__ scale, const float* __restrict__ rot,
                                                         const float* __restrict__ sh, HpViewK V, float r_min,
                                                         float sh_off, const float* __restrict__ acc,
@@ -260,10 +273,10 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(int64_t P, int deg, cons
     gV[1][k] = 2.f * (G01 * Vm[0][k] + G11 * Vm[1][k]);
   }
   // V = M diag(s) / r
-  float gr = 0.f, gM[2][3];
+  float gr = 0.f, gM[2][3], dscale[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    gscale[k * P + i] += (gV[0][k] * M[0][k] + gV[1][k] * M[1][k]) * ir;
+    dscale[k] = (gV[0][k] * M[0][k] + gV[1][k] * M[1][k]) * ir;
     gM[0][k] = gV[0][k] * s[k] * ir;
     gM[1][k] = gV[1][k] * s[k] * ir;
     gr -= (gV[0][k] * Vm[0][k] + gV[1][k] * Vm[1][k]) * ir;
@@ -305,11 +318,8 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(int64_t P, int deg, cons
   const float gz_q = 2.f * (-2.f * z * gR[0][0] - w * gR[0][1] + x * gR[0][2] + w * gR[1][0] - 2.f * z * gR[1][1] +
                             y * gR[1][2] + x * gR[2][0] + y * gR[2][1]);
   const float dotq = w * gw_q + x * gx_q + y * gy_q + z * gz_q;
-  grot[i] += (gw_q - w * dotq) * qn;
-  grot[P + i] += (gx_q - x * dotq) * qn;
-  grot[2 * P + i] += (gy_q - y * dotq) * qn;
-  grot[3 * P + i] += (gz_q - z * dotq) * qn;
-  gopac[i] += gy[3];
+  const float drot[4] = {(gw_q - w * dotq) * qn, (gx_q - x * dotq) * qn, (gy_q - y * dotq) * qn,
+                         (gz_q - z * dotq) * qn};
   // colour: SH coefficients and the viewing direction
   const float vx = mx - V.c[0], vy = my - V.c[1], vz = mz - V.c[2];
   const float ivn = rsqrtf(vx * vx + vy * vy + vz * vz);
@@ -317,8 +327,8 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(int64_t P, int deg, cons
   float Y[16];
 #pragma unroll
   for (int k = 0; k < 16; ++k) Y[k] = 0.f;  // basis functions above the degree stay 0
-  hp_sh_eval(deg, dx, dy, dz, Y);
-  const int K = (deg + 1) * (deg + 1);
+  hp_sh_eval(DEG, dx, dy, dz, Y);
+  constexpr int K = (DEG + 1) * (DEG + 1);
   // all coefficients first (independent loads, all in flight at once)
   float shc[48];
 #pragma unroll
@@ -334,27 +344,51 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(int64_t P, int deg, cons
   float wk[16];
 #pragma unroll
   for (int k = 0; k < 16; ++k) wk[k] = gcol[0] * shc[3 * k] + gcol[1] * shc[3 * k + 1] + gcol[2] * shc[3 * k + 2];
-#pragma unroll
-  for (int k = 0; k < 48; ++k)
-    if (k < 3 * K) gsh[(int64_t)k * P + i] += gcol[k % 3] * Y[k / 3];
-  if (deg > 0) {
+
+  if (DEG > 0) {
     float ddx, ddy, ddz;
-    hp_sh_grad(deg, dx, dy, dz, wk, &ddx, &ddy, &ddz);
+    hp_sh_grad(DEG, dx, dy, dz, wk, &ddx, &ddy, &ddz);
     const float dd = ddx * dx + ddy * dy + ddz * dz;
     gmx += (ddx - dx * dd) * ivn;
     gmy += (ddy - dy * dd) * ivn;
     gmz += (ddz - dz * dd) * ivn;
   }
-  gmean[i] += gmx;
-  gmean[P + i] += gmy;
-  gmean[2 * P + i] += gmz;
+  // accumulate into the gradient buffers: every read first, then every write,
+  // so that the read-modify-writes of this Gaussian overlap
+  float om[3], osc[3], orot[4], oop, osh[3 * K];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) { om[k] = gmean[k * P + i]; osc[k] = gscale[k * P + i]; }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) orot[k] = grot[k * P + i];
+  oop = gopac[i];
+#pragma unroll
+  for (int k = 0; k < 3 * K; ++k) osh[k] = gsh[(int64_t)k * P + i];
+  gmean[i] = om[0] + gmx;
+  gmean[P + i] = om[1] + gmy;
+  gmean[2 * P + i] = om[2] + gmz;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) gscale[k * P + i] = osc[k] + dscale[k];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) grot[k * P + i] = orot[k] + drot[k];
+  gopac[i] = oop + gy[3];
+#pragma unroll
+  for (int k = 0; k < 3 * K; ++k) gsh[(int64_t)k * P + i] = osh[k] + gcol[k % 3] * Y[k / 3];
 }
 
 hp_status hp_preprocess_bwd_launch(const hp_gaussians* g, const hp_view* view, const hp_params* prm, const float* acc,
                                    hp_gaussians_grad* grad, hipStream_t s) {
-  hipLaunchKernelGGL(k_preprocess_bwd, dim3(hp_blocks(g->P, 256)), dim3(256), 0, s, g->P, g->sh_degree, g->mean,
-                     g->scale, g->rot, g->sh, hp_viewk(view), prm->r_min, prm->sh_offset, acc, grad->mean, grad->scale,
-                     grad->rot, grad->opacity, grad->sh);
+  const dim3 grid(hp_blocks(g->P, 256)), block(256);
+  const HpViewK vk = hp_viewk(view);
+#define HP_PRE_BWD(D)                                                                                                \
+  hipLaunchKernelGGL(k_preprocess_bwd<D>, grid, block, 0, s, g->P, g->mean, g->scale, g->rot, g->sh, vk, prm->r_min, \
+                     prm->sh_offset, acc, grad->mean, grad->scale, grad->rot, grad->opacity, grad->sh)
+  switch (g->sh_degree) {
+    case 0: HP_PRE_BWD(0); break;
+    case 1: HP_PRE_BWD(1); break;
+    case 2: HP_PRE_BWD(2); break;
+    default: HP_PRE_BWD(3); break;
+  }
+#undef HP_PRE_BWD
   HP_CHECK_LAUNCH();
   return HP_OK;
 }

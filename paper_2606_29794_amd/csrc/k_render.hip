@@ -71,16 +71,38 @@ struct RenderOut {
 #define HP_CHUNK 64
 #define HP_STAGE (4 * HP_CHUNK)  // float4 per chunk buffer = threads per block
 
-// quarter `q` of the record of Gaussian `g`, as written to LDS: quarter 3
-// carries the id in its last word (the render does not use that word).  The
-// id goes in only when the quarter is stored, so that a load still in flight
-// is never waited for early.
 __device__ __forceinline__ float4 stage_load(const float4* __restrict__ rec, uint32_t g, int q) {
   return rec[4 * (size_t)g + q];
 }
-__device__ __forceinline__ void stage_store(float4* dst, float4 v, uint32_t g, int q) {
-  if (q == 3) v.w = __uint_as_float(g);
-  *dst = v;
+
+// Bounding cap of the wave's pixels: centre = normalised sum of their
+// directions, (sin, cos) of half the largest angle to them, rounded up.  A
+// list entry whose r_s disc misses this cap has q > 9 at every pixel of the
+// wave (the 3-sigma ellipse lies inside the disc), so the wave skips it.
+struct WaveCap {
+  float cx, cy, cz, sr, cr;
+};
+__device__ __forceinline__ WaveCap wave_cap(bool valid, const float p[3]) {
+  WaveCap w;
+  const float sx = hp_wave_sum(valid ? p[0] : 0.f), sy = hp_wave_sum(valid ? p[1] : 0.f),
+              sz = hp_wave_sum(valid ? p[2] : 0.f);
+  const float inv = rsqrtf(sx * sx + sy * sy + sz * sz);  // no valid pixel: NaN centre, no entry passes
+  w.cx = sx * inv; w.cy = sy * inv; w.cz = sz * inv;
+  const float dx = p[0] - w.cx, dy = p[1] - w.cy, dz = p[2] - w.cz;
+  float c2 = valid ? dx * dx + dy * dy + dz * dz : 0.f;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) c2 = fmaxf(c2, __shfl_xor(c2, off, 64));
+  w.sr = fminf(1.f, 0.5f * sqrtf(c2) * 1.0001f + 1e-6f);  // sin(R/2) = chord / 2
+  w.cr = sqrtf(fmaxf(0.f, 1.f - w.sr * w.sr));
+  return w;
+}
+// entry with unit direction u and sg = sin((r_s + guard) / 2) (record word 15)
+__device__ __forceinline__ bool wave_cap_hit(const WaveCap& w, float4 r0, float sg) {
+  const float cg = sqrtf(fmaxf(0.f, 1.f - sg * sg));
+  const float dx = w.cx - r0.x, dy = w.cy - r0.y, dz = w.cz - r0.z;
+  const float sh = w.sr * cg + w.cr * sg;  // sin((R + theta) / 2)
+  const float ch = w.cr * cg - w.sr * sg;  // cos((R + theta) / 2)
+  return (ch <= 0.f) || (dx * dx + dy * dy + dz * dz <= 4.f * sh * sh);
 }
 
 __device__ __forceinline__ void render_fwd_tile(const RenderArgs& A, const RenderOut& O, int ct, float4* s_rec) {
@@ -102,10 +124,7 @@ __device__ __forceinline__ void render_fwd_tile(const RenderArgs& A, const Rende
   // that a wave already writing the next chunk's flag never overwrites one
   // that a slower wave has yet to read
   __shared__ int s_live[2][4];
-  {
-    const uint32_t g = e < n ? vals[e] : 0u;
-    stage_store(&s_rec[tid], e < n ? stage_load(A.rec, g, q) : make_float4(0.f, 0.f, 0.f, 0.f), g, q);
-  }
+  s_rec[tid] = e < n ? stage_load(A.rec, vals[e], q) : make_float4(0.f, 0.f, 0.f, 0.f);
   uint32_t gnext = HP_CHUNK + e < n ? vals[HP_CHUNK + e] : 0u;
   __syncthreads();
   const uint32_t nch = (n + HP_CHUNK - 1) / HP_CHUNK;
@@ -143,7 +162,7 @@ __device__ __forceinline__ void render_fwd_tile(const RenderArgs& A, const Rende
     }
     // one barrier both publishes the next chunk and tells whether any pixel
     // of the block still composites
-    stage_store(&s_rec[((c + 1) & 1) * HP_STAGE + tid], stage, gstage, q);
+    s_rec[((c + 1) & 1) * HP_STAGE + tid] = stage;
     const int par = c & 1;
     const uint64_t live = __ballot(!done);  // all lanes vote, before one lane writes
     if (hp_lane() == 0) s_live[par][tid >> 6] = live != 0;
@@ -195,6 +214,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(RenderArgs A, int64_t P, con
   // per chunk entry: the block's gradient totals (the 4 waves' sums), sent to
   // memory with one atomic per non-zero value once the chunk is done
   __shared__ float s_acc[HP_CHUNK * HP_NACC];
+  __shared__ uint32_t s_gid[2][HP_CHUNK];  // Gaussian id of every staged entry
   const int ct = hp_xcd_tile(blockIdx.x, gridDim.x);
   bool valid;
   int64_t slot;
@@ -217,6 +237,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(RenderArgs A, int64_t P, con
   for (int off = 32; off >= 1; off >>= 1) ncmax = max(ncmax, __shfl_xor(ncmax, off, 64));
   ncmax = (int)hp_uniform((uint32_t)ncmax);
   const int tid = threadIdx.x, lane = hp_lane();
+  const WaveCap wc = wave_cap(valid, p);
   if (lane == 0) s_nc[tid >> 6] = ncmax;
   for (int t = tid; t < HP_CHUNK * HP_NACC; t += 256) s_acc[t] = 0.f;
   __syncthreads();
@@ -234,7 +255,8 @@ __global__ __launch_bounds__(256) void k_render_bwd(RenderArgs A, int64_t P, con
   if (ctop >= 0) {
     const uint32_t k0 = (uint32_t)ctop * HP_CHUNK + e;
     const uint32_t g = k0 < (uint32_t)nb ? vals[k0] : 0u;
-    stage_store(&s_rec[tid], k0 < (uint32_t)nb ? stage_load(A.rec, g, qs) : make_float4(0.f, 0.f, 0.f, 0.f), g, qs);
+    s_rec[tid] = k0 < (uint32_t)nb ? stage_load(A.rec, g, qs) : make_float4(0.f, 0.f, 0.f, 0.f);
+    if (qs == 3) s_gid[0][e] = g;
     if (ctop >= 1) gnext = vals[(uint32_t)(ctop - 1) * HP_CHUNK + e];
   }
   __syncthreads();
@@ -246,75 +268,85 @@ __global__ __launch_bounds__(256) void k_render_bwd(RenderArgs A, int64_t P, con
     const float4* cur = s_rec + ((ctop - ch) & 1) * HP_STAGE;
     const int kbase = ch * HP_CHUNK;
     const int ktop = min(kbase + HP_CHUNK, ncmax) - 1;  // this wave's last entry in the chunk
-    for (int k = ktop; k >= kbase; --k) {
-      const int i = k - kbase;
+    // lane j tests entry kbase + j against the wave's cap; walk the hits from the back
+    uint64_t todo = 0;
+    if (ktop >= kbase)
+      todo = __ballot(lane <= ktop - kbase && wave_cap_hit(wc, cur[4 * lane], cur[4 * lane + 3].w));
+    while (todo != 0) {
+      const int i = 63 - __builtin_clzll(todo);
+      todo &= ~(1ull << i);
+      const int k = kbase + i;
       const float4 r0 = cur[4 * i], r1 = cur[4 * i + 1], r2 = cur[4 * i + 2], r3 = cur[4 * i + 3];
-      float v[HP_NACC];
-#pragma unroll
-      for (int m = 0; m < HP_NACC; ++m) v[m] = 0.f;
-      bool hit = false;
-      if (k < nc) {
-        const float a = p[0] * r1.x + p[2] * r1.y;
-        const float b = p[0] * r1.z + p[1] * r1.w + p[2] * r2.x;
-        const float qt = a * (r2.y * a + 2.f * r2.z * b) + r2.w * b * b;
-        if (qt <= A.q_cut) {
-          const float c = p[0] * r0.x + p[1] * r0.y + p[2] * r0.z;
-          const float s2 = a * a + b * b;
-          float dk2_ds2, dk2_dc;
-          const float k2 = hp_k2_grad(s2, c, &dk2_ds2, &dk2_dc);
-          const float q = qt * k2;
-          if (q <= A.q_cut) {
-            hit = true;
-            const float G = __expf(-0.5f * q);
-            const float oG = r0.w * G;
-            const float alpha = fminf(A.alpha_max, oG);
-            const float om = 1.f - alpha;
-            const float iom = __builtin_amdgcn_rcpf(om);
-            const float Tb = Tcur * iom;  // transmittance before this entry
-            const float wgt = alpha * Tb;
-            v[0] = g0 * wgt;
-            v[1] = g1 * wgt;
-            v[2] = g2 * wgt;
-            const float dLda = g0 * (r3.x * Tb - S0 * iom) + g1 * (r3.y * Tb - S1 * iom) +
-                               g2 * (r3.z * Tb - S2 * iom) - gTT * iom;
-            S0 += wgt * r3.x;
-            S1 += wgt * r3.y;
-            S2 += wgt * r3.z;
-            Tcur = Tb;
-            if (oG < A.alpha_max) {
-              v[3] = dLda * G;
-              const float dLdq = -0.5f * alpha * dLda;
-              v[4] = dLdq * k2 * a * a;
-              v[5] = dLdq * k2 * 2.f * a * b;
-              v[6] = dLdq * k2 * b * b;
-              // dq/d(a, b, c) with k2 = k2(s2, c)
-              const float dqa = k2 * 2.f * (r2.y * a + r2.z * b) + qt * dk2_ds2 * 2.f * a;
-              const float dqb = k2 * 2.f * (r2.z * a + r2.w * b) + qt * dk2_ds2 * 2.f * b;
-              const float dqc = qt * dk2_dc;
-              // motion of (a, b, c) with the Gaussian's longitude / latitude:
-              // da/dw = -cos(phi) c + sin(phi) b, db/dw = -sin(phi) a, dc/dw = cos(phi) a
-              // da/dp = 0, db/dp = -c, dc/dp = b
-              const float cph = r1.w, sph = r0.y;
-              v[7] = dLdq * (dqa * (sph * b - cph * c) - dqb * sph * a + dqc * cph * a);
-              v[8] = dLdq * (-dqb * c + dqc * b);
-            }
-          }
-        }
+      // Wave-uniform skips only; inside, every lane computes and the lanes
+      // without a hit carry zero weight (their inputs are made finite first),
+      // which avoids masked branches and zero-initialised accumulators.
+      const float a = p[0] * r1.x + p[2] * r1.y;
+      const float b = p[0] * r1.z + p[1] * r1.w + p[2] * r2.x;
+      const float qt = a * (r2.y * a + 2.f * r2.z * b) + r2.w * b * b;
+      const bool pass1 = k < nc && qt <= A.q_cut;  // q >= qt
+      if (__ballot(pass1) == 0) continue;
+      const float c = p[0] * r0.x + p[1] * r0.y + p[2] * r0.z;
+      const float s2 = a * a + b * b;
+      float k2, dk2_ds2, dk2_dc;
+      if (__ballot(pass1 && !(c > 0.f && s2 < HP_K2_S2MAX)) == 0) {
+        k2 = hp_k2_series(s2);
+        dk2_ds2 = hp_k2_series_deriv(s2);
+        dk2_dc = 0.f;
+      } else {
+        k2 = hp_k2_grad(s2, c, &dk2_ds2, &dk2_dc);
       }
+      const bool hit = pass1 && qt * k2 <= A.q_cut;
       if (__ballot(hit) == 0) continue;
+      const float k2h = hit ? k2 : 1.f, d1 = hit ? dk2_ds2 : 0.f, d2 = hit ? dk2_dc : 0.f;
+      const float q = qt * k2h;
+      const float G = __expf(-0.5f * (hit ? q : 0.f));
+      const float oG = r0.w * G;
+      const float alpha = fminf(A.alpha_max, oG);
+      const float iom = __builtin_amdgcn_rcpf(1.f - alpha);
+      const float Tb = Tcur * iom;  // transmittance before this entry
+      const float wgt = hit ? alpha * Tb : 0.f;
+      float v[HP_NACC];
+      v[0] = g0 * wgt;
+      v[1] = g1 * wgt;
+      v[2] = g2 * wgt;
+      const float dLda_all = g0 * (r3.x * Tb - S0 * iom) + g1 * (r3.y * Tb - S1 * iom) + g2 * (r3.z * Tb - S2 * iom) -
+                             gTT * iom;
+      S0 += wgt * r3.x;
+      S1 += wgt * r3.y;
+      S2 += wgt * r3.z;
+      Tcur = hit ? Tb : Tcur;
+      // alpha clamped at alpha_max passes no gradient to opacity, conic or centre
+      const float dLda = (hit && oG < A.alpha_max) ? dLda_all : 0.f;
+      v[3] = dLda * G;
+      const float dLdq = -0.5f * alpha * dLda;
+      const float dk = dLdq * k2h;
+      v[4] = dk * a * a;
+      v[5] = dk * 2.f * a * b;
+      v[6] = dk * b * b;
+      // dq/d(a, b, c) with k2 = k2(s2, c)
+      const float dqa = k2h * 2.f * (r2.y * a + r2.z * b) + qt * d1 * 2.f * a;
+      const float dqb = k2h * 2.f * (r2.z * a + r2.w * b) + qt * d1 * 2.f * b;
+      const float dqc = qt * d2;
+      // motion of (a, b, c) with the Gaussian's longitude / latitude:
+      // da/dw = -cos(phi) c + sin(phi) b, db/dw = -sin(phi) a, dc/dw = cos(phi) a
+      // da/dp = 0, db/dp = -c, dc/dp = b
+      const float cph = r1.w, sph = r0.y;
+      v[7] = dLdq * (dqa * (sph * b - cph * c) - dqb * sph * a + dqc * cph * a);
+      v[8] = dLdq * (-dqb * c + dqc * b);
       // values 0..7: lane 8m holds the wave's total of value m; value 8: lane 63
       const float t8 = hp_wave_totals8_spread(v);
       hp_wave_totals_lane63<1>(&v[8]);
       if ((lane & 7) == 0) atomicAdd(&s_acc[i * HP_NACC + (lane >> 3)], t8);
       if (lane == 63) atomicAdd(&s_acc[i * HP_NACC + 8], v[8]);
     }
-    stage_store(&s_rec[((ctop - ch + 1) & 1) * HP_STAGE + tid], stage, gstage, qs);
+    s_rec[((ctop - ch + 1) & 1) * HP_STAGE + tid] = stage;
+    if (qs == 3) s_gid[(ctop - ch + 1) & 1][e] = gstage;
     __syncthreads();  // the chunk's totals are complete and the next chunk is staged
     for (int t = tid; t < HP_CHUNK * HP_NACC; t += 256) {
       const float x = s_acc[t];
       if (x != 0.f) {
         const int i = t / HP_NACC, m = t - i * HP_NACC;
-        const uint32_t g = __float_as_uint(cur[4 * i + 3].w);
+        const uint32_t g = s_gid[(ctop - ch) & 1][i];
         unsafeAtomicAdd(&acc[(int64_t)m * P + g], x);
         s_acc[t] = 0.f;
       }
