@@ -164,7 +164,7 @@ def kernel_breakdown(R, params, cams, targets, torch, A):
     times = {}
     reps = 3
     for _ in range(reps):
-        e = [ev() for _ in range(8)]
+        e = [ev() for _ in range(9)]
         e[0].record()
         proj = R.preprocess(g, cam)
         e[1].record()
@@ -181,12 +181,15 @@ def kernel_breakdown(R, params, cams, targets, torch, A):
         st = FwdState(cam, m, proj, vals, ranges, n, rgb, T, nc, g.P)
         z = torch.zeros_like
         gr = Gaussians(z(g.mean), z(g.scale), z(g.rot), z(g.opacity), z(g.sh))
+        acc = torch.zeros((9, g.P), dtype=torch.float32, device=g.mean.device)
         e[6].record()
-        R.backward(g, st, dimg, None, gr)
+        R.backward_pixels(st, dimg, None, acc)  # k_render_bwd alone
         e[7].record()
+        R.backward_preprocess(g, cam, acc, gr)
+        e[8].record()
         torch.cuda.synchronize()
-        for k, (a, b) in enumerate([(0, 1), (1, 2), (3, 4), (4, 5), (6, 7)]):
-            name = ["preprocess", "bin_and_sort", "render_fwd", "ssim_fwd_bwd", "render_bwd"][k]
+        for k, (a, b) in enumerate([(0, 1), (1, 2), (3, 4), (4, 5), (6, 7), (7, 8)]):
+            name = ["preprocess", "bin_and_sort", "render_fwd", "ssim_fwd_bwd", "render_bwd", "preprocess_bwd"][k]
             times.setdefault(name, []).append(e[a].elapsed_time(e[b]))
     med = {k: float(np.median(v)) for k, v in times.items()}
     evals = int(nc.to(torch.int64).sum().item())
@@ -218,8 +221,37 @@ def kernel_breakdown(R, params, cams, targets, torch, A):
     bwd_flops = 21 * evals + 93 * used
     res["roofline"]["achieved"] = bwd_flops / (med["render_bwd"] * 1e-3) / 1e12
     res["roofline"]["frac"] = res["roofline"]["achieved"] / PEAK_VALU_TFLOPS
+    res["roofline"]["traffic"] = measured_traffic("paper_2606_29794_amd/csrc/k_render.hip",
+                                                  "profiles/k_render_bwd_cfg2_counters.md")
+    res["roofline"]["flop_per_launch"] = bwd_flops
+    # the packed-FP32 peak, which this build does not use (packed FP32 is disabled)
+    res["roofline"]["frac_of_packed_fp32_peak"] = res["roofline"]["achieved"] / (2 * PEAK_VALU_TFLOPS)
     res["stage_roofline"]["render_fwd_TFLOPs"] = fwd_flops / (med["render_fwd"] * 1e-3) / 1e12
     return res
+
+
+def measured_traffic(kernel_src: str, summary: str):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE passes, scaled by the copy-kernel
+    calibration), or None when the kernel source has changed since the
+    counters were taken (the summary records the source's SHA-256)."""
+    import hashlib
+    try:
+        text = open(os.path.join(ROOT, summary)).read()
+        src = open(os.path.join(ROOT, kernel_src), "rb").read()
+    except OSError:
+        return None
+    fields = {}
+    for line in text.splitlines():
+        if line.startswith("- ") and ": " in line:
+            k, v = line[2:].split(": ", 1)
+            fields[k.strip()] = v.strip().strip("`")
+    if fields.get("source_sha256") != hashlib.sha256(src).hexdigest():
+        return None
+    try:
+        return float(fields["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(wl, n_pix):

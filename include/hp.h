@@ -261,6 +261,21 @@ hp_status hp_render_bwd(const hp_gaussians* g, const void* projected, const uint
                         const void* mask, int64_t n_active, const float* T, const int32_t* n_contrib,
                         const float* dL_drgb, const float* dL_dT, hp_gaussians_grad* grad, void* ws, size_t ws_bytes,
                         void* stream);
+/* The two halves of hp_render_bwd (which zeroes its workspace, then runs
+ * both).  hp_render_bwd_pixels is the pixel pass: per Gaussian, dL with
+ * respect to its colour (3), opacity (1), conic (A, B, C) and the longitude
+ * and latitude of its centre (omega, phi), ACCUMULATED into acc
+ * [9][P] (float, device, laid out value-major: acc[m * P + i]).  It needs
+ * no Gaussian parameters, only the projected records.  hp_preprocess_bwd
+ * carries such accumulators back through Sec. 3.2's chain (conic -> Sigma_arc
+ * -> scale, rotation and centre; colour -> SH and view direction) into
+ * `grad` (accumulated).  Errors as hp_render_bwd. */
+hp_status hp_render_bwd_pixels(const void* projected, int64_t P, const uint32_t* vals, const uint32_t* tile_ranges,
+                               int32_t n_tiles, const hp_view* view, const hp_params* prm, const void* mask,
+                               int64_t n_active, const float* T, const int32_t* n_contrib, const float* dL_drgb,
+                               const float* dL_dT, float* acc, void* stream);
+hp_status hp_preprocess_bwd(const hp_gaussians* g, const hp_view* view, const hp_params* prm, const float* acc,
+                            hp_gaussians_grad* grad, void* stream);
 
 /* ---- HEALPix-SSIM and the training loss (Sec. 4.1) ------------------------
  * Per active pixel and channel, Gaussian-weighted 11x11 statistics over

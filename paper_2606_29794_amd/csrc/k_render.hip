@@ -136,18 +136,15 @@ __device__ __forceinline__ void render_fwd_tile(const RenderArgs& A, const Rende
     gnext = base + 2 * HP_CHUNK + e < n ? vals[base + 2 * HP_CHUNK + e] : 0u;
     const float4* cur = s_rec + (c & 1) * HP_STAGE;
     const uint32_t cnt = n - base < HP_CHUNK ? n - base : HP_CHUNK;
-    for (uint32_t i = 0; i < cnt; ++i) {
-      if (__ballot(!done) == 0) break;
-      const float4 r1 = cur[4 * i + 1], r2 = cur[4 * i + 2];
-      if (done) continue;
-      const float a = p[0] * r1.x + p[2] * r1.y;
-      const float b = p[0] * r1.z + p[1] * r1.w + p[2] * r2.x;
-      const float qt = a * (r2.y * a + 2.f * r2.z * b) + r2.w * b * b;
-      if (!(qt <= A.q_cut)) continue;  // q >= qt
+    // entry i: Mahalanobis bound first (q >= qt), then the exact q and the
+    // compositing step; entries go two at a time so that the second one's
+    // loads and bound overlap the first one's work
+    auto step = [&](uint32_t i, float a, float b, float qt) {
+      if (done || !(qt <= A.q_cut)) return;
       const float4 r0 = cur[4 * i], r3 = cur[4 * i + 3];
       const float cc = p[0] * r0.x + p[1] * r0.y + p[2] * r0.z;
       const float qq = qt * hp_k2(a * a + b * b, cc);
-      if (!(qq <= A.q_cut)) continue;
+      if (!(qq <= A.q_cut)) return;
       const float alpha = fminf(A.alpha_max, r0.w * __expf(-0.5f * qq));
       const float w = alpha * T;
       C0 += w * r3.x;
@@ -158,6 +155,23 @@ __device__ __forceinline__ void render_fwd_tile(const RenderArgs& A, const Rende
       if (T < A.eps_T) {
         done = true;
         used = base + i + 1;
+      }
+    };
+    for (uint32_t i = 0; i < cnt; i += 2) {
+      if (__ballot(!done) == 0) break;
+      const float4 a1 = cur[4 * i + 1], a2 = cur[4 * i + 2];
+      const float aa = p[0] * a1.x + p[2] * a1.y;
+      const float ab = p[0] * a1.z + p[1] * a1.w + p[2] * a2.x;
+      const float aqt = aa * (a2.y * aa + 2.f * a2.z * ab) + a2.w * ab * ab;
+      if (i + 1 < cnt) {
+        const float4 b1 = cur[4 * i + 5], b2 = cur[4 * i + 6];
+        const float ba = p[0] * b1.x + p[2] * b1.y;
+        const float bb = p[0] * b1.z + p[1] * b1.w + p[2] * b2.x;
+        const float bqt = ba * (b2.y * ba + 2.f * b2.z * bb) + b2.w * bb * bb;
+        step(i, aa, ab, aqt);
+        step(i + 1, ba, bb, bqt);
+      } else {
+        step(i, aa, ab, aqt);
       }
     }
     // one barrier both publishes the next chunk and tells whether any pixel
@@ -433,12 +447,37 @@ extern "C" hp_status hp_render_bwd(const hp_gaussians* gs, const void* projected
   float* acc = (float*)ws;
   hipLaunchKernelGGL(k_zero_f32, dim3(hp_blocks(gs->P * HP_NACC, 256)), dim3(256), 0, s, acc, gs->P * HP_NACC);
   HP_CHECK_LAUNCH();
-  if (n_tiles > 0 && n_active > 0) {
-    RenderArgs A = make_args(g, hp_mask_view((const char*)mask, g), hp_proj_view((const char*)projected, gs->P), vals,
-                             tile_ranges, prm, n_active);
-    hipLaunchKernelGGL(k_render_bwd, dim3((unsigned)n_tiles), dim3(256), 0, s, A, gs->P, T, n_contrib, dL_drgb, dL_dT,
-                       acc);
-    HP_CHECK_LAUNCH();
-  }
+  HP_TRY(hp_render_bwd_pixels(projected, gs->P, vals, tile_ranges, n_tiles, view, prm, mask, n_active, T, n_contrib,
+                              dL_drgb, dL_dT, acc, stream));
   return hp_preprocess_bwd_launch(gs, view, prm, acc, grad, s);
+}
+
+extern "C" hp_status hp_render_bwd_pixels(const void* projected, int64_t P, const uint32_t* vals,
+                                          const uint32_t* tile_ranges, int32_t n_tiles, const hp_view* view,
+                                          const hp_params* prm, const void* mask, int64_t n_active, const float* T,
+                                          const int32_t* n_contrib, const float* dL_drgb, const float* dL_dT,
+                                          float* acc, void* stream) {
+  HP_TRY(hp_check_view(view, prm));
+  if (P < 0 || !projected || !mask || n_tiles < 0 || n_active < 0) return HP_ERR_INVALID_ARG;
+  if (P > 0 && !acc) return HP_ERR_INVALID_ARG;
+  if (n_active > 0 && n_tiles > 0 && (!T || !n_contrib || !dL_drgb || !tile_ranges || !vals)) return HP_ERR_INVALID_ARG;
+  const HpGeom g = hp_geom(view->order, prm->tile_log2);
+  if (n_tiles > g.ntile || n_active > g.npix) return HP_ERR_INVALID_ARG;
+  if (P == 0 || n_tiles == 0 || n_active == 0) return HP_OK;
+  RenderArgs A = make_args(g, hp_mask_view((const char*)mask, g), hp_proj_view((const char*)projected, P), vals,
+                           tile_ranges, prm, n_active);
+  hipLaunchKernelGGL(k_render_bwd, dim3((unsigned)n_tiles), dim3(256), 0, (hipStream_t)stream, A, P, T, n_contrib,
+                     dL_drgb, dL_dT, acc);
+  HP_CHECK_LAUNCH();
+  return HP_OK;
+}
+
+extern "C" hp_status hp_preprocess_bwd(const hp_gaussians* gs, const hp_view* view, const hp_params* prm,
+                                       const float* acc, hp_gaussians_grad* grad, void* stream) {
+  HP_TRY(hp_check_gaussians(gs));
+  HP_TRY(hp_check_view(view, prm));
+  if (!grad) return HP_ERR_INVALID_ARG;
+  if (gs->P == 0) return HP_OK;
+  if (!acc || !grad->mean || !grad->scale || !grad->rot || !grad->opacity || !grad->sh) return HP_ERR_INVALID_ARG;
+  return hp_preprocess_bwd_launch(gs, view, prm, acc, grad, (hipStream_t)stream);
 }

@@ -264,6 +264,22 @@ class Rasterizer:
                _p(dL_drgb.contiguous()), _p(None if dL_dT is None else dL_dT.contiguous()), C.byref(gg), _p(ws),
                ws_n, _stream())
 
+    def backward_pixels(self, st: FwdState, dL_drgb, dL_dT, acc: torch.Tensor) -> None:
+        """Pixel pass of the backward alone: per-Gaussian dL/d(colour,
+        opacity, conic, omega, phi) accumulated into acc [9, P]."""
+        v = st.camera.view()
+        A.call("hp_render_bwd_pixels", _p(st.projected), st.P, _p(st.vals), _p(st.ranges), st.mask.n_tiles,
+               C.byref(v), C.byref(self.prm), _p(st.mask.buf), st.mask.n_active, _p(st.T), _p(st.n_contrib),
+               _p(dL_drgb.contiguous()), _p(None if dL_dT is None else dL_dT.contiguous()), _p(acc), _stream())
+
+    def backward_preprocess(self, g: Gaussians, cam: Camera, acc: torch.Tensor, grads: Gaussians) -> None:
+        """Second half of the backward: acc [9, P] -> parameter gradients (accumulated)."""
+        v = cam.view()
+        gs = g.struct()
+        gg = A.hp_gaussians_grad(grads.mean.data_ptr(), grads.scale.data_ptr(), grads.rot.data_ptr(),
+                                 grads.opacity.data_ptr(), grads.sh.data_ptr())
+        A.call("hp_preprocess_bwd", C.byref(gs), C.byref(v), C.byref(self.prm), _p(acc), C.byref(gg), _stream())
+
     # ---- loss ----------------------------------------------------------------
     def ssim_loss(self, img, ref, cam: Camera, sp: A.hp_ssim_params | None = None, dL_dloss=None, want_map=False):
         """Returns (out[3] = (mean SSIM, L1, loss), ssim_map or None, dL/dimg or None)."""

@@ -51,3 +51,31 @@ def test_autograd_step_equals_direct_calls(variant):
     L_o = O.loss(camd["order"], act, rgb.detach().cpu().numpy(), target.cpu().numpy())
     L_o = L_o[0] if isinstance(L_o, tuple) else L_o
     assert abs(float(loss.item()) - float(L_o)) < 2e-6
+
+
+def test_split_backward_equals_fused():
+    """hp_render_bwd_pixels followed by hp_preprocess_bwd gives what
+    hp_render_bwd gives (same kernels; only float-atomic order may differ)."""
+    import torch
+    from paper_2606_29794_amd.raster import Camera, Gaussians, Rasterizer
+    wl = SC.config1_fd("overlap")
+    sc, camd = wl.scene, wl.cameras[0]
+    R = Rasterizer()
+    cam = Camera.from_dict(camd)
+    g = Gaussians.from_scene(sc)
+    st = R.forward(g, cam)
+    rng = np.random.default_rng(3)
+    dC = torch.as_tensor(rng.normal(size=(3, st.mask.n_active)).astype(np.float32), device="cuda")
+    dT = torch.as_tensor(rng.normal(size=st.mask.n_active).astype(np.float32), device="cuda")
+    z = torch.zeros_like
+    g1 = Gaussians(z(g.mean), z(g.scale), z(g.rot), z(g.opacity), z(g.sh))
+    g2 = Gaussians(z(g.mean), z(g.scale), z(g.rot), z(g.opacity), z(g.sh))
+    R.backward(g, st, dC, dT, g1)
+    acc = torch.zeros((9, g.P), dtype=torch.float32, device="cuda")
+    R.backward_pixels(st, dC, dT, acc)
+    R.backward_preprocess(g, cam, acc, g2)
+    torch.cuda.synchronize()
+    for k in ("mean", "scale", "rot", "opacity", "sh"):
+        a = getattr(g1, k).double().cpu().numpy().ravel()
+        b = getattr(g2, k).double().cpu().numpy().ravel()
+        assert np.linalg.norm(a - b) <= 1e-5 * np.linalg.norm(a), k
