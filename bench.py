@@ -212,7 +212,7 @@ def kernel_breakdown(R, params, cams, targets, torch, A):
             "preprocess_GBs": pre_bytes / (med["preprocess"] * 1e-3) / 1e9,
         },
     }
-    # algorithmic flops (FMA = 2) per pixel-Gaussian pair, see the design doc:
+    # algorithmic flops (FMA = 2) per pixel-Gaussian pair:
     # every evaluated pair: offset projections a, b and the Mahalanobis bound
     # qt (21 flop); every composited pair in addition: c, the distance factor,
     # q, alpha and the compositing update (33 flop) in the forward, and the
