@@ -146,11 +146,18 @@ def serve_bench(n_requests):
     srv.serve(reqs[:16], realtime=False)
     srv.serve_sequential(reqs[:8], realtime=False)
     torch.cuda.synchronize()
+    # throughput: the whole backlog queued at t = 0 (the server is never idle)
+    n_sat = min(len(reqs), 600)
+    sat_b = srv.serve(reqs[:n_sat], realtime=False)
+    sat_s = srv.serve_sequential(reqs[:n_sat], realtime=False)
+    # latency: the trace replayed at its arrival times
     batched = srv.serve(reqs, realtime=True)
     seq = srv.serve_sequential(reqs, realtime=True)
     return {"workload": f"cfg4: 2M SH-3 Gaussians resident, {n_requests} requests, Poisson 200 req/s, "
                         "pinhole 60-90 / fisheye 180-220 / full sphere, Nside 128-1024",
-            "batched": batched.summary(), "sequential": seq.summary()}
+            "saturated": {"n": n_sat, "batched": sat_b.summary(), "sequential": sat_s.summary(),
+                          "speedup": sat_b.summary()["renders_per_s"] / sat_s.summary()["renders_per_s"]},
+            "realtime": {"batched": batched.summary(), "sequential": seq.summary()}}
 
 
 def kernel_breakdown(R, params, cams, targets, torch, A):
@@ -227,6 +234,32 @@ def kernel_breakdown(R, params, cams, targets, torch, A):
     # the packed-FP32 peak, which this build does not use (packed FP32 is disabled)
     res["roofline"]["frac_of_packed_fp32_peak"] = res["roofline"]["achieved"] / (2 * PEAK_VALU_TFLOPS)
     res["stage_roofline"]["render_fwd_TFLOPs"] = fwd_flops / (med["render_fwd"] * 1e-3) / 1e12
+    # whole-view roofline: per stage the ideal time is its algorithmic bytes at
+    # the HBM peak or its algorithmic flops at the VALU peak; the fraction is
+    # the sum of ideal times over the sum of measured stage times
+    n_act = int(m.n_active)
+    ideal_s = {
+        "preprocess": pre_bytes / (PEAK_HBM_GBS * 1e9),
+        # count/scan per Gaussian, 12 B per emitted pair, one read + write of
+        # 12 B key/value per pair for the ordering, 8 B of range per tile
+        "bin_and_sort": (24 * P + 36 * n + 8 * int(m.n_tiles)) / (PEAK_HBM_GBS * 1e9),
+        "render_fwd": fwd_flops / (PEAK_VALU_TFLOPS * 1e12),
+        # image and reference read, gradient written: 36 B per active pixel;
+        # separable 11-tap window sums (two passes) of the weight and 5
+        # statistics x 3 channels in the forward (16 x 22 FMA = 704 flop), of
+        # 3 gradient partials x 3 channels in the backward (396 flop), plus
+        # the per-pixel SSIM algebra (~90 flop)
+        "ssim_fwd_bwd": max(36 * n_act / (PEAK_HBM_GBS * 1e9), 1190 * n_act / (PEAK_VALU_TFLOPS * 1e12)),
+        "render_bwd": bwd_flops / (PEAK_VALU_TFLOPS * 1e12),
+        # accumulators read, parameters read, gradients read and written
+        "preprocess_bwd": P * (4 * 9 + 3 * 4 * (11 + 3 * K)) / (PEAK_HBM_GBS * 1e9),
+    }
+    res["overall_roofline"] = {
+        "ideal_ms": 1e3 * sum(ideal_s.values()),
+        "measured_ms": sum(med[k] for k in ideal_s),
+        "frac": 1e3 * sum(ideal_s.values()) / sum(med[k] for k in ideal_s),
+        "per_stage_frac": {k: 1e3 * v / med[k] for k, v in ideal_s.items()},
+    }
     return res
 
 

@@ -353,6 +353,25 @@ __device__ __forceinline__ float hp_wave_totals8_spread(const float* v) {
   return y;
 }
 
+// A ninth sum beside hp_wave_totals8_spread: the same exchanges applied to
+// one value alone (each swap pairs the value with itself), so every lane ends
+// with the wave's total.
+__device__ __forceinline__ float hp_wave_total_all(float z) {
+  {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(z), __float_as_uint(z), false, false);
+    z = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
+  {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(z), __float_as_uint(z), false, false);
+    z = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
+  z += hp_dpp<0x128>(z);  // row_ror:8
+  z += hp_dpp<0xB1>(z);
+  z += hp_dpp<0x4E>(z);
+  z += hp_dpp<0x141>(z);
+  return z;
+}
+
 __device__ __forceinline__ float hp_wave_sum(float v) {
   // butterfly over 64 lanes with cross-lane shuffles
 #pragma unroll

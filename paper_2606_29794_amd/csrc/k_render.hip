@@ -105,6 +105,22 @@ __device__ __forceinline__ bool wave_cap_hit(const WaveCap& w, float4 r0, float 
   return (ch <= 0.f) || (dx * dx + dy * dy + dz * dz <= 4.f * sh * sh);
 }
 
+// Second per-wave test, on the 3-sigma ellipse instead of the r_s disc:
+// (a, b) = E p with E's rows orthonormal, so |(a, b)(p) - (a, b)(w)| <= |p - w|
+// and sqrt(qt) = |L (a, b)| (conic = L^T L) changes by at most
+// sqrt(lambda_max(conic)) |p - w|.  Every pixel of the wave lies within the
+// chord 2 sr of the cap centre w, so if sqrt(qt(w)) exceeds sqrt(q_cut) +
+// 2 sr sqrt(lambda_max) no pixel of the wave reaches qt <= q_cut.  The bound
+// is widened by 1e-4 relative against float rounding.
+__device__ __forceinline__ bool wave_ellipse_hit(const WaveCap& w, float4 r1, float4 r2, float rq_cut) {
+  const float wp[3] = {w.cx, w.cy, w.cz};
+  const HpOffset o = hp_offset(wp, r1, r2);
+  const float h = 0.5f * (r2.y - r2.w);
+  const float lmax = 0.5f * (r2.y + r2.w) + sqrtf(h * h + r2.z * r2.z);
+  const float lim = rq_cut + 2.f * w.sr * sqrtf(fmaxf(lmax, 0.f));
+  return o.qt <= lim * lim * 1.0001f + 1e-6f;
+}
+
 __device__ __forceinline__ void render_fwd_tile(const RenderArgs& A, const RenderOut& O, int ct, float4* s_rec) {
   bool valid;
   int64_t slot;
@@ -139,13 +155,12 @@ __device__ __forceinline__ void render_fwd_tile(const RenderArgs& A, const Rende
     // entry i: Mahalanobis bound first (q >= qt), then the exact q and the
     // compositing step; entries go two at a time so that the second one's
     // loads and bound overlap the first one's work
-    auto step = [&](uint32_t i, float a, float b, float qt) {
-      if (done || !(qt <= A.q_cut)) return;
+    auto step = [&](uint32_t i, const HpOffset& o) {
+      if (done || !(o.qt <= A.q_cut)) return;
       const float4 r0 = cur[4 * i], r3 = cur[4 * i + 3];
-      const float cc = p[0] * r0.x + p[1] * r0.y + p[2] * r0.z;
-      const float qq = qt * hp_k2(a * a + b * b, cc);
+      const float qq = o.qt * hp_k2(hp_offset_s2(o), hp_offset_c(p, r0));
       if (!(qq <= A.q_cut)) return;
-      const float alpha = fminf(A.alpha_max, r0.w * __expf(-0.5f * qq));
+      const float alpha = fminf(A.alpha_max, r0.w * hp_exp_neg_half(qq));
       const float w = alpha * T;
       C0 += w * r3.x;
       C1 += w * r3.y;
@@ -159,19 +174,13 @@ __device__ __forceinline__ void render_fwd_tile(const RenderArgs& A, const Rende
     };
     for (uint32_t i = 0; i < cnt; i += 2) {
       if (__ballot(!done) == 0) break;
-      const float4 a1 = cur[4 * i + 1], a2 = cur[4 * i + 2];
-      const float aa = p[0] * a1.x + p[2] * a1.y;
-      const float ab = p[0] * a1.z + p[1] * a1.w + p[2] * a2.x;
-      const float aqt = aa * (a2.y * aa + 2.f * a2.z * ab) + a2.w * ab * ab;
+      const HpOffset oa = hp_offset(p, cur[4 * i + 1], cur[4 * i + 2]);
       if (i + 1 < cnt) {
-        const float4 b1 = cur[4 * i + 5], b2 = cur[4 * i + 6];
-        const float ba = p[0] * b1.x + p[2] * b1.y;
-        const float bb = p[0] * b1.z + p[1] * b1.w + p[2] * b2.x;
-        const float bqt = ba * (b2.y * ba + 2.f * b2.z * bb) + b2.w * bb * bb;
-        step(i, aa, ab, aqt);
-        step(i + 1, ba, bb, bqt);
+        const HpOffset ob = hp_offset(p, cur[4 * i + 5], cur[4 * i + 6]);
+        step(i, oa);
+        step(i + 1, ob);
       } else {
-        step(i, aa, ab, aqt);
+        step(i, oa);
       }
     }
     // one barrier both publishes the next chunk and tells whether any pixel
@@ -219,6 +228,12 @@ __global__ __launch_bounds__(256) void k_render_fwd_batch(RenderBatch B) {
 // Per-Gaussian gradient accumulators written by the pixel pass:
 // [0..2] colour, [3] opacity, [4..6] conic (A, B, C), [7] omega, [8] phi.
 #define HP_NACC 9
+// constant factor of each value as the per-pixel terms leave it out
+__constant__ float kFlushScale[HP_NACC] = {1.f, 1.f, 1.f, 1.f, -0.5f, -1.f, -0.5f, -1.f, -1.f};
+template <bool B>
+struct HpBool {
+  static constexpr bool value = B;
+};
 
 __global__ __launch_bounds__(256) void k_render_bwd(RenderArgs A, int64_t P, const float* __restrict__ Tfin,
                                                     const int32_t* __restrict__ ncon, const float* __restrict__ gC,
@@ -252,13 +267,15 @@ __global__ __launch_bounds__(256) void k_render_bwd(RenderArgs A, int64_t P, con
   ncmax = (int)hp_uniform((uint32_t)ncmax);
   const int tid = threadIdx.x, lane = hp_lane();
   const WaveCap wc = wave_cap(valid, p);
+  const float rq_cut = sqrtf(A.q_cut);
   if (lane == 0) s_nc[tid >> 6] = ncmax;
   for (int t = tid; t < HP_CHUNK * HP_NACC; t += 256) s_acc[t] = 0.f;
   __syncthreads();
   const int nb = max(max(s_nc[0], s_nc[1]), max(s_nc[2], s_nc[3]));
-  float Tcur = Tf;                     // transmittance after the current entry
-  float S0 = 0.f, S1 = 0.f, S2 = 0.f;  // colour composited behind the current entry
-  const float gTT = gT * Tf;
+  float Tcur = Tf;  // transmittance after the current entry
+  // g . (colour composited behind the current entry) + dL/dT_final * T_final
+  float SgT = gT * Tf;
+  const float amax = A.alpha_max;
   // entries nb-1 .. 0 in chunks of HP_CHUNK aligned at j0, last chunk first;
   // the staging runs a chunk ahead as in the forward pass
   const uint32_t e = (uint32_t)tid >> 2;
@@ -282,76 +299,104 @@ __global__ __launch_bounds__(256) void k_render_bwd(RenderArgs A, int64_t P, con
     const float4* cur = s_rec + ((ctop - ch) & 1) * HP_STAGE;
     const int kbase = ch * HP_CHUNK;
     const int ktop = min(kbase + HP_CHUNK, ncmax) - 1;  // this wave's last entry in the chunk
-    // lane j tests entry kbase + j against the wave's cap; walk the hits from the back
+    const int nrel = nc - kbase;                          // entries of the chunk this pixel composited
+    // lane j tests entry kbase + j against the wave's cap and ellipse bound; walk the hits from the back
     uint64_t todo = 0;
     if (ktop >= kbase)
-      todo = __ballot(lane <= ktop - kbase && wave_cap_hit(wc, cur[4 * lane], cur[4 * lane + 3].w));
+      todo = __ballot(lane <= ktop - kbase && wave_cap_hit(wc, cur[4 * lane], cur[4 * lane + 3].w) &&
+                      wave_ellipse_hit(wc, cur[4 * lane + 1], cur[4 * lane + 2], rq_cut));
     while (todo != 0) {
       const int i = 63 - __builtin_clzll(todo);
       todo &= ~(1ull << i);
-      const int k = kbase + i;
       const float4 r0 = cur[4 * i], r1 = cur[4 * i + 1], r2 = cur[4 * i + 2], r3 = cur[4 * i + 3];
+      const HpOffset o = hp_offset(p, r1, r2);
+      const float a = o.a, b = o.b, qt = o.qt;
+      const bool pass1 = i < nrel && qt <= A.q_cut;  // entry k = kbase + i < nc, and q >= qt
+      // lane predicates are combined as wave masks (scalar ANDs), which keeps
+      // every test below a single compare
+      const uint64_t m1 = __builtin_amdgcn_ballot_w64(i < nrel) & __builtin_amdgcn_ballot_w64(qt <= A.q_cut);
+      if (m1 == 0) continue;
+      const float c = hp_offset_c(p, r0);
+      const float s2 = hp_offset_s2(o);
       // Wave-uniform skips only; inside, every lane computes and the lanes
       // without a hit carry zero weight (their inputs are made finite first),
-      // which avoids masked branches and zero-initialised accumulators.
-      const float a = p[0] * r1.x + p[2] * r1.y;
-      const float b = p[0] * r1.z + p[1] * r1.w + p[2] * r2.x;
-      const float qt = a * (r2.y * a + 2.f * r2.z * b) + r2.w * b * b;
-      const bool pass1 = k < nc && qt <= A.q_cut;  // q >= qt
-      if (__ballot(pass1) == 0) continue;
-      const float c = p[0] * r0.x + p[1] * r0.y + p[2] * r0.z;
-      const float s2 = a * a + b * b;
-      float k2, dk2_ds2, dk2_dc;
-      if (__ballot(pass1 && !(c > 0.f && s2 < HP_K2_S2MAX)) == 0) {
-        k2 = hp_k2_series(s2);
-        dk2_ds2 = hp_k2_series_deriv(s2);
-        dk2_dc = 0.f;
-      } else {
-        k2 = hp_k2_grad(s2, c, &dk2_ds2, &dk2_dc);
-      }
-      const bool hit = pass1 && qt * k2 <= A.q_cut;
-      if (__ballot(hit) == 0) continue;
-      const float k2h = hit ? k2 : 1.f, d1 = hit ? dk2_ds2 : 0.f, d2 = hit ? dk2_dc : 0.f;
-      const float q = qt * k2h;
-      const float G = __expf(-0.5f * (hit ? q : 0.f));
-      const float oG = r0.w * G;
-      const float alpha = fminf(A.alpha_max, oG);
-      const float iom = __builtin_amdgcn_rcpf(1.f - alpha);
-      const float Tb = Tcur * iom;  // transmittance before this entry
-      const float wgt = hit ? alpha * Tb : 0.f;
-      float v[HP_NACC];
-      v[0] = g0 * wgt;
-      v[1] = g1 * wgt;
-      v[2] = g2 * wgt;
-      const float dLda_all = g0 * (r3.x * Tb - S0 * iom) + g1 * (r3.y * Tb - S1 * iom) + g2 * (r3.z * Tb - S2 * iom) -
-                             gTT * iom;
-      S0 += wgt * r3.x;
-      S1 += wgt * r3.y;
-      S2 += wgt * r3.z;
-      Tcur = hit ? Tb : Tcur;
-      // alpha clamped at alpha_max passes no gradient to opacity, conic or centre
-      const float dLda = (hit && oG < A.alpha_max) ? dLda_all : 0.f;
-      v[3] = dLda * G;
-      const float dLdq = -0.5f * alpha * dLda;
-      const float dk = dLdq * k2h;
-      v[4] = dk * a * a;
-      v[5] = dk * 2.f * a * b;
-      v[6] = dk * b * b;
-      // dq/d(a, b, c) with k2 = k2(s2, c)
-      const float dqa = k2h * 2.f * (r2.y * a + r2.z * b) + qt * d1 * 2.f * a;
-      const float dqb = k2h * 2.f * (r2.z * a + r2.w * b) + qt * d1 * 2.f * b;
-      const float dqc = qt * d2;
-      // motion of (a, b, c) with the Gaussian's longitude / latitude:
-      // da/dw = -cos(phi) c + sin(phi) b, db/dw = -sin(phi) a, dc/dw = cos(phi) a
-      // da/dp = 0, db/dp = -c, dc/dp = b
-      const float cph = r1.w, sph = r0.y;
-      v[7] = dLdq * (dqa * (sph * b - cph * c) - dqb * sph * a + dqc * cph * a);
-      v[8] = dLdq * (-dqb * c + dqc * b);
-      // values 0..7: lane 8m holds the wave's total of value m; value 8: lane 63
-      const float t8 = hp_wave_totals8_spread(v);
-      hp_wave_totals_lane63<1>(&v[8]);
-      if ((lane & 7) == 0) atomicAdd(&s_acc[i * HP_NACC + (lane >> 3)], t8);
-      if (lane == 63) atomicAdd(&s_acc[i * HP_NACC + 8], v[8]);
+      // which avoids masked branches.  FAR: some lane of the wave is outside
+      // the series range of k2, so k2 depends on c as well.
+      auto composite = [&](auto far_tag) {
+        constexpr bool FAR = decltype(far_tag)::value;
+        float k2, d1, d2 = 0.f;  // k2, dk2/ds2, dk2/dc
+        if constexpr (FAR) {
+          k2 = hp_k2_grad(s2, c, &d1, &d2);
+        } else {
+          k2 = hp_k2_series(s2);
+          d1 = hp_k2_series_deriv(s2);
+        }
+        const bool inq = qt * k2 <= A.q_cut;
+        if ((__builtin_amdgcn_ballot_w64(inq) & m1) == 0) return;
+        const bool hit = pass1 && inq;
+        // series k2 is finite everywhere; far from the centre it is not
+        // (antipode), so there the lanes without a hit take neutral values
+        float k2h = k2;
+        if constexpr (FAR) {
+          k2h = hit ? k2 : 1.f;
+          d1 = hit ? d1 : 0.f;
+          d2 = hit ? d2 : 0.f;
+        }
+        const float q = qt * k2h;  // finite on every lane
+        const float G = hp_exp_neg_half(q);
+        const float oG = r0.w * G;
+        const bool lin = oG < amax;  // below the clamp alpha depends on q and opacity
+        const float alpha = lin ? oG : amax;
+        const float iom = __builtin_amdgcn_rcpf(1.f - alpha);
+        const float Tb = Tcur * iom;  // transmittance before this entry
+        const float wgt = hit ? alpha * Tb : 0.f;
+        float v[HP_NACC];
+        v[0] = g0 * wgt;
+        v[1] = g1 * wgt;
+        v[2] = g2 * wgt;
+        // dL/dalpha = Tb (g . rgb) - (g . S + dL/dT_final T_final) / (1 - alpha)
+        const float gr = g0 * r3.x + g1 * r3.y + g2 * r3.z;
+        const float dLda = (hit && lin) ? Tb * gr - iom * SgT : 0.f;
+        SgT += wgt * gr;
+        Tcur = hit ? Tb : Tcur;
+        v[3] = dLda * G;
+        // m = -2 dL/dq; values 4..8 leave out their constant factors, which
+        // the flush applies once per Gaussian (kFlushScale)
+        const float m = alpha * dLda;
+        const float mk = m * k2h;
+        const float ma = mk * a, mb = mk * b;
+        v[4] = ma * a;  // dL/dA = -v4 / 2
+        v[5] = ma * b;  // dL/dB = -v5
+        v[6] = mb * b;  // dL/dC = -v6 / 2
+        // dq/da = 2 fa, dq/db = 2 fb, dq/dc = 2 hc, with k2 = k2(s2, c)
+        const float e = qt * d1;
+        const float fa = k2h * o.u1 + e * a;
+        const float fb = k2h * o.u2 + e * b;
+        // motion of (a, b, c) with the Gaussian's longitude / latitude:
+        // da/dw = -cos(phi) c + sin(phi) b, db/dw = -sin(phi) a, dc/dw = cos(phi) a
+        // da/dp = 0, db/dp = -c, dc/dp = b
+        const float cph = r1.w, sph = r0.y;
+        float t2, t3;
+        if constexpr (FAR) {
+          const float hc = 0.5f * qt * d2;
+          t2 = hc * a - fa * c;
+          t3 = hc * b - fb * c;
+        } else {
+          t2 = -(fa * c);
+          t3 = -(fb * c);
+        }
+        v[7] = m * (sph * (fa * b - fb * a) + cph * t2);  // dL/domega = -v7
+        v[8] = m * t3;                                     // dL/dphi = -v8
+        // values 0..7: lane 8m holds the wave's total of value m; value 8: every lane
+        const float t8 = hp_wave_totals8_spread(v);
+        const float t9 = hp_wave_total_all(v[8]);
+        if ((lane & 7) == 0 || lane == 1)
+          atomicAdd(&s_acc[i * HP_NACC + (lane == 1 ? 8 : lane >> 3)], lane == 1 ? t9 : t8);
+      };
+      if (((__builtin_amdgcn_ballot_w64(!(c > 0.f)) | __builtin_amdgcn_ballot_w64(!(s2 < HP_K2_S2MAX))) & m1) == 0)
+        composite(HpBool<false>{});
+      else
+        composite(HpBool<true>{});
     }
     s_rec[((ctop - ch + 1) & 1) * HP_STAGE + tid] = stage;
     if (qs == 3) s_gid[(ctop - ch + 1) & 1][e] = gstage;
@@ -361,7 +406,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(RenderArgs A, int64_t P, con
       if (x != 0.f) {
         const int i = t / HP_NACC, m = t - i * HP_NACC;
         const uint32_t g = s_gid[(ctop - ch) & 1][i];
-        unsafeAtomicAdd(&acc[(int64_t)m * P + g], x);
+        unsafeAtomicAdd(&acc[(int64_t)m * P + g], x * kFlushScale[m]);
         s_acc[t] = 0.f;
       }
     }

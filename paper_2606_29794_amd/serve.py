@@ -219,8 +219,9 @@ class Server:
                     t = clock()
                     for k, r in enumerate(b.reqs):
                         rgb, T = b.outs[k][0], b.outs[k][1]
-                        results[r.rid] = Result(r.rid, r.arrival, t, rgb if keep_outputs else None,
-                                                T if keep_outputs else None)
+                        # without real-time replay every request is queued at t = 0
+                        results[r.rid] = Result(r.rid, r.arrival if realtime else 0.0, t,
+                                                rgb if keep_outputs else None, T if keep_outputs else None)
                     inflight.remove(b)
                     mem -= b.nbytes
                     free.append(b._slot)
@@ -257,7 +258,7 @@ class Server:
             st = self.R.forward(self.g, r.camera)
             torch.cuda.synchronize()
             t = time.perf_counter() - t0
-            results.append(Result(r.rid, r.arrival, t, st.rgb if keep_outputs else None,
+            results.append(Result(r.rid, r.arrival if realtime else 0.0, t, st.rgb if keep_outputs else None,
                                   st.T if keep_outputs else None))
         makespan = max(x.done for x in results)
         return ServeStats.of(results, makespan)
