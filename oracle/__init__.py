@@ -399,3 +399,80 @@ def loss(order, active, img, ref, lam=LAMBDA, want_grad=False):
         return L, None
     g = (1 - lam) * np.sign(img - ref) / img.size - lam * gs
     return L, g
+
+
+# ---------------------------------------------------------------------------
+# Image synthesis between the sphere and camera images (Eq. camera_synthesis,
+# Interp_H; supp. camera models; supp. Eq. supp_image_to_healpix).  Readings:
+# one y-up camera frame for every model, pixel centres at half-integers,
+# ring-bilinear Interp_H with the pole as the mean of the nearest ring and
+# renormalisation over active neighbours (see hp_oracle.cpp).
+# ---------------------------------------------------------------------------
+
+def _cam_args(cam):
+    return int(cam["cam_type"]), float(np.float32(cam["fov_x"])), float(np.float32(cam["fov_y"]))
+
+
+def cam_rays(cam: dict, W: int, H: int, uv) -> tuple:
+    """Camera-frame unit rays [n][3] through image positions uv [n][2], and
+    whether each lies in the camera's valid domain."""
+    uv = np.ascontiguousarray(uv, np.float64).reshape(-1, 2)
+    d = np.empty((uv.shape[0], 3), np.float64)
+    ok = np.empty(uv.shape[0], np.int32)
+    t, fx, fy = _cam_args(cam)
+    lib().or_cam_rays(t, int(W), int(H), C.c_double(fx), C.c_double(fy), C.c_int64(uv.shape[0]), _p(uv), _p(d), _p(ok))
+    return d, ok.astype(bool)
+
+
+def cam_project(cam: dict, W: int, H: int, d) -> tuple:
+    """Image positions [n][2] of camera-frame directions d [n][3] and validity."""
+    d = np.ascontiguousarray(d, np.float64).reshape(-1, 3)
+    uv = np.empty((d.shape[0], 2), np.float64)
+    ok = np.empty(d.shape[0], np.int32)
+    t, fx, fy = _cam_args(cam)
+    lib().or_cam_project(t, int(W), int(H), C.c_double(fx), C.c_double(fy), C.c_int64(d.shape[0]), _p(d), _p(uv), _p(ok))
+    return uv, ok.astype(bool)
+
+
+_r2n_cache = {}
+
+
+def _ring2nest(order):
+    if order not in _r2n_cache:
+        _r2n_cache[order] = np.ascontiguousarray(ring2nest_table(order))
+    return _r2n_cache[order]
+
+
+def interp_weights(order: int, d) -> tuple:
+    """Interp_H at directions d [n][3]: NESTED pixels [n][4] and weights [n][4]."""
+    d = np.ascontiguousarray(d, np.float64).reshape(-1, 3)
+    pix = np.empty((d.shape[0], 4), np.int64)
+    w = np.empty((d.shape[0], 4), np.float64)
+    lib().or_interp_weights(order, _p(_ring2nest(order)), C.c_int64(d.shape[0]), _p(d), _p(pix), _p(w))
+    return pix, w
+
+
+def sphere_to_image(cam: dict, active, img, W: int, H: int) -> tuple:
+    """Camera image [3][H][W] (and valid flags [H][W]) from the HEALPix image
+    img [3][n_active] on the sorted active pixels (Eq. camera_synthesis)."""
+    active = np.ascontiguousarray(active, np.int64)
+    img = np.ascontiguousarray(img, np.float64).reshape(3, active.size)
+    out = np.empty((3, H, W), np.float64)
+    ok = np.empty((H, W), np.int32)
+    t, fx, fy = _cam_args(cam)
+    lib().or_sphere_to_image(int(cam["order"]), _p(_ring2nest(cam["order"])), C.c_int64(active.size), _p(active),
+                             _p(img), t, int(W), int(H), C.c_double(fx), C.c_double(fy), _p(out), _p(ok))
+    return out, ok.astype(bool)
+
+
+def image_to_sphere(cam: dict, active, img, W: int, H: int) -> tuple:
+    """Samples [3][n_active] of the camera image img [3][H][W] at the active
+    HEALPix pixel centres (supp. Eq. supp_image_to_healpix) and validity."""
+    active = np.ascontiguousarray(active, np.int64)
+    img = np.ascontiguousarray(img, np.float64).reshape(3, H, W)
+    out = np.empty((3, active.size), np.float64)
+    ok = np.empty(active.size, np.int32)
+    t, fx, fy = _cam_args(cam)
+    lib().or_image_to_sphere(int(cam["order"]), C.c_int64(active.size), _p(active), _p(img), t, int(W), int(H),
+                             C.c_double(fx), C.c_double(fy), _p(out), _p(ok))
+    return out, ok.astype(bool)

@@ -890,3 +890,243 @@ double or_hssim(int order, i64 n, const i64* active, const double* img, const do
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Image synthesis between the HEALPix grid and camera images (Eq.
+// camera_synthesis, Interp_H; supp. "Preprocessing of Omnidirectional
+// Images" for the camera mappings; supp. Eq. supp_image_to_healpix for the
+// reverse direction).
+//
+// Readings where the paper is silent or at odds with itself:
+//  * One camera frame for all models, y up: the pinhole and fisheye formulas
+//    measure image v downwards, the panorama formula looks up at v = 0, so
+//    v is flipped in the first two (the optical axis is +z, +x is right).
+//  * Pixel (i, j) of a W x H image has its centre at (u, v) = (i + 1/2, j + 1/2).
+//  * Interp_H is bilinear over the ring structure: the two rings enclosing
+//    the colatitude, in each ring the two pixels enclosing the longitude,
+//    linear in longitude within a ring and linear in colatitude between the
+//    rings.  Above the first ring (below the last) the pole is taken as the
+//    mean of that ring's four pixels.  Neighbours outside the active set get
+//    weight zero and the remaining weights are renormalised; a camera pixel
+//    with no active neighbour (or outside the camera's valid domain) is 0.
+//  * Image to sphere: bilinear in the image at the projected position of
+//    the pixel centre, clamped to the border (wrapping in longitude for the
+//    panorama).
+// ---------------------------------------------------------------------------
+static void cam_focal(int cam, int W, int H, double fovx, double fovy, double* fx, double* fy) {
+  if (cam == CAM_PINHOLE) {
+    *fx = W / (2.0 * std::tan(0.5 * fovx));
+    *fy = H / (2.0 * std::tan(0.5 * fovy));
+  } else {  // fisheye: valid ellipse tangent to the image border
+    *fx = W / M_PI;
+    *fy = H / M_PI;
+  }
+}
+
+// Ray through image position (u, v), camera frame; false outside the domain.
+static bool cam_ray(int cam, int W, int H, double fovx, double fovy, double u, double v, double d[3]) {
+  if (cam == CAM_FULL) {  // equirectangular panorama
+    double om = 2.0 * M_PI * u / W - M_PI, ph = 0.5 * M_PI - M_PI * v / H;
+    d[0] = std::cos(ph) * std::sin(om);
+    d[1] = std::sin(ph);
+    d[2] = std::cos(ph) * std::cos(om);
+    return true;
+  }
+  double fx, fy;
+  cam_focal(cam, W, H, fovx, fovy, &fx, &fy);
+  double mx = (u - 0.5 * W) / fx, my = -(v - 0.5 * H) / fy;
+  if (cam == CAM_PINHOLE) {
+    double n = std::sqrt(mx * mx + my * my + 1.0);
+    d[0] = mx / n; d[1] = my / n; d[2] = 1.0 / n;
+    return true;
+  }
+  // anisotropic equidistant fisheye: psi = r_m w_eff(gamma), w = FoV / pi
+  double rm = std::sqrt(mx * mx + my * my);
+  double gam = std::atan2(my, mx);
+  double wx = fovx / M_PI, wy = fovy / M_PI;
+  double weff = std::sqrt(wx * std::cos(gam) * wx * std::cos(gam) + wy * std::sin(gam) * wy * std::sin(gam));
+  double psi = rm * weff;
+  d[0] = std::sin(psi) * std::cos(gam);
+  d[1] = std::sin(psi) * std::sin(gam);
+  d[2] = std::cos(psi);
+  return rm <= 0.5 * M_PI;
+}
+
+// Image position of direction d (inverse of cam_ray); false outside the domain.
+static bool cam_project(int cam, int W, int H, double fovx, double fovy, const double d[3], double* u, double* v) {
+  if (cam == CAM_FULL) {
+    double om = std::atan2(d[0], d[2]);
+    double ph = std::asin(std::max(-1.0, std::min(1.0, d[1])));
+    *u = (om + M_PI) * W / (2.0 * M_PI);
+    *v = (0.5 * M_PI - ph) * H / M_PI;
+    return true;
+  }
+  double fx, fy;
+  cam_focal(cam, W, H, fovx, fovy, &fx, &fy);
+  if (cam == CAM_PINHOLE) {
+    if (!(d[2] > 0)) return false;
+    double mx = d[0] / d[2], my = d[1] / d[2];
+    *u = 0.5 * W + fx * mx;
+    *v = 0.5 * H - fy * my;
+    return *u >= 0 && *u <= W && *v >= 0 && *v <= H;
+  }
+  double psi = std::acos(std::max(-1.0, std::min(1.0, d[2])));
+  double gam = std::atan2(d[1], d[0]);
+  double wx = fovx / M_PI, wy = fovy / M_PI;
+  double weff = std::sqrt(wx * std::cos(gam) * wx * std::cos(gam) + wy * std::sin(gam) * wy * std::sin(gam));
+  double rm = psi / weff;
+  *u = 0.5 * W + fx * rm * std::cos(gam);
+  *v = 0.5 * H - fy * rm * std::sin(gam);
+  return rm <= 0.5 * M_PI;
+}
+
+// z of ring i (1 .. 4N-1) and its colatitude, from the ring definitions.
+static double ring_z(i64 N, i64 i) {
+  if (i < N) return 1.0 - (double)(i * i) / (3.0 * (double)(N * N));
+  if (i > 3 * N) return -(1.0 - (double)((4 * N - i) * (4 * N - i)) / (3.0 * (double)(N * N)));
+  return (double)(2 * N - i) * 2.0 / (3.0 * (double)N);
+}
+static double ring_theta(i64 N, i64 i) {
+  // polar caps: 1 - |z| = 2 sin^2(theta/2), so theta = 2 asin(i / (N sqrt 6)) without cancellation
+  if (i < N) return 2.0 * std::asin((double)i / ((double)N * std::sqrt(6.0)));
+  if (i > 3 * N) return M_PI - 2.0 * std::asin((double)(4 * N - i) / ((double)N * std::sqrt(6.0)));
+  return std::acos(ring_z(N, i));
+}
+// pixels in ring i, RING index of its first pixel, longitude offset (in pixels) of pixel 0's centre
+static void ring_info(i64 N, i64 i, i64* n, i64* first, double* off) {
+  if (i < N) { *n = 4 * i; *first = 2 * i * (i - 1); *off = 0.5; }
+  else if (i > 3 * N) { i64 s = 4 * N - i; *n = 4 * s; *first = 12 * N * N - 2 * s * (s + 1); *off = 0.5; }
+  else { *n = 4 * N; *first = 2 * N * (N - 1) + (i - N) * 4 * N; *off = ((i - N) & 1) ? 0.0 : 0.5; }
+}
+
+// The four RING-scheme pixels and weights of Interp_H at camera-frame direction d.
+static void interp_ring(int order, const double d[3], i64 pix[4], double w[4]) {
+  i64 N = (i64)1 << order;
+  // HEALPix frame (x_h, y_h, z_h) = (d_z, d_x, d_y)
+  double xh = d[2], yh = d[0], zh = d[1];
+  double theta = std::atan2(std::sqrt(xh * xh + yh * yh), zh);
+  double phi = std::atan2(yh, xh);
+  if (phi < 0) phi += 2.0 * M_PI;
+  // ring above: the last ring whose colatitude is <= theta (0 = north pole)
+  i64 lo = 0, hi = 4 * N;  // ring_theta(lo) <= theta < ring_theta(hi), pole rings at 0 and 4N
+  while (hi - lo > 1) {
+    i64 mid = (lo + hi) / 2;
+    if (ring_theta(N, mid) <= theta) lo = mid; else hi = mid;
+  }
+  i64 i1 = lo, i2 = lo + 1;
+  auto pair = [&](i64 i, i64* a, i64* b, double* wb) {
+    i64 n, first; double off;
+    ring_info(N, i, &n, &first, &off);
+    double t = phi / (2.0 * M_PI / (double)n) - off;
+    double j1 = std::floor(t);
+    *wb = t - j1;
+    i64 ja = ((i64)j1 % n + n) % n, jb = (ja + 1) % n;
+    *a = first + ja; *b = first + jb;
+  };
+  if (i1 >= 1 && i2 <= 4 * N - 1) {
+    double t1 = ring_theta(N, i1), t2 = ring_theta(N, i2);
+    double wt = (theta - t1) / (t2 - t1);
+    double f1, f2;
+    pair(i1, &pix[0], &pix[1], &f1);
+    pair(i2, &pix[2], &pix[3], &f2);
+    w[0] = (1 - wt) * (1 - f1); w[1] = (1 - wt) * f1;
+    w[2] = wt * (1 - f2); w[3] = wt * f2;
+    return;
+  }
+  // polar cap: between the pole (mean of the four pixels of the nearest
+  // ring) and that ring
+  i64 ir = (i1 == 0) ? 1 : 4 * N - 1;
+  double tr = ring_theta(N, ir);
+  double wr = (i1 == 0) ? theta / tr : (M_PI - theta) / (M_PI - tr);  // weight of the ring pair
+  i64 n, first; double off;
+  ring_info(N, ir, &n, &first, &off);
+  i64 a, b; double f;
+  pair(ir, &a, &b, &f);
+  for (int k = 0; k < 4; ++k) { pix[k] = first + k; w[k] = 0.25 * (1 - wr); }
+  w[a - first] += wr * (1 - f);
+  w[b - first] += wr * f;
+}
+
+// slot of nested pixel q in the sorted active list, or -1
+static i64 active_slot(i64 n_active, const i64* active, i64 q) {
+  const i64* it = std::lower_bound(active, active + n_active, q);
+  return (it != active + n_active && *it == q) ? (i64)(it - active) : -1;
+}
+
+extern "C" {
+
+void or_cam_rays(int cam, int W, int H, double fovx, double fovy, i64 n, const double* uv, double* d, int* valid) {
+  for (i64 k = 0; k < n; ++k) valid[k] = cam_ray(cam, W, H, fovx, fovy, uv[2 * k], uv[2 * k + 1], d + 3 * k) ? 1 : 0;
+}
+
+void or_cam_project(int cam, int W, int H, double fovx, double fovy, i64 n, const double* d, double* uv, int* valid) {
+  for (i64 k = 0; k < n; ++k)
+    valid[k] = cam_project(cam, W, H, fovx, fovy, d + 3 * k, &uv[2 * k], &uv[2 * k + 1]) ? 1 : 0;
+}
+
+// Interp_H weights: NESTED pixels [n][4] and weights [n][4] at directions [n][3];
+// ring2nest = the NESTED index of every RING index (length 12 N^2).
+void or_interp_weights(int order, const i64* ring2nest, i64 n, const double* d, i64* pix, double* w) {
+  for (i64 k = 0; k < n; ++k) {
+    i64 r[4];
+    interp_ring(order, d + 3 * k, r, w + 4 * k);
+    for (int m = 0; m < 4; ++m) pix[4 * k + m] = ring2nest[r[m]];
+  }
+}
+
+// HEALPix image on the active pixels [3][n_active] -> camera image [3][H][W]
+// and its valid flags [H][W] (Eq. camera_synthesis).
+void or_sphere_to_image(int order, const i64* ring2nest, i64 n_active, const i64* active, const double* img, int cam,
+                        int W, int H, double fovx, double fovy, double* out, int* valid) {
+  const i64 HW = (i64)W * H;
+#pragma omp parallel for schedule(static)
+  for (i64 k = 0; k < HW; ++k) {
+    const int i = (int)(k % W), j = (int)(k / W);
+    double d[3];
+    double acc[3] = {0, 0, 0}, ws = 0;
+    if (cam_ray(cam, W, H, fovx, fovy, i + 0.5, j + 0.5, d)) {
+      i64 r[4]; double w[4];
+      interp_ring(order, d, r, w);
+      for (int m = 0; m < 4; ++m) {
+        i64 s = active_slot(n_active, active, ring2nest[r[m]]);
+        if (s < 0) continue;
+        for (int c = 0; c < 3; ++c) acc[c] += w[m] * img[c * n_active + s];
+        ws += w[m];
+      }
+    }
+    valid[k] = ws > 0 ? 1 : 0;
+    for (int c = 0; c < 3; ++c) out[c * HW + k] = ws > 0 ? acc[c] / ws : 0.0;
+  }
+}
+
+// Camera image [3][H][W] -> samples at the active HEALPix pixels [3][n_active]
+// (supp. Eq. supp_image_to_healpix) and their valid flags.
+void or_image_to_sphere(int order, i64 n_active, const i64* active, const double* img, int cam, int W, int H,
+                        double fovx, double fovy, double* out, int* valid) {
+  const i64 HW = (i64)W * H;
+#pragma omp parallel for schedule(static)
+  for (i64 k = 0; k < n_active; ++k) {
+    double t[3], u = 0.5 * W, v = 0.5 * H;
+    pix_vec(order, active[k], t);
+    bool ok = cam_project(cam, W, H, fovx, fovy, t, &u, &v);
+    valid[k] = ok ? 1 : 0;
+    // bilinear over pixel centres at half-integers
+    double x = u - 0.5, y = v - 0.5;
+    double x0 = std::floor(x), y0 = std::floor(y);
+    double fx = x - x0, fy = y - y0;
+    i64 xs[2] = {(i64)x0, (i64)x0 + 1}, ys[2] = {(i64)y0, (i64)y0 + 1};
+    for (int a = 0; a < 2; ++a) {
+      if (cam == CAM_FULL) xs[a] = ((xs[a] % W) + W) % W;
+      else xs[a] = std::max<i64>(0, std::min<i64>(W - 1, xs[a]));
+      ys[a] = std::max<i64>(0, std::min<i64>(H - 1, ys[a]));
+    }
+    double wgt[4] = {(1 - fx) * (1 - fy), fx * (1 - fy), (1 - fx) * fy, fx * fy};
+    for (int c = 0; c < 3; ++c) {
+      double s = wgt[0] * img[c * HW + ys[0] * W + xs[0]] + wgt[1] * img[c * HW + ys[0] * W + xs[1]] +
+                 wgt[2] * img[c * HW + ys[1] * W + xs[0]] + wgt[3] * img[c * HW + ys[1] * W + xs[1]];
+      out[c * n_active + k] = ok ? s : 0.0;
+    }
+  }
+}
+
+}  // extern "C"
