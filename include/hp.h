@@ -309,6 +309,40 @@ hp_status hp_ssim_backward_saved(const float* img, const float* ref, int64_t n_a
                                  const hp_params* prm, const hp_ssim_params* sp, const void* mask, const void* ws,
                                  size_t ws_bytes, const float* dL_dloss, float* dL_dimg, void* stream);
 
+/* ---- image synthesis (Eq. camera_synthesis; supp. camera models) ----------
+ * Camera images are planar float [3][H][W] (channel, row, column), row 0 at
+ * the top; pixel (i, j) is centred at (u, v) = (i + 1/2, j + 1/2).  The camera
+ * model is view->cam_type with view->fov_x / fov_y (radians): HP_CAM_PINHOLE
+ * (focal lengths W / (2 tan(fov_x / 2)), H / (2 tan(fov_y / 2))),
+ * HP_CAM_FISHEYE (anisotropic equidistant, Eq. fish_weff, f = W / pi, H / pi,
+ * valid inside the inscribed ellipse), HP_CAM_FULL (equirectangular
+ * panorama, longitude 2 pi u / W - pi, latitude pi / 2 - pi v / H).  All
+ * models share one camera frame: +z optical axis, +x right, +y up.
+ *
+ * hp_sphere_to_image: I_C(u, v) = Interp_H(I_H, P_C(u, v)).  img holds the
+ * HEALPix image [3][n_active] in the order of `mask` (hp_mask for the same
+ * view and order; n_active from hp_mask_counts).  Interp_H is bilinear over
+ * the ring structure (two enclosing rings, two enclosing pixels per ring,
+ * linear in longitude and in colatitude; the pole value is the mean of the
+ * nearest ring's four pixels); neighbours outside the mask get weight 0 and
+ * the rest are renormalised.  out [3][H][W] receives the image; valid
+ * [H][W] (nullable) 1 where the pixel lies in the camera's domain and has an
+ * active neighbour, else 0 and out = 0.
+ *
+ * hp_image_to_sphere: samples of the camera image img [3][H][W] at the
+ * centres of the mask's active pixels (supp. Eq. supp_image_to_healpix):
+ * bilinear over image pixel centres, clamped at the border (wrapped in
+ * longitude for the panorama).  out [3][n_active]; valid [n_active]
+ * (nullable) 1 where the centre projects into the camera's domain.
+ *
+ * Both: asynchronous on `stream`; HP_ERR_INVALID_ARG for null pointers,
+ * W or H <= 0, W * H > 2^31, n_active outside [0, 12 * 4^order], or an
+ * invalid view.  All buffers are device memory owned by the caller. */
+hp_status hp_sphere_to_image(const void* mask, const hp_view* view, const hp_params* prm, int64_t n_active,
+                             const float* img, int32_t W, int32_t H, float* out, uint8_t* valid, void* stream);
+hp_status hp_image_to_sphere(const void* mask, const hp_view* view, const hp_params* prm, int64_t n_active,
+                             const float* img, int32_t W, int32_t H, float* out, uint8_t* valid, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

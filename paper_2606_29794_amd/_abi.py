@@ -94,6 +94,8 @@ _PROTOS = {
                                     P_, P_, SZ, P_]),
     "hp_ssim_backward_saved": (I32, [P_, P_, I64, I32, I32, C.POINTER(hp_params), C.POINTER(hp_ssim_params), P_,
                                      P_, SZ, P_, P_, P_]),
+    "hp_sphere_to_image": (I32, [P_, C.POINTER(hp_view), C.POINTER(hp_params), I64, P_, I32, I32, P_, P_, P_]),
+    "hp_image_to_sphere": (I32, [P_, C.POINTER(hp_view), C.POINTER(hp_params), I64, P_, I32, I32, P_, P_, P_]),
 }
 
 # every symbol the header declares

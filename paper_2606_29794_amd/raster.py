@@ -280,6 +280,31 @@ class Rasterizer:
                                  grads.opacity.data_ptr(), grads.sh.data_ptr())
         A.call("hp_preprocess_bwd", C.byref(gs), C.byref(v), C.byref(self.prm), _p(acc), C.byref(gg), _stream())
 
+    # ---- image synthesis (Eq. camera_synthesis; supp. camera models) ----------
+    def sphere_to_image(self, img: torch.Tensor, cam: Camera, W: int, H: int, want_valid: bool = False):
+        """Camera image [3][H][W] from the HEALPix image img [3][n_active] of
+        `cam` (Interp_H over ring neighbours, renormalised over the active
+        set); with want_valid also the uint8 validity map [H][W]."""
+        m = self.mask(cam)
+        out = torch.empty((3, H, W), dtype=torch.float32, device=self.device)
+        valid = torch.empty((H, W), dtype=torch.uint8, device=self.device) if want_valid else None
+        v = cam.view()
+        A.call("hp_sphere_to_image", _p(m.buf), C.byref(v), C.byref(self.prm), m.n_active,
+               _p(img.contiguous()), int(W), int(H), _p(out), _p(valid), _stream())
+        return (out, valid) if want_valid else out
+
+    def image_to_sphere(self, img: torch.Tensor, cam: Camera, want_valid: bool = False):
+        """Samples [3][n_active] of the camera image img [3][H][W] at the
+        centres of cam's active HEALPix pixels (bilinear in the image)."""
+        m = self.mask(cam)
+        H, W = int(img.shape[1]), int(img.shape[2])
+        out = torch.empty((3, max(m.n_active, 1)), dtype=torch.float32, device=self.device)[:, :m.n_active]
+        valid = torch.empty(max(m.n_active, 1), dtype=torch.uint8, device=self.device)[:m.n_active] if want_valid else None
+        v = cam.view()
+        A.call("hp_image_to_sphere", _p(m.buf), C.byref(v), C.byref(self.prm), m.n_active,
+               _p(img.contiguous()), W, H, _p(out), _p(valid), _stream())
+        return (out, valid) if want_valid else out
+
     # ---- loss ----------------------------------------------------------------
     def ssim_loss(self, img, ref, cam: Camera, sp: A.hp_ssim_params | None = None, dL_dloss=None, want_map=False):
         """Returns (out[3] = (mean SSIM, L1, loss), ssim_map or None, dL/dimg or None)."""
