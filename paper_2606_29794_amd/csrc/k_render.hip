@@ -136,6 +136,9 @@ __device__ __forceinline__ void render_fwd_tile(const RenderArgs& A, const Rende
   const uint32_t e = (uint32_t)tid >> 2;  // entry of a chunk this thread stages
   const int q = tid & 3;                  // and which quarter of its record
   const uint32_t* vals = A.vals + j0;
+  const int lane = hp_lane();
+  const WaveCap wc = wave_cap(valid, p);
+  const float rq_cut = sqrtf(A.q_cut);
   // per wave: does any pixel still composite; two sets by chunk parity, so
   // that a wave already writing the next chunk's flag never overwrites one
   // that a slower wave has yet to read
@@ -154,7 +157,9 @@ __device__ __forceinline__ void render_fwd_tile(const RenderArgs& A, const Rende
     const uint32_t cnt = n - base < HP_CHUNK ? n - base : HP_CHUNK;
     // entry i: Mahalanobis bound first (q >= qt), then the exact q and the
     // compositing step; entries go two at a time so that the second one's
-    // loads and bound overlap the first one's work
+    // loads and bound overlap the first one's work.  Entries the wave skips
+    // have qt > q_cut at every pixel of the wave, so skipping them changes
+    // nothing; n_contrib still counts list positions.
     auto step = [&](uint32_t i, const HpOffset& o) {
       if (done || !(o.qt <= A.q_cut)) return;
       const float4 r0 = cur[4 * i], r3 = cur[4 * i + 3];
@@ -172,15 +177,23 @@ __device__ __forceinline__ void render_fwd_tile(const RenderArgs& A, const Rende
         used = base + i + 1;
       }
     };
-    for (uint32_t i = 0; i < cnt; i += 2) {
+    // only entries that can reach a pixel of this wave (lane j tests entry j
+    // against the wave's cap and ellipse bound), front to back
+    uint64_t todo = __ballot((uint32_t)lane < cnt && wave_cap_hit(wc, cur[4 * lane], cur[4 * lane + 3].w) &&
+                             wave_ellipse_hit(wc, cur[4 * lane + 1], cur[4 * lane + 2], rq_cut));
+    while (todo != 0) {
       if (__ballot(!done) == 0) break;
-      const HpOffset oa = hp_offset(p, cur[4 * i + 1], cur[4 * i + 2]);
-      if (i + 1 < cnt) {
-        const HpOffset ob = hp_offset(p, cur[4 * i + 5], cur[4 * i + 6]);
-        step(i, oa);
-        step(i + 1, ob);
+      const uint32_t ia = (uint32_t)__builtin_ctzll(todo);
+      todo &= todo - 1;
+      const HpOffset oa = hp_offset(p, cur[4 * ia + 1], cur[4 * ia + 2]);
+      if (todo != 0) {
+        const uint32_t ib = (uint32_t)__builtin_ctzll(todo);
+        todo &= todo - 1;
+        const HpOffset ob = hp_offset(p, cur[4 * ib + 1], cur[4 * ib + 2]);
+        step(ia, oa);
+        step(ib, ob);
       } else {
-        step(i, oa);
+        step(ia, oa);
       }
     }
     // one barrier both publishes the next chunk and tells whether any pixel
@@ -188,7 +201,7 @@ __device__ __forceinline__ void render_fwd_tile(const RenderArgs& A, const Rende
     s_rec[((c + 1) & 1) * HP_STAGE + tid] = stage;
     const int par = c & 1;
     const uint64_t live = __ballot(!done);  // all lanes vote, before one lane writes
-    if (hp_lane() == 0) s_live[par][tid >> 6] = live != 0;
+    if (lane == 0) s_live[par][tid >> 6] = live != 0;
     __syncthreads();
     if (!(s_live[par][0] | s_live[par][1] | s_live[par][2] | s_live[par][3])) break;
   }
