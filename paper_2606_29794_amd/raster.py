@@ -5,6 +5,7 @@ from __future__ import annotations
 
 import ctypes as C
 import math
+import threading
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -119,6 +120,8 @@ class Rasterizer:
         # cached tables are written on the stream current at creation; a
         # later user on another stream waits for this event first
         self._ready = {}
+        # the caches may be used from several host threads (serving workers)
+        self._lock = threading.RLock()
 
     def _created(self, key):
         ev = torch.cuda.Event()
@@ -133,6 +136,10 @@ class Rasterizer:
 
     # ---- camera-independent tables ------------------------------------
     def grid(self, order: int) -> torch.Tensor:
+        with self._lock:
+            return self._grid(order)
+
+    def _grid(self, order: int) -> torch.Tensor:
         key = (order, self.prm.tile_log2)
         g = self._grids.get(key)
         if g is None:
@@ -148,6 +155,10 @@ class Rasterizer:
         return g
 
     def mask(self, cam: Camera) -> MaskInfo:
+        with self._lock:
+            return self._mask(cam)
+
+    def _mask(self, cam: Camera) -> MaskInfo:
         key = cam.mask_key(self.prm.tile_log2)
         m = self._masks.get(key)
         if m is None:

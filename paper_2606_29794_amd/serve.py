@@ -2,15 +2,16 @@
 
 Requests (camera pose, camera model, field of view, HEALPix order) arrive
 over time.  A dispatcher admits the requests that have arrived whenever a
-stream slot is free and the HBM budget allows, and launches them as one
-batch on that slot's stream:
+stream slot is free and the HBM budget allows, and hands them as one batch
+to that slot's worker thread, which launches it on the slot's stream:
 
   masks of the batch's cameras -> one preprocessing launch that reads every
   Gaussian once for all views -> per request: pair count, read-back of its
   sizes, pairs emitted in per-tile depth order -> ONE render launch whose
   workgroups cover the active tiles of every request in the batch.
 
-Batches on different streams overlap on the device, so requests that arrive
+Batches on different streams overlap on the device, and a worker blocked on
+its batch's read-backs does not hold up the others, so requests that arrive
 while others are on the GPU start as soon as a slot and memory free up.
 Latency is completion time minus arrival time; the forward pass has no
 atomics, so a request renders bit-identically alone or inside a batch.
@@ -20,6 +21,8 @@ from __future__ import annotations
 import collections
 import ctypes as C
 import math
+import queue
+import threading
 import time
 from dataclasses import dataclass, field
 
@@ -97,6 +100,7 @@ class Server:
         self.budget = hbm_budget_bytes
         self._pairs_per_order = {}
         self._mask_cache = collections.OrderedDict()
+        self._cache_lock = threading.Lock()
 
     # ---- memory accounting ---------------------------------------------------
     def _estimate(self, cam: Camera) -> int:
@@ -109,6 +113,10 @@ class Server:
     def _mask_async(self, cam: Camera):
         """Mask buffer for the camera model (cached; computed on the current
         stream, counts read back later together with the pair counts)."""
+        with self._cache_lock:
+            return self._mask_async_locked(cam)
+
+    def _mask_async_locked(self, cam: Camera):
         key = cam.mask_key(self.R.prm.tile_log2)
         cur = torch.cuda.current_stream()
         ent = self._mask_cache.get(key)
@@ -197,50 +205,83 @@ class Server:
         return b
 
     # ---- the request loop -----------------------------------------------------
-    def serve(self, requests: list, realtime: bool = True, keep_outputs: bool = False, poll_s: float = 2e-5):
+    def serve(self, requests: list, realtime: bool = True, keep_outputs: bool = False):
+        """Continuous batching.  One worker thread per stream slot launches
+        its batch (the pair-count read-backs inside block only that worker),
+        waits for the batch's completion event and records the results; the
+        dispatcher admits arrived requests into a batch whenever a slot is
+        free and the HBM budget allows.  Host waits release the interpreter
+        lock, so while one worker waits the others keep the GPU fed."""
         reqs = sorted(requests, key=lambda r: r.arrival)
-        pending = collections.deque()
-        inflight = []
+        n = len(reqs)
+        dev = self.g.mean.device
+        cv = threading.Condition()
         results = {}
-        mem = 0
-        nxt = 0
         free = list(range(len(self.streams)))
+        st = {"mem": 0, "error": None}
+        inbox = [queue.SimpleQueue() for _ in self.streams]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         clock = lambda: time.perf_counter() - t0
-        while len(results) < len(reqs):
-            now = clock()
-            while nxt < len(reqs) and (not realtime or reqs[nxt].arrival <= now):
-                pending.append(reqs[nxt])
-                nxt += 1
-            progressed = False
-            for b in list(inflight):
-                if b.event.query():
-                    t = clock()
-                    for k, r in enumerate(b.reqs):
-                        rgb, T = b.outs[k][0], b.outs[k][1]
-                        # without real-time replay every request is queued at t = 0
-                        results[r.rid] = Result(r.rid, r.arrival if realtime else 0.0, t,
-                                                rgb if keep_outputs else None, T if keep_outputs else None)
-                    inflight.remove(b)
-                    mem -= b.nbytes
-                    free.append(b._slot)
-                    progressed = True
-            if pending and free:
-                batch = select_batch(pending, lambda r: self._estimate(r.camera), mem, self.budget, self.max_batch,
-                                     bool(inflight))
-                if batch:
-                    slot = free.pop(0)
+
+        def worker(slot):
+            torch.cuda.set_device(dev)
+            while True:
+                item = inbox[slot].get()
+                if item is None:
+                    return
+                batch, est = item
+                try:
                     b = self._launch(batch, self.streams[slot], keep_outputs)
-                    b._slot = slot
-                    inflight.append(b)
-                    mem += b.nbytes
-                    progressed = True
-            if not progressed:
-                if inflight and not pending:
-                    time.sleep(poll_s)
-                elif not inflight and not pending and nxt < len(reqs):
-                    time.sleep(max(0.0, min(reqs[nxt].arrival - clock(), 1e-3)))
+                    b.event.synchronize()
+                    t = clock()
+                    with cv:
+                        for k, r in enumerate(batch):
+                            rgb, T = b.outs[k]
+                            # without real-time replay every request is queued at t = 0
+                            results[r.rid] = Result(r.rid, r.arrival if realtime else 0.0, t,
+                                                    rgb if keep_outputs else None, T if keep_outputs else None)
+                        st["mem"] -= est
+                        free.append(slot)
+                        cv.notify_all()
+                except BaseException as e:  # surfaced by the dispatcher
+                    with cv:
+                        st["error"] = e
+                        cv.notify_all()
+                    return
+
+        threads = [threading.Thread(target=worker, args=(k,), daemon=True) for k in range(len(self.streams))]
+        for th in threads:
+            th.start()
+        pending = collections.deque()
+        nxt = 0
+        try:
+            with cv:
+                while len(results) < n and st["error"] is None:
+                    now = clock()
+                    while nxt < n and (not realtime or reqs[nxt].arrival <= now):
+                        pending.append(reqs[nxt])
+                        nxt += 1
+                    if pending and free:
+                        batch = select_batch(pending, lambda r: self._estimate(r.camera), st["mem"], self.budget,
+                                             self.max_batch, len(free) < len(self.streams))
+                        if batch:
+                            est = sum(self._estimate(r.camera) for r in batch)
+                            st["mem"] += est
+                            inbox[free.pop(0)].put((batch, est))
+                            continue
+                    # sleep until a batch completes or the next request arrives
+                    wait = 0.05
+                    if realtime and nxt < n:
+                        wait = min(wait, max(0.0, reqs[nxt].arrival - clock()))
+                    cv.wait(timeout=wait)
+        finally:
+            for q in inbox:
+                q.put(None)
+            for th in threads:
+                th.join()
+        if st["error"] is not None:
+            raise st["error"]
         makespan = max(r.done for r in results.values())
         return ServeStats.of([results[r.rid] for r in reqs], makespan)
 
