@@ -79,18 +79,28 @@ struct BinTables {
   int kt, ls;
 };
 
-// cap test of node `node`: angle(centre, u) <= R + r_s + guard, as a chord
-// comparison: |c - u|^2 <= 4 sin^2((R + theta)/2), always true past pi
+// Cap test: angle(cap centre c, u) <= R + theta as a chord comparison,
+// |c - u|^2 <= (2 sin((R + theta) / 2))^2, always true once R + theta >= pi
+// (cos((R + theta) / 2) <= 0).  (sR, cR) = (sin R/2, cos R/2) of the cap,
+// (sg, cg) = (sin theta/2, cos theta/2) of the Gaussian (theta = r_s + guard).
+// Every binning kernel tests through this one function with explicit FMAs,
+// so the sorted and the unsorted emission take identical decisions.
+__device__ __forceinline__ bool hp_cap_test(float cx, float cy, float cz, float sR, float cR, float ux, float uy,
+                                            float uz, float sg, float cg) {
+  const float dx = cx - ux, dy = cy - uy, dz = cz - uz;
+  const float chord2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+  const float sh2 = fmaf(2.f * sR, cg, (2.f * cR) * sg);  // 2 sin((R + theta) / 2)
+  const float ch = fmaf(cR, cg, -(sR * sg));               // cos((R + theta) / 2)
+  return (ch <= 0.f) | (chord2 <= sh2 * sh2);
+}
+
+// cap test of node `node` (inactive nodes fail)
 __device__ __forceinline__ bool node_pass(const BinTables& T, int64_t node, float ux, float uy, float uz, float sg,
                                           float cg) {
   if (T.node_active && !T.node_active[node]) return false;
   const float4 c = T.cap[node];
   const float2 h = T.sc[node];
-  const float dx = c.x - ux, dy = c.y - uy, dz = c.z - uz;
-  const float chord2 = dx * dx + dy * dy + dz * dz;
-  const float sh = h.x * cg + h.y * sg;  // sin((R + theta) / 2)
-  const float ch = h.y * cg - h.x * sg;  // cos((R + theta) / 2)
-  return (ch <= 0.f) || (chord2 <= 4.f * sh * sh);
+  return hp_cap_test(c.x, c.y, c.z, h.x, h.y, ux, uy, uz, sg, cg);
 }
 
 // Stackless depth-first walk of the implicit quadtree (node (l, i) has
@@ -202,20 +212,47 @@ __global__ __launch_bounds__(256) void k_bin_coarse(int64_t P, const uint32_t* _
       if (!s_act[node]) return false;
       const float4 c = s_cap[node];
       const float2 h = s_sc[node];
-      const float dx = c.x - u[0], dy = c.y - u[1], dz = c.z - u[2];
-      const float sh = h.x * cg + h.y * sg, ch = h.y * cg - h.x * sg;
-      return (ch <= 0.f) || (dx * dx + dy * dy + dz * dz <= 4.f * sh * sh);
+      return hp_cap_test(c.x, c.y, c.z, h.x, h.y, u[0], u[1], u[2], sg, cg);
     }
     return node_pass(T, node, u[0], u[1], u[2], sg, cg);
   };
-  quad_walk(-1, 0, T.ls, pass, [&](int64_t i) {
+  auto emit = [&](int64_t i) {
     if (EMIT && cnt < room) {
       task_g[base + cnt] = gid;
       task_n[base + cnt] = (uint32_t)i;
     }
     if (!EMIT && slots && cnt < (uint32_t)kSlots) slots[(int64_t)cnt * P + k] = (uint32_t)i;
     ++cnt;
-  });
+  };
+  // Passing nodes at level ls in increasing order.  Level 1 (48 nodes) is
+  // tested by every lane in the same order, which keeps the wave converged
+  // where a walk from the 12 faces would diverge at once; below a passing
+  // level-1 node the children are tested in order (level 2) and deeper
+  // levels are walked depth-first.
+  if (T.ls == 0) {
+    for (int f = 0; f < 12; ++f)
+      if (pass(f)) emit(f);
+  } else {
+    uint64_t m1 = 0;
+#pragma unroll 4
+    for (int j = 0; j < 48; ++j) m1 |= pass(12 + j) ? (1ull << j) : 0ull;
+    while (m1 != 0) {
+      const int j = __builtin_ctzll(m1);
+      m1 &= m1 - 1;
+      if (T.ls == 1) {
+        emit(j);
+        continue;
+      }
+      for (int c = 0; c < 4; ++c) {
+        const int64_t i2 = 4 * (int64_t)j + c;
+        if (T.ls == 2) {
+          if (pass(60 + i2)) emit(i2);
+        } else {
+          quad_walk(2, i2, T.ls, pass, emit);
+        }
+      }
+    }
+  }
   if (!EMIT) tcount[k] = cnt;
 }
 
@@ -279,11 +316,8 @@ __global__ __launch_bounds__(256) void k_bin_fine_count(const uint32_t* __restri
 #pragma unroll
       for (int q = 0; q < kFineGroup; ++q) {
         const float cg = sqrtf(fmaxf(0.f, 1.f - sg[q] * sg[q]));
-        const float dx = cap[q].x - ux[q], dy = cap[q].y - uy[q], dz = cap[q].z - uz[q];
-        const float chord2 = dx * dx + dy * dy + dz * dz;
-        const float sh = sc[q].x * cg + sc[q].y * sg[q];  // sin((R + theta) / 2)
-        const float ch = sc[q].y * cg - sc[q].x * sg[q];  // cos((R + theta) / 2)
-        const bool hit = leaf_lane && (act[q] != 0u) && ((ch <= 0.f) || (chord2 <= 4.f * sh * sh));
+        const bool hit = leaf_lane && (act[q] != 0u) &&
+                         hp_cap_test(cap[q].x, cap[q].y, cap[q].z, sc[q].x, sc[q].y, ux[q], uy[q], uz[q], sg[q], cg);
         const uint64_t m = __ballot(hit);
         if (lane == i0 + q) mine = m;
       }
@@ -423,6 +457,7 @@ __global__ __launch_bounds__(256) void k_bin_cols(const uint32_t* __restrict__ c
   const uint32_t waves = gridDim.x * (blockDim.x >> 6);
   for (uint32_t c = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); c < nchunks; c += waves) {
     const ChunkInfo ci = chunk_info(choff, nn, seg, c);
+    const uint32_t ntask = hp_uniform(ci.ntask);
     // this lane's leaf below the chunk's node (lanes past the leaves test a
     // valid leaf and drop the result)
     const int64_t leaf = leaf_off + ((int64_t)ci.node << (2 * depth)) + (lane & (nleaf - 1));
@@ -430,27 +465,36 @@ __global__ __launch_bounds__(256) void k_bin_cols(const uint32_t* __restrict__ c
     const float cx = cp[0], cy = cp[1], cz = cp[2];
     const float2 h = T.sc[leaf];
     const bool act = leaf_lane && T.leaf_active[leaf] != 0;
-    const uint32_t tg = (uint32_t)lane < ci.ntask ? tgid[ci.t0 + lane] : 0u;
-    uint64_t W = 0;
-    for (uint32_t j0 = 0; j0 < ci.ntask; j0 += kFineGroup) {
-      float ux[kFineGroup], uy[kFineGroup], uz[kFineGroup], sg[kFineGroup];
+    const uint32_t tg = (uint32_t)lane < ntask ? tgid[ci.t0 + lane] : 0u;
+    // cos((r_s + guard) / 2) of every task, one per lane, by the same
+    // expression as the rest of the binning (identical decisions)
+    const float sgl = (uint32_t)lane < ntask ? rec[4 * (size_t)tg + 3].w : 0.f;
+    const float cgl = sqrtf(fmaxf(0.f, 1.f - sgl * sgl));
+    // bits of tasks 0..31 and 32..63 are kept apart so that every set is a
+    // 32-bit select-or
+    uint32_t Wh[2] = {0u, 0u};
 #pragma unroll
-      for (int q = 0; q < kFineGroup; ++q) {
-        const uint32_t j = j0 + q < ci.ntask ? j0 + q : ci.ntask - 1;
-        const hp_cfloatp r = rp + 16 * (int64_t)(uint32_t)__builtin_amdgcn_readlane((int)tg, (int)j);
-        ux[q] = r[0]; uy[q] = r[1]; uz[q] = r[2]; sg[q] = r[15];
-      }
+    for (int half = 0; half < 2; ++half) {
+      const uint32_t jend = ntask < 32u * (half + 1) ? ntask : 32u * (half + 1);
+      for (uint32_t j0 = 32u * half; j0 < jend; j0 += kFineGroup) {
+        float ux[kFineGroup], uy[kFineGroup], uz[kFineGroup], sg[kFineGroup], cg[kFineGroup];
 #pragma unroll
-      for (int q = 0; q < kFineGroup; ++q) {
-        const float cg = sqrtf(fmaxf(0.f, 1.f - sg[q] * sg[q]));
-        const float dx = cx - ux[q], dy = cy - uy[q], dz = cz - uz[q];
-        const float chord2 = dx * dx + dy * dy + dz * dz;
-        const float sh = h.x * cg + h.y * sg[q];  // sin((R + theta) / 2)
-        const float chh = h.y * cg - h.x * sg[q]; // cos((R + theta) / 2)
-        const bool hit = act && j0 + q < ci.ntask && ((chh <= 0.f) || (chord2 <= 4.f * sh * sh));
-        W |= hit ? (1ull << ((j0 + q) & 63u)) : 0ull;
+        for (int q = 0; q < kFineGroup; ++q) {
+          // past the chunk's end the last task is read again and its bit dropped
+          const uint32_t j = j0 + q < ntask ? j0 + q : ntask - 1;
+          const hp_cfloatp r = rp + 16 * (int64_t)(uint32_t)__builtin_amdgcn_readlane((int)tg, (int)j);
+          ux[q] = r[0]; uy[q] = r[1]; uz[q] = r[2]; sg[q] = r[15];
+          cg[q] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cgl), (int)j));
+        }
+#pragma unroll
+        for (int q = 0; q < kFineGroup; ++q) {
+          const bool in = hp_cap_test(cx, cy, cz, h.x, h.y, ux[q], uy[q], uz[q], sg[q], cg[q]);
+          const uint32_t bit = j0 + q < jend ? (1u << ((j0 + q) & 31u)) : 0u;
+          Wh[half] |= in ? bit : 0u;
+        }
       }
     }
+    const uint64_t W = act ? ((uint64_t)Wh[1] << 32) | Wh[0] : 0ull;
     if (leaf_lane) {
       wcol[(int64_t)c * 64 + lane] = W;
       const int64_t flat = (int64_t)(c - ci.local) * nleaf + (int64_t)lane * ci.nchn + ci.local;
@@ -550,8 +594,7 @@ extern "C" hp_status hp_bin(int32_t phase, const void* projected, int64_t P, con
     HP_TRY((hpsort::scan_exclusive<uint32_t, uint32_t>(w.tcount, w.toff, P, w.t_total, w.scan_ws, s)));
     // the number of tasks must fit the workspace: read it back once
     uint32_t nt = 0;
-    if (hipMemcpyAsync(&nt, w.t_total, 4, hipMemcpyDeviceToHost, s) != hipSuccess) return HP_ERR_DEVICE;
-    if (hipStreamSynchronize(s) != hipSuccess) return HP_ERR_DEVICE;
+    HP_TRY(hp_read_small(&nt, w.t_total, 4, s));
     if ((int64_t)nt > w.cap_t) return HP_ERR_CAPACITY;
     hipLaunchKernelGGL((k_bin_coarse<true>), dim3(hp_blocks(P, 256)), dim3(256), 0, s, P, w.order, pv.rec, pv.radius,
                        T, prm->bin_guard, w.tcount, w.toff, w.task_g, w.task_n, (uint32_t*)nullptr);
@@ -571,8 +614,7 @@ extern "C" hp_status hp_bin(int32_t phase, const void* projected, int64_t P, con
     // the task count is read on the device; the grid covers the capacity bound
     // only up to the tasks present when the count phase ran on this stream
     uint32_t nt = 0;
-    if (hipMemcpyAsync(&nt, w.t_total, 4, hipMemcpyDeviceToHost, s) != hipSuccess) return HP_ERR_DEVICE;
-    if (hipStreamSynchronize(s) != hipSuccess) return HP_ERR_DEVICE;
+    HP_TRY(hp_read_small(&nt, w.t_total, 4, s));
     if (nt > 0) {
       hipLaunchKernelGGL(k_bin_fine_emit, dim3(fine_grid(nt)), dim3(256), 0, s, (const uint32_t*)w.t_total, w.cap_t,
                          w.task_g, w.task_n, T, (const uint64_t*)w.pmask, (const uint64_t*)w.poff, n_pairs, capacity,
@@ -681,8 +723,7 @@ extern "C" hp_status hp_bin_sorted(int32_t phase, const void* projected, int64_t
     HP_CHECK_LAUNCH();
     HP_TRY((hpsort::scan_exclusive<uint32_t, uint32_t>(w.tcount, w.toff, P, w.t_total, w.scan_ws, s)));
     uint32_t nt = 0;
-    if (hipMemcpyAsync(&nt, w.t_total, 4, hipMemcpyDeviceToHost, s) != hipSuccess) return HP_ERR_DEVICE;
-    if (hipStreamSynchronize(s) != hipSuccess) return HP_ERR_DEVICE;
+    HP_TRY(hp_read_small(&nt, w.t_total, 4, s));
     if ((int64_t)nt > w.cap_t) return HP_ERR_CAPACITY;
     hipLaunchKernelGGL((k_bin_coarse<true>), dim3(hp_blocks(P, 256)), dim3(256), 0, s, P, w.order, pv.rec, pv.radius,
                        T, prm->bin_guard, w.tcount, w.toff, w.task_g, w.task_n, sw.slots);
@@ -716,8 +757,7 @@ extern "C" hp_status hp_bin_sorted(int32_t phase, const void* projected, int64_t
   }
   if ((phase & HP_BIN_EMIT) && P > 0) {
     uint32_t nt = 0;
-    if (hipMemcpyAsync(&nt, w.t_total, 4, hipMemcpyDeviceToHost, s) != hipSuccess) return HP_ERR_DEVICE;
-    if (hipStreamSynchronize(s) != hipSuccess) return HP_ERR_DEVICE;
+    HP_TRY(hp_read_small(&nt, w.t_total, 4, s));
     if ((int64_t)nt > w.cap_t) return HP_ERR_CAPACITY;
     const int64_t nchunk_bound = (int64_t)nt / 64 + sw.nn + 1;
     hipLaunchKernelGGL(k_bin_emit_sorted, dim3(chunk_grid(nchunk_bound)), dim3(256), 0, s, (const uint32_t*)sw.choff,
