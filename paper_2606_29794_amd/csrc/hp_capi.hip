@@ -37,8 +37,7 @@ extern "C" hp_status hp_read_total(const int64_t* dev_value, int64_t* host_value
   if (!dev_value || !host_value) return HP_ERR_INVALID_ARG;
   hipStream_t s = (hipStream_t)stream;
   int64_t v = 0;
-  if (hipMemcpyAsync(&v, dev_value, sizeof(v), hipMemcpyDeviceToHost, s) != hipSuccess) return HP_ERR_DEVICE;
-  if (hipStreamSynchronize(s) != hipSuccess) return HP_ERR_DEVICE;
+  HP_TRY(hp_read_small(&v, dev_value, sizeof(v), s));
   *host_value = v;
   return HP_OK;
 }

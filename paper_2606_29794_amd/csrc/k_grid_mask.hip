@@ -243,10 +243,13 @@ extern "C" hp_status hp_mask_counts(const void* mask, int32_t order, int32_t til
   if (order < 0 || order > HP_MAX_ORDER || tile_log2 < 0 || tile_log2 > 4) return HP_ERR_INVALID_ARG;
   HpMaskView m = hp_mask_view((const char*)mask, hp_geom(order, tile_log2));
   hipStream_t s = (hipStream_t)stream;
-  int64_t a = 0; int32_t t = 0;
-  if (hipMemcpyAsync(&a, m.n_active, 8, hipMemcpyDeviceToHost, s) != hipSuccess) return HP_ERR_DEVICE;
-  if (hipMemcpyAsync(&t, m.n_tiles, 4, hipMemcpyDeviceToHost, s) != hipSuccess) return HP_ERR_DEVICE;
-  if (hipStreamSynchronize(s) != hipSuccess) return HP_ERR_DEVICE;
+  // n_active (int64) and n_tiles (int32) lead the mask's header
+  static_assert(sizeof(int64_t) == 8, "header layout");
+  char head[16];
+  HP_TRY(hp_read_small(head, m.n_active, 16, s));
+  int64_t a; int32_t t;
+  memcpy(&a, head, 8);
+  memcpy(&t, head + ((const char*)m.n_tiles - (const char*)m.n_active), 4);
   *n_active = a; *n_tiles = t;
   return HP_OK;
 }
