@@ -317,20 +317,22 @@ def sorted_tile_lists(order, proj: Projected, g, t, inn, prm=None):
     return lst, np.stack([starts, ends], axis=1).astype(np.int64)
 
 
-def render(scene, cam, proj: Projected, pix, prm=None, qtol=0.0, ttol=0.0):
+def render(scene, cam, proj: Projected, pix, prm=None, qtol=0.0, ttol=0.0, want_depth=False):
     """Brute-force compositing at nested pixels `pix` (Eq. unified_rendering).
-    Returns rgb [3][n], T [n], n_used [n], frag [n]."""
+    Returns rgb [3][n], T [n], n_used [n], frag [n]; with want_depth also the
+    composited inverse radial depth [n] (sum of alpha T / rho, Sec. 3.2)."""
     prm = prm or params()
     S = SceneRef(scene)
     v = view_struct(cam)
     pix = np.ascontiguousarray(pix, np.int64)
     n = pix.size
     rgb = np.zeros((3, n)); T = np.zeros(n); nu = np.zeros(n, np.int64); fr = np.zeros(n)
+    D = np.zeros(n) if want_depth else None
     lib().or_render(C.byref(S.s), C.byref(v), C.byref(prm), _p(proj.valid), _p(proj.omega), _p(proj.phi),
                     _p(proj.rho), _p(np.ascontiguousarray(proj.conic)), _p(proj.rs),
                     _p(np.ascontiguousarray(proj.rgb)), C.c_int64(n), _p(pix), C.c_double(qtol),
-                    C.c_double(ttol), _p(rgb), _p(T), _p(nu), _p(fr))
-    return rgb, T, nu, fr
+                    C.c_double(ttol), _p(rgb), _p(T), _p(nu), _p(fr), _p(D))
+    return (rgb, T, nu, fr, D) if want_depth else (rgb, T, nu, fr)
 
 
 def n_contrib(scene, cam, proj: Projected, lst, ranges, pix, prm=None):
@@ -356,8 +358,10 @@ class Grads:
     sh: np.ndarray
 
 
-def render_bwd(scene, cam, proj: Projected, pix, dLdC, dLdT=None, prm=None) -> Grads:
-    """Exact gradients of L at pixels `pix` given dL/dC [3][n] and dL/dT [n]."""
+def render_bwd(scene, cam, proj: Projected, pix, dLdC, dLdT=None, prm=None, dLdD=None, want_angles=False):
+    """Exact gradients of L at pixels `pix` given dL/dC [3][n], dL/dT [n] and
+    (optionally) dL/d(inverse depth) [n].  With want_angles also returns the
+    per-Gaussian gradient with respect to the centre's (omega, phi) [2][P]."""
     prm = prm or params()
     S = SceneRef(scene)
     v = view_struct(cam)
@@ -367,11 +371,13 @@ def render_bwd(scene, cam, proj: Projected, pix, dLdC, dLdT=None, prm=None) -> G
     g = Grads(np.zeros((3, P)), np.zeros((3, P)), np.zeros((4, P)), np.zeros(P), np.zeros((S.K, 3, P)))
     dLdC = np.ascontiguousarray(dLdC, np.float64)
     dLdT = None if dLdT is None else np.ascontiguousarray(dLdT, np.float64)
+    dLdD = None if dLdD is None else np.ascontiguousarray(dLdD, np.float64)
+    ang = np.zeros((2, P)) if want_angles else None
     lib().or_render_bwd(C.byref(S.s), C.byref(v), C.byref(prm), _p(proj.valid), _p(proj.omega), _p(proj.phi),
                         _p(proj.rho), _p(np.ascontiguousarray(proj.conic)), _p(proj.rs),
                         _p(np.ascontiguousarray(proj.rgb)), C.c_int64(n), _p(pix), _p(dLdC), _p(dLdT),
-                        _p(g.mean), _p(g.scale), _p(g.rot), _p(g.opacity), _p(g.sh))
-    return g
+                        _p(g.mean), _p(g.scale), _p(g.rot), _p(g.opacity), _p(g.sh), _p(dLdD), _p(ang))
+    return (g, ang) if want_angles else g
 
 
 def hssim(order, active, img, ref, sigma=SSIM_SIGMA, c1=SSIM_C1, c2=SSIM_C2, want_map=False, want_grad=False):
@@ -476,3 +482,19 @@ def image_to_sphere(cam: dict, active, img, W: int, H: int) -> tuple:
     lib().or_image_to_sphere(int(cam["order"]), C.c_int64(active.size), _p(active), _p(img), t, int(W), int(H),
                              C.c_double(fx), C.c_double(fy), _p(out), _p(ok))
     return out, ok.astype(bool)
+
+
+def density_stats(rs, visible, g_ang, phi, rs_max, grad_accum, count):
+    """Radian-space statistics for adaptive density control (Sec. 4,
+    density control): for every Gaussian visible in the view, r_s,max <-
+    max(r_s,max, r_s), the norm of the gradient with respect to the centre's
+    displacement along the sphere (east = d omega cos phi, north = d phi),
+    |(dL/domega / cos phi, dL/dphi)|, is added to grad_accum and count is
+    incremented.  Returns new arrays."""
+    rs = np.asarray(rs, np.float64); vis = np.asarray(visible, bool)
+    g = np.asarray(g_ang, np.float64); phi = np.asarray(phi, np.float64)
+    rs_max = np.where(vis, np.maximum(rs_max, rs), rs_max)
+    norm = np.hypot(g[0] / np.cos(phi), g[1])
+    grad_accum = np.where(vis, grad_accum + norm, grad_accum)
+    count = np.where(vis, count + 1, count)
+    return rs_max, grad_accum, count

@@ -624,7 +624,7 @@ static void pixel_candidates(const or_scene& S, const or_params& prm, const int*
 void or_render(const or_scene* S, const or_view* V, const or_params* prm, const int* valid, const double* omega,
                const double* phi, const double* rho, const double* conic, const double* rs, const double* rgbg,
                i64 n, const i64* pix, double qtol_abs, double ttol_rel, double* rgb, double* T, i64* n_used,
-               double* frag) {
+               double* frag, double* invd) {
   i64 P = S->P;
   const double* op_ = nullptr;
   std::vector<double> opac(P);
@@ -636,7 +636,7 @@ void or_render(const or_scene* S, const or_view* V, const or_params* prm, const 
     pix_angles(V->order, pix[k], &om_p, &ph_p, pv);
     std::vector<Cand> c;
     pixel_candidates(*S, *prm, valid, omega, phi, rho, conic, rs, om_p, ph_p, pv, c);
-    double Tr = 1.0, C[3] = {0, 0, 0}, fr = 0;
+    double Tr = 1.0, C[3] = {0, 0, 0}, fr = 0, D = 0;
     i64 used = 0;
     for (const Cand& e : c) {
       double cmax = std::max(std::fabs(rgbg[e.i]), std::max(std::fabs(rgbg[P + e.i]), std::fabs(rgbg[2 * P + e.i])));
@@ -644,6 +644,7 @@ void or_render(const or_scene* S, const or_view* V, const or_params* prm, const 
       if (e.q > prm->q_cut) continue;
       double a = std::min(prm->alpha_max, op_[e.i] * std::exp(-0.5 * e.q));
       for (int ch = 0; ch < 3; ++ch) C[ch] += Tr * a * rgbg[ch * P + e.i];
+      D += Tr * a / rho[e.i];  // inverse radial depth composited like a colour (Sec. 3.2)
       double Tn = Tr * (1 - a);
       ++used;
       if (std::fabs(Tn - prm->eps_T) <= ttol_rel * prm->eps_T) fr += std::max(Tr, prm->eps_T) * 1.0 * cmax;
@@ -652,6 +653,7 @@ void or_render(const or_scene* S, const or_view* V, const or_params* prm, const 
     }
     for (int ch = 0; ch < 3; ++ch) rgb[ch * n + k] = C[ch];
     T[k] = Tr; n_used[k] = used; frag[k] = fr;
+    if (invd) invd[k] = D;
   }
 }
 
@@ -696,12 +698,13 @@ void or_n_contrib(const or_scene* S, const or_view* V, const or_params* prm, con
 void or_render_bwd(const or_scene* S, const or_view* V, const or_params* prm, const int* valid, const double* omega,
                    const double* phi, const double* rho, const double* conic, const double* rs, const double* rgbg,
                    i64 n, const i64* pix, const double* dLdC, const double* dLdT, double* g_mean, double* g_scale,
-                   double* g_rot, double* g_opac, double* g_sh) {
+                   double* g_rot, double* g_opac, double* g_sh, const double* dLdD, double* g_ang) {
   i64 P = S->P;
   int K = (S->sh_degree + 1) * (S->sh_degree + 1);
   // per-Gaussian gradients of the projected quantities
-  // [0] omega [1] phi [2] A [3] B [4] C [5] opacity [6..8] rgb
-  std::vector<double> gy((size_t)P * 9, 0.0);
+  // [0] omega [1] phi [2] A [3] B [4] C [5] opacity [6..8] rgb [9] 1/rho
+  const int NG = 10;
+  std::vector<double> gy((size_t)P * NG, 0.0);
   int nth = or_num_threads();
   std::vector<std::vector<double>> gyt(nth);
 #pragma omp parallel
@@ -711,7 +714,7 @@ void or_render_bwd(const or_scene* S, const or_view* V, const or_params* prm, co
     tid = omp_get_thread_num();
 #endif
     std::vector<double>& acc = gyt[tid];
-    acc.assign((size_t)P * 9, 0.0);
+    acc.assign((size_t)P * NG, 0.0);
 #pragma omp for schedule(dynamic, 16)
     for (i64 k = 0; k < n; ++k) {
       double om_p, ph_p, pv[3];
@@ -733,36 +736,44 @@ void or_render_bwd(const or_scene* S, const or_view* V, const or_params* prm, co
       double Tfin = Tr;
       double gT = dLdT ? dLdT[k] : 0.0;
       double gC[3] = {dLdC[k], dLdC[n + k], dLdC[2 * n + k]};
+      double gD = dLdD ? dLdD[k] : 0.0;
       double behind[3] = {0, 0, 0};  // colour accumulated behind entry j
+      double behindD = 0;            // inverse depth accumulated behind entry j
       for (i64 j = (i64)ids.size() - 1; j >= 0; --j) {
         i64 i = ids[j];
         double a = al[j], Tj = Ts[j];
         double ci[3] = {rgbg[i], rgbg[P + i], rgbg[2 * P + i]};
         double dLda = 0;
         for (int ch = 0; ch < 3; ++ch) {
-          acc[(size_t)i * 9 + 6 + ch] += gC[ch] * a * Tj;
+          acc[(size_t)i * NG + 6 + ch] += gC[ch] * a * Tj;
           dLda += gC[ch] * (Tj * ci[ch] - behind[ch] / (1 - a));
         }
         dLda += gT * (-Tfin / (1 - a));
         for (int ch = 0; ch < 3; ++ch) behind[ch] += Tj * a * ci[ch];
+        if (gD != 0.0) {
+          double ir = 1.0 / rho[i];
+          acc[(size_t)i * NG + 9] += gD * a * Tj;
+          dLda += gD * (Tj * ir - behindD / (1 - a));
+          behindD += Tj * a * ir;
+        }
         if (clampa[j]) continue;
         double o = S->opacity[i];
         double G = std::exp(-0.5 * qs[j]);
-        acc[(size_t)i * 9 + 5] += dLda * G;
+        acc[(size_t)i * NG + 5] += dLda * G;
         double dLdq = dLda * (-0.5 * o * G);
         // q = A dx^2 + 2 B dx dy + C dy^2 ; d = offset(omega_i, phi_i)
         double A = conic[i], B = conic[P + i], Cc = conic[2 * P + i];
         double dx, dy, dg;
         sph_offset<double>(omega[i], phi[i], om_p, ph_p, &dx, &dy, &dg);
-        acc[(size_t)i * 9 + 2] += dLdq * dx * dx;
-        acc[(size_t)i * 9 + 3] += dLdq * 2 * dx * dy;
-        acc[(size_t)i * 9 + 4] += dLdq * dy * dy;
+        acc[(size_t)i * NG + 2] += dLdq * dx * dx;
+        acc[(size_t)i * NG + 3] += dLdq * 2 * dx * dy;
+        acc[(size_t)i * NG + 4] += dLdq * dy * dy;
         for (int dir = 0; dir < 2; ++dir) {
           Dual om(omega[i], dir == 0 ? 1.0 : 0.0), ph(phi[i], dir == 1 ? 1.0 : 0.0);
           Dual ddx, ddy, ddg;
           sph_offset<Dual>(om, ph, om_p, ph_p, &ddx, &ddy, &ddg);
           double dq = 2 * (A * dx + B * dy) * ddx.d + 2 * (B * dx + Cc * dy) * ddy.d;
-          acc[(size_t)i * 9 + dir] += dLdq * dq;
+          acc[(size_t)i * NG + dir] += dLdq * dq;
         }
       }
     }
@@ -773,9 +784,10 @@ void or_render_bwd(const or_scene* S, const or_view* V, const or_params* prm, co
   // chain through the preprocessing
 #pragma omp parallel for schedule(dynamic, 64)
   for (i64 i = 0; i < P; ++i) {
-    const double* g = &gy[(size_t)i * 9];
+    const double* g = &gy[(size_t)i * NG];
+    if (g_ang) { g_ang[i] += g[0]; g_ang[P + i] += g[1]; }
     bool any = false;
-    for (int j = 0; j < 9; ++j) any = any || g[j] != 0.0;
+    for (int j = 0; j < NG; ++j) any = any || g[j] != 0.0;
     if (!any || !valid[i]) continue;
     double mu[3], s[3], q[4];
     std::vector<double> shc;
@@ -801,6 +813,7 @@ void or_render_bwd(const or_scene* S, const or_view* V, const or_params* prm, co
       ProjT<Dual> o = preprocess_one<Dual>(dm, ds, dq, shc.data(), S->sh_degree, *V, *prm);
       double d = g[0] * o.omega.d + g[1] * o.phi.d + g[2] * o.A.d + g[3] * o.B.d + g[4] * o.C.d;
       for (int ch = 0; ch < 3; ++ch) d += g[6 + ch] * o.rgb[ch].d;
+      d += g[9] * (-o.rho.d / (o.rho.v * o.rho.v));  // d(1/rho) = -d rho / rho^2
       if (dir < 3) g_mean[dir * P + i] += d;
       else if (dir < 6) g_scale[(dir - 3) * P + i] += d;
       else g_rot[(dir - 6) * P + i] += d;
