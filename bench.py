@@ -188,7 +188,7 @@ def kernel_breakdown(R, params, cams, targets, torch, A):
         st = FwdState(cam, m, proj, vals, ranges, n, rgb, T, nc, g.P)
         z = torch.zeros_like
         gr = Gaussians(z(g.mean), z(g.scale), z(g.rot), z(g.opacity), z(g.sh))
-        acc = torch.zeros((9, g.P), dtype=torch.float32, device=g.mean.device)
+        acc = torch.zeros((10, g.P), dtype=torch.float32, device=g.mean.device)
         e[6].record()
         R.backward_pixels(st, dimg, None, acc)  # k_render_bwd alone
         e[7].record()

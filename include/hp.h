@@ -222,11 +222,13 @@ hp_status hp_sort(uint32_t* keys, uint32_t* vals, int64_t n_pairs, int32_t n_til
  * C += T alpha c, T *= 1 - alpha, stop once T < eps_T.
  * Outputs over the n_active active pixels (mask order): rgb [3][n_active],
  * T [n_active] (final transmittance; background is left to the caller),
- * n_contrib [n_active] (list entries consumed, skipped ones included), and
- * n_used [n_active] (nullable: Gaussians actually composited). */
+ * n_contrib [n_active] (list entries consumed, skipped ones included),
+ * n_used [n_active] (nullable: Gaussians actually composited), and
+ * inv_depth [n_active] (nullable: the inverse radial depth 1/r composited
+ * like a colour, sum_i T_i alpha_i / r_i, for depth supervision, Sec. 3.2). */
 hp_status hp_render_fwd(const void* projected, int64_t P, const uint32_t* vals, const uint32_t* tile_ranges,
                         int32_t n_tiles, const hp_view* view, const hp_params* prm, const void* mask, int64_t n_active,
-                        float* rgb, float* T, int32_t* n_contrib, int32_t* n_used, void* stream);
+                        float* rgb, float* T, int32_t* n_contrib, int32_t* n_used, float* inv_depth, void* stream);
 
 /* Serving form of hp_render_fwd: up to 16 independent renders (different
  * cameras, orders and scenes) in ONE launch whose workgroups cover the union
@@ -253,29 +255,48 @@ hp_status hp_render_fwd_batch(int32_t n_req, const hp_render_req* reqs, const hp
  * of alpha through q to the conic and the Gaussian direction, then per
  * Gaussian through Sigma_arc, S_phi, J, W to scale and rotation and through
  * t = W mu + b and the SH view direction to the mean; SH coefficients and
- * opacities directly.  dL_drgb [3][n_active], dL_dT [n_active] (nullable).
+ * opacities directly.  dL_drgb [3][n_active], dL_dT [n_active] (nullable),
+ * dL_dinv_depth [n_active] (nullable: upstream gradient of hp_render_fwd's
+ * inv_depth; it reaches the means also through d(1/r)/dt = -t / r^3).
  * Gradients are accumulated into `grad`.  ws: hp_render_bwd_workspace_bytes(P). */
 size_t hp_render_bwd_workspace_bytes(int64_t P);
 hp_status hp_render_bwd(const hp_gaussians* g, const void* projected, const uint32_t* vals,
                         const uint32_t* tile_ranges, int32_t n_tiles, const hp_view* view, const hp_params* prm,
                         const void* mask, int64_t n_active, const float* T, const int32_t* n_contrib,
-                        const float* dL_drgb, const float* dL_dT, hp_gaussians_grad* grad, void* ws, size_t ws_bytes,
-                        void* stream);
+                        const float* dL_drgb, const float* dL_dT, const float* dL_dinv_depth, hp_gaussians_grad* grad,
+                        void* ws, size_t ws_bytes, void* stream);
 /* The two halves of hp_render_bwd (which zeroes its workspace, then runs
  * both).  hp_render_bwd_pixels is the pixel pass: per Gaussian, dL with
  * respect to its colour (3), opacity (1), conic (A, B, C) and the longitude
- * and latitude of its centre (omega, phi), ACCUMULATED into acc
- * [9][P] (float, device, laid out value-major: acc[m * P + i]).  It needs
- * no Gaussian parameters, only the projected records.  hp_preprocess_bwd
+ * and latitude of its centre (omega, phi), and (only when dL_dinv_depth is
+ * given) its inverse radial depth 1/r, ACCUMULATED into acc [10][P] (float,
+ * device, laid out value-major: acc[m * P + i]; row 9 is left untouched
+ * without a depth gradient, so the caller zeroes it).  It needs no Gaussian
+ * parameters, only the projected records.  hp_preprocess_bwd
  * carries such accumulators back through Sec. 3.2's chain (conic -> Sigma_arc
  * -> scale, rotation and centre; colour -> SH and view direction) into
  * `grad` (accumulated).  Errors as hp_render_bwd. */
 hp_status hp_render_bwd_pixels(const void* projected, int64_t P, const uint32_t* vals, const uint32_t* tile_ranges,
                                int32_t n_tiles, const hp_view* view, const hp_params* prm, const void* mask,
                                int64_t n_active, const float* T, const int32_t* n_contrib, const float* dL_drgb,
-                               const float* dL_dT, float* acc, void* stream);
+                               const float* dL_dT, const float* dL_dinv_depth, float* acc, void* stream);
 hp_status hp_preprocess_bwd(const hp_gaussians* g, const hp_view* view, const hp_params* prm, const float* acc,
                             hp_gaussians_grad* grad, void* stream);
+
+/* ---- radian-space statistics for adaptive density control -----------------
+ * (Sec. 4.2: r_s,max tracked across iterations, thresholds in radians.)
+ * hp_mark_visible sets visible[i] = 1 for every Gaussian id in
+ * vals[0 .. n_pairs) (the view's tile lists; visible [P] uint8 is zeroed by
+ * the caller).  hp_density_stats then, for every Gaussian with visible[i],
+ * sets rs_max[i] = max(rs_max[i], r_s,i), adds to grad_accum[i] the norm of
+ * the loss gradient with respect to a displacement of its centre along the
+ * sphere, |(dL/domega / cos phi, dL/dphi)| (rows 7 and 8 of the pixel pass's
+ * acc [10][P], cos phi from the projected record), and increments count[i].
+ * rs_max, grad_accum [P] float and count [P] int32 are device arrays owned by
+ * the caller and updated in place. */
+hp_status hp_mark_visible(const uint32_t* vals, int64_t n_pairs, int64_t P, uint8_t* visible, void* stream);
+hp_status hp_density_stats(const void* projected, int64_t P, const float* acc, const uint8_t* visible, float* rs_max,
+                           float* grad_accum, int32_t* count, void* stream);
 
 /* ---- HEALPix-SSIM and the training loss (Sec. 4.1) ------------------------
  * Per active pixel and channel, Gaussian-weighted 11x11 statistics over

@@ -485,8 +485,8 @@ def image_to_sphere(cam: dict, active, img, W: int, H: int) -> tuple:
 
 
 def density_stats(rs, visible, g_ang, phi, rs_max, grad_accum, count):
-    """Radian-space statistics for adaptive density control (Sec. 4,
-    density control): for every Gaussian visible in the view, r_s,max <-
+    """Radian-space statistics for adaptive density control (Sec. 4.2): for
+    every Gaussian visible in the view (in at least one tile), r_s,max <-
     max(r_s,max, r_s), the norm of the gradient with respect to the centre's
     displacement along the sphere (east = d omega cos phi, north = d phi),
     |(dL/domega / cos phi, dL/dphi)|, is added to grad_accum and count is

@@ -212,10 +212,11 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(int64_t P, const float* 
                                                         float* __restrict__ gsh) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= P) return;
-  float gy[9];
+  // [0..8] as the pixel pass writes them, [9] dL/d(1/r) of the depth channel
+  float gy[10];
   bool any = false;
 #pragma unroll
-  for (int m = 0; m < 9; ++m) {
+  for (int m = 0; m < 10; ++m) {
     gy[m] = acc[m * P + i];
     any = any || gy[m] != 0.f;
   }
@@ -298,6 +299,8 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(int64_t P, const float* 
 #pragma unroll
     for (int k = 0; k < 3; ++k) gE[a][k] = gEW[a][0] * V.W[3 * k] + gEW[a][1] * V.W[3 * k + 1] + gEW[a][2] * V.W[3 * k + 2];
   // frame motion: de_w/dw = (-so, 0, -co), de_p/dw = -sin(phi) e_w, de_p/dp = -u
+  // inverse depth: d(1/r)/dr = -1/r^2, so d(1/r)/dt = -t / r^3 (Sec. 3.2)
+  gr -= gy[9] * ir * ir;
   float gw = gy[7] + gE[0][0] * (-so) + gE[0][2] * (-co) - sp * (gE[1][0] * co + gE[1][2] * (-so));
   float gp = gy[8] - (gE[1][0] * ux + gE[1][1] * uy + gE[1][2] * uz);
   // (omega, phi, r) -> t:  d omega/dt = e_w / (r cos phi), d phi/dt = e_p / r, dr/dt = u

@@ -16,6 +16,7 @@ struct RenderArgs {
   const int32_t* tile_count;
   const int32_t* active_pix;
   const float4* rec;
+  const float* depth;  // radial depth r of every Gaussian (inverse-depth channel)
   const uint32_t* vals;
   const uint32_t* ranges;
   float eps_T, alpha_max, q_cut;
@@ -46,6 +47,7 @@ static RenderArgs make_args(const HpGeom& g, const HpMaskView& mv, const HpProjV
   A.tile_count = mv.tile_count;
   A.active_pix = mv.active_pix;
   A.rec = pv.rec;
+  A.depth = pv.depth;
   A.vals = vals;
   A.ranges = ranges;
   A.eps_T = prm->eps_T;
@@ -60,6 +62,7 @@ struct RenderOut {
   float* T;
   int32_t* ncon;
   int32_t* nused;  // nullable: Gaussians composited per pixel
+  float* invd;     // nullable: composited inverse radial depth (Sec. 3.2 depth supervision)
 };
 
 // A tile's list is walked in chunks of HP_CHUNK entries staged in LDS: each of
@@ -121,14 +124,18 @@ __device__ __forceinline__ bool wave_ellipse_hit(const WaveCap& w, float4 r1, fl
   return o.qt <= lim * lim * 1.0001f + 1e-6f;
 }
 
-__device__ __forceinline__ void render_fwd_tile(const RenderArgs& A, const RenderOut& O, int ct, float4* s_rec) {
+// DEPTH: also composite 1/r like a colour channel; the entries' 1/r ride
+// along with their records through LDS.
+template <bool DEPTH>
+__device__ __forceinline__ void render_fwd_tile(const RenderArgs& A, const RenderOut& O, int ct, float4* s_rec,
+                                                float* s_invd) {
   bool valid;
   int64_t slot;
   float p[3];
   pixel_of_lane(A, ct, &valid, &slot, p);
   const uint32_t j0 = hp_uniform(A.ranges[2 * ct]), j1 = hp_uniform(A.ranges[2 * ct + 1]);
   const uint32_t n = j1 - j0;
-  float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
+  float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f, Dinv = 0.f;
   bool done = !valid;
   uint32_t used = n;
   int nu = 0;
@@ -143,7 +150,11 @@ __device__ __forceinline__ void render_fwd_tile(const RenderArgs& A, const Rende
   // that a wave already writing the next chunk's flag never overwrites one
   // that a slower wave has yet to read
   __shared__ int s_live[2][4];
-  s_rec[tid] = e < n ? stage_load(A.rec, vals[e], q) : make_float4(0.f, 0.f, 0.f, 0.f);
+  {
+    const uint32_t g0 = e < n ? vals[e] : 0u;
+    s_rec[tid] = e < n ? stage_load(A.rec, g0, q) : make_float4(0.f, 0.f, 0.f, 0.f);
+    if (DEPTH && q == 0) s_invd[e] = e < n ? 1.f / A.depth[g0] : 0.f;
+  }
   uint32_t gnext = HP_CHUNK + e < n ? vals[HP_CHUNK + e] : 0u;
   __syncthreads();
   const uint32_t nch = (n + HP_CHUNK - 1) / HP_CHUNK;
@@ -151,9 +162,14 @@ __device__ __forceinline__ void render_fwd_tile(const RenderArgs& A, const Rende
     const uint32_t base = c * HP_CHUNK;
     float4 stage = make_float4(0.f, 0.f, 0.f, 0.f);
     const uint32_t gstage = gnext;
-    if (base + HP_CHUNK + e < n) stage = stage_load(A.rec, gstage, q);
+    float dstage = 1.f;
+    if (base + HP_CHUNK + e < n) {
+      stage = stage_load(A.rec, gstage, q);
+      if (DEPTH && q == 0) dstage = A.depth[gstage];
+    }
     gnext = base + 2 * HP_CHUNK + e < n ? vals[base + 2 * HP_CHUNK + e] : 0u;
     const float4* cur = s_rec + (c & 1) * HP_STAGE;
+    const float* curd = s_invd + (c & 1) * HP_CHUNK;
     const uint32_t cnt = n - base < HP_CHUNK ? n - base : HP_CHUNK;
     // entry i: Mahalanobis bound first (q >= qt), then the exact q and the
     // compositing step; entries go two at a time so that the second one's
@@ -170,6 +186,7 @@ __device__ __forceinline__ void render_fwd_tile(const RenderArgs& A, const Rende
       C0 += w * r3.x;
       C1 += w * r3.y;
       C2 += w * r3.z;
+      if (DEPTH) Dinv += w * curd[i];
       T -= w;
       ++nu;
       if (T < A.eps_T) {
@@ -199,6 +216,7 @@ __device__ __forceinline__ void render_fwd_tile(const RenderArgs& A, const Rende
     // one barrier both publishes the next chunk and tells whether any pixel
     // of the block still composites
     s_rec[((c + 1) & 1) * HP_STAGE + tid] = stage;
+    if (DEPTH && q == 0) s_invd[((c + 1) & 1) * HP_CHUNK + e] = 1.f / dstage;
     const int par = c & 1;
     const uint64_t live = __ballot(!done);  // all lanes vote, before one lane writes
     if (lane == 0) s_live[par][tid >> 6] = live != 0;
@@ -212,12 +230,15 @@ __device__ __forceinline__ void render_fwd_tile(const RenderArgs& A, const Rende
     O.T[slot] = T;
     O.ncon[slot] = (int32_t)used;
     if (O.nused) O.nused[slot] = nu;
+    if (DEPTH) O.invd[slot] = Dinv;
   }
 }
 
+template <bool DEPTH>
 __global__ __launch_bounds__(256) void k_render_fwd(RenderArgs A, RenderOut O) {
   __shared__ float4 s_rec[2 * HP_STAGE];
-  render_fwd_tile(A, O, hp_xcd_tile(blockIdx.x, gridDim.x), s_rec);
+  __shared__ float s_invd[2 * HP_CHUNK];
+  render_fwd_tile<DEPTH>(A, O, hp_xcd_tile(blockIdx.x, gridDim.x), s_rec, s_invd);
 }
 
 // Several requests in one launch: block b renders tile b - first[r] of
@@ -235,28 +256,36 @@ __global__ __launch_bounds__(256) void k_render_fwd_batch(RenderBatch B) {
   const int b = hp_xcd_tile(blockIdx.x, gridDim.x);
   int r = 0;
   while (r + 1 < B.n && b >= B.first[r + 1]) ++r;
-  render_fwd_tile(B.A[r], B.O[r], b - B.first[r], s_rec);
+  render_fwd_tile<false>(B.A[r], B.O[r], b - B.first[r], s_rec, nullptr);
 }
 
 // Per-Gaussian gradient accumulators written by the pixel pass:
-// [0..2] colour, [3] opacity, [4..6] conic (A, B, C), [7] omega, [8] phi.
-#define HP_NACC 9
+// [0..2] colour, [3] opacity, [4..6] conic (A, B, C), [7] omega, [8] phi,
+// [9] inverse radial depth 1/r (written only with a depth gradient).
+#define HP_NACC 10
 // constant factor of each value as the per-pixel terms leave it out
-__constant__ float kFlushScale[HP_NACC] = {1.f, 1.f, 1.f, 1.f, -0.5f, -1.f, -0.5f, -1.f, -1.f};
+__constant__ float kFlushScale[HP_NACC] = {1.f, 1.f, 1.f, 1.f, -0.5f, -1.f, -0.5f, -1.f, -1.f, 1.f};
 template <bool B>
 struct HpBool {
   static constexpr bool value = B;
 };
 
+// DEPTH: the upstream gradient also holds dL/d(inverse depth) per pixel; the
+// inverse depth enters the compositing like a colour channel, and the tenth
+// accumulator receives dL/d(1/r) per Gaussian.
+template <bool DEPTH>
 __global__ __launch_bounds__(256) void k_render_bwd(RenderArgs A, int64_t P, const float* __restrict__ Tfin,
                                                     const int32_t* __restrict__ ncon, const float* __restrict__ gC,
-                                                    const float* __restrict__ gTfin, float* __restrict__ acc) {
+                                                    const float* __restrict__ gTfin, const float* __restrict__ gDinv,
+                                                    float* __restrict__ acc) {
+  constexpr int NA = DEPTH ? 10 : 9;  // values reduced per (wave, entry)
   __shared__ float4 s_rec[2 * HP_STAGE];
   __shared__ int s_nc[4];
   // per chunk entry: the block's gradient totals (the 4 waves' sums), sent to
   // memory with one atomic per non-zero value once the chunk is done
-  __shared__ float s_acc[HP_CHUNK * HP_NACC];
+  __shared__ float s_acc[HP_CHUNK * NA];
   __shared__ uint32_t s_gid[2][HP_CHUNK];  // Gaussian id of every staged entry
+  __shared__ float s_invd[2][HP_CHUNK];    // 1/r of every staged entry (DEPTH)
   const int ct = hp_xcd_tile(blockIdx.x, gridDim.x);
   bool valid;
   int64_t slot;
@@ -264,7 +293,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(RenderArgs A, int64_t P, con
   pixel_of_lane(A, ct, &valid, &slot, p);
   const uint32_t j0 = hp_uniform(A.ranges[2 * ct]);
   int nc = 0;
-  float Tf = 1.f, g0 = 0.f, g1 = 0.f, g2 = 0.f, gT = 0.f;
+  float Tf = 1.f, g0 = 0.f, g1 = 0.f, g2 = 0.f, gT = 0.f, gD = 0.f;
   if (valid) {
     nc = ncon[slot];
     Tf = Tfin[slot];
@@ -272,6 +301,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(RenderArgs A, int64_t P, con
     g1 = gC[A.n_active + slot];
     g2 = gC[2 * A.n_active + slot];
     gT = gTfin ? gTfin[slot] : 0.f;
+    if (DEPTH) gD = gDinv[slot];
   }
   // trip counts: the largest n_contrib of the wave and of the block
   int ncmax = nc;
@@ -282,11 +312,12 @@ __global__ __launch_bounds__(256) void k_render_bwd(RenderArgs A, int64_t P, con
   const WaveCap wc = wave_cap(valid, p);
   const float rq_cut = sqrtf(A.q_cut);
   if (lane == 0) s_nc[tid >> 6] = ncmax;
-  for (int t = tid; t < HP_CHUNK * HP_NACC; t += 256) s_acc[t] = 0.f;
+  for (int t = tid; t < HP_CHUNK * NA; t += 256) s_acc[t] = 0.f;
   __syncthreads();
   const int nb = max(max(s_nc[0], s_nc[1]), max(s_nc[2], s_nc[3]));
   float Tcur = Tf;  // transmittance after the current entry
   // g . (colour composited behind the current entry) + dL/dT_final * T_final
+  // (with DEPTH the inverse depth counts as a fourth colour channel)
   float SgT = gT * Tf;
   const float amax = A.alpha_max;
   // entries nb-1 .. 0 in chunks of HP_CHUNK aligned at j0, last chunk first;
@@ -301,15 +332,21 @@ __global__ __launch_bounds__(256) void k_render_bwd(RenderArgs A, int64_t P, con
     const uint32_t g = k0 < (uint32_t)nb ? vals[k0] : 0u;
     s_rec[tid] = k0 < (uint32_t)nb ? stage_load(A.rec, g, qs) : make_float4(0.f, 0.f, 0.f, 0.f);
     if (qs == 3) s_gid[0][e] = g;
+    if (DEPTH && qs == 2) s_invd[0][e] = k0 < (uint32_t)nb ? 1.f / A.depth[g] : 0.f;
     if (ctop >= 1) gnext = vals[(uint32_t)(ctop - 1) * HP_CHUNK + e];
   }
   __syncthreads();
   for (int ch = ctop; ch >= 0; --ch) {
     float4 stage = make_float4(0.f, 0.f, 0.f, 0.f);
     const uint32_t gstage = gnext;
-    if (ch >= 1) stage = stage_load(A.rec, gstage, qs);  // chunk ch - 1 is full
+    float dstage = 1.f;
+    if (ch >= 1) {
+      stage = stage_load(A.rec, gstage, qs);  // chunk ch - 1 is full
+      if (DEPTH && qs == 2) dstage = A.depth[gstage];
+    }
     if (ch >= 2) gnext = vals[(uint32_t)(ch - 2) * HP_CHUNK + e];
     const float4* cur = s_rec + ((ctop - ch) & 1) * HP_STAGE;
+    const float* curd = s_invd[(ctop - ch) & 1];
     const int kbase = ch * HP_CHUNK;
     const int ktop = min(kbase + HP_CHUNK, ncmax) - 1;  // this wave's last entry in the chunk
     const int nrel = nc - kbase;                          // entries of the chunk this pixel composited
@@ -363,12 +400,13 @@ __global__ __launch_bounds__(256) void k_render_bwd(RenderArgs A, int64_t P, con
         const float iom = __builtin_amdgcn_rcpf(1.f - alpha);
         const float Tb = Tcur * iom;  // transmittance before this entry
         const float wgt = hit ? alpha * Tb : 0.f;
-        float v[HP_NACC];
+        float v[NA];
         v[0] = g0 * wgt;
         v[1] = g1 * wgt;
         v[2] = g2 * wgt;
         // dL/dalpha = Tb (g . rgb) - (g . S + dL/dT_final T_final) / (1 - alpha)
-        const float gr = g0 * r3.x + g1 * r3.y + g2 * r3.z;
+        float gr = g0 * r3.x + g1 * r3.y + g2 * r3.z;
+        if (DEPTH) gr += gD * curd[i];
         const float dLda = (hit && lin) ? Tb * gr - iom * SgT : 0.f;
         SgT += wgt * gr;
         Tcur = hit ? Tb : Tcur;
@@ -400,11 +438,19 @@ __global__ __launch_bounds__(256) void k_render_bwd(RenderArgs A, int64_t P, con
         }
         v[7] = m * (sph * (fa * b - fb * a) + cph * t2);  // dL/domega = -v7
         v[8] = m * t3;                                     // dL/dphi = -v8
+        if constexpr (DEPTH) v[9] = gD * wgt;              // dL/d(1/r)
         // values 0..7: lane 8m holds the wave's total of value m; value 8: every lane
         const float t8 = hp_wave_totals8_spread(v);
         const float t9 = hp_wave_total_all(v[8]);
-        if ((lane & 7) == 0 || lane == 1)
-          atomicAdd(&s_acc[i * HP_NACC + (lane == 1 ? 8 : lane >> 3)], lane == 1 ? t9 : t8);
+        if constexpr (DEPTH) {
+          const float t10 = hp_wave_total_all(v[9]);
+          if ((lane & 7) == 0 || lane == 1 || lane == 2)
+            atomicAdd(&s_acc[i * NA + (lane == 1 ? 8 : (lane == 2 ? 9 : lane >> 3))],
+                      lane == 1 ? t9 : (lane == 2 ? t10 : t8));
+        } else {
+          if ((lane & 7) == 0 || lane == 1)
+            atomicAdd(&s_acc[i * NA + (lane == 1 ? 8 : lane >> 3)], lane == 1 ? t9 : t8);
+        }
       };
       if (((__builtin_amdgcn_ballot_w64(!(c > 0.f)) | __builtin_amdgcn_ballot_w64(!(s2 < HP_K2_S2MAX))) & m1) == 0)
         composite(HpBool<false>{});
@@ -413,11 +459,12 @@ __global__ __launch_bounds__(256) void k_render_bwd(RenderArgs A, int64_t P, con
     }
     s_rec[((ctop - ch + 1) & 1) * HP_STAGE + tid] = stage;
     if (qs == 3) s_gid[(ctop - ch + 1) & 1][e] = gstage;
+    if (DEPTH && qs == 2) s_invd[(ctop - ch + 1) & 1][e] = 1.f / dstage;
     __syncthreads();  // the chunk's totals are complete and the next chunk is staged
-    for (int t = tid; t < HP_CHUNK * HP_NACC; t += 256) {
+    for (int t = tid; t < HP_CHUNK * NA; t += 256) {
       const float x = s_acc[t];
       if (x != 0.f) {
-        const int i = t / HP_NACC, m = t - i * HP_NACC;
+        const int i = t / NA, m = t - i * NA;
         const uint32_t g = s_gid[(ctop - ch) & 1][i];
         unsafeAtomicAdd(&acc[(int64_t)m * P + g], x * kFlushScale[m]);
         s_acc[t] = 0.f;
@@ -430,7 +477,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(RenderArgs A, int64_t P, con
 extern "C" hp_status hp_render_fwd(const void* projected, int64_t P, const uint32_t* vals, const uint32_t* tile_ranges,
                                    int32_t n_tiles, const hp_view* view, const hp_params* prm, const void* mask,
                                    int64_t n_active, float* rgb, float* T, int32_t* n_contrib, int32_t* n_used,
-                                   void* stream) {
+                                   float* inv_depth, void* stream) {
   HP_TRY(hp_check_view(view, prm));
   if (P < 0 || n_tiles < 0 || n_active < 0) return HP_ERR_INVALID_ARG;
   if (!projected || !mask || (n_tiles > 0 && !tile_ranges)) return HP_ERR_INVALID_ARG;
@@ -440,8 +487,11 @@ extern "C" hp_status hp_render_fwd(const void* projected, int64_t P, const uint3
   if (n_tiles > g.ntile || n_active > g.npix) return HP_ERR_INVALID_ARG;
   RenderArgs A = make_args(g, hp_mask_view((const char*)mask, g), hp_proj_view((const char*)projected, P), vals,
                            tile_ranges, prm, n_active);
-  RenderOut O{rgb, T, n_contrib, n_used};
-  hipLaunchKernelGGL(k_render_fwd, dim3((unsigned)n_tiles), dim3(256), 0, (hipStream_t)stream, A, O);
+  RenderOut O{rgb, T, n_contrib, n_used, inv_depth};
+  if (inv_depth)
+    hipLaunchKernelGGL(k_render_fwd<true>, dim3((unsigned)n_tiles), dim3(256), 0, (hipStream_t)stream, A, O);
+  else
+    hipLaunchKernelGGL(k_render_fwd<false>, dim3((unsigned)n_tiles), dim3(256), 0, (hipStream_t)stream, A, O);
   HP_CHECK_LAUNCH();
   return HP_OK;
 }
@@ -464,7 +514,7 @@ extern "C" hp_status hp_render_fwd_batch(int32_t n_req, const hp_render_req* req
     B.first[r] = (int)total;
     B.A[r] = make_args(g, hp_mask_view((const char*)q.mask, g), hp_proj_view((const char*)q.projected, q.P), q.vals,
                        q.tile_ranges, prm, q.n_active);
-    B.O[r] = RenderOut{q.rgb, q.T, q.n_contrib, nullptr};
+    B.O[r] = RenderOut{q.rgb, q.T, q.n_contrib, nullptr, nullptr};
     total += q.n_tiles;
   }
   B.first[n_req] = (int)total;
@@ -490,7 +540,8 @@ extern "C" hp_status hp_render_bwd(const hp_gaussians* gs, const void* projected
                                    const uint32_t* tile_ranges, int32_t n_tiles, const hp_view* view,
                                    const hp_params* prm, const void* mask, int64_t n_active, const float* T,
                                    const int32_t* n_contrib, const float* dL_drgb, const float* dL_dT,
-                                   hp_gaussians_grad* grad, void* ws, size_t ws_bytes, void* stream) {
+                                   const float* dL_dinv_depth, hp_gaussians_grad* grad, void* ws, size_t ws_bytes,
+                                   void* stream) {
   HP_TRY(hp_check_gaussians(gs));
   HP_TRY(hp_check_view(view, prm));
   if (!projected || !mask || !grad || n_tiles < 0 || n_active < 0) return HP_ERR_INVALID_ARG;
@@ -506,7 +557,7 @@ extern "C" hp_status hp_render_bwd(const hp_gaussians* gs, const void* projected
   hipLaunchKernelGGL(k_zero_f32, dim3(hp_blocks(gs->P * HP_NACC, 256)), dim3(256), 0, s, acc, gs->P * HP_NACC);
   HP_CHECK_LAUNCH();
   HP_TRY(hp_render_bwd_pixels(projected, gs->P, vals, tile_ranges, n_tiles, view, prm, mask, n_active, T, n_contrib,
-                              dL_drgb, dL_dT, acc, stream));
+                              dL_drgb, dL_dT, dL_dinv_depth, acc, stream));
   return hp_preprocess_bwd_launch(gs, view, prm, acc, grad, s);
 }
 
@@ -514,7 +565,7 @@ extern "C" hp_status hp_render_bwd_pixels(const void* projected, int64_t P, cons
                                           const uint32_t* tile_ranges, int32_t n_tiles, const hp_view* view,
                                           const hp_params* prm, const void* mask, int64_t n_active, const float* T,
                                           const int32_t* n_contrib, const float* dL_drgb, const float* dL_dT,
-                                          float* acc, void* stream) {
+                                          const float* dL_dinv_depth, float* acc, void* stream) {
   HP_TRY(hp_check_view(view, prm));
   if (P < 0 || !projected || !mask || n_tiles < 0 || n_active < 0) return HP_ERR_INVALID_ARG;
   if (P > 0 && !acc) return HP_ERR_INVALID_ARG;
@@ -524,8 +575,12 @@ extern "C" hp_status hp_render_bwd_pixels(const void* projected, int64_t P, cons
   if (P == 0 || n_tiles == 0 || n_active == 0) return HP_OK;
   RenderArgs A = make_args(g, hp_mask_view((const char*)mask, g), hp_proj_view((const char*)projected, P), vals,
                            tile_ranges, prm, n_active);
-  hipLaunchKernelGGL(k_render_bwd, dim3((unsigned)n_tiles), dim3(256), 0, (hipStream_t)stream, A, P, T, n_contrib,
-                     dL_drgb, dL_dT, acc);
+  if (dL_dinv_depth)
+    hipLaunchKernelGGL(k_render_bwd<true>, dim3((unsigned)n_tiles), dim3(256), 0, (hipStream_t)stream, A, P, T,
+                       n_contrib, dL_drgb, dL_dT, dL_dinv_depth, acc);
+  else
+    hipLaunchKernelGGL(k_render_bwd<false>, dim3((unsigned)n_tiles), dim3(256), 0, (hipStream_t)stream, A, P, T,
+                       n_contrib, dL_drgb, dL_dT, (const float*)nullptr, acc);
   HP_CHECK_LAUNCH();
   return HP_OK;
 }
@@ -538,4 +593,49 @@ extern "C" hp_status hp_preprocess_bwd(const hp_gaussians* gs, const hp_view* vi
   if (gs->P == 0) return HP_OK;
   if (!acc || !grad->mean || !grad->scale || !grad->rot || !grad->opacity || !grad->sh) return HP_ERR_INVALID_ARG;
   return hp_preprocess_bwd_launch(gs, view, prm, acc, grad, (hipStream_t)stream);
+}
+
+// ---- radian-space statistics for adaptive density control -------------------
+__global__ void k_mark_visible(const uint32_t* __restrict__ vals, int64_t n, int64_t P, uint8_t* __restrict__ vis) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const uint32_t g = vals[k];
+  if ((int64_t)g < P) vis[g] = 1;
+}
+
+// r_s,max and the norm of the gradient with respect to the centre's
+// displacement along the sphere: east = d omega cos(phi), north = d phi, so
+// dL/d east = (dL/d omega) / cos(phi); cos(phi) is e_phi.y, record word 7
+__global__ void k_density_stats(HpProjView pv, int64_t P, const float* __restrict__ acc,
+                                const uint8_t* __restrict__ vis, float* __restrict__ rs_max,
+                                float* __restrict__ gacc, int32_t* __restrict__ cnt) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= P || !vis[i]) return;
+  const float rs = pv.radius[i];
+  if (!(rs > 0.f)) return;
+  rs_max[i] = fmaxf(rs_max[i], rs);
+  const float cph = pv.rec[4 * i + 1].w;
+  const float ge = acc[7 * P + i] / cph, gn = acc[8 * P + i];
+  gacc[i] += sqrtf(ge * ge + gn * gn);
+  cnt[i] += 1;
+}
+
+extern "C" hp_status hp_mark_visible(const uint32_t* vals, int64_t n_pairs, int64_t P, uint8_t* visible, void* stream) {
+  if (n_pairs < 0 || P < 0 || (n_pairs > 0 && !vals) || (P > 0 && !visible)) return HP_ERR_INVALID_ARG;
+  if (n_pairs == 0) return HP_OK;
+  hipLaunchKernelGGL(k_mark_visible, dim3(hp_blocks(n_pairs, 256)), dim3(256), 0, (hipStream_t)stream, vals, n_pairs,
+                     P, visible);
+  HP_CHECK_LAUNCH();
+  return HP_OK;
+}
+
+extern "C" hp_status hp_density_stats(const void* projected, int64_t P, const float* acc, const uint8_t* visible,
+                                      float* rs_max, float* grad_accum, int32_t* count, void* stream) {
+  if (P < 0) return HP_ERR_INVALID_ARG;
+  if (P == 0) return HP_OK;
+  if (!projected || !acc || !visible || !rs_max || !grad_accum || !count) return HP_ERR_INVALID_ARG;
+  hipLaunchKernelGGL(k_density_stats, dim3(hp_blocks(P, 256)), dim3(256), 0, (hipStream_t)stream,
+                     hp_proj_view((const char*)projected, P), P, acc, visible, rs_max, grad_accum, count);
+  HP_CHECK_LAUNCH();
+  return HP_OK;
 }

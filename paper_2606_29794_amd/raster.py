@@ -106,6 +106,7 @@ class FwdState:
     T: torch.Tensor
     n_contrib: torch.Tensor
     P: int
+    inv_depth: torch.Tensor | None = None
 
 
 class Rasterizer:
@@ -241,28 +242,30 @@ class Rasterizer:
         return ranges
 
     # ---- stage 3 ---------------------------------------------------------
-    def render_fwd(self, proj, P, vals, ranges, cam: Camera, want_used: bool = False):
-        """rgb [3, n], T [n], n_contrib [n] (and n_used [n] if want_used)."""
+    def render_fwd(self, proj, P, vals, ranges, cam: Camera, want_used: bool = False, want_depth: bool = False):
+        """rgb [3, n], T [n], n_contrib [n] (and n_used [n] if want_used, and
+        the composited inverse radial depth [n] last if want_depth)."""
         m = self.mask(cam)
         v = cam.view()
         rgb = torch.empty((3, max(m.n_active, 1)), dtype=torch.float32, device=self.device)
         T = torch.empty(max(m.n_active, 1), dtype=torch.float32, device=self.device)
         nc = torch.empty(max(m.n_active, 1), dtype=torch.int32, device=self.device)
         nu = torch.empty(max(m.n_active, 1), dtype=torch.int32, device=self.device) if want_used else None
+        dinv = torch.empty(max(m.n_active, 1), dtype=torch.float32, device=self.device) if want_depth else None
         A.call("hp_render_fwd", _p(proj), P, _p(vals), _p(ranges), m.n_tiles, C.byref(v), C.byref(self.prm),
-               _p(m.buf), m.n_active, _p(rgb), _p(T), _p(nc), _p(nu), _stream())
-        if want_used:
-            return rgb, T, nc, nu
-        return rgb, T, nc
+               _p(m.buf), m.n_active, _p(rgb), _p(T), _p(nc), _p(nu), _p(dinv), _stream())
+        out = (rgb, T, nc) + ((nu,) if want_used else ()) + ((dinv,) if want_depth else ())
+        return out
 
-    def forward(self, g: Gaussians, cam: Camera) -> FwdState:
+    def forward(self, g: Gaussians, cam: Camera, want_depth: bool = False) -> FwdState:
         m = self.mask(cam)
         proj = self.preprocess(g, cam)
         vals, ranges, n = self.bin_sorted(proj, g.P, cam)
-        rgb, T, nc = self.render_fwd(proj, g.P, vals, ranges, cam)
-        return FwdState(cam, m, proj, vals, ranges, n, rgb, T, nc, g.P)
+        out = self.render_fwd(proj, g.P, vals, ranges, cam, want_depth=want_depth)
+        rgb, T, nc = out[:3]
+        return FwdState(cam, m, proj, vals, ranges, n, rgb, T, nc, g.P, out[3] if want_depth else None)
 
-    def backward(self, g: Gaussians, st: FwdState, dL_drgb, dL_dT, grads: Gaussians) -> None:
+    def backward(self, g: Gaussians, st: FwdState, dL_drgb, dL_dT, grads: Gaussians, dL_dinv_depth=None) -> None:
         """Accumulates gradients into the tensors of `grads`."""
         v = st.camera.view()
         gs = g.struct()
@@ -272,24 +275,36 @@ class Rasterizer:
         ws = _bytes(ws_n, self.device)
         A.call("hp_render_bwd", C.byref(gs), _p(st.projected), _p(st.vals), _p(st.ranges), st.mask.n_tiles,
                C.byref(v), C.byref(self.prm), _p(st.mask.buf), st.mask.n_active, _p(st.T), _p(st.n_contrib),
-               _p(dL_drgb.contiguous()), _p(None if dL_dT is None else dL_dT.contiguous()), C.byref(gg), _p(ws),
-               ws_n, _stream())
+               _p(dL_drgb.contiguous()), _p(None if dL_dT is None else dL_dT.contiguous()),
+               _p(None if dL_dinv_depth is None else dL_dinv_depth.contiguous()), C.byref(gg), _p(ws), ws_n, _stream())
 
-    def backward_pixels(self, st: FwdState, dL_drgb, dL_dT, acc: torch.Tensor) -> None:
+    def backward_pixels(self, st: FwdState, dL_drgb, dL_dT, acc: torch.Tensor, dL_dinv_depth=None) -> None:
         """Pixel pass of the backward alone: per-Gaussian dL/d(colour,
-        opacity, conic, omega, phi) accumulated into acc [9, P]."""
+        opacity, conic, omega, phi[, 1/r]) accumulated into acc [10, P]."""
         v = st.camera.view()
         A.call("hp_render_bwd_pixels", _p(st.projected), st.P, _p(st.vals), _p(st.ranges), st.mask.n_tiles,
                C.byref(v), C.byref(self.prm), _p(st.mask.buf), st.mask.n_active, _p(st.T), _p(st.n_contrib),
-               _p(dL_drgb.contiguous()), _p(None if dL_dT is None else dL_dT.contiguous()), _p(acc), _stream())
+               _p(dL_drgb.contiguous()), _p(None if dL_dT is None else dL_dT.contiguous()),
+               _p(None if dL_dinv_depth is None else dL_dinv_depth.contiguous()), _p(acc), _stream())
 
     def backward_preprocess(self, g: Gaussians, cam: Camera, acc: torch.Tensor, grads: Gaussians) -> None:
-        """Second half of the backward: acc [9, P] -> parameter gradients (accumulated)."""
+        """Second half of the backward: acc [10, P] -> parameter gradients (accumulated)."""
         v = cam.view()
         gs = g.struct()
         gg = A.hp_gaussians_grad(grads.mean.data_ptr(), grads.scale.data_ptr(), grads.rot.data_ptr(),
                                  grads.opacity.data_ptr(), grads.sh.data_ptr())
         A.call("hp_preprocess_bwd", C.byref(gs), C.byref(v), C.byref(self.prm), _p(acc), C.byref(gg), _stream())
+
+    # ---- radian-space density-control statistics -----------------------------
+    def density_stats(self, st: FwdState, acc: torch.Tensor, rs_max: torch.Tensor, grad_accum: torch.Tensor,
+                      count: torch.Tensor) -> None:
+        """Updates rs_max / grad_accum [P] float and count [P] int32 in place for
+        the Gaussians visible in this view (in any tile list), from the pixel
+        pass's accumulators acc [10, P]."""
+        vis = torch.zeros(max(st.P, 1), dtype=torch.uint8, device=self.device)
+        A.call("hp_mark_visible", _p(st.vals), st.n_pairs, st.P, _p(vis), _stream())
+        A.call("hp_density_stats", _p(st.projected), st.P, _p(acc), _p(vis), _p(rs_max), _p(grad_accum), _p(count),
+               _stream())
 
     # ---- image synthesis (Eq. camera_synthesis; supp. camera models) ----------
     def sphere_to_image(self, img: torch.Tensor, cam: Camera, W: int, H: int, want_valid: bool = False):

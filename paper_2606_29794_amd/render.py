@@ -30,31 +30,37 @@ def default_rasterizer(device="cuda") -> Rasterizer:
 
 class _Render(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, mean, scale, rot, opacity, sh, rasterizer, camera):
+    def forward(ctx, mean, scale, rot, opacity, sh, rasterizer, camera, want_depth):
         g = Gaussians(mean.detach().contiguous(), scale.detach().contiguous(), rot.detach().contiguous(),
                       opacity.detach().contiguous(), sh.detach().contiguous())
-        st = rasterizer.forward(g, camera)
+        st = rasterizer.forward(g, camera, want_depth=want_depth)
         ctx.g, ctx.st, ctx.R = g, st, rasterizer
         ctx.mark_non_differentiable(st.n_contrib)
+        if want_depth:
+            return st.rgb, st.T, st.inv_depth
         return st.rgb, st.T
 
     @staticmethod
-    def backward(ctx, grad_rgb, grad_T):
+    def backward(ctx, grad_rgb, grad_T, grad_inv_depth=None):
         g, st, R = ctx.g, ctx.st, ctx.R
         z = torch.zeros_like
         gr = Gaussians(z(g.mean), z(g.scale), z(g.rot), z(g.opacity), z(g.sh))
         if grad_rgb is None:
             grad_rgb = torch.zeros_like(st.rgb)
-        R.backward(g, st, grad_rgb, grad_T, gr)
+        R.backward(g, st, grad_rgb, grad_T, gr, dL_dinv_depth=grad_inv_depth)
         ctx.g = ctx.st = None
-        return gr.mean, gr.scale, gr.rot, gr.opacity, gr.sh, None, None
+        return gr.mean, gr.scale, gr.rot, gr.opacity, gr.sh, None, None, None
 
 
-def render(mean, scale, rot, opacity, sh, camera: Camera, rasterizer: Rasterizer | None = None):
+def render(mean, scale, rot, opacity, sh, camera: Camera, rasterizer: Rasterizer | None = None,
+           want_depth: bool = False):
     """Differentiable HEALPix render of one camera.  Returns (rgb [3, n], T [n])
-    over the camera's active pixels (see ``rasterizer.mask(camera)``)."""
+    over the camera's active pixels (see ``rasterizer.mask(camera)``), and with
+    want_depth also the composited inverse radial depth [n] (Sec. 3.2 depth
+    supervision), whose gradient reaches the means through alpha and through
+    d(1/r)/dt = -t / r^3."""
     R = rasterizer or default_rasterizer(mean.device)
-    return _Render.apply(mean, scale, rot, opacity, sh, R, camera)
+    return _Render.apply(mean, scale, rot, opacity, sh, R, camera, want_depth)
 
 
 class _HSSIMLoss(torch.autograd.Function):

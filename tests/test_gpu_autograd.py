@@ -71,7 +71,7 @@ def test_split_backward_equals_fused():
     g1 = Gaussians(z(g.mean), z(g.scale), z(g.rot), z(g.opacity), z(g.sh))
     g2 = Gaussians(z(g.mean), z(g.scale), z(g.rot), z(g.opacity), z(g.sh))
     R.backward(g, st, dC, dT, g1)
-    acc = torch.zeros((9, g.P), dtype=torch.float32, device="cuda")
+    acc = torch.zeros((10, g.P), dtype=torch.float32, device="cuda")
     R.backward_pixels(st, dC, dT, acc)
     R.backward_preprocess(g, cam, acc, g2)
     torch.cuda.synchronize()
