@@ -33,6 +33,8 @@ __device__ __forceinline__ int64_t ss_slot(const SsimArgs& A, int64_t q) {
   const int per_b = 2 * A.b;
   const int64_t t = q >> per_b;
   const int loc = (int)(q - (t << per_b));
+  // a fully active tile holds its pixels in nested order: no rank to count
+  if (A.tile_count[t] == (1 << per_b)) return (int64_t)A.tile_start[t] + loc;
   const uint32_t* bits = A.tile_bits + 8 * t;
   const uint32_t word = bits[loc >> 5];
   if (!((word >> (loc & 31)) & 1u)) return -1;

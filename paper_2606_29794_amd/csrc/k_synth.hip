@@ -230,6 +230,8 @@ __device__ int64_t synth_slot(const HpMaskView& m, const HpGeom& g, int64_t q) {
   const int per_b = 2 * g.b;
   const int64_t t = q >> per_b;
   const int loc = (int)(q - (t << per_b));
+  // a fully active tile holds its pixels in nested order: no rank to count
+  if (m.tile_count[t] == (1 << per_b)) return (int64_t)m.tile_start[t] + loc;
   const uint32_t* bits = m.tile_bits + 8 * t;
   const uint32_t word = bits[loc >> 5];
   if (!((word >> (loc & 31)) & 1u)) return -1;
