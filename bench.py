@@ -89,7 +89,7 @@ def main():
             p.grad = None
         tot = 0.0
         for v, cam in enumerate(cams):
-            rgb, T = render(*params, cam, R)
+            rgb, T = render(*params, cam, R, fused_grad=True)
             loss, _ = hssim_loss(rgb, targets[v], cam, 0.2, R)
             loss.backward()
         return tot

@@ -28,13 +28,23 @@ def default_rasterizer(device="cuda") -> Rasterizer:
     return r
 
 
+def _fusable(params):
+    return all(p.is_leaf and p.requires_grad and p.dtype == torch.float32 and p.is_contiguous() and
+               (p.grad is None or (p.grad.is_contiguous() and p.grad.dtype == torch.float32
+                                   and p.grad.shape == p.shape)) for p in params)
+
+
 class _Render(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, mean, scale, rot, opacity, sh, rasterizer, camera, want_depth):
+    def forward(ctx, mean, scale, rot, opacity, sh, rasterizer, camera, want_depth, fused_grad):
         g = Gaussians(mean.detach().contiguous(), scale.detach().contiguous(), rot.detach().contiguous(),
                       opacity.detach().contiguous(), sh.detach().contiguous())
         st = rasterizer.forward(g, camera, want_depth=want_depth)
         ctx.g, ctx.st, ctx.R = g, st, rasterizer
+        ctx.leaves = (mean, scale, rot, opacity, sh) if fused_grad else None
+        # unused outputs (often T, or the depth) reach the backward as None
+        # instead of zero-filled tensors
+        ctx.set_materialize_grads(False)
         ctx.mark_non_differentiable(st.n_contrib)
         if want_depth:
             return st.rgb, st.T, st.inv_depth
@@ -43,24 +53,42 @@ class _Render(torch.autograd.Function):
     @staticmethod
     def backward(ctx, grad_rgb, grad_T, grad_inv_depth=None):
         g, st, R = ctx.g, ctx.st, ctx.R
-        z = torch.zeros_like
-        gr = Gaussians(z(g.mean), z(g.scale), z(g.rot), z(g.opacity), z(g.sh))
         if grad_rgb is None:
             grad_rgb = torch.zeros_like(st.rgb)
+        leaves = ctx.leaves
+        ctx.g = ctx.st = ctx.leaves = None
+        if leaves is not None and _fusable(leaves):
+            # the library accumulates straight into the leaves' .grad (no
+            # zeroed temporaries, no separate add); autograd then has nothing
+            # left to add for them
+            for p in leaves:
+                if p.grad is None:
+                    p.grad = torch.zeros_like(p)
+            gr = Gaussians(*[p.grad for p in leaves])
+            R.backward(g, st, grad_rgb, grad_T, gr, dL_dinv_depth=grad_inv_depth)
+            return None, None, None, None, None, None, None, None, None
+        z = torch.zeros_like
+        gr = Gaussians(z(g.mean), z(g.scale), z(g.rot), z(g.opacity), z(g.sh))
         R.backward(g, st, grad_rgb, grad_T, gr, dL_dinv_depth=grad_inv_depth)
-        ctx.g = ctx.st = None
-        return gr.mean, gr.scale, gr.rot, gr.opacity, gr.sh, None, None, None
+        return gr.mean, gr.scale, gr.rot, gr.opacity, gr.sh, None, None, None, None
 
 
 def render(mean, scale, rot, opacity, sh, camera: Camera, rasterizer: Rasterizer | None = None,
-           want_depth: bool = False):
+           want_depth: bool = False, fused_grad: bool = False):
     """Differentiable HEALPix render of one camera.  Returns (rgb [3, n], T [n])
     over the camera's active pixels (see ``rasterizer.mask(camera)``), and with
     want_depth also the composited inverse radial depth [n] (Sec. 3.2 depth
     supervision), whose gradient reaches the means through alpha and through
-    d(1/r)/dt = -t / r^3."""
+    d(1/r)/dt = -t / r^3.
+
+    fused_grad: for training loops that call ``loss.backward()`` on leaf
+    float32 parameters, the backward accumulates straight into their
+    ``.grad`` (created as zeros when absent) instead of returning fresh
+    gradient tensors that autograd would add; the result is the same.  Do not
+    use it with ``torch.autograd.grad``, which reads returned gradients only.
+    Falls back to the plain path when a parameter is not such a leaf."""
     R = rasterizer or default_rasterizer(mean.device)
-    return _Render.apply(mean, scale, rot, opacity, sh, R, camera, want_depth)
+    return _Render.apply(mean, scale, rot, opacity, sh, R, camera, want_depth, fused_grad)
 
 
 class _HSSIMLoss(torch.autograd.Function):

@@ -79,3 +79,32 @@ def test_split_backward_equals_fused():
         a = getattr(g1, k).double().cpu().numpy().ravel()
         b = getattr(g2, k).double().cpu().numpy().ravel()
         assert np.linalg.norm(a - b) <= 1e-5 * np.linalg.norm(a), k
+
+
+def test_fused_grad_equals_plain_autograd():
+    """render(..., fused_grad=True) accumulates into the leaves' .grad in
+    place; over two views (one creating .grad, one adding to it) the result
+    equals the plain autograd path."""
+    import torch
+    from paper_2606_29794_amd.raster import Camera, Gaussians, Rasterizer
+    from paper_2606_29794_amd.render import hssim_loss, render
+    wl = SC.config1_fd("overlap")
+    sc = wl.scene
+    R = Rasterizer()
+    g = Gaussians.from_scene(sc)
+    cams = [Camera.from_dict(wl.cameras[0]), Camera.from_dict(SC.make_camera(np.random.default_rng(5), 4, SC.CAM_FULL))]
+    grads = []
+    for fused in (False, True):
+        params = [t.clone().requires_grad_(True) for t in (g.mean, g.scale, g.rot, g.opacity, g.sh)]
+        for k, cam in enumerate(cams):
+            rgb, T = render(*params, cam, R, fused_grad=fused)
+            m = R.mask(cam)
+            target = torch.as_tensor(SC.target_image(wl.seed, k, m.n_active), device="cuda")
+            loss, _ = hssim_loss(rgb, target, cam, 0.2, R)
+            loss.backward()
+        torch.cuda.synchronize()
+        grads.append([p.grad.double().cpu().numpy().ravel() for p in params])
+    for a, b, k in zip(grads[0], grads[1], ("mean", "scale", "rot", "opacity", "sh")):
+        nb = np.linalg.norm(a)
+        assert nb > 0, k
+        assert np.linalg.norm(a - b) <= 1e-5 * nb, k
