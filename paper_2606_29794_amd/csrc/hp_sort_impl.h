@@ -253,7 +253,14 @@ inline size_t radix_ws_bytes(int64_t n) {
 
 // Stable sort of (keys, vals) by the low `nbits` bits of the key; the result
 // ends in keys/vals.
-inline hp_status radix_sort(uint32_t* keys, uint32_t* vals, int64_t n, int nbits, void* ws, hipStream_t s) {
+// Stable sort of n (key, value) pairs by the low nbits of the key.  The
+// result is left in (keys, vals), or, when out_keys / out_vals are given, in
+// whichever of (keys, vals) and the workspace's second buffer the last pass
+// wrote (returned through them; no copy back).
+inline hp_status radix_sort(uint32_t* keys, uint32_t* vals, int64_t n, int nbits, void* ws, hipStream_t s,
+                            uint32_t** out_keys = nullptr, uint32_t** out_vals = nullptr) {
+  if (out_keys) *out_keys = keys;
+  if (out_vals) *out_vals = vals;
   if (n <= 1 || nbits <= 0) return HP_OK;
   const int passes = (nbits + 7) / 8;
   const int bits = (nbits + passes - 1) / passes;
@@ -276,6 +283,11 @@ inline hp_status radix_sort(uint32_t* keys, uint32_t* vals, int64_t n, int nbits
     HP_CHECK_LAUNCH();
     uint32_t* t = ka; ka = kb; kb = t;
     t = va; va = vb; vb = t;
+  }
+  if (out_keys && out_vals) {
+    *out_keys = ka;
+    *out_vals = va;
+    return HP_OK;
   }
   if (ka != keys) {
     hipLaunchKernelGGL(k_copy_u32, dim3(hp_blocks(n, 256)), dim3(256), 0, s, ka, keys, n);

@@ -731,11 +731,20 @@ extern "C" hp_status hp_bin_sorted(int32_t phase, const void* projected, int64_t
     // stable sort of the tasks by node; segments and chunk offsets per node
     int nbits = 0;
     while (((int64_t)1 << nbits) < sw.nn) ++nbits;
-    HP_TRY(hpsort::radix_sort(w.task_n, w.task_g, nt, nbits, sw.tsort_ws, s));
+    // the sorted node keys are only needed here: read them where the last
+    // pass left them; the Gaussian ids go back to task_g for the emit phase
+    uint32_t *snode = w.task_n, *sgid = w.task_g;
+    HP_TRY(hpsort::radix_sort(w.task_n, w.task_g, nt, nbits, sw.tsort_ws, s, &snode, &sgid));
+    if (sgid != w.task_g && nt > 0) {
+      hipLaunchKernelGGL(hpsort::k_copy_u32, dim3(hp_blocks(nt, 256)), dim3(256), 0, s, (const uint32_t*)sgid, w.task_g,
+                         (int64_t)nt);
+      HP_CHECK_LAUNCH();
+    }
     hipLaunchKernelGGL(k_fill_zero_u32, dim3(hp_blocks(2 * sw.nn, 256)), dim3(256), 0, s, sw.seg, 2 * sw.nn);
     HP_CHECK_LAUNCH();
     if (nt > 0) {
-      hipLaunchKernelGGL(k_seg_ranges, dim3(hp_blocks(nt, 256)), dim3(256), 0, s, w.task_n, (int64_t)nt, nn, sw.seg);
+      hipLaunchKernelGGL(k_seg_ranges, dim3(hp_blocks(nt, 256)), dim3(256), 0, s, (const uint32_t*)snode, (int64_t)nt,
+                         nn, sw.seg);
       HP_CHECK_LAUNCH();
     }
     hipLaunchKernelGGL(k_seg_chunks, dim3(hp_blocks(sw.nn, 256)), dim3(256), 0, s, sw.seg, nn, sw.nch);
