@@ -81,6 +81,7 @@ def lib():
         _lib.or_chart_pixel.restype = C.c_int64
         _lib.or_hssim.restype = C.c_double
         _lib.or_num_threads.restype = C.c_int
+        _lib.or_query_tiles.restype = C.c_int64
     return _lib
 
 
@@ -347,6 +348,61 @@ def n_contrib(scene, cam, proj: Projected, lst, ranges, pix, prm=None):
                        _p(np.ascontiguousarray(proj.conic)), _p(lst), _p(ranges), C.c_int64(pix.size), _p(pix),
                        _p(out))
     return out
+
+
+def render_lists(scene, cam, proj: Projected, lst, ranges, pix, prm=None, qtol=0.0, ttol=0.0):
+    """Compositing at nested pixels `pix` where each pixel sees only its
+    tile's list (lst / ranges as from sorted_tile_lists): the approximate
+    tile sets of the paper's queries can leave a Gaussian out of a tile it
+    reaches.  Returns rgb [3][n], T [n], n_used [n], frag [n] as render()."""
+    prm = prm or params()
+    S = SceneRef(scene)
+    v = view_struct(cam)
+    pix = np.ascontiguousarray(pix, np.int64)
+    n = pix.size
+    rgb = np.zeros((3, n)); T = np.zeros(n); nu = np.zeros(n, np.int64); fr = np.zeros(n)
+    lib().or_render_lists(C.byref(S.s), C.byref(v), C.byref(prm), _p(proj.omega), _p(proj.phi), _p(proj.rho),
+                          _p(np.ascontiguousarray(proj.conic)), _p(np.ascontiguousarray(proj.rgb)),
+                          _p(np.ascontiguousarray(lst, np.int64)), _p(np.ascontiguousarray(ranges, np.int64)),
+                          C.c_int64(n), _p(pix), C.c_double(qtol), C.c_double(ttol), _p(rgb), _p(T), _p(nu), _p(fr))
+    return rgb, T, nu, fr
+
+
+# ---------------------------------------------------------------------------
+# The paper's tile queries (Sec. 3.3; Alg. 2 NESTED traversal, Alg. 3 RING scan)
+# ---------------------------------------------------------------------------
+QUERY_RING = 1
+QUERY_NESTED = 2
+
+
+def pixrad(kq: int) -> np.ndarray:
+    """PixRad(o), o = 0 .. kq: the largest angle from a node centre at order o
+    to the centre of one of its descendants at order kq (0 at o = kq)."""
+    out = np.zeros(kq + 1)
+    lib().or_pixrad(int(kq), _p(out))
+    return out
+
+
+def query_tiles(mode: int, order: int, proj: Projected, active, f: int, gids=None, drs_rel=0.0, drs_abs=0.0,
+                prm=None, tile_active_mask=None):
+    """(gid, tile) pairs of the paper's query `mode` (QUERY_RING / QUERY_NESTED)
+    at search depth f (query order kt + log2 f), restricted to active tiles.
+    The radius used is max(0, r_s (1 + drs_rel) + drs_abs)."""
+    prm = prm or params()
+    kt = tile_order(order, prm.tile_log2)
+    fl = int(round(math.log2(f)))
+    assert 1 << fl == f and kt + fl <= order
+    ta = tile_active(order, active, prm.tile_log2) if tile_active_mask is None else \
+        np.ascontiguousarray(tile_active_mask, np.uint8)
+    P = proj.valid.size
+    gids = np.arange(P, dtype=np.int64) if gids is None else np.ascontiguousarray(gids, np.int64)
+    r2n = _ring2nest(kt + fl) if mode == QUERY_RING else None
+    args = (int(mode), kt, fl, _p(r2n), _p(ta), C.c_int64(gids.size), _p(gids), _p(proj.valid),
+            _p(proj.omega), _p(proj.phi), _p(proj.rs), C.c_double(drs_rel), C.c_double(drs_abs))
+    n = lib().or_query_tiles(*args, C.c_int64(0), None, None)
+    g = np.empty(n, np.int64); t = np.empty(n, np.int64)
+    lib().or_query_tiles(*args, C.c_int64(n), _p(g), _p(t))
+    return g, t
 
 
 @dataclass

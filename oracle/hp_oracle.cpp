@@ -621,39 +621,81 @@ static void pixel_candidates(const or_scene& S, const or_params& prm, const int*
   std::sort(out.begin(), out.end(), [](const Cand& a, const Cand& b) { return a.rho < b.rho || (a.rho == b.rho && a.i < b.i); });
 }
 
+// Front-to-back compositing of one pixel's candidates (already ordered by
+// (rho, index)); see or_render for the outputs.
+static void composite(const std::vector<Cand>& c, const or_params& prm, const double* opac, const double* rho,
+                      const double* rgbg, i64 P, double qtol_abs, double ttol_rel, double C[3], double* Tout,
+                      i64* n_used, double* frag, double* Dout) {
+  double Tr = 1.0, fr = 0, D = 0;
+  C[0] = C[1] = C[2] = 0;
+  i64 used = 0;
+  for (const Cand& e : c) {
+    double cmax = std::max(std::fabs(rgbg[e.i]), std::max(std::fabs(rgbg[P + e.i]), std::fabs(rgbg[2 * P + e.i])));
+    if (std::fabs(e.q - prm.q_cut) <= qtol_abs) fr += Tr * std::min(prm.alpha_max, opac[e.i] * std::exp(-0.5 * prm.q_cut)) * cmax;
+    if (e.q > prm.q_cut) continue;
+    double a = std::min(prm.alpha_max, opac[e.i] * std::exp(-0.5 * e.q));
+    for (int ch = 0; ch < 3; ++ch) C[ch] += Tr * a * rgbg[ch * P + e.i];
+    D += Tr * a / rho[e.i];  // inverse radial depth composited like a colour (Sec. 3.2)
+    double Tn = Tr * (1 - a);
+    ++used;
+    if (std::fabs(Tn - prm.eps_T) <= ttol_rel * prm.eps_T) fr += std::max(Tr, prm.eps_T) * 1.0 * cmax;
+    Tr = Tn;
+    if (Tr < prm.eps_T) break;
+  }
+  *Tout = Tr; *n_used = used; *frag = fr; *Dout = D;
+}
+
 void or_render(const or_scene* S, const or_view* V, const or_params* prm, const int* valid, const double* omega,
                const double* phi, const double* rho, const double* conic, const double* rs, const double* rgbg,
                i64 n, const i64* pix, double qtol_abs, double ttol_rel, double* rgb, double* T, i64* n_used,
                double* frag, double* invd) {
   i64 P = S->P;
-  const double* op_ = nullptr;
   std::vector<double> opac(P);
   for (i64 i = 0; i < P; ++i) opac[i] = S->opacity[i];
-  op_ = opac.data();
 #pragma omp parallel for schedule(dynamic, 16)
   for (i64 k = 0; k < n; ++k) {
     double om_p, ph_p, pv[3];
     pix_angles(V->order, pix[k], &om_p, &ph_p, pv);
     std::vector<Cand> c;
     pixel_candidates(*S, *prm, valid, omega, phi, rho, conic, rs, om_p, ph_p, pv, c);
-    double Tr = 1.0, C[3] = {0, 0, 0}, fr = 0, D = 0;
-    i64 used = 0;
-    for (const Cand& e : c) {
-      double cmax = std::max(std::fabs(rgbg[e.i]), std::max(std::fabs(rgbg[P + e.i]), std::fabs(rgbg[2 * P + e.i])));
-      if (std::fabs(e.q - prm->q_cut) <= qtol_abs) fr += Tr * std::min(prm->alpha_max, op_[e.i] * std::exp(-0.5 * prm->q_cut)) * cmax;
-      if (e.q > prm->q_cut) continue;
-      double a = std::min(prm->alpha_max, op_[e.i] * std::exp(-0.5 * e.q));
-      for (int ch = 0; ch < 3; ++ch) C[ch] += Tr * a * rgbg[ch * P + e.i];
-      D += Tr * a / rho[e.i];  // inverse radial depth composited like a colour (Sec. 3.2)
-      double Tn = Tr * (1 - a);
-      ++used;
-      if (std::fabs(Tn - prm->eps_T) <= ttol_rel * prm->eps_T) fr += std::max(Tr, prm->eps_T) * 1.0 * cmax;
-      Tr = Tn;
-      if (Tr < prm->eps_T) break;
-    }
+    double C[3], D;
+    composite(c, *prm, opac.data(), rho, rgbg, P, qtol_abs, ttol_rel, C, &T[k], &n_used[k], &frag[k], &D);
     for (int ch = 0; ch < 3; ++ch) rgb[ch * n + k] = C[ch];
-    T[k] = Tr; n_used[k] = used; frag[k] = fr;
     if (invd) invd[k] = D;
+  }
+}
+
+// The same render where pixel p sees only the Gaussians of its tile's list
+// (list/ranges as in or_n_contrib): the entries with q <= q_cut, ordered by
+// (rho, index).  With the approximate tile sets of the paper's queries a list
+// can miss Gaussians that reach the pixel, and then the image differs from
+// the exact one (the aliasing the paper reports for coarse queries).
+void or_render_lists(const or_scene* S, const or_view* V, const or_params* prm, const double* omega,
+                     const double* phi, const double* rho, const double* conic, const double* rgbg, const i64* list,
+                     const i64* ranges, i64 n, const i64* pix, double qtol_abs, double ttol_rel, double* rgb,
+                     double* T, i64* n_used, double* frag) {
+  i64 P = S->P;
+  int kt = tile_order(V->order, *prm);
+  int sh = 2 * (V->order - kt);
+  std::vector<double> opac(P);
+  for (i64 i = 0; i < P; ++i) opac[i] = S->opacity[i];
+#pragma omp parallel for schedule(dynamic, 16)
+  for (i64 k = 0; k < n; ++k) {
+    double om_p, ph_p, pv[3];
+    pix_angles(V->order, pix[k], &om_p, &ph_p, pv);
+    i64 t = pix[k] >> sh;
+    std::vector<Cand> c;
+    for (i64 j = ranges[2 * t]; j < ranges[2 * t + 1]; ++j) {
+      i64 i = list[j];
+      double dx, dy, dgc;
+      sph_offset<double>(omega[i], phi[i], om_p, ph_p, &dx, &dy, &dgc);
+      double q = conic[i] * dx * dx + 2 * conic[P + i] * dx * dy + conic[2 * P + i] * dy * dy;
+      if (q <= prm->q_cut * (1 + 1e-3)) c.push_back(Cand{rho[i], i, q, dx, dy});
+    }
+    std::sort(c.begin(), c.end(), [](const Cand& a, const Cand& b) { return a.rho < b.rho || (a.rho == b.rho && a.i < b.i); });
+    double C[3], D;
+    composite(c, *prm, opac.data(), rho, rgbg, P, qtol_abs, ttol_rel, C, &T[k], &n_used[k], &frag[k], &D);
+    for (int ch = 0; ch < 3; ++ch) rgb[ch * n + k] = C[ch];
   }
 }
 
@@ -1140,6 +1182,156 @@ void or_image_to_sphere(int order, i64 n_active, const i64* active, const double
       out[c * n_active + k] = ok ? s : 0.0;
     }
   }
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// The paper's tile queries (Sec. 3.3 and the supplementary description of
+// stage 2; Alg. 2 NESTED quadtree traversal, Alg. 3 RING sequential scan).
+// Both search at the query order kq = kt + log2 f (f = 2^fl, the "x f" search
+// depth of the ablation) and report tiles, the ancestors at the tile order kt
+// of what they find.  They approximate the tile overlap by tests on centres,
+// so a tile set can miss tiles the disc reaches.
+// Readings where the listings leave room:
+//  * ZtoRingRange keeps the rings whose centre z lies in [z_min, z_max].
+//  * RingInfo's omega_0 is the longitude of the centre of the ring's first
+//    pixel in RING order, and Ring2Nest(i_r, j) the nested index of the j-th
+//    pixel of ring i_r.
+//  * The pole threshold epsilon is 1e-12.
+//  * Classify: zone 0 when d > r_s + R, 3 when d <= r_s - R, 2 when d <= r_s,
+//    else 1, with R = PixRad(o) the largest angle from a node centre at order
+//    o to the centre of one of its descendants at the query order (zero at
+//    o = kq).  The traversal then prunes exactly the subtrees that hold no
+//    query-order centre within r_s, and leaves report centre hits.
+//  * A result is restricted to active tiles (a tile without an active pixel
+//    is never rendered).
+// ---------------------------------------------------------------------------
+static double haversine(double om1, double ph1, double om2, double ph2) {
+  double a = std::sin(0.5 * (ph2 - ph1)), b = std::sin(0.5 * (om2 - om1));
+  double h = a * a + std::cos(ph1) * std::cos(ph2) * b * b;
+  return 2.0 * std::asin(std::sqrt(std::min(1.0, std::max(0.0, h))));
+}
+
+// PixRad(o) for o = 0 .. kq by enumerating every query-order centre.
+static const std::vector<double>& pixrad_table(int kq) {
+  static std::vector<std::vector<double>> cache(32);
+  std::vector<double>& R = cache[kq];
+  if (!R.empty()) return R;
+  const i64 nq = 12ll << (2 * kq);
+  std::vector<double> vq(3 * nq);
+#pragma omp parallel for schedule(static)
+  for (i64 p = 0; p < nq; ++p) pix_vec(kq, p, &vq[3 * p]);
+  R.assign(kq + 1, 0.0);
+  for (int o = 0; o < kq; ++o) {
+    const i64 no = 12ll << (2 * o);
+    std::vector<double> vo(3 * no);
+    for (i64 a = 0; a < no; ++a) pix_vec(o, a, &vo[3 * a]);
+    double m = 0;
+#pragma omp parallel for schedule(static) reduction(max : m)
+    for (i64 p = 0; p < nq; ++p) m = std::max(m, angle_between(&vo[3 * (p >> (2 * (kq - o)))], &vq[3 * p]));
+    R[o] = m;
+  }
+  return R;
+}
+
+// Alg. 2: depth-first search from the 12 base pixels with an explicit stack.
+static void query_nested(int kt, int kq, const std::vector<double>& R, double om, double ph, double rs,
+                         std::vector<i64>& T) {
+  std::vector<std::pair<i64, int>> stack;
+  for (i64 p = 11; p >= 0; --p) stack.push_back({p, 0});
+  while (!stack.empty()) {
+    const i64 p = stack.back().first;
+    const int o = stack.back().second;
+    stack.pop_back();
+    double omn, phn, v[3];
+    pix_angles(o, p, &omn, &phn, v);
+    const double d = haversine(om, ph, omn, phn);
+    const int zone = d > rs + R[o] ? 0 : (d <= rs - R[o] ? 3 : (d <= rs ? 2 : 1));
+    if (zone == 0) continue;
+    if (zone >= 2 && o >= kt) T.push_back(p >> (2 * (o - kt)));
+    else if (o < kq) for (int c = 3; c >= 0; --c) stack.push_back({4 * p + c, o + 1});
+    else T.push_back(p >> (2 * (o - kt)));
+  }
+}
+
+// Alg. 3: the rings of the disc's z range, and on each the pixels whose
+// centres fall in the longitude window of Eq. ring_phi_range (its end pixels
+// included by the floor / ceil).
+static void query_ring(int kt, int kq, const i64* r2n, double om, double ph, double rs, std::vector<i64>& T) {
+  const i64 N = (i64)1 << kq;
+  const double zc = std::sin(ph);
+  const double phmin = std::max(-0.5 * M_PI, ph - rs), phmax = std::min(0.5 * M_PI, ph + rs);
+  const double zmin = std::sin(phmin), zmax = std::sin(phmax);
+  const double crs = std::cos(rs);
+  const int sh = 2 * (kq - kt);
+  for (i64 ir = 1; ir <= 4 * N - 1; ++ir) {
+    const double zr = ring_z(N, ir);
+    if (zr < zmin || zr > zmax) continue;
+    i64 nr, first;
+    double off;
+    ring_info(N, ir, &nr, &first, &off);
+    const double om0 = off * 2.0 * M_PI / (double)nr;
+    const double delta = std::sqrt(std::max(0.0, 1 - zc * zc)) * std::sqrt(std::max(0.0, 1 - zr * zr));
+    if (delta < 1e-12) {
+      if (zc * zr >= crs)
+        for (i64 j = 0; j < nr; ++j) T.push_back(r2n[first + j] >> sh);
+      continue;
+    }
+    const double cw = (crs - zc * zr) / delta;
+    if (cw <= -1) {
+      for (i64 j = 0; j < nr; ++j) T.push_back(r2n[first + j] >> sh);
+    } else if (cw < 1) {
+      const double dw = std::acos(std::min(1.0, std::max(-1.0, cw)));
+      const i64 lo = (i64)std::floor((om - dw - om0) * (double)nr / (2.0 * M_PI));
+      const i64 hi = (i64)std::ceil((om + dw - om0) * (double)nr / (2.0 * M_PI));
+      for (i64 ip = lo; ip <= hi; ++ip) T.push_back(r2n[first + (((ip % nr) + nr) % nr)] >> sh);
+    }
+  }
+}
+
+extern "C" {
+
+// Tile sets of the paper's queries: mode 1 = RING scan (Alg. 3), 2 = NESTED
+// traversal (Alg. 2), at query order kt + fl.  Gaussian i (valid ones among
+// gids) is queried with radius max(0, rs_i (1 + drs_rel) + drs_abs); the
+// widened and narrowed radii bracket a float32 evaluation of the same query
+// (the result only grows with the radius).  ring2nest: the RING -> NESTED
+// table at the query order (RING mode).  Pairs come Gaussian by Gaussian,
+// tiles ascending; returns their number (written only while below cap).
+i64 or_query_tiles(int mode, int kt, int fl, const i64* ring2nest, const unsigned char* tile_active, i64 n_g,
+                   const i64* gids, const int* valid, const double* omega, const double* phi, const double* rs,
+                   double drs_rel, double drs_abs, i64 cap, i64* out_gid, i64* out_tile) {
+  const int kq = kt + fl;
+  static const std::vector<double> none;
+  const std::vector<double>& R = mode == 2 ? pixrad_table(kq) : none;
+  std::vector<std::vector<i64>> res(n_g);
+#pragma omp parallel for schedule(dynamic, 16)
+  for (i64 k = 0; k < n_g; ++k) {
+    const i64 i = gids[k];
+    if (!valid[i]) continue;
+    const double r = std::max(0.0, rs[i] * (1 + drs_rel) + drs_abs);
+    std::vector<i64> T;
+    if (mode == 1) query_ring(kt, kq, ring2nest, omega[i], phi[i], r, T);
+    else query_nested(kt, kq, R, omega[i], phi[i], r, T);
+    std::sort(T.begin(), T.end());
+    T.erase(std::unique(T.begin(), T.end()), T.end());
+    for (i64 t : T)
+      if (tile_active[t]) res[k].push_back(t);
+  }
+  i64 n = 0;
+  for (i64 k = 0; k < n_g; ++k)
+    for (i64 t : res[k]) {
+      if (out_gid && n < cap) { out_gid[n] = gids[k]; out_tile[n] = t; }
+      ++n;
+    }
+  return n;
+}
+
+// PixRad(o), o = 0 .. kq (as used by the NESTED query).
+void or_pixrad(int kq, double* out) {
+  const std::vector<double>& R = pixrad_table(kq);
+  for (int o = 0; o <= kq; ++o) out[o] = R[o];
 }
 
 }  // extern "C"
