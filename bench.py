@@ -44,6 +44,7 @@ def parse():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--profile-only", action="store_true", help="run warmup+steps without the extra passes")
+    ap.add_argument("--no-queries", action="store_true", help="skip the paper-query (RING / NESTED x f) comparison")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB device-to-device (known bytes for scaling FETCH_SIZE / WRITE_SIZE)")
     return ap.parse_args()
@@ -84,12 +85,17 @@ def main():
     m = R.mask(cams[0])
     targets = [torch.as_tensor(SC.target_image(wl.seed, v, m.n_active), device=dev) for v in range(len(cams))]
 
-    def step():
+    g_det = Gaussians(*[p.detach() for p in params])
+
+    def step(query=None):
         for p in params:
             p.grad = None
         tot = 0.0
+        # preprocess + binning of every view on a side stream, overlapping the
+        # rendering of the views before it
+        pf = R.prefetch(g_det, cams, query)
         for v, cam in enumerate(cams):
-            rgb, T = render(*params, cam, R, fused_grad=True)
+            rgb, T = render(*params, cam, R, fused_grad=True, prepared=pf.get(v))
             loss, _ = hssim_loss(rgb, targets[v], cam, 0.2, R)
             loss.backward()
         return tot
@@ -118,6 +124,8 @@ def main():
         out.update(kernel_breakdown(R, params, cams, targets, torch, A))
         # Gaussian-pixel evaluations per second over the whole fwd+bwd step (view 0's counts)
         out["gaussian_pixel_evaluations_per_s"] = out["evaluated_pixel_pairs"] * renders_per_s
+        if not args.no_queries:
+            out["tile_queries"] = query_bench(R, params, cams, targets, torch, step, args.steps)
         if not args.no_cpu_baseline:
             out["cpu_baseline"] = cpu_baseline(wl, args.cpu_pixels)
         if not args.no_serve:
@@ -125,6 +133,67 @@ def main():
             torch.cuda.empty_cache()
             out["serve"] = serve_bench(args.serve_requests)
     print(json.dumps(out), flush=True)
+
+
+QUERIES = [("exact", None), ("ring_x1", ("ring", 1)), ("ring_x2", ("ring", 2)), ("ring_x4", ("ring", 4)),
+           ("nested_x1", ("nested", 1)), ("nested_x2", ("nested", 2)), ("nested_x4", ("nested", 4))]
+
+
+def query_bench(R, params, cams, targets, torch, step, steps):
+    """The paper's own tile queries (RING scan, NESTED traversal at search
+    depth f) against the exact binning on view 0: binning time, pairs kept,
+    and forward / backward render time over each query's lists (HIP events,
+    median of 3); then whole training steps (all views, loss, fwd+bwd) with
+    R x4 and D x4, the pair the paper's ablation times."""
+    from paper_2606_29794_amd.raster import FwdState, Gaussians
+    g = Gaussians(*[p.detach() for p in params])
+    cam = cams[0]
+    m = R.mask(cam)
+    proj = R.preprocess(g, cam)
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    up = torch.ones(1, device=g.mean.device)
+    res = {}
+    for name, q in QUERIES:
+        tb, tf, tw = [], [], []
+        for _ in range(3):
+            e = [ev() for _ in range(6)]
+            e[0].record()
+            if q is None:
+                vals, ranges, n = R.bin_sorted(proj, g.P, cam)
+                cand = n
+            else:
+                vals, ranges, cand, n = R.bin_query(proj, g.P, cam, q[0], q[1])
+            e[1].record()
+            e[2].record()
+            rgb, T, nc = R.render_fwd(proj, g.P, vals, ranges, cam)
+            e[3].record()
+            _, _, dimg = R.ssim_loss(rgb, targets[0], cam, dL_dloss=up)
+            st = FwdState(cam, m, proj, vals, ranges, n, rgb, T, nc, g.P)
+            acc = torch.zeros((10, g.P), dtype=torch.float32, device=g.mean.device)
+            e[4].record()
+            R.backward_pixels(st, dimg, None, acc)
+            e[5].record()
+            torch.cuda.synchronize()
+            tb.append(e[0].elapsed_time(e[1]))
+            tf.append(e[2].elapsed_time(e[3]))
+            tw.append(e[4].elapsed_time(e[5]))
+        r = {"bin_ms": float(np.median(tb)), "render_fwd_ms": float(np.median(tf)),
+             "render_bwd_ms": float(np.median(tw)), "pairs": int(n), "candidates": int(cand)}
+        r["bin_render_ms"] = r["bin_ms"] + r["render_fwd_ms"] + r["render_bwd_ms"]
+        res[name] = r
+    # whole training steps with the two queries the ablation compares
+    whole = {}
+    for name, q in (("ring_x4", ("ring", 4)), ("nested_x4", ("nested", 4)), ("exact", None)):
+        step(q)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step(q)
+        torch.cuda.synchronize()
+        whole[name] = (time.perf_counter() - t0) * 1e3 / steps
+    res["step_ms"] = whole
+    res["nested_x4_over_ring_x4_step"] = whole["nested_x4"] / whole["ring_x4"]
+    return res
 
 
 def serve_bench(n_requests):

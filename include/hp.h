@@ -202,6 +202,35 @@ size_t hp_bin_sorted_workspace_bytes(int64_t P, int32_t order, int32_t tile_log2
 hp_status hp_bin_sorted(int32_t phase, const void* projected, int64_t P, const hp_view* view, const hp_params* prm,
                         const void* grid, const void* mask, uint32_t* vals, uint32_t* tile_ranges, int32_t n_tiles,
                         int64_t capacity, int64_t* n_pairs, void* ws, size_t ws_bytes, void* stream);
+/* hp_bin_query: tile lists from the paper's own queries (Sec. 3.3 and its
+ * supplementary stage-2 description), which decide on centres at the query
+ * order kq = kt + log2 f ("x f" search depth of the ablation, f = 1 .. B):
+ *  HP_QUERY_RING   (Alg. 3): tile t holds Gaussian i when a pixel of order kq
+ *    in t lies on a ring whose centre latitude is within r_s of the disc's
+ *    and at a position between floor and ceil of the ring's window of
+ *    Eq. ring_phi_range (all of the ring when the ring lies inside the disc);
+ *  HP_QUERY_NESTED (Alg. 2): tile t holds i when a node of order kt .. kq in
+ *    t has its centre within r_s (the DFS from the 12 base pixels with
+ *    PixRad bounding the distance from a node centre to its descendants'
+ *    centres at order kq).
+ * These sets can leave out tiles that the Gaussian reaches (unlike
+ * hp_bin_sorted's), so the image can differ from the exact one.  Lists are in
+ * the same per-tile front-to-back order as hp_bin_sorted's.
+ * Arguments as for hp_bin_sorted, plus mode, f (a power of two, at most the
+ * tile side B) and n_kept (device int64, nullable).  COUNT writes *n_pairs,
+ * the number of candidates (the capacity EMIT needs: hp_bin_sorted's pairs
+ * with the test angle widened to contain the query's set).  EMIT writes the
+ * candidates and filters every tile's list in place: tile_ranges[k] =
+ * (start, start + kept), entries past a tile's end are stale, *n_kept = the
+ * total kept.  HP_ERR_INVALID_ARG for an unknown mode or f.
+ * ws: hp_bin_query_workspace_bytes(P, order, tile_log2) bytes. */
+#define HP_QUERY_RING 1
+#define HP_QUERY_NESTED 2
+size_t hp_bin_query_workspace_bytes(int64_t P, int32_t order, int32_t tile_log2);
+hp_status hp_bin_query(int32_t phase, int32_t mode, int32_t f, const void* projected, int64_t P, const hp_view* view,
+                       const hp_params* prm, const void* grid, const void* mask, uint32_t* vals, uint32_t* tile_ranges,
+                       int32_t n_tiles, int64_t capacity, int64_t* n_pairs, int64_t* n_kept, void* ws,
+                       size_t ws_bytes, void* stream);
 /* Waits for `stream` and copies one device int64 to the host. */
 hp_status hp_read_total(const int64_t* dev_value, int64_t* host_value, void* stream);
 

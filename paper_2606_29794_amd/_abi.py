@@ -12,6 +12,7 @@ LIB_PATH = os.path.join(HERE, "libhp.so")
 HP_OK, HP_ERR_INVALID_ARG, HP_ERR_UNSUPPORTED, HP_ERR_CAPACITY, HP_ERR_DEVICE = 0, 1, 2, 3, 4
 HP_CAM_FULL, HP_CAM_FISHEYE, HP_CAM_PINHOLE = 0, 1, 2
 HP_BIN_COUNT, HP_BIN_EMIT, HP_BIN_ALL = 1, 2, 3
+HP_QUERY_RING, HP_QUERY_NESTED = 1, 2
 
 
 class HPError(RuntimeError):
@@ -75,6 +76,9 @@ _PROTOS = {
     "hp_bin_sorted_workspace_bytes": (SZ, [I64, I32, I32]),
     "hp_bin_sorted": (I32, [I32, P_, I64, C.POINTER(hp_view), C.POINTER(hp_params), P_, P_, P_, P_, I32, I64, P_, P_,
                             SZ, P_]),
+    "hp_bin_query_workspace_bytes": (SZ, [I64, I32, I32]),
+    "hp_bin_query": (I32, [I32, I32, I32, P_, I64, C.POINTER(hp_view), C.POINTER(hp_params), P_, P_, P_, P_, I32, I64,
+                           P_, P_, P_, SZ, P_]),
     "hp_read_total": (I32, [P_, C.POINTER(I64), P_]),
     "hp_sort_workspace_bytes": (SZ, [I64, I32]),
     "hp_sort": (I32, [P_, P_, I64, I32, P_, P_, SZ, P_]),

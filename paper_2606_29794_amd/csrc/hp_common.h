@@ -88,3 +88,10 @@ static inline hp_status hp_read_small(void* dst, const void* src, size_t n, hipS
   memcpy(dst, pin, n);
   return HP_OK;
 }
+
+// hp_bin_sorted with every Gaussian's test angle widened by `widen` radians
+// (0: identical to hp_bin_sorted); the candidate stage of hp_bin_query.
+hp_status hp_bin_sorted_widened(int32_t phase, const void* projected, int64_t P, const hp_view* view,
+                                const hp_params* prm, const void* grid, const void* mask, uint32_t* vals,
+                                uint32_t* tile_ranges, int32_t n_tiles, int64_t capacity, int64_t* n_pairs, void* ws,
+                                size_t ws_bytes, void* stream, double widen);

@@ -77,6 +77,10 @@ struct BinTables {
   const uint8_t* leaf_active;  // never null: active flags of every node (all set for the full sphere)
   const int32_t* tile_compact;
   int kt, ls;
+  // (sin, cos) of half an angle added to every Gaussian's test angle: (0, 1)
+  // for the binning itself, a margin when the pairs are candidates for a
+  // narrower query that filters them afterwards
+  float wsin, wcos;
 };
 
 // Cap test: angle(cap centre c, u) <= R + theta as a chord comparison,
@@ -141,12 +145,19 @@ __device__ __forceinline__ void quad_walk(int l0, int64_t i0, int stop, Pass&& p
   }
 }
 
+// (sin, cos) of half the test angle widened by the table's margin: the sum
+// of half-angles, exact (bit for bit) when the margin is zero
+__device__ __forceinline__ void widen_half(float wsin, float wcos, float* sg, float* cg) {
+  const float s0 = *sg, c0 = *cg;
+  *sg = fmaf(s0, wcos, c0 * wsin);
+  *cg = fmaf(c0, wcos, -(s0 * wsin));
+}
+
 // direction and (sin, cos) of half the test angle r_s + guard (the sine is
 // precomputed in the record; the half angle is at most pi/2, so the cosine is
-// the non-negative root)
-__device__ __forceinline__ void gauss_dir(const float4* rec, const float* radius, uint32_t gid, float guard, float* u,
-                                          float* sg, float* cg, bool* ok) {
-  (void)guard;
+// the non-negative root), widened by the table's margin
+__device__ __forceinline__ void gauss_dir(const float4* rec, const float* radius, uint32_t gid, const BinTables& T,
+                                          float* u, float* sg, float* cg, bool* ok) {
   const float rs = radius[gid];
   *ok = rs > 0.f;
   if (!*ok) return;
@@ -154,6 +165,7 @@ __device__ __forceinline__ void gauss_dir(const float4* rec, const float* radius
   u[0] = r[0]; u[1] = r[1]; u[2] = r[2];
   *sg = r[15];
   *cg = sqrtf(fmaxf(0.f, 1.f - *sg * *sg));
+  widen_half(T.wsin, T.wcos, sg, cg);
 }
 
 // coarse walk: tasks of Gaussian order[k].  With `slots` (slot-major
@@ -197,7 +209,7 @@ __global__ __launch_bounds__(256) void k_bin_coarse(int64_t P, const uint32_t* _
   }
   float u[3], sg, cg;
   bool ok;
-  gauss_dir(rec, radius, gid, guard, u, &sg, &cg, &ok);
+  gauss_dir(rec, radius, gid, T, u, &sg, &cg, &ok);
   if (!ok) {
     if (!EMIT) tcount[k] = 0;
     return;
@@ -466,10 +478,11 @@ __global__ __launch_bounds__(256) void k_bin_cols(const uint32_t* __restrict__ c
     const float2 h = T.sc[leaf];
     const bool act = leaf_lane && T.leaf_active[leaf] != 0;
     const uint32_t tg = (uint32_t)lane < ntask ? tgid[ci.t0 + lane] : 0u;
-    // cos((r_s + guard) / 2) of every task, one per lane, by the same
-    // expression as the rest of the binning (identical decisions)
-    const float sgl = (uint32_t)lane < ntask ? rec[4 * (size_t)tg + 3].w : 0.f;
-    const float cgl = sqrtf(fmaxf(0.f, 1.f - sgl * sgl));
+    // (sin, cos) of (r_s + guard) / 2 of every task, one per lane, by the
+    // same expressions as the rest of the binning (identical decisions)
+    float sgl = (uint32_t)lane < ntask ? rec[4 * (size_t)tg + 3].w : 0.f;
+    float cgl = sqrtf(fmaxf(0.f, 1.f - sgl * sgl));
+    widen_half(T.wsin, T.wcos, &sgl, &cgl);
     // bits of tasks 0..31 and 32..63 are kept apart so that every set is a
     // 32-bit select-or
     uint32_t Wh[2] = {0u, 0u};
@@ -483,7 +496,8 @@ __global__ __launch_bounds__(256) void k_bin_cols(const uint32_t* __restrict__ c
           // past the chunk's end the last task is read again and its bit dropped
           const uint32_t j = j0 + q < ntask ? j0 + q : ntask - 1;
           const hp_cfloatp r = rp + 16 * (int64_t)(uint32_t)__builtin_amdgcn_readlane((int)tg, (int)j);
-          ux[q] = r[0]; uy[q] = r[1]; uz[q] = r[2]; sg[q] = r[15];
+          ux[q] = r[0]; uy[q] = r[1]; uz[q] = r[2];
+          sg[q] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(sgl), (int)j));
           cg[q] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cgl), (int)j));
         }
 #pragma unroll
@@ -577,7 +591,7 @@ extern "C" hp_status hp_bin(int32_t phase, const void* projected, int64_t P, con
   BinWs w = bin_ws(ws, P);
   const int ls = g.kt > kSplitDepth ? g.kt - kSplitDepth : 0;
   BinTables T{gv.cap, gv.sc, view->cam_type == HP_CAM_FULL ? nullptr : mv.node_active, mv.node_active,
-              mv.tile_compact, g.kt, ls};
+              mv.tile_compact, g.kt, ls, 0.f, 1.f};
   if (phase & HP_BIN_COUNT) {
     if (P == 0) {
       hipLaunchKernelGGL(k_store_zero, dim3(1), dim3(1), 0, s, n_pairs);
@@ -683,10 +697,12 @@ static unsigned chunk_grid(int64_t nchunks) {
   return (unsigned)(blocks < 8192 ? (blocks > 0 ? blocks : 1) : 8192);
 }
 
-extern "C" hp_status hp_bin_sorted(int32_t phase, const void* projected, int64_t P, const hp_view* view,
-                                   const hp_params* prm, const void* grid, const void* mask, uint32_t* vals,
-                                   uint32_t* tile_ranges, int32_t n_tiles, int64_t capacity, int64_t* n_pairs,
-                                   void* ws, size_t ws_bytes, void* stream) {
+// The sorted emission with every Gaussian's test angle widened by `widen`
+// radians (0: the binning of hp_bin_sorted).
+hp_status hp_bin_sorted_widened(int32_t phase, const void* projected, int64_t P, const hp_view* view,
+                                const hp_params* prm, const void* grid, const void* mask, uint32_t* vals,
+                                uint32_t* tile_ranges, int32_t n_tiles, int64_t capacity, int64_t* n_pairs, void* ws,
+                                size_t ws_bytes, void* stream, double widen) {
   if (phase < HP_BIN_COUNT || phase > HP_BIN_ALL) return HP_ERR_INVALID_ARG;
   HP_TRY(hp_check_view(view, prm));
   if (P < 0 || P > ((int64_t)1 << 31) - 1 || capacity < 0 || capacity > ((int64_t)1 << 32) - 1 || n_tiles < 0)
@@ -705,7 +721,7 @@ extern "C" hp_status hp_bin_sorted(int32_t phase, const void* projected, int64_t
   const int ls = g.kt > kSplitDepth ? g.kt - kSplitDepth : 0;
   const int depth = g.kt - ls;
   BinTables T{gv.cap, gv.sc, view->cam_type == HP_CAM_FULL ? nullptr : mv.node_active, mv.node_active,
-              mv.tile_compact, g.kt, ls};
+              mv.tile_compact, g.kt, ls, (float)sin(0.5 * widen), (float)cos(0.5 * widen)};
   const uint32_t nn = (uint32_t)sw.nn;
   if (phase & HP_BIN_COUNT) {
     if (P == 0) {
@@ -784,4 +800,12 @@ extern "C" hp_status hp_bin_sorted(int32_t phase, const void* projected, int64_t
     HP_CHECK_LAUNCH();
   }
   return HP_OK;
+}
+
+extern "C" hp_status hp_bin_sorted(int32_t phase, const void* projected, int64_t P, const hp_view* view,
+                                   const hp_params* prm, const void* grid, const void* mask, uint32_t* vals,
+                                   uint32_t* tile_ranges, int32_t n_tiles, int64_t capacity, int64_t* n_pairs,
+                                   void* ws, size_t ws_bytes, void* stream) {
+  return hp_bin_sorted_widened(phase, projected, P, view, prm, grid, mask, vals, tile_ranges, n_tiles, capacity,
+                               n_pairs, ws, ws_bytes, stream, 0.0);
 }

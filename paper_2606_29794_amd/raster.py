@@ -6,6 +6,7 @@ from __future__ import annotations
 import ctypes as C
 import math
 import threading
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -109,6 +110,43 @@ class FwdState:
     inv_depth: torch.Tensor | None = None
 
 
+@dataclass
+class Prepared:
+    """Stages 1-2 of one view (projected records and tile lists), made on
+    the stream `stream_id`; `event` marks their completion there."""
+    camera: Camera
+    projected: torch.Tensor
+    vals: torch.Tensor
+    ranges: torch.Tensor
+    n_pairs: int
+    event: torch.cuda.Event
+    stream_id: int
+
+
+class Prefetch:
+    """Stages 1-2 of a sequence of views, made in order on a side stream by a
+    host thread of its own, so that they overlap the caller's rendering of
+    the views before them (the binning waits on its stream for small counts,
+    which then no longer stalls the caller).  get(i) returns view i."""
+
+    def __init__(self, R: "Rasterizer", g: "Gaussians", cams, query=None):
+        stream = R.side_stream()
+        # the side stream first waits for the work the caller queued so far
+        # (e.g. an update of the Gaussians)
+        start = torch.cuda.Event()
+        start.record(torch.cuda.current_stream(R.device))
+        stream.wait_event(start)
+
+        def run(cam):
+            with torch.cuda.device(R.device), torch.cuda.stream(stream):
+                return R.prepare(g, cam, query)
+
+        self._futures = [R.side_pool().submit(run, c) for c in cams]
+
+    def get(self, i: int) -> Prepared:
+        return self._futures[i].result()
+
+
 class Rasterizer:
     """Grid tables per HEALPix order and masks per camera model are built once
     and cached; everything else is per call."""
@@ -123,6 +161,26 @@ class Rasterizer:
         self._ready = {}
         # the caches may be used from several host threads (serving workers)
         self._lock = threading.RLock()
+        self._side = None
+        self._pool = None
+
+    def side_stream(self) -> torch.cuda.Stream:
+        """The stream of prefetch() (default priority), created once."""
+        with self._lock:
+            if self._side is None:
+                self._side = torch.cuda.Stream(device=self.device)
+            return self._side
+
+    def side_pool(self) -> ThreadPoolExecutor:
+        with self._lock:
+            if self._pool is None:
+                self._pool = ThreadPoolExecutor(max_workers=1, thread_name_prefix="hp-prefetch")
+            return self._pool
+
+    def prefetch(self, g: "Gaussians", cams, query=None) -> Prefetch:
+        """Start stages 1-2 of every camera in `cams` on the side stream;
+        pass prefetch.get(i) as forward(..., prepared=) / render(..., prepared=)."""
+        return Prefetch(self, g, cams, query)
 
     def _created(self, key):
         ev = torch.cuda.Event()
@@ -234,6 +292,32 @@ class Rasterizer:
                _p(vals), _p(ranges), m.n_tiles, n, _p(npairs), _p(ws), ws_n, _stream())
         return vals, ranges, n
 
+    def bin_query(self, proj: torch.Tensor, P: int, cam: Camera, mode: str, f: int):
+        """Tile lists of the paper's own queries (mode "ring": Alg. 3 RING scan,
+        "nested": Alg. 2 quadtree traversal) at search depth f, in per-tile
+        depth order: (vals, ranges, n_candidates, n_kept).  A tile's list is
+        vals[ranges[k, 0]:ranges[k, 1]]; entries past a tile's end are stale."""
+        code = {"ring": A.HP_QUERY_RING, "nested": A.HP_QUERY_NESTED}[mode]
+        m = self.mask(cam)
+        v = cam.view()
+        ws_n = A.lib().hp_bin_query_workspace_bytes(P, cam.order, self.prm.tile_log2)
+        ws = _bytes(ws_n, self.device)
+        cnt = torch.zeros(2, dtype=torch.int64, device=self.device)
+        grid = self.grid(cam.order)
+        A.call("hp_bin_query", A.HP_BIN_COUNT, code, f, _p(proj), P, C.byref(v), C.byref(self.prm), _p(grid),
+               _p(m.buf), None, None, m.n_tiles, 0, _p(cnt), None, _p(ws), ws_n, _stream())
+        total = C.c_int64(0)
+        A.call("hp_read_total", _p(cnt), C.byref(total), _stream())
+        n = int(total.value)
+        vals = torch.empty(max(n, 1), dtype=torch.int32, device=self.device)
+        ranges = torch.empty((max(m.n_tiles, 1), 2), dtype=torch.int32, device=self.device)
+        A.call("hp_bin_query", A.HP_BIN_EMIT, code, f, _p(proj), P, C.byref(v), C.byref(self.prm), _p(grid),
+               _p(m.buf), _p(vals), _p(ranges), m.n_tiles, n, _p(cnt), C.c_void_p(cnt.data_ptr() + 8), _p(ws), ws_n,
+               _stream())
+        kept = C.c_int64(0)
+        A.call("hp_read_total", C.c_void_p(cnt.data_ptr() + 8), C.byref(kept), _stream())
+        return vals, ranges, n, int(kept.value)
+
     def sort(self, keys, vals, n: int, n_tiles: int):
         ranges = torch.zeros((max(n_tiles, 1), 2), dtype=torch.int32, device=self.device)
         ws_n = A.lib().hp_sort_workspace_bytes(n, n_tiles)
@@ -257,10 +341,37 @@ class Rasterizer:
         out = (rgb, T, nc) + ((nu,) if want_used else ()) + ((dinv,) if want_depth else ())
         return out
 
-    def forward(self, g: Gaussians, cam: Camera, want_depth: bool = False) -> FwdState:
-        m = self.mask(cam)
+    def prepare(self, g: Gaussians, cam: Camera, query=None) -> Prepared:
+        """Stages 1-2 for one view on the current stream.  query: None for the
+        binning of hp_bin_sorted, or (mode, f) for the paper's own tile query
+        (bin_query)."""
+        self.mask(cam)
         proj = self.preprocess(g, cam)
-        vals, ranges, n = self.bin_sorted(proj, g.P, cam)
+        if query is None:
+            vals, ranges, n = self.bin_sorted(proj, g.P, cam)
+        else:
+            vals, ranges, _, n = self.bin_query(proj, g.P, cam, query[0], query[1])
+        cur = torch.cuda.current_stream(self.device)
+        ev = torch.cuda.Event()
+        ev.record(cur)
+        return Prepared(cam, proj, vals, ranges, n, ev, cur.cuda_stream)
+
+    def forward(self, g: Gaussians, cam: Camera, want_depth: bool = False, query=None,
+                prepared: Prepared | None = None) -> FwdState:
+        """Stages 1-3 for one view (query as for prepare()).  With `prepared`
+        (from prepare() or prefetch() for the same Gaussians and camera),
+        stages 1-2 are taken from it: the current stream waits for them."""
+        m = self.mask(cam)
+        if prepared is None:
+            prepared = self.prepare(g, cam, query)
+        else:
+            cur = torch.cuda.current_stream(self.device)
+            if cur.cuda_stream != prepared.stream_id:
+                cur.wait_event(prepared.event)
+                # made on another stream, used (and freed) on this one
+                for t in (prepared.projected, prepared.vals, prepared.ranges):
+                    t.record_stream(cur)
+        proj, vals, ranges, n = prepared.projected, prepared.vals, prepared.ranges, prepared.n_pairs
         out = self.render_fwd(proj, g.P, vals, ranges, cam, want_depth=want_depth)
         rgb, T, nc = out[:3]
         return FwdState(cam, m, proj, vals, ranges, n, rgb, T, nc, g.P, out[3] if want_depth else None)

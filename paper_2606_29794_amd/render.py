@@ -36,10 +36,10 @@ def _fusable(params):
 
 class _Render(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, mean, scale, rot, opacity, sh, rasterizer, camera, want_depth, fused_grad):
+    def forward(ctx, mean, scale, rot, opacity, sh, rasterizer, camera, want_depth, fused_grad, query, prepared):
         g = Gaussians(mean.detach().contiguous(), scale.detach().contiguous(), rot.detach().contiguous(),
                       opacity.detach().contiguous(), sh.detach().contiguous())
-        st = rasterizer.forward(g, camera, want_depth=want_depth)
+        st = rasterizer.forward(g, camera, want_depth=want_depth, query=query, prepared=prepared)
         ctx.g, ctx.st, ctx.R = g, st, rasterizer
         ctx.leaves = (mean, scale, rot, opacity, sh) if fused_grad else None
         # unused outputs (often T, or the depth) reach the backward as None
@@ -66,15 +66,15 @@ class _Render(torch.autograd.Function):
                     p.grad = torch.zeros_like(p)
             gr = Gaussians(*[p.grad for p in leaves])
             R.backward(g, st, grad_rgb, grad_T, gr, dL_dinv_depth=grad_inv_depth)
-            return None, None, None, None, None, None, None, None, None
+            return None, None, None, None, None, None, None, None, None, None, None
         z = torch.zeros_like
         gr = Gaussians(z(g.mean), z(g.scale), z(g.rot), z(g.opacity), z(g.sh))
         R.backward(g, st, grad_rgb, grad_T, gr, dL_dinv_depth=grad_inv_depth)
-        return gr.mean, gr.scale, gr.rot, gr.opacity, gr.sh, None, None, None, None
+        return gr.mean, gr.scale, gr.rot, gr.opacity, gr.sh, None, None, None, None, None, None
 
 
 def render(mean, scale, rot, opacity, sh, camera: Camera, rasterizer: Rasterizer | None = None,
-           want_depth: bool = False, fused_grad: bool = False):
+           want_depth: bool = False, fused_grad: bool = False, query=None, prepared=None):
     """Differentiable HEALPix render of one camera.  Returns (rgb [3, n], T [n])
     over the camera's active pixels (see ``rasterizer.mask(camera)``), and with
     want_depth also the composited inverse radial depth [n] (Sec. 3.2 depth
@@ -86,9 +86,18 @@ def render(mean, scale, rot, opacity, sh, camera: Camera, rasterizer: Rasterizer
     ``.grad`` (created as zeros when absent) instead of returning fresh
     gradient tensors that autograd would add; the result is the same.  Do not
     use it with ``torch.autograd.grad``, which reads returned gradients only.
-    Falls back to the plain path when a parameter is not such a leaf."""
+    Falls back to the plain path when a parameter is not such a leaf.
+
+    query: None (tile lists that hold every Gaussian reaching a tile), or
+    ("ring" | "nested", f) for the paper's own tile query at search depth f
+    (Alg. 3 / Alg. 2), whose lists can leave Gaussians out of tiles they
+    reach; the backward then runs over the same lists.
+
+    prepared: stages 1-2 made ahead for these parameters and this camera
+    (``rasterizer.prepare`` or ``rasterizer.prefetch(...).get(i)``, which
+    overlaps them with the rendering of earlier views); query is then ignored."""
     R = rasterizer or default_rasterizer(mean.device)
-    return _Render.apply(mean, scale, rot, opacity, sh, R, camera, want_depth, fused_grad)
+    return _Render.apply(mean, scale, rot, opacity, sh, R, camera, want_depth, fused_grad, query, prepared)
 
 
 class _HSSIMLoss(torch.autograd.Function):

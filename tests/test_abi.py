@@ -1,0 +1,63 @@
+"""The C ABI without a GPU: the library loads, exports every function that
+include/hp.h declares, the Python binding names each of them, and argument
+checks that happen on the host before any device work return their status."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+
+from paper_2606_29794_amd import _abi as A
+
+_HDR = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "hp.h")
+
+
+def _declared():
+    src = open(_HDR).read()
+    src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)   # comments name functions too
+    return sorted(set(re.findall(r"^[A-Za-z_][\w \t\*]*?\b(hp_\w+)\s*\(", src, re.M)))
+
+
+def test_library_exports_every_declared_function():
+    names = _declared()
+    assert len(names) >= 30
+    L = A.lib()
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_binding_names_every_declared_function():
+    missing = [n for n in _declared() if n not in A._PROTOS]
+    assert not missing, missing
+
+
+def test_status_strings():
+    L = A.lib()
+    L.hp_status_string.restype = C.c_char_p
+    texts = {L.hp_status_string(s) for s in range(5)}
+    assert len(texts) == 5 and all(t for t in texts)
+
+
+def _view(order=6):
+    W = np.eye(3, dtype=np.float32)
+    return A.make_view(W, np.zeros(3, np.float32), np.zeros(3, np.float32), A.HP_CAM_FULL, 0.0, 0.0, order)
+
+
+def _query(mode, f, order=6):
+    L = A.lib()
+    v = _view(order)
+    prm = A.default_params()
+    dummy = C.c_void_p(16)   # never dereferenced: the checks fail first
+    return L.hp_bin_query(A.HP_BIN_ALL, mode, f, dummy, 10, C.byref(v), C.byref(prm), dummy, dummy, dummy, dummy, 1,
+                          10, dummy, None, dummy, 1 << 20, None)
+
+
+def test_bin_query_rejects_bad_mode_and_depth():
+    """Mode outside {RING, NESTED}; f not a power of two, or deeper than the
+    pixel order (f > B = 16, or f > Nside when the tile order is 0)."""
+    inv = 1   # HP_ERR_INVALID_ARG
+    assert _query(0, 4) == inv
+    assert _query(3, 4) == inv
+    for f in (0, 3, 6, 32, -4):
+        assert _query(A.HP_QUERY_RING, f) == inv, f
+    assert _query(A.HP_QUERY_NESTED, 8, order=2) == inv   # Nside 4: at most f = 4

@@ -108,3 +108,37 @@ def test_fused_grad_equals_plain_autograd():
         nb = np.linalg.norm(a)
         assert nb > 0, k
         assert np.linalg.norm(a - b) <= 1e-5 * nb, k
+
+
+def test_prefetched_views_equal_plain_render():
+    """Stages 1-2 made ahead on the side stream (prefetch) give the same
+    images and gradients as the plain path, over several views in one step;
+    the tile lists made on the side stream are used and freed on the main
+    stream."""
+    import torch
+    from paper_2606_29794_amd.raster import Camera, Gaussians, Rasterizer
+    from paper_2606_29794_amd.render import hssim_loss, render
+    wl = SC.config1(P=20000, order=7)
+    R = Rasterizer()
+    g = Gaussians.from_scene(wl.scene)
+    rng = np.random.default_rng(9)
+    cams = [Camera.from_dict(SC.make_camera(rng, 7, SC.CAM_FULL)) for _ in range(3)]
+    targets = [torch.as_tensor(SC.target_image(wl.seed, k, R.mask(c).n_active), device="cuda")
+               for k, c in enumerate(cams)]
+    out = []
+    for use_prefetch in (False, True, True):
+        params = [t.clone().requires_grad_(True) for t in (g.mean, g.scale, g.rot, g.opacity, g.sh)]
+        pf = R.prefetch(Gaussians(*[p.detach() for p in params]), cams) if use_prefetch else None
+        imgs = []
+        for k, cam in enumerate(cams):
+            rgb, T = render(*params, cam, R, fused_grad=True, prepared=pf.get(k) if pf else None)
+            loss, _ = hssim_loss(rgb, targets[k], cam, 0.2, R)
+            loss.backward()
+            imgs.append(rgb.detach().clone())
+        torch.cuda.synchronize()
+        out.append((imgs, [p.grad.double().cpu().numpy().ravel() for p in params]))
+    for imgs, grads in out[1:]:
+        for a, b in zip(out[0][0], imgs):
+            assert torch.equal(a, b)
+        for a, b, k in zip(out[0][1], grads, ("mean", "scale", "rot", "opacity", "sh")):
+            assert np.linalg.norm(a - b) <= 1e-5 * np.linalg.norm(a), k
