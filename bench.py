@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--profile-only", action="store_true", help="run warmup+steps without the extra passes")
     ap.add_argument("--no-queries", action="store_true", help="skip the paper-query (RING / NESTED x f) comparison")
+    ap.add_argument("--query", default=None,
+                    help="mode:f (ring:4, nested:4, ...): the timed steps use the paper's own tile query")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB device-to-device (known bytes for scaling FETCH_SIZE / WRITE_SIZE)")
     return ap.parse_args()
@@ -100,12 +102,16 @@ def main():
             loss.backward()
         return tot
 
+    query = None
+    if args.query:
+        mode, f = args.query.split(":")
+        query = (mode, int(f))
     for _ in range(args.warmup):
-        step()
+        step(query)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        step()
+        step(query)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ms_per_step = dt * 1e3 / args.steps
@@ -120,6 +126,8 @@ def main():
                                f"{1 << args.order}, L1+HSSIM loss, fwd+bwd per view",
                    "views_per_step": len(cams), "n_active": m.n_active},
     }
+    if query is not None:
+        out["config"]["tile_query"] = args.query
     if not args.profile_only:
         out.update(kernel_breakdown(R, params, cams, targets, torch, A))
         # Gaussian-pixel evaluations per second over the whole fwd+bwd step (view 0's counts)
@@ -273,8 +281,9 @@ def kernel_breakdown(R, params, cams, targets, torch, A):
     P = g.P
     K = g.sh.shape[0]
     # algorithmic bytes: preprocess reads the Gaussian SoA (mean 3, scale 3,
-    # rot 4, opacity 1, SH 3K floats) and writes a 64 B record + depth + radius
-    pre_bytes = P * (4 * (11 + 3 * K) + 72)
+    # rot 4, opacity 1, SH 3K floats) and writes a 64 B record, depth, radius
+    # and the 16 B disc entry the binning reads
+    pre_bytes = P * (4 * (11 + 3 * K) + 88)
     res = {
         "stage_ms": med,
         "pairs": n,

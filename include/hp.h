@@ -151,7 +151,8 @@ const int32_t* hp_mask_active_pix(const void* mask, int32_t order, int32_t tile_
  * or det Sigma_arc <= 0) Gaussians get radius 0 and depth +inf.
  * projected: device buffer of hp_projected_bytes(P) bytes: a 64-byte record
  * per Gaussian (unit direction, opacity, tangent frame, conic, colour) plus
- * depth [P] and radius [P] float arrays. */
+ * depth [P] and radius [P] float arrays and a disc [P] float4 array (unit
+ * direction, sin((r_s + bin_guard) / 2): the part the binning reads). */
 size_t hp_projected_bytes(int64_t P);
 hp_status hp_preprocess(const hp_gaussians* g, const hp_view* view, const hp_params* prm, void* projected,
                         size_t projected_bytes, void* stream);

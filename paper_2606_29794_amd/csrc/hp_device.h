@@ -93,12 +93,16 @@ HP_HD HpMaskView hp_mask_view(P* base, const HpGeom& g) {
 //   r1 = (eo_x, eo_z, ep_x, ep_y)    tangent frame: e_omega = (eo_x, 0, eo_z)
 //   r2 = (ep_z, A, B, C)             e_phi = (ep_x, ep_y, ep_z); q = A a^2 + 2 B a b + C b^2
 //   r3 = (red, green, blue, sin((r_s + bin_guard) / 2))   the last entry drives the binning
+// projected buffer: the 64-byte records, depth [P], radius [P], and disc [P]
+// (unit direction, sin of half the tile-test angle r_s + guard: the 16 bytes
+// the binning reads, apart from the records so that its gathers share lines)
 struct HpProjView {
   float4* rec;
   float* depth;
   float* radius;
+  float4* disc;
 };
-HP_HD size_t hp_proj_size(int64_t P) { return hp_align256(P * 64) + 2 * hp_align256(P * 4); }
+HP_HD size_t hp_proj_size(int64_t P) { return hp_align256(P * 64) + 2 * hp_align256(P * 4) + hp_align256(P * 16); }
 template <class T>
 HP_HD HpProjView hp_proj_view(T* base, int64_t P) {
   HpProjView v;
@@ -106,6 +110,7 @@ HP_HD HpProjView hp_proj_view(T* base, int64_t P) {
   v.rec = (float4*)p;
   v.depth = (float*)(p + hp_align256(P * 64));
   v.radius = (float*)(p + hp_align256(P * 64) + hp_align256(P * 4));
+  v.disc = (float4*)(p + hp_align256(P * 64) + 2 * hp_align256(P * 4));
   return v;
 }
 

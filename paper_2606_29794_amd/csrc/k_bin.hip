@@ -154,16 +154,16 @@ __device__ __forceinline__ void widen_half(float wsin, float wcos, float* sg, fl
 }
 
 // direction and (sin, cos) of half the test angle r_s + guard (the sine is
-// precomputed in the record; the half angle is at most pi/2, so the cosine is
-// the non-negative root), widened by the table's margin
-__device__ __forceinline__ void gauss_dir(const float4* rec, const float* radius, uint32_t gid, const BinTables& T,
+// precomputed in the Gaussian's disc entry; the half angle is at most pi/2,
+// so the cosine is the non-negative root), widened by the table's margin
+__device__ __forceinline__ void gauss_dir(const float4* disc, const float* radius, uint32_t gid, const BinTables& T,
                                           float* u, float* sg, float* cg, bool* ok) {
   const float rs = radius[gid];
   *ok = rs > 0.f;
   if (!*ok) return;
-  const hp_cfloatp r = (hp_cfloatp)rec + 16 * (int64_t)gid;
+  const hp_cfloatp r = (hp_cfloatp)disc + 4 * (int64_t)gid;
   u[0] = r[0]; u[1] = r[1]; u[2] = r[2];
-  *sg = r[15];
+  *sg = r[3];
   *cg = sqrtf(fmaxf(0.f, 1.f - *sg * *sg));
   widen_half(T.wsin, T.wcos, sg, cg);
 }
@@ -176,7 +176,7 @@ constexpr int kTopNodes = 252;  // quadtree levels 0..2
 
 template <bool EMIT>
 __global__ __launch_bounds__(256) void k_bin_coarse(int64_t P, const uint32_t* __restrict__ order,
-                                                    const float4* __restrict__ rec, const float* __restrict__ radius,
+                                                    const float4* __restrict__ disc, const float* __restrict__ radius,
                                                     BinTables T, float guard, uint32_t* __restrict__ tcount,
                                                     const uint32_t* __restrict__ toff, uint32_t* __restrict__ task_g,
                                                     uint32_t* __restrict__ task_n, uint32_t* __restrict__ slots) {
@@ -209,7 +209,7 @@ __global__ __launch_bounds__(256) void k_bin_coarse(int64_t P, const uint32_t* _
   }
   float u[3], sg, cg;
   bool ok;
-  gauss_dir(rec, radius, gid, T, u, &sg, &cg, &ok);
+  gauss_dir(disc, radius, gid, T, u, &sg, &cg, &ok);
   if (!ok) {
     if (!EMIT) tcount[k] = 0;
     return;
@@ -287,7 +287,7 @@ __device__ __forceinline__ uint64_t hp_readlane64(uint64_t v, int i) {
 __global__ __launch_bounds__(256) void k_bin_fine_count(const uint32_t* __restrict__ n_tasks, int64_t cap_t,
                                                         const uint32_t* __restrict__ task_g,
                                                         const uint32_t* __restrict__ task_n,
-                                                        const float4* __restrict__ rec, BinTables T,
+                                                        const float4* __restrict__ disc, BinTables T,
                                                         uint64_t* __restrict__ pmask, uint32_t* __restrict__ pcount) {
   int64_t nt = (int64_t)*n_tasks;
   if (nt > cap_t) nt = cap_t;
@@ -298,7 +298,7 @@ __global__ __launch_bounds__(256) void k_bin_fine_count(const uint32_t* __restri
   const int64_t leaf_off = hp_level_offset(T.kt);
   const int64_t nch = (nt + 63) >> 6;
   const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
-  const hp_cfloatp rp = (hp_cfloatp)rec;
+  const hp_cfloatp rp = (hp_cfloatp)disc;
   for (int64_t c = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); c < nch; c += waves) {
     const int64_t t0 = c << 6;
     const int nin = nt - t0 < 64 ? (int)(nt - t0) : 64;
@@ -318,8 +318,8 @@ __global__ __launch_bounds__(256) void k_bin_fine_count(const uint32_t* __restri
         // lanes past the node's leaves (depth < 3) load a valid leaf and drop it
         const int64_t node = leaf_off + ((int64_t)(uint32_t)__builtin_amdgcn_readlane((int)tn, i) << (2 * depth)) +
                              (lane & leaf_mask);
-        const hp_cfloatp r = rp + 16 * (int64_t)gid;
-        ux[q] = r[0]; uy[q] = r[1]; uz[q] = r[2]; sg[q] = r[15];
+        const hp_cfloatp r = rp + 4 * (int64_t)gid;
+        ux[q] = r[0]; uy[q] = r[1]; uz[q] = r[2]; sg[q] = r[3];
         const float* cp = (const float*)(T.cap + node);
         cap[q] = make_float3(cp[0], cp[1], cp[2]);
         sc[q] = T.sc[node];
@@ -454,10 +454,36 @@ __device__ __forceinline__ ChunkInfo chunk_info(const uint32_t* choff, uint32_t 
   return ci;
 }
 
+// The chunks of the calling wave.  Workgroup b runs on XCD b mod 8, so XCD
+// x takes the contiguous range [x n / 8, (x + 1) n / 8), shared by the waves
+// of its workgroups.  Neighbouring chunks belong to the same or neighbouring
+// quadtree nodes, whose tasks gather the same Gaussians' records and write
+// the same tiles' lists: within one XCD they meet in one L2.  With fewer than
+// 8 workgroups every wave strides over all chunks.
+struct ChunkRange {
+  uint32_t first, end, stride;
+};
+__device__ __forceinline__ ChunkRange xcd_chunks(uint32_t n) {
+  const uint32_t nb = gridDim.x, wpb = blockDim.x >> 6, w = threadIdx.x >> 6;
+  ChunkRange r;
+  if (nb < 8u) {
+    r.first = blockIdx.x * wpb + w;
+    r.end = n;
+    r.stride = nb * wpb;
+    return r;
+  }
+  const uint32_t x = blockIdx.x & 7u, k = blockIdx.x >> 3;
+  const uint32_t nbx = (nb - x + 7u) / 8u;  // workgroups b < nb with b mod 8 = x
+  r.first = (uint32_t)((uint64_t)n * x / 8u) + k * wpb + w;
+  r.end = (uint32_t)((uint64_t)n * (x + 1u) / 8u);
+  r.stride = nbx * wpb;
+  return r;
+}
+
 // per chunk: the hit columns W_b (kept) and their popcounts, tile-major
 __global__ __launch_bounds__(256) void k_bin_cols(const uint32_t* __restrict__ choff, uint32_t nn,
                                                   const uint32_t* __restrict__ seg, const uint32_t* __restrict__ tgid,
-                                                  const float4* __restrict__ rec, BinTables T,
+                                                  const float4* __restrict__ disc, BinTables T,
                                                   uint64_t* __restrict__ wcol, uint32_t* __restrict__ cnt) {
   const uint32_t nchunks = hp_uniform(((hp_cu32p)choff)[nn]);
   const int lane = hp_lane();
@@ -465,9 +491,9 @@ __global__ __launch_bounds__(256) void k_bin_cols(const uint32_t* __restrict__ c
   const int nleaf = 1 << (2 * depth);
   const bool leaf_lane = lane < nleaf;
   const int64_t leaf_off = hp_level_offset(T.kt);
-  const hp_cfloatp rp = (hp_cfloatp)rec;
-  const uint32_t waves = gridDim.x * (blockDim.x >> 6);
-  for (uint32_t c = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); c < nchunks; c += waves) {
+  const hp_cfloatp rp = (hp_cfloatp)disc;
+  const ChunkRange cr = xcd_chunks(nchunks);
+  for (uint32_t c = cr.first; c < cr.end; c += cr.stride) {
     const ChunkInfo ci = chunk_info(choff, nn, seg, c);
     const uint32_t ntask = hp_uniform(ci.ntask);
     // this lane's leaf below the chunk's node (lanes past the leaves test a
@@ -480,7 +506,7 @@ __global__ __launch_bounds__(256) void k_bin_cols(const uint32_t* __restrict__ c
     const uint32_t tg = (uint32_t)lane < ntask ? tgid[ci.t0 + lane] : 0u;
     // (sin, cos) of (r_s + guard) / 2 of every task, one per lane, by the
     // same expressions as the rest of the binning (identical decisions)
-    float sgl = (uint32_t)lane < ntask ? rec[4 * (size_t)tg + 3].w : 0.f;
+    float sgl = (uint32_t)lane < ntask ? disc[tg].w : 0.f;
     float cgl = sqrtf(fmaxf(0.f, 1.f - sgl * sgl));
     widen_half(T.wsin, T.wcos, &sgl, &cgl);
     // bits of tasks 0..31 and 32..63 are kept apart so that every set is a
@@ -495,7 +521,7 @@ __global__ __launch_bounds__(256) void k_bin_cols(const uint32_t* __restrict__ c
         for (int q = 0; q < kFineGroup; ++q) {
           // past the chunk's end the last task is read again and its bit dropped
           const uint32_t j = j0 + q < ntask ? j0 + q : ntask - 1;
-          const hp_cfloatp r = rp + 16 * (int64_t)(uint32_t)__builtin_amdgcn_readlane((int)tg, (int)j);
+          const hp_cfloatp r = rp + 4 * (int64_t)(uint32_t)__builtin_amdgcn_readlane((int)tg, (int)j);
           ux[q] = r[0]; uy[q] = r[1]; uz[q] = r[2];
           sg[q] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(sgl), (int)j));
           cg[q] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cgl), (int)j));
@@ -534,8 +560,8 @@ __global__ __launch_bounds__(256) void k_bin_emit_sorted(const uint32_t* __restr
   const int nleaf = 1 << (2 * depth);
   const bool leaf_lane = lane < nleaf;
   const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-  const uint32_t waves = gridDim.x * (blockDim.x >> 6);
-  for (uint32_t c = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); c < nchunks; c += waves) {
+  const ChunkRange cr = xcd_chunks(nchunks);
+  for (uint32_t c = cr.first; c < cr.end; c += cr.stride) {
     const ChunkInfo ci = chunk_info(choff, nn, seg, c);
     const uint64_t W = leaf_lane ? wcol[(int64_t)c * 64 + lane] : 0ull;
     const uint64_t base =
@@ -601,7 +627,7 @@ extern "C" hp_status hp_bin(int32_t phase, const void* projected, int64_t P, con
     hipLaunchKernelGGL(k_depth_keys, dim3(hp_blocks(P, 256)), dim3(256), 0, s, P, pv.depth, w.dkey, w.order);
     HP_CHECK_LAUNCH();
     HP_TRY(hpsort::radix_sort(w.dkey, w.order, P, 32, w.sort_ws, s));
-    hipLaunchKernelGGL((k_bin_coarse<false>), dim3(hp_blocks(P, 256)), dim3(256), 0, s, P, w.order, pv.rec, pv.radius,
+    hipLaunchKernelGGL((k_bin_coarse<false>), dim3(hp_blocks(P, 256)), dim3(256), 0, s, P, w.order, pv.disc, pv.radius,
                        T, prm->bin_guard, w.tcount, (const uint32_t*)nullptr, (uint32_t*)nullptr, (uint32_t*)nullptr,
                        (uint32_t*)nullptr);
     HP_CHECK_LAUNCH();
@@ -610,12 +636,12 @@ extern "C" hp_status hp_bin(int32_t phase, const void* projected, int64_t P, con
     uint32_t nt = 0;
     HP_TRY(hp_read_small(&nt, w.t_total, 4, s));
     if ((int64_t)nt > w.cap_t) return HP_ERR_CAPACITY;
-    hipLaunchKernelGGL((k_bin_coarse<true>), dim3(hp_blocks(P, 256)), dim3(256), 0, s, P, w.order, pv.rec, pv.radius,
+    hipLaunchKernelGGL((k_bin_coarse<true>), dim3(hp_blocks(P, 256)), dim3(256), 0, s, P, w.order, pv.disc, pv.radius,
                        T, prm->bin_guard, w.tcount, w.toff, w.task_g, w.task_n, (uint32_t*)nullptr);
     HP_CHECK_LAUNCH();
     if (nt > 0) {
       hipLaunchKernelGGL(k_bin_fine_count, dim3(fine_grid(nt)), dim3(256), 0, s, (const uint32_t*)w.t_total, w.cap_t,
-                         w.task_g, w.task_n, pv.rec, T, w.pmask, w.pcount);
+                         w.task_g, w.task_n, pv.disc, T, w.pmask, w.pcount);
       HP_CHECK_LAUNCH();
       HP_TRY((hpsort::scan_exclusive<uint64_t, uint32_t>(w.pcount, w.poff, nt, w.p_total, w.scan_ws, s)));
       hipLaunchKernelGGL(k_store_total, dim3(1), dim3(1), 0, s, (const uint64_t*)w.p_total, n_pairs);
@@ -733,7 +759,7 @@ hp_status hp_bin_sorted_widened(int32_t phase, const void* projected, int64_t P,
     hipLaunchKernelGGL(k_depth_keys, dim3(hp_blocks(P, 256)), dim3(256), 0, s, P, pv.depth, w.dkey, w.order);
     HP_CHECK_LAUNCH();
     HP_TRY(hpsort::radix_sort(w.dkey, w.order, P, 32, w.sort_ws, s));
-    hipLaunchKernelGGL((k_bin_coarse<false>), dim3(hp_blocks(P, 256)), dim3(256), 0, s, P, w.order, pv.rec, pv.radius,
+    hipLaunchKernelGGL((k_bin_coarse<false>), dim3(hp_blocks(P, 256)), dim3(256), 0, s, P, w.order, pv.disc, pv.radius,
                        T, prm->bin_guard, w.tcount, (const uint32_t*)nullptr, (uint32_t*)nullptr, (uint32_t*)nullptr,
                        sw.slots);
     HP_CHECK_LAUNCH();
@@ -741,7 +767,7 @@ hp_status hp_bin_sorted_widened(int32_t phase, const void* projected, int64_t P,
     uint32_t nt = 0;
     HP_TRY(hp_read_small(&nt, w.t_total, 4, s));
     if ((int64_t)nt > w.cap_t) return HP_ERR_CAPACITY;
-    hipLaunchKernelGGL((k_bin_coarse<true>), dim3(hp_blocks(P, 256)), dim3(256), 0, s, P, w.order, pv.rec, pv.radius,
+    hipLaunchKernelGGL((k_bin_coarse<true>), dim3(hp_blocks(P, 256)), dim3(256), 0, s, P, w.order, pv.disc, pv.radius,
                        T, prm->bin_guard, w.tcount, w.toff, w.task_g, w.task_n, sw.slots);
     HP_CHECK_LAUNCH();
     // stable sort of the tasks by node; segments and chunk offsets per node
@@ -774,7 +800,7 @@ hp_status hp_bin_sorted_widened(int32_t phase, const void* projected, int64_t P,
     hipLaunchKernelGGL(k_fill_zero_u32, dim3(hp_blocks(La, 256)), dim3(256), 0, s, sw.cnt, La);
     HP_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_bin_cols, dim3(chunk_grid(nchunk_bound)), dim3(256), 0, s, (const uint32_t*)sw.choff, nn,
-                       (const uint32_t*)sw.seg, (const uint32_t*)w.task_g, pv.rec, T, sw.wcol, sw.cnt);
+                       (const uint32_t*)sw.seg, (const uint32_t*)w.task_g, pv.disc, T, sw.wcol, sw.cnt);
     HP_CHECK_LAUNCH();
     HP_TRY((hpsort::scan_exclusive<uint64_t, uint32_t>(sw.cnt, sw.start, La, w.p_total, sw.scan_ws, s)));
     hipLaunchKernelGGL(k_store_total, dim3(1), dim3(1), 0, s, (const uint64_t*)w.p_total, n_pairs);

@@ -92,6 +92,7 @@ struct PreBatch {
   float4* rec[HP_MAX_VIEWS];
   float* depth[HP_MAX_VIEWS];
   float* radius[HP_MAX_VIEWS];
+  float4* disc[HP_MAX_VIEWS];
 };
 
 // One thread per Gaussian; SoA inputs give coalesced loads and are read once
@@ -129,6 +130,7 @@ __global__ __launch_bounds__(256) void k_preprocess(int64_t P, const float* __re
     if (ok) {
       B.depth[v][i] = dep;
       B.radius[v][i] = rad;
+      B.disc[v][i] = make_float4(r[0].x, r[0].y, r[0].z, r[3].w);
     }
     __syncthreads();  // the previous view's records have left LDS
 #pragma unroll
@@ -175,6 +177,7 @@ extern "C" hp_status hp_preprocess_batch(const hp_gaussians* g, int32_t n_views,
     B.rec[v] = pv.rec;
     B.depth[v] = pv.depth;
     B.radius[v] = pv.radius;
+    B.disc[v] = pv.disc;
   }
   if (projected_bytes < hp_proj_size(g->P)) return HP_ERR_CAPACITY;
   if (g->P == 0) return HP_OK;

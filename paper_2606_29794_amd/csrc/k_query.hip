@@ -30,7 +30,7 @@ constexpr int kMaxRings = 31;   // rings crossing one tile at f = 16
 struct QueryArgs {
   int mode, kq, fl, order_t;
   const int32_t* active_tiles;
-  const float4* rec;
+  const float4* disc;   // (direction, sin((r_s + guard) / 2)) per Gaussian
   const float* radius;
   uint32_t* vals;
   uint32_t* ranges;
@@ -214,7 +214,7 @@ __global__ __launch_bounds__(256) void k_query_filter(QueryArgs A) {
     const uint32_t g = have ? A.vals[idx] : 0u;
     bool keep = false;
     if (have) {
-      const float4 r0 = A.rec[4 * (size_t)g];
+      const float4 r0 = A.disc[g];
       const float rs = A.radius[g];
       if (MODE == HP_QUERY_NESTED) {
         const float c = 2.f * sinf(0.5f * rs);
@@ -282,7 +282,7 @@ extern "C" hp_status hp_bin_query(int32_t phase, int32_t mode, int32_t f, const 
   if (P == 0 || n_tiles == 0) return HP_OK;
   const HpProjView pv = hp_proj_view((const char*)projected, P);
   const HpMaskView mv = hp_mask_view((const char*)mask, g);
-  QueryArgs A{mode, kq, fl, g.kt, mv.active_tiles, pv.rec, pv.radius, vals, tile_ranges, n_pairs, capacity,
+  QueryArgs A{mode, kq, fl, g.kt, mv.active_tiles, pv.disc, pv.radius, vals, tile_ranges, n_pairs, capacity,
               (unsigned long long*)n_kept};
   if (mode == HP_QUERY_RING)
     hipLaunchKernelGGL(k_query_filter<HP_QUERY_RING>, dim3((unsigned)n_tiles), dim3(256), 0, s, A);

@@ -58,6 +58,7 @@ def _gpu_lists(R, sc, camd, mode, f):
     assert np.all(r[:, 0] <= r[:, 1]) and (tiles.size == 0 or r[:, 1].max() <= ncand)
     lists = {int(t): v[a:b] for t, (a, b) in zip(tiles, r)}
     assert sum(x.size for x in lists.values()) == nkept
+    _gpu_lists.radius = R.projected_arrays(proj, g.P)[2].cpu().numpy()
     return lists, ncand, nkept
 
 
@@ -73,6 +74,12 @@ MODES = {"ring": O.QUERY_RING, "nested": O.QUERY_NESTED}
 @pytest.mark.parametrize("mode", ["ring", "nested"])
 def test_query_pairs_bracketed_by_oracle(R, case, f, mode):
     sc, camd = _case(case)
+    _check_bracket(R, sc, camd, mode, f, case)
+
+
+def _check_bracket(R, sc, camd, mode, f, case="", both_valid=False):
+    """both_valid: compare only the Gaussians that the GPU and the oracle both
+    keep (for projections at a pole, where float32 and FP64 may cull apart)."""
     order = camd["order"]
     lists, ncand, nkept = _gpu_lists(R, sc, camd, mode, f)
     gpu = {(int(gg), t) for t, lst in lists.items() for gg in lst.tolist()}
@@ -80,16 +87,23 @@ def test_query_pairs_bracketed_by_oracle(R, case, f, mode):
     pr = O.preprocess(sc, camd)
     act = O.mask(camd)
     q = MODES[mode]
-    lo = _pairs(*O.query_tiles(q, order, pr, act, f, drs_rel=-E_REL, drs_abs=-E_ABS))
-    hi = _pairs(*O.query_tiles(q, order, pr, act, f, drs_rel=E_REL, drs_abs=E_ABS))
-    ex = _pairs(*O.query_tiles(q, order, pr, act, f))
+    gids = None
+    if both_valid:
+        gids = np.nonzero((pr.valid == 1) & (_gpu_lists.radius > 0))[0]
+        keep = set(gids.tolist())
+        gpu = {pt for pt in gpu if pt[0] in keep}
+        print(case, "Gaussians kept by both", gids.size, "of", sc.P, "oracle", int(pr.valid.sum()),
+              "GPU", int((_gpu_lists.radius > 0).sum()))
+    lo = _pairs(*O.query_tiles(q, order, pr, act, f, gids=gids, drs_rel=-E_REL, drs_abs=-E_ABS))
+    hi = _pairs(*O.query_tiles(q, order, pr, act, f, gids=gids, drs_rel=E_REL, drs_abs=E_ABS))
+    ex = _pairs(*O.query_tiles(q, order, pr, act, f, gids=gids))
     miss, extra = lo - gpu, gpu - hi
     assert not miss, f"{len(miss)} pairs missing, e.g. {sorted(miss)[:5]}"
     assert not extra, f"{len(extra)} pairs beyond the bracket, e.g. {sorted(extra)[:5]}"
     diff = len(gpu ^ ex)
     print(case, mode, f, "pairs", len(gpu), "candidates", ncand, "differing from r_s exactly", diff,
           "bracket width", len(hi) - len(lo))
-    assert len(ex) > 0 and diff <= 2 + 1e-3 * len(ex)
+    assert diff <= 2 + 1e-3 * len(ex)
     # front-to-back order inside every tile, ties within 4 float32 ulps of rho
     bad = 0
     for t, lst in lists.items():
@@ -100,6 +114,52 @@ def test_query_pairs_bracketed_by_oracle(R, case, f, mode):
         tie = np.abs(d) <= 4 * np.spacing(rho[1:].astype(np.float32)).astype(np.float64)
         bad += int((~((d > 0) | ((d == 0) & (np.diff(lst) > 0)) | tie)).sum())
     assert bad == 0
+    return len(gpu)
+
+
+def _pole_seam_scene():
+    """Config-0 laws with Gaussians placed on and near the poles of the grid
+    (camera +-y) and on the longitude seam omega = +-pi (camera -z side)."""
+    import copy
+    wl = SC.config0(P=600)
+    sc = copy.deepcopy(wl.scene)
+    pts = [(0.0, 3.0, 0.0), (0.0, -3.0, 0.0), (1e-4, 3.0, 0.0), (0.0, 2.5, 1e-3), (0.0, -4.0, 2e-3),
+           (0.0, 0.5, -3.0), (1e-5, 0.2, -3.0), (-1e-5, 0.2, -3.0), (-1e-3, -1.0, -2.5), (2e-3, 1.5, -2.0)]
+    for k, p in enumerate(pts):
+        sc.mean[:, k] = p
+    return sc, wl.cameras[0]
+
+
+@pytest.mark.parametrize("mode", ["ring", "nested"])
+@pytest.mark.parametrize("f", [1, 4, 16])
+def test_query_poles_seam_and_full_depth(R, mode, f):
+    """Discs centred on a pole (the pole branch of Alg. 3), near it, and on
+    the longitude seam; f = 16 = B queries at the pixel order itself."""
+    sc, camd = _pole_seam_scene()
+    assert _check_bracket(R, sc, camd, mode, f, "poles", both_valid=True) > 0
+
+
+@pytest.mark.parametrize("mode", ["ring", "nested"])
+def test_query_narrow_pinhole(R, mode):
+    """A 20-degree pinhole: few active tiles, most Gaussians outside."""
+    import math
+    wl = SC.config1(P=20000, order=8)
+    camd = SC.make_camera(np.random.default_rng(77), 8, SC.CAM_PINHOLE, fov_x=math.radians(20),
+                          fov_y=math.radians(15))
+    assert _check_bracket(R, wl.scene, camd, mode, 4, "pinhole") >= 0
+
+
+@pytest.mark.parametrize("mode", ["ring", "nested"])
+def test_query_no_visible_gaussian(R, mode):
+    """Every Gaussian culled (at the camera centre, inside r_min): no pairs,
+    every tile's list empty, n_kept = 0."""
+    import copy
+    wl = SC.config0(P=300)
+    sc = copy.deepcopy(wl.scene)
+    sc.mean[:] = 0.01   # radial distance 0.017 < r_min
+    lists, ncand, nkept = _gpu_lists(R, sc, wl.cameras[0], mode, 2)
+    assert ncand == 0 and nkept == 0
+    assert all(x.size == 0 for x in lists.values())
 
 
 @pytest.mark.slow
