@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--profile-only", action="store_true", help="run warmup+steps without the extra passes")
     ap.add_argument("--no-queries", action="store_true", help="skip the paper-query (RING / NESTED x f) comparison")
+    ap.add_argument("--prefetch-streams", type=int, default=2,
+                    help="side streams that prepare later views during the step (0: none)")
     ap.add_argument("--query", default=None,
                     help="mode:f (ring:4, nested:4, ...): the timed steps use the paper's own tile query")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -95,9 +97,9 @@ def main():
         tot = 0.0
         # preprocess + binning of every view on a side stream, overlapping the
         # rendering of the views before it
-        pf = R.prefetch(g_det, cams, query)
+        pf = R.prefetch(g_det, cams, query, args.prefetch_streams) if args.prefetch_streams > 0 else None
         for v, cam in enumerate(cams):
-            rgb, T = render(*params, cam, R, fused_grad=True, prepared=pf.get(v))
+            rgb, T = render(*params, cam, R, fused_grad=True, query=query, prepared=pf.get(v) if pf else None)
             loss, _ = hssim_loss(rgb, targets[v], cam, 0.2, R)
             loss.backward()
         return tot

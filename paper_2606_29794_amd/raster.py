@@ -124,24 +124,31 @@ class Prepared:
 
 
 class Prefetch:
-    """Stages 1-2 of a sequence of views, made in order on a side stream by a
-    host thread of its own, so that they overlap the caller's rendering of
-    the views before them (the binning waits on its stream for small counts,
-    which then no longer stalls the caller).  get(i) returns view i."""
+    """Stages 1-2 of a sequence of views, made on side streams by host threads
+    of their own (view i on stream i mod n), so that they overlap the
+    caller's rendering of the views before them.  The binning waits on its
+    stream for small counts, which then no longer stalls the caller, and its
+    many short kernels, which queue behind the caller's long render kernels,
+    progress for several views at once.  get(i) returns view i."""
 
-    def __init__(self, R: "Rasterizer", g: "Gaussians", cams, query=None):
-        stream = R.side_stream()
-        # the side stream first waits for the work the caller queued so far
+    def __init__(self, R: "Rasterizer", g: "Gaussians", cams, query=None, streams: int = 2):
+        n = max(1, min(streams, len(cams)))
+        side = R.side_streams(n)
+        # the side streams first wait for the work the caller queued so far
         # (e.g. an update of the Gaussians)
         start = torch.cuda.Event()
         start.record(torch.cuda.current_stream(R.device))
-        stream.wait_event(start)
+        for st in side:
+            st.wait_event(start)
 
-        def run(cam):
-            with torch.cuda.device(R.device), torch.cuda.stream(stream):
+        def run(cam, st):
+            with torch.cuda.device(R.device), torch.cuda.stream(st):
                 return R.prepare(g, cam, query)
 
-        self._futures = [R.side_pool().submit(run, c) for c in cams]
+        # n host threads: views 0 .. n-1 start at once, and each later view
+        # when an earlier one is done
+        pool = R.side_pool(n)
+        self._futures = [pool.submit(run, c, side[i % n]) for i, c in enumerate(cams)]
 
     def get(self, i: int) -> Prepared:
         return self._futures[i].result()
@@ -161,26 +168,33 @@ class Rasterizer:
         self._ready = {}
         # the caches may be used from several host threads (serving workers)
         self._lock = threading.RLock()
-        self._side = None
+        self._sides = []
         self._pool = None
+        self._pool_n = 0
 
-    def side_stream(self) -> torch.cuda.Stream:
-        """The stream of prefetch() (default priority), created once."""
+    def side_streams(self, n: int) -> list:
+        """The first n streams of prefetch() (default priority), created once."""
         with self._lock:
-            if self._side is None:
-                self._side = torch.cuda.Stream(device=self.device)
-            return self._side
+            while len(self._sides) < n:
+                self._sides.append(torch.cuda.Stream(device=self.device))
+            return self._sides[:n]
 
-    def side_pool(self) -> ThreadPoolExecutor:
+    def side_pool(self, n: int) -> ThreadPoolExecutor:
+        """Host threads of prefetch(), at least n."""
         with self._lock:
-            if self._pool is None:
-                self._pool = ThreadPoolExecutor(max_workers=1, thread_name_prefix="hp-prefetch")
+            if self._pool_n < n:
+                if self._pool is not None:
+                    self._pool.shutdown(wait=False)  # its queued work still runs
+                self._pool = ThreadPoolExecutor(max_workers=n, thread_name_prefix="hp-prefetch")
+                self._pool_n = n
             return self._pool
 
-    def prefetch(self, g: "Gaussians", cams, query=None) -> Prefetch:
-        """Start stages 1-2 of every camera in `cams` on the side stream;
-        pass prefetch.get(i) as forward(..., prepared=) / render(..., prepared=)."""
-        return Prefetch(self, g, cams, query)
+    def prefetch(self, g: "Gaussians", cams, query=None, streams: int = 2) -> Prefetch:
+        """Start stages 1-2 of every camera in `cams` on up to `streams` side
+        streams (with the caller's stream, 4: the hardware queues a process
+        gets by default); pass prefetch.get(i) as forward(..., prepared=) /
+        render(..., prepared=)."""
+        return Prefetch(self, g, cams, query, streams)
 
     def _created(self, key):
         ev = torch.cuda.Event()
