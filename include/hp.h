@@ -197,7 +197,10 @@ hp_status hp_bin(int32_t phase, const void* projected, int64_t P, const hp_view*
  * phase as for hp_bin (COUNT writes *n_pairs; EMIT fills vals [capacity] with
  * Gaussian ids grouped by tile and tile_ranges [n_tiles][2] with each active
  * tile's (start, end) in vals, n_tiles from hp_mask_counts).  If *n_pairs >
- * capacity, EMIT writes no vals.  COUNT and EMIT each wait once for `stream`.
+ * capacity, EMIT writes neither vals nor tile_ranges.  COUNT waits once for
+ * `stream` (the task count sizes the task sort); EMIT does not wait.  Until
+ * COUNT's work completes, *n_pairs holds INT64_MAX, so an EMIT after a COUNT
+ * that returned an error writes nothing.
  * ws: hp_bin_sorted_workspace_bytes(P, order, tile_log2) bytes. */
 size_t hp_bin_sorted_workspace_bytes(int64_t P, int32_t order, int32_t tile_log2);
 hp_status hp_bin_sorted(int32_t phase, const void* projected, int64_t P, const hp_view* view, const hp_params* prm,

@@ -578,7 +578,8 @@ __global__ __launch_bounds__(256) void k_bin_emit_sorted(const uint32_t* __restr
 // (start, end) of every active tile from the scanned column counts
 __global__ void k_bin_ranges(int32_t n_tiles, const int32_t* __restrict__ active_tiles, int depth,
                              const uint32_t* __restrict__ choff, const uint64_t* __restrict__ start,
-                             uint32_t* __restrict__ ranges) {
+                             const int64_t* __restrict__ n_pairs, int64_t capacity, uint32_t* __restrict__ ranges) {
+  if (*n_pairs > capacity) return;  // nothing was emitted (or the count did not complete)
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n_tiles) return;
   const int t = active_tiles[k];
@@ -591,6 +592,8 @@ __global__ void k_bin_ranges(int32_t n_tiles, const int32_t* __restrict__ active
 
 __global__ void k_store_total(const uint64_t* grand, int64_t* n_pairs) { *n_pairs = (int64_t)*grand; }
 __global__ void k_store_zero(int64_t* n_pairs) { *n_pairs = 0; }
+// a pair count no buffer holds: the emission kernels then write nothing
+__global__ void k_store_unfinished(int64_t* n_pairs) { *n_pairs = INT64_MAX; }
 
 // one wave per 64 tasks, at most 8192 blocks of 4 waves that loop over them
 static unsigned fine_grid(int64_t nt) {
@@ -755,6 +758,11 @@ hp_status hp_bin_sorted_widened(int32_t phase, const void* projected, int64_t P,
       HP_CHECK_LAUNCH();
       return HP_OK;
     }
+    // until the count below completes, *n_pairs says that nothing may be
+    // emitted: an EMIT after a COUNT that failed (too many tasks) writes
+    // nothing, without reading the task count back
+    hipLaunchKernelGGL(k_store_unfinished, dim3(1), dim3(1), 0, s, n_pairs);
+    HP_CHECK_LAUNCH();
     // tasks (Gaussian, node at the split level) in depth order
     hipLaunchKernelGGL(k_depth_keys, dim3(hp_blocks(P, 256)), dim3(256), 0, s, P, pv.depth, w.dkey, w.order);
     HP_CHECK_LAUNCH();
@@ -807,17 +815,15 @@ hp_status hp_bin_sorted_widened(int32_t phase, const void* projected, int64_t P,
     HP_CHECK_LAUNCH();
   }
   if ((phase & HP_BIN_EMIT) && P > 0) {
-    uint32_t nt = 0;
-    HP_TRY(hp_read_small(&nt, w.t_total, 4, s));
-    if ((int64_t)nt > w.cap_t) return HP_ERR_CAPACITY;
-    const int64_t nchunk_bound = (int64_t)nt / 64 + sw.nn + 1;
-    hipLaunchKernelGGL(k_bin_emit_sorted, dim3(chunk_grid(nchunk_bound)), dim3(256), 0, s, (const uint32_t*)sw.choff,
+    // the chunk count is read on the device: launch for the workspace's bound
+    hipLaunchKernelGGL(k_bin_emit_sorted, dim3(chunk_grid(sw.nchunk_max)), dim3(256), 0, s, (const uint32_t*)sw.choff,
                        nn, (const uint32_t*)sw.seg, (const uint32_t*)w.task_g, depth, (const uint64_t*)sw.wcol,
                        (const uint64_t*)sw.start, (const int64_t*)n_pairs, capacity, vals);
     HP_CHECK_LAUNCH();
     if (n_tiles > 0) {
       hipLaunchKernelGGL(k_bin_ranges, dim3(hp_blocks(n_tiles, 256)), dim3(256), 0, s, n_tiles, mv.active_tiles, depth,
-                         (const uint32_t*)sw.choff, (const uint64_t*)sw.start, tile_ranges);
+                         (const uint32_t*)sw.choff, (const uint64_t*)sw.start, (const int64_t*)n_pairs, capacity,
+                         tile_ranges);
       HP_CHECK_LAUNCH();
     }
   } else if ((phase & HP_BIN_EMIT) && n_tiles > 0) {
