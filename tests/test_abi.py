@@ -61,3 +61,25 @@ def test_bin_query_rejects_bad_mode_and_depth():
     for f in (0, 3, 6, 32, -4):
         assert _query(A.HP_QUERY_RING, f) == inv, f
     assert _query(A.HP_QUERY_NESTED, 8, order=2) == inv   # Nside 4: at most f = 4
+
+
+def test_every_entry_point_checks_null_arguments_on_the_host():
+    """Every hp_status entry point called with null pointers and zero sizes
+    returns OK (nothing to do), INVALID_ARG or CAPACITY from its host-side
+    checks, before any device work: a launch would fail here without a GPU
+    and show up as HP_ERR_DEVICE."""
+    L = A.lib()
+    statuses = {}
+    for name, (res, args) in A._PROTOS.items():
+        if res is not C.c_int32 or name in ("hp_read_total",):
+            continue
+        vals = []
+        for t in args:
+            if t in (C.c_int32, C.c_int64, C.c_size_t):
+                vals.append(t(0))
+            else:
+                vals.append(None)
+        statuses[name] = int(getattr(L, name)(*vals))
+    bad = {k: v for k, v in statuses.items() if v not in (0, 1, 3)}
+    assert not bad, bad
+    assert sum(v == 1 for v in statuses.values()) >= 15, statuses
