@@ -464,7 +464,10 @@ struct ChunkRange {
   uint32_t first, end, stride;
 };
 __device__ __forceinline__ ChunkRange xcd_chunks(uint32_t n) {
-  const uint32_t nb = gridDim.x, wpb = blockDim.x >> 6, w = threadIdx.x >> 6;
+  // the wave index is uniform, which the compiler cannot see: without the
+  // readfirstlane every chunk index (and the node search below) would live
+  // in vector registers, with a vector load per search step
+  const uint32_t nb = gridDim.x, wpb = blockDim.x >> 6, w = hp_uniform(threadIdx.x >> 6);
   ChunkRange r;
   if (nb < 8u) {
     r.first = blockIdx.x * wpb + w;
@@ -561,17 +564,36 @@ __global__ __launch_bounds__(256) void k_bin_emit_sorted(const uint32_t* __restr
   const bool leaf_lane = lane < nleaf;
   const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   const ChunkRange cr = xcd_chunks(nchunks);
-  for (uint32_t c = cr.first; c < cr.end; c += cr.stride) {
+  // a chunk's columns, output slots and Gaussian ids
+  auto fetch = [&](uint32_t c, uint64_t* W, uint64_t* base, uint32_t* g) {
     const ChunkInfo ci = chunk_info(choff, nn, seg, c);
-    const uint64_t W = leaf_lane ? wcol[(int64_t)c * 64 + lane] : 0ull;
-    const uint64_t base =
-        leaf_lane ? start[(int64_t)(c - ci.local) * nleaf + (int64_t)lane * ci.nchn + ci.local] : 0ull;
-    const uint32_t g = (uint32_t)lane < ci.ntask ? tgid[ci.t0 + lane] : 0u;
+    *W = leaf_lane ? wcol[(int64_t)c * 64 + lane] : 0ull;
+    *base = leaf_lane ? start[(int64_t)(c - ci.local) * nleaf + (int64_t)lane * ci.nchn + ci.local] : 0ull;
+    *g = (uint32_t)lane < ci.ntask ? tgid[ci.t0 + lane] : 0u;
+  };
+  uint32_t c = cr.first;
+  if (c >= cr.end) return;
+  uint64_t W, base;
+  uint32_t g;
+  fetch(c, &W, &base, &g);
+  while (true) {
+    // the next chunk's loads go out before this chunk's stores, so their
+    // latency overlaps the store loop instead of following it
+    const uint32_t cn = c + cr.stride;
+    const bool more = cn < cr.end;
+    uint64_t Wn = 0ull, basen = 0ull;
+    uint32_t gn = 0u;
+    if (more) fetch(cn, &Wn, &basen, &gn);
     for (int b = 0; b < nleaf; ++b) {
       const uint64_t Wb = hp_readlane64(W, b);
       if (Wb == 0) continue;
       if ((Wb >> lane) & 1ull) vals[hp_readlane64(base, b) + (uint64_t)__popcll(Wb & below)] = g;
     }
+    if (!more) break;
+    c = cn;
+    W = Wn;
+    base = basen;
+    g = gn;
   }
 }
 
