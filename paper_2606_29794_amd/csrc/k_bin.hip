@@ -494,7 +494,11 @@ __global__ __launch_bounds__(256) void k_bin_cols(const uint32_t* __restrict__ c
   const int nleaf = 1 << (2 * depth);
   const bool leaf_lane = lane < nleaf;
   const int64_t leaf_off = hp_level_offset(T.kt);
-  const hp_cfloatp rp = (hp_cfloatp)disc;
+  // the chunk's 64 tasks' discs, one per lane, published for the whole wave:
+  // (direction, sin) and cos of half the widened test angle
+  __shared__ float4 s_disc[4][64];
+  __shared__ float s_cg[4][64];
+  const int wv = threadIdx.x >> 6;
   const ChunkRange cr = xcd_chunks(nchunks);
   for (uint32_t c = cr.first; c < cr.end; c += cr.stride) {
     const ChunkInfo ci = chunk_info(choff, nn, seg, c);
@@ -507,11 +511,17 @@ __global__ __launch_bounds__(256) void k_bin_cols(const uint32_t* __restrict__ c
     const float2 h = T.sc[leaf];
     const bool act = leaf_lane && T.leaf_active[leaf] != 0;
     const uint32_t tg = (uint32_t)lane < ntask ? tgid[ci.t0 + lane] : 0u;
-    // (sin, cos) of (r_s + guard) / 2 of every task, one per lane, by the
-    // same expressions as the rest of the binning (identical decisions)
-    float sgl = (uint32_t)lane < ntask ? disc[tg].w : 0.f;
+    // every task's disc in one gather (lane j: task j); (sin, cos) of
+    // (r_s + guard) / 2 by the same expressions as the rest of the binning
+    // (identical decisions)
+    const float4 dl = (uint32_t)lane < ntask ? disc[tg] : make_float4(0.f, 0.f, 0.f, 0.f);
+    float sgl = dl.w;
     float cgl = sqrtf(fmaxf(0.f, 1.f - sgl * sgl));
     widen_half(T.wsin, T.wcos, &sgl, &cgl);
+    __builtin_amdgcn_wave_barrier();  // the previous chunk's reads are done
+    s_disc[wv][lane] = make_float4(dl.x, dl.y, dl.z, sgl);
+    s_cg[wv][lane] = cgl;
+    __builtin_amdgcn_wave_barrier();
     // bits of tasks 0..31 and 32..63 are kept apart so that every set is a
     // 32-bit select-or
     uint32_t Wh[2] = {0u, 0u};
@@ -524,10 +534,9 @@ __global__ __launch_bounds__(256) void k_bin_cols(const uint32_t* __restrict__ c
         for (int q = 0; q < kFineGroup; ++q) {
           // past the chunk's end the last task is read again and its bit dropped
           const uint32_t j = j0 + q < ntask ? j0 + q : ntask - 1;
-          const hp_cfloatp r = rp + 4 * (int64_t)(uint32_t)__builtin_amdgcn_readlane((int)tg, (int)j);
-          ux[q] = r[0]; uy[q] = r[1]; uz[q] = r[2];
-          sg[q] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(sgl), (int)j));
-          cg[q] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cgl), (int)j));
+          const float4 d = s_disc[wv][j];  // same address on every lane: a broadcast
+          ux[q] = d.x; uy[q] = d.y; uz[q] = d.z; sg[q] = d.w;
+          cg[q] = s_cg[wv][j];
         }
 #pragma unroll
         for (int q = 0; q < kFineGroup; ++q) {
