@@ -43,6 +43,25 @@ __device__ __forceinline__ int64_t ss_slot(const SsimArgs& A, int64_t q) {
   return (int64_t)A.tile_start[t] + rank;
 }
 
+// Patch cell of gather index i (a bijection of [0, H*H)): the first B*B
+// indices are the tile's own pixels in NESTED order, which a fully active
+// tile stores contiguously (coalesced loads), the rest the halo row by row.
+__device__ __forceinline__ int ss_cell(int i, int B, int H) {
+  if (i < B * B) {
+    const int x = (int)hp_compact_bits((uint32_t)i), y = (int)hp_compact_bits((uint32_t)i >> 1);
+    return (y + SS_R) * H + x + SS_R;
+  }
+  int h = i - B * B;
+  if (h < SS_R * H) return h;  // rows above the tile
+  h -= SS_R * H;
+  if (h < 2 * SS_R * B) {  // left and right of the tile's rows
+    const int row = SS_R + h / (2 * SS_R), c = h % (2 * SS_R);
+    return row * H + (c < SS_R ? c : c + B);
+  }
+  h -= 2 * SS_R * B;
+  return (SS_R + B) * H + h;  // rows below
+}
+
 __device__ __forceinline__ void ss_tile_origin(const SsimArgs& A, int ct, int* f, int* x0, int* y0) {
   const int t = A.active_tiles[ct];
   int tx, ty;
@@ -67,7 +86,8 @@ __global__ __launch_bounds__(256) void k_ssim_fwd(SsimArgs A, const float* __res
   const int B = 1 << A.b, H = B + 2 * SS_R;
   int f, x0, y0;
   ss_tile_origin(A, ct, &f, &x0, &y0);
-  for (int cell = tid; cell < H * H; cell += 256) {
+  for (int i = tid; i < H * H; i += 256) {
+    const int cell = ss_cell(i, B, H);
     const int cx = cell % H, cy = cell / H;
     const int64_t slot = ss_slot(A, hp_chart_pixel(A.order, f, x0 + cx - SS_R, y0 + cy - SS_R));
     float m = 0.f, v[6] = {0, 0, 0, 0, 0, 0};
@@ -221,7 +241,8 @@ __global__ __launch_bounds__(256) void k_ssim_bwd(SsimArgs A, const float* __res
   const int B = 1 << A.b, H = B + 2 * SS_R;
   int f, x0, y0;
   ss_tile_origin(A, ct, &f, &x0, &y0);
-  for (int cell = tid; cell < H * H; cell += 256) {
+  for (int i = tid; i < H * H; i += 256) {
+    const int cell = ss_cell(i, B, H);
     const int cx = cell % H, cy = cell / H;
     const int64_t slot = ss_slot(A, hp_chart_pixel(A.order, f, x0 + cx - SS_R, y0 + cy - SS_R));
 #pragma unroll
