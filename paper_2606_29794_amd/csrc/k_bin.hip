@@ -298,12 +298,17 @@ __global__ __launch_bounds__(256) void k_bin_fine_count(const uint32_t* __restri
   const int64_t leaf_off = hp_level_offset(T.kt);
   const int64_t nch = (nt + 63) >> 6;
   const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
-  const hp_cfloatp rp = (hp_cfloatp)disc;
-  for (int64_t c = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); c < nch; c += waves) {
+  // the 64 tasks' discs, one gather per lane, read back as LDS broadcasts
+  __shared__ float4 s_disc[4][64];
+  const int wv = threadIdx.x >> 6;
+  for (int64_t c = (int64_t)blockIdx.x * (blockDim.x >> 6) + hp_uniform(threadIdx.x >> 6); c < nch; c += waves) {
     const int64_t t0 = c << 6;
     const int nin = nt - t0 < 64 ? (int)(nt - t0) : 64;
     const uint32_t tg = lane < nin ? task_g[t0 + lane] : 0u;
     const uint32_t tn = lane < nin ? task_n[t0 + lane] : 0u;
+    __builtin_amdgcn_wave_barrier();  // the previous chunk's reads are done
+    s_disc[wv][lane] = lane < nin ? disc[tg] : make_float4(0.f, 0.f, 0.f, 0.f);
+    __builtin_amdgcn_wave_barrier();
     uint64_t mine = 0;
     for (int i0 = 0; i0 < nin; i0 += kFineGroup) {
       float3 cap[kFineGroup];  // cap centre (the radius enters through sc)
@@ -314,12 +319,11 @@ __global__ __launch_bounds__(256) void k_bin_fine_count(const uint32_t* __restri
       for (int q = 0; q < kFineGroup; ++q) {
         // past the chunk's end the last task is loaded again; its result is dropped
         const int i = i0 + q < nin ? i0 + q : nin - 1;
-        const uint32_t gid = (uint32_t)__builtin_amdgcn_readlane((int)tg, i);
         // lanes past the node's leaves (depth < 3) load a valid leaf and drop it
         const int64_t node = leaf_off + ((int64_t)(uint32_t)__builtin_amdgcn_readlane((int)tn, i) << (2 * depth)) +
                              (lane & leaf_mask);
-        const hp_cfloatp r = rp + 4 * (int64_t)gid;
-        ux[q] = r[0]; uy[q] = r[1]; uz[q] = r[2]; sg[q] = r[3];
+        const float4 d = s_disc[wv][i];  // same address on every lane: a broadcast
+        ux[q] = d.x; uy[q] = d.y; uz[q] = d.z; sg[q] = d.w;
         const float* cp = (const float*)(T.cap + node);
         cap[q] = make_float3(cp[0], cp[1], cp[2]);
         sc[q] = T.sc[node];
@@ -356,7 +360,7 @@ __global__ __launch_bounds__(256) void k_bin_fine_emit(const uint32_t* __restric
   const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   const int64_t nch = (nt + 63) >> 6;
   const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
-  for (int64_t c = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); c < nch; c += waves) {
+  for (int64_t c = (int64_t)blockIdx.x * (blockDim.x >> 6) + hp_uniform(threadIdx.x >> 6); c < nch; c += waves) {
     const int64_t t0 = c << 6;
     const int nin = nt - t0 < 64 ? (int)(nt - t0) : 64;
     const uint32_t tg = lane < nin ? task_g[t0 + lane] : 0u;
