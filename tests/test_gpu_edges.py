@@ -78,3 +78,35 @@ def test_empty_scene(R):
     g, c, st = PT.gpu_forward(R, sc, wl.cameras[0])
     assert st.n_pairs == 0
     assert float(st.T.min()) == 1.0 and float(st.rgb.abs().max()) == 0.0
+
+
+def test_wide_footprints_every_k2_range(R):
+    """Gaussians 20-70 degrees across at order 5: a large share of the pixels
+    they reach lie 14.5-30 degrees from the centre (the twelve-term series
+    range of k2 = (angle / sin angle)^2) or farther (the atan2 form), so every
+    form of k2 is checked, forward over every pixel and backward over the
+    robust ones."""
+    import torch
+    from paper_2606_29794_amd.raster import Gaussians
+    rng = np.random.default_rng(83)
+    sc = SC.make_scene(24, 3, "volume", 2.0, 6.0, 83, log_scale_mu=-0.3, log_scale_sigma=0.3, rng=rng)
+    cam = SC.make_camera(rng, 5, SC.CAM_FULL)
+    pr = O.preprocess(sc, cam)
+    act = O.mask(cam)
+    ang = np.arccos(np.clip(O.pix_vec(5, act) @ pr.dirs(), -1, 1))
+    s2 = np.sin(ang[ang <= pr.rs[None, :]]) ** 2
+    assert np.mean((s2 >= 1 / 16) & (s2 < 1 / 4)) > 0.2 and np.mean(s2 < 1 / 16) > 0.05
+    g, c, st = PT.gpu_forward(R, sc, cam)
+    rgb_o, T_o, nu_o, frag = O.render(sc, cam, pr, act, qtol=PT.qtol_for(), ttol=1e-3)
+    worst, nfrag = PT.compare_render(st.rgb.cpu().numpy().astype(np.float64), st.T.cpu().numpy().astype(np.float64),
+                                     rgb_o, T_o, frag)
+    dC = rng.normal(size=(3, act.size))
+    dC[:, frag > 0] = 0
+    z = torch.zeros_like
+    gr = Gaussians(z(g.mean), z(g.scale), z(g.rot), z(g.opacity), z(g.sh))
+    R.backward(g, st, torch.as_tensor(dC, dtype=torch.float32, device="cuda"), None, gr)
+    torch.cuda.synchronize()
+    go = O.render_bwd(sc, cam, pr, act, dC, None)
+    for k in ("mean", "scale", "rot", "opacity", "sh"):
+        PT.grad_compare(f"wide:{k}", getattr(gr, k).cpu().numpy(), getattr(go, k))
+    print("wide footprints: max err", worst, "fragile", nfrag)
