@@ -5,6 +5,7 @@ from __future__ import annotations
 
 import ctypes as C
 import math
+import queue
 import threading
 from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass, field
@@ -125,8 +126,8 @@ class Prepared:
 
 class Prefetch:
     """Stages 1-2 of a sequence of views, made on side streams by host threads
-    of their own (view i on stream i mod n), so that they overlap the
-    caller's rendering of the views before them.  The binning waits on its
+    of their own (each view on a stream no other view is using at the time),
+    so that they overlap the caller's rendering of the views before them.  The binning waits on its
     stream for small counts, which then no longer stalls the caller, and its
     many short kernels, which queue behind the caller's long render kernels,
     progress for several views at once.  get(i) returns view i."""
@@ -141,14 +142,25 @@ class Prefetch:
         for st in side:
             st.wait_event(start)
 
-        def run(cam, st):
-            with torch.cuda.device(R.device), torch.cuda.stream(st):
-                return R.prepare(g, cam, query)
+        # a view takes whichever stream is free: views finish out of order,
+        # and two views on one stream would interleave their kernels and
+        # each wait for the other's at its read-backs
+        free = queue.SimpleQueue()
+        for st in side:
+            free.put(st)
+
+        def run(cam):
+            st = free.get()  # waits only if the pool has more threads than streams
+            try:
+                with torch.cuda.device(R.device), torch.cuda.stream(st):
+                    return R.prepare(g, cam, query)
+            finally:
+                free.put(st)
 
         # n host threads: views 0 .. n-1 start at once, and each later view
         # when an earlier one is done
         pool = R.side_pool(n)
-        self._futures = [pool.submit(run, c, side[i % n]) for i, c in enumerate(cams)]
+        self._futures = [pool.submit(run, c) for c in cams]
 
     def get(self, i: int) -> Prepared:
         return self._futures[i].result()
