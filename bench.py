@@ -40,7 +40,7 @@ def parse():
     ap.add_argument("--views", type=int, default=4)
     ap.add_argument("--order", type=int, default=9)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-pixels", type=int, default=64)
+    ap.add_argument("--cpu-pixels", type=int, default=3072)
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--profile-only", action="store_true", help="run warmup+steps without the extra passes")
