@@ -82,3 +82,39 @@ def test_backward_sparse_upstream_full_size(R, name, n_pix):
     for k in ("mean", "scale", "rot", "opacity", "sh"):
         e = PT.grad_compare(f"{name}:{k}", getattr(gr, k).cpu().numpy(), getattr(go, k))
         print(name, k, "rel err", e)
+
+
+def test_timed_step_equals_plain_views_full_size(R):
+    """The step the benchmark times on config 2 (four full-sphere views at
+    Nside 512, stages 1-2 prepared on two side streams while earlier views
+    render, loss and backward accumulating into the parameters' .grad) gives
+    the same images, bit for bit, and the same gradients, up to the order of
+    float atomics, as rendering each view through the plain forward, which
+    the tests above check against the oracle."""
+    import torch
+    from paper_2606_29794_amd.raster import Camera, Gaussians
+    from paper_2606_29794_amd.render import hssim_loss, render
+    wl = SC.config2()
+    g = Gaussians.from_scene(wl.scene)
+    cams = [Camera.from_dict(c) for c in wl.cameras]
+    targets = [torch.as_tensor(SC.target_image(wl.seed, v, R.mask(c).n_active), device="cuda")
+               for v, c in enumerate(cams)]
+    out = []
+    for streams in (0, 2, 2):
+        params = [t.clone().requires_grad_(True) for t in (g.mean, g.scale, g.rot, g.opacity, g.sh)]
+        pf = R.prefetch(Gaussians(*[p.detach() for p in params]), cams, streams=streams) if streams else None
+        imgs = []
+        for v, cam in enumerate(cams):
+            rgb, T = render(*params, cam, R, fused_grad=True, prepared=pf.get(v) if pf else None)
+            loss, _ = hssim_loss(rgb, targets[v], cam, 0.2, R)
+            loss.backward()
+            imgs.append(rgb.detach().clone())
+        torch.cuda.synchronize()
+        out.append((imgs, [p.grad.double().cpu().numpy().ravel() for p in params]))
+        del params, pf
+    for imgs, grads in out[1:]:
+        for a, b in zip(out[0][0], imgs):
+            assert torch.equal(a, b)
+        for a, b, k in zip(out[0][1], grads, ("mean", "scale", "rot", "opacity", "sh")):
+            assert np.linalg.norm(a - b) <= 1e-5 * np.linalg.norm(a), k
+    print("config 2 timed step: 4 views equal to the plain path")
