@@ -256,3 +256,68 @@ def test_tile_sets_are_conservative_and_lists_sorted():
     nc = O.n_contrib(sc, cam, pr, lst, ranges, act)
     rgb, T, nu, fr = O.render(sc, cam, pr, act)
     assert np.all(nc >= nu)
+
+
+def _hand_list_scene(order, p, opac_near):
+    """A pixel p, four or five 'near' Gaussians centred on its direction
+    (q ~ 0 there) and four 'far' ones 0.2 rad away (q ~ 400 at p), interleaved
+    in depth.  Returns the scene, the list (front to back) and which entries
+    are near."""
+    d0 = O.pix_vec(order, np.array([p]))[0]
+    ax = np.cross(d0, [0.0, 1.0, 0.0]); ax /= np.linalg.norm(ax)
+    th = 0.2
+    d1 = d0 * math.cos(th) + np.cross(ax, d0) * math.sin(th)
+    kinds = ["far", "near", "far", "near", "near", "far", "near", "near", "far"]
+    radii = np.linspace(1.5, 5.5, len(kinds))
+    means = np.stack([(d0 if k == "near" else d1) * r for k, r in zip(kinds, radii)], 1)
+    scales = np.stack([[0.01 * r] * 3 for r in radii], 1)   # 0.01 rad angular sigma
+    opac = np.array([opac_near if k == "near" else 0.9 for k in kinds])
+    sc = _scene(means, scales, opac=opac, dc=np.full((3, len(kinds)), 0.1))
+    return sc, np.arange(len(kinds), dtype=np.int64), np.array([k == "near" for k in kinds])
+
+
+@pytest.mark.parametrize("case", ["saturates", "never_saturates"])
+def test_n_contrib_hand_counted(case):
+    """n_contrib counts the tile-list entries a pixel consumes (Alg. 1
+    rendering loop): entries whose q > 9 are skipped but counted, compositing
+    stops right after the entry that takes T below eps_T, and a pixel that
+    never saturates consumes its whole list.  Hand-built list of nine entries,
+    near ones (q ~ 0 at the pixel) interleaved with far ones (q ~ 400):
+      saturating: opacity 0.95 near entries, T = 0.05^k < 1e-4 first at k = 4,
+                  the fourth near entry is list position 6 -> n_contrib = 7
+                  (9 without the stop, 4 if skipped entries went uncounted);
+      never:      opacity 0.1, T = 0.9^5 -> n_contrib = 9.
+    A second pixel of the same tile, 0.05+ rad from every centre, composites
+    nothing and consumes the whole list."""
+    order = 6
+    kt = O.tile_order(order)
+    sh = 2 * (order - kt)
+    p = (5 << (2 * order)) + 0x155          # a pixel inside face 5
+    t = p >> sh
+    sc, lst, near = _hand_list_scene(order, p, 0.95 if case == "saturates" else 0.1)
+    cam = _cam(order)
+    pr = O.preprocess(sc, cam)
+    assert np.all(pr.valid == 1)
+    ntile = 12 << (2 * kt)
+    ranges = np.zeros((ntile, 2), np.int64)
+    ranges[t] = (0, lst.size)
+    # the other pixel: same tile, farthest from p
+    cand = np.arange(t << sh, (t + 1) << sh)
+    u = O.pix_vec(order, cand)
+    p2 = int(cand[np.argmin(u @ O.pix_vec(order, np.array([p]))[0])])
+    pix = np.array([p, p2], np.int64)
+    nc = O.n_contrib(sc, cam, pr, lst, ranges, pix)
+    rgb, T, nu, fr = O.render(sc, cam, pr, pix)
+    if case == "saturates":
+        assert nc[0] == 7, nc
+        assert nu[0] == 4 and T[0] < 1e-4 and T[0] > 0.05 ** 4 * 0.99
+    else:
+        assert nc[0] == lst.size, nc
+        assert nu[0] == near.sum() and abs(T[0] - 0.9 ** 5) < 1e-6
+    assert nc[1] == lst.size and nu[1] == 0 and T[1] == 1.0
+    # a list in which the pixel sees only far entries is consumed whole
+    ranges[t] = (0, 1)
+    assert O.n_contrib(sc, cam, pr, lst, ranges, pix)[0] == 1
+    # an empty list consumes nothing
+    ranges[t] = (0, 0)
+    assert np.all(O.n_contrib(sc, cam, pr, lst, ranges, pix) == 0)
