@@ -86,7 +86,14 @@ def lib():
 
 
 def _p(a):
-    return C.c_void_p(a.ctypes.data) if a is not None else None
+    """Pointer argument for a call; the returned object keeps `a` alive, so a
+    temporary (np.ascontiguousarray of a strided view) lives until the call
+    that receives it returns."""
+    if a is None:
+        return None
+    v = C.c_void_p(a.ctypes.data)
+    v._keep = a
+    return v
 
 
 def num_threads() -> int:
@@ -318,10 +325,16 @@ def sorted_tile_lists(order, proj: Projected, g, t, inn, prm=None):
     return lst, np.stack([starts, ends], axis=1).astype(np.int64)
 
 
-def render(scene, cam, proj: Projected, pix, prm=None, qtol=0.0, ttol=0.0, want_depth=False):
+def render(scene, cam, proj: Projected, pix, prm=None, qtol=0.0, ttol=0.0, want_depth=False, qtol_rel=0.0,
+           qtol_dir=0.0):
     """Brute-force compositing at nested pixels `pix` (Eq. unified_rendering).
     Returns rgb [3][n], T [n], n_used [n], frag [n]; with want_depth also the
-    composited inverse radial depth [n] (sum of alpha T / rho, Sec. 3.2)."""
+    composited inverse radial depth [n] (sum of alpha T / rho, Sec. 3.2).
+    frag is the allowance of the pixel's fragile decisions (0: none): q within
+    qtol + qtol_rel (|A| dx^2 + 2 |B dx dy| + |C| dy^2) + 2 qtol_dir
+    sqrt(q_cut lambda_max(conic)) of q_cut (the magnitudes of q's terms, and
+    the change of q an offset error of qtol_dir radians causes), T within
+    ttol (relative) of eps_T."""
     prm = prm or params()
     S = SceneRef(scene)
     v = view_struct(cam)
@@ -329,9 +342,10 @@ def render(scene, cam, proj: Projected, pix, prm=None, qtol=0.0, ttol=0.0, want_
     n = pix.size
     rgb = np.zeros((3, n)); T = np.zeros(n); nu = np.zeros(n, np.int64); fr = np.zeros(n)
     D = np.zeros(n) if want_depth else None
+    qb = np.array([qtol, qtol_rel, qtol_dir])   # held until the call returns
     lib().or_render(C.byref(S.s), C.byref(v), C.byref(prm), _p(proj.valid), _p(proj.omega), _p(proj.phi),
                     _p(proj.rho), _p(np.ascontiguousarray(proj.conic)), _p(proj.rs),
-                    _p(np.ascontiguousarray(proj.rgb)), C.c_int64(n), _p(pix), C.c_double(qtol),
+                    _p(np.ascontiguousarray(proj.rgb)), C.c_int64(n), _p(pix), _p(qb),
                     C.c_double(ttol), _p(rgb), _p(T), _p(nu), _p(fr), _p(D))
     return (rgb, T, nu, fr, D) if want_depth else (rgb, T, nu, fr)
 
@@ -350,7 +364,8 @@ def n_contrib(scene, cam, proj: Projected, lst, ranges, pix, prm=None):
     return out
 
 
-def render_lists(scene, cam, proj: Projected, lst, ranges, pix, prm=None, qtol=0.0, ttol=0.0):
+def render_lists(scene, cam, proj: Projected, lst, ranges, pix, prm=None, qtol=0.0, ttol=0.0, qtol_rel=0.0,
+                 qtol_dir=0.0):
     """Compositing at nested pixels `pix` where each pixel sees only its
     tile's list (lst / ranges as from sorted_tile_lists): the approximate
     tile sets of the paper's queries can leave a Gaussian out of a tile it
@@ -361,10 +376,12 @@ def render_lists(scene, cam, proj: Projected, lst, ranges, pix, prm=None, qtol=0
     pix = np.ascontiguousarray(pix, np.int64)
     n = pix.size
     rgb = np.zeros((3, n)); T = np.zeros(n); nu = np.zeros(n, np.int64); fr = np.zeros(n)
+    qb = np.array([qtol, qtol_rel, qtol_dir])   # held until the call returns
     lib().or_render_lists(C.byref(S.s), C.byref(v), C.byref(prm), _p(proj.omega), _p(proj.phi), _p(proj.rho),
                           _p(np.ascontiguousarray(proj.conic)), _p(np.ascontiguousarray(proj.rgb)),
                           _p(np.ascontiguousarray(lst, np.int64)), _p(np.ascontiguousarray(ranges, np.int64)),
-                          C.c_int64(n), _p(pix), C.c_double(qtol), C.c_double(ttol), _p(rgb), _p(T), _p(nu), _p(fr))
+                          C.c_int64(n), _p(pix), _p(qb), C.c_double(ttol),
+                          _p(rgb), _p(T), _p(nu), _p(fr))
     return rgb, T, nu, fr
 
 

@@ -597,15 +597,31 @@ i64 or_tile_sets(int order, const or_params* prm, const double* tc, const double
 //
 // Outputs per pixel: rgb [3][n], T [n], n_used [n] (Gaussians composited),
 // frag [n]: an allowance (colour units) covering the decisions whose FP32
-// outcome may legitimately differ: q within qtol of q_cut, and T within
-// ttol (relative) of eps_T at the stopping point.
+// outcome may legitimately differ (fragility bookkeeping): q within the band
+// q_band(qtol = {abs, rel, dir}) of q_cut, and T within ttol (relative) of
+// eps_T at the stopping point.
 // A conservative pre-filter (angular distance <= r_s (1 + 1e-9) + 1e-12)
 // skips Gaussians that cannot reach q <= q_cut, since q <= 9 implies d_gc <= r_s.
-struct Cand { double rho; i64 i; double q, dx, dy; };
+struct Cand { double rho; i64 i; double q, dx, dy, qband; };
+
+
+// band of q around q_cut inside which the FP32 decision may differ: qtol_abs,
+// plus qtol_rel times the magnitudes of the terms of q (|A| dx^2 + 2 |B| |dx dy|
+// + |C| dy^2, which covers cancellation in an ill-conditioned conic), plus
+// the change of q that an offset error of qtol_dir radians causes on the
+// q = q_cut ellipse, |dq| <= 2 |conic d| |delta d| <= 2 sqrt(q_cut lmax) |delta d|
+static double q_band(const double* conic, i64 P, i64 i, double q_cut, double dx, double dy, double qtol_abs,
+                     double qtol_rel, double qtol_dir) {
+  const double A = conic[i], B = conic[P + i], Cc = conic[2 * P + i];
+  const double lmax = 0.5 * (A + Cc) + std::sqrt(0.25 * (A - Cc) * (A - Cc) + B * B);
+  const double terms = std::fabs(A) * dx * dx + 2 * std::fabs(B * dx * dy) + std::fabs(Cc) * dy * dy;
+  return qtol_abs + qtol_rel * terms + 2.0 * std::sqrt(q_cut * std::max(lmax, 0.0)) * qtol_dir;
+}
 
 static void pixel_candidates(const or_scene& S, const or_params& prm, const int* valid, const double* omega,
                              const double* phi, const double* rho, const double* conic, const double* rs,
-                             double om_p, double ph_p, const double pv[3], std::vector<Cand>& out) {
+                             double om_p, double ph_p, const double pv[3], const double qtol[3],
+                             std::vector<Cand>& out) {
   i64 P = S.P;
   out.clear();
   for (i64 i = 0; i < P; ++i) {
@@ -616,7 +632,8 @@ static void pixel_candidates(const or_scene& S, const or_params& prm, const int*
     double dx, dy, dgc;
     sph_offset<double>(omega[i], phi[i], om_p, ph_p, &dx, &dy, &dgc);
     double q = conic[i] * dx * dx + 2 * conic[P + i] * dx * dy + conic[2 * P + i] * dy * dy;
-    if (q <= prm.q_cut * (1 + 1e-3)) out.push_back(Cand{rho[i], i, q, dx, dy});
+    if (q <= prm.q_cut * (1 + 1e-3))
+      out.push_back(Cand{rho[i], i, q, dx, dy, q_band(conic, P, i, prm.q_cut, dx, dy, qtol[0], qtol[1], qtol[2])});
   }
   std::sort(out.begin(), out.end(), [](const Cand& a, const Cand& b) { return a.rho < b.rho || (a.rho == b.rho && a.i < b.i); });
 }
@@ -624,14 +641,14 @@ static void pixel_candidates(const or_scene& S, const or_params& prm, const int*
 // Front-to-back compositing of one pixel's candidates (already ordered by
 // (rho, index)); see or_render for the outputs.
 static void composite(const std::vector<Cand>& c, const or_params& prm, const double* opac, const double* rho,
-                      const double* rgbg, i64 P, double qtol_abs, double ttol_rel, double C[3], double* Tout,
+                      const double* rgbg, i64 P, double ttol_rel, double C[3], double* Tout,
                       i64* n_used, double* frag, double* Dout) {
   double Tr = 1.0, fr = 0, D = 0;
   C[0] = C[1] = C[2] = 0;
   i64 used = 0;
   for (const Cand& e : c) {
     double cmax = std::max(std::fabs(rgbg[e.i]), std::max(std::fabs(rgbg[P + e.i]), std::fabs(rgbg[2 * P + e.i])));
-    if (std::fabs(e.q - prm.q_cut) <= qtol_abs) fr += Tr * std::min(prm.alpha_max, opac[e.i] * std::exp(-0.5 * prm.q_cut)) * cmax;
+    if (std::fabs(e.q - prm.q_cut) <= e.qband) fr += Tr * std::min(prm.alpha_max, opac[e.i] * std::exp(-0.5 * prm.q_cut)) * cmax;
     if (e.q > prm.q_cut) continue;
     double a = std::min(prm.alpha_max, opac[e.i] * std::exp(-0.5 * e.q));
     for (int ch = 0; ch < 3; ++ch) C[ch] += Tr * a * rgbg[ch * P + e.i];
@@ -647,8 +664,8 @@ static void composite(const std::vector<Cand>& c, const or_params& prm, const do
 
 void or_render(const or_scene* S, const or_view* V, const or_params* prm, const int* valid, const double* omega,
                const double* phi, const double* rho, const double* conic, const double* rs, const double* rgbg,
-               i64 n, const i64* pix, double qtol_abs, double ttol_rel, double* rgb, double* T, i64* n_used,
-               double* frag, double* invd) {
+               i64 n, const i64* pix, const double* qtol, double ttol_rel, double* rgb, double* T,
+               i64* n_used, double* frag, double* invd) {
   i64 P = S->P;
   std::vector<double> opac(P);
   for (i64 i = 0; i < P; ++i) opac[i] = S->opacity[i];
@@ -657,9 +674,9 @@ void or_render(const or_scene* S, const or_view* V, const or_params* prm, const 
     double om_p, ph_p, pv[3];
     pix_angles(V->order, pix[k], &om_p, &ph_p, pv);
     std::vector<Cand> c;
-    pixel_candidates(*S, *prm, valid, omega, phi, rho, conic, rs, om_p, ph_p, pv, c);
+    pixel_candidates(*S, *prm, valid, omega, phi, rho, conic, rs, om_p, ph_p, pv, qtol, c);
     double C[3], D;
-    composite(c, *prm, opac.data(), rho, rgbg, P, qtol_abs, ttol_rel, C, &T[k], &n_used[k], &frag[k], &D);
+    composite(c, *prm, opac.data(), rho, rgbg, P, ttol_rel, C, &T[k], &n_used[k], &frag[k], &D);
     for (int ch = 0; ch < 3; ++ch) rgb[ch * n + k] = C[ch];
     if (invd) invd[k] = D;
   }
@@ -672,8 +689,8 @@ void or_render(const or_scene* S, const or_view* V, const or_params* prm, const 
 // the exact one (the aliasing the paper reports for coarse queries).
 void or_render_lists(const or_scene* S, const or_view* V, const or_params* prm, const double* omega,
                      const double* phi, const double* rho, const double* conic, const double* rgbg, const i64* list,
-                     const i64* ranges, i64 n, const i64* pix, double qtol_abs, double ttol_rel, double* rgb,
-                     double* T, i64* n_used, double* frag) {
+                     const i64* ranges, i64 n, const i64* pix, const double* qtol, double ttol_rel,
+                     double* rgb, double* T, i64* n_used, double* frag) {
   i64 P = S->P;
   int kt = tile_order(V->order, *prm);
   int sh = 2 * (V->order - kt);
@@ -690,11 +707,12 @@ void or_render_lists(const or_scene* S, const or_view* V, const or_params* prm, 
       double dx, dy, dgc;
       sph_offset<double>(omega[i], phi[i], om_p, ph_p, &dx, &dy, &dgc);
       double q = conic[i] * dx * dx + 2 * conic[P + i] * dx * dy + conic[2 * P + i] * dy * dy;
-      if (q <= prm->q_cut * (1 + 1e-3)) c.push_back(Cand{rho[i], i, q, dx, dy});
+      if (q <= prm->q_cut * (1 + 1e-3))
+        c.push_back(Cand{rho[i], i, q, dx, dy, q_band(conic, P, i, prm->q_cut, dx, dy, qtol[0], qtol[1], qtol[2])});
     }
     std::sort(c.begin(), c.end(), [](const Cand& a, const Cand& b) { return a.rho < b.rho || (a.rho == b.rho && a.i < b.i); });
     double C[3], D;
-    composite(c, *prm, opac.data(), rho, rgbg, P, qtol_abs, ttol_rel, C, &T[k], &n_used[k], &frag[k], &D);
+    composite(c, *prm, opac.data(), rho, rgbg, P, ttol_rel, C, &T[k], &n_used[k], &frag[k], &D);
     for (int ch = 0; ch < 3; ++ch) rgb[ch * n + k] = C[ch];
   }
 }
@@ -762,7 +780,8 @@ void or_render_bwd(const or_scene* S, const or_view* V, const or_params* prm, co
       double om_p, ph_p, pv[3];
       pix_angles(V->order, pix[k], &om_p, &ph_p, pv);
       std::vector<Cand> c;
-      pixel_candidates(*S, *prm, valid, omega, phi, rho, conic, rs, om_p, ph_p, pv, c);
+      const double no_band[3] = {0.0, 0.0, 0.0};
+      pixel_candidates(*S, *prm, valid, omega, phi, rho, conic, rs, om_p, ph_p, pv, no_band, c);
       // forward sequence
       std::vector<i64> ids; std::vector<double> al, Ts, qs; std::vector<bool> clampa;
       double Tr = 1.0;

@@ -17,7 +17,25 @@ from . import _abi as A
 
 
 def _p(t):
-    return None if t is None else C.c_void_p(t.data_ptr())
+    """Pointer argument for a call into the library.  The returned object keeps
+    `t` alive, so a temporary (x.contiguous() of a strided tensor) is not
+    returned to the caching allocator, and handed to the next temporary of the
+    same call, before the call has enqueued its kernels."""
+    if t is None:
+        return None
+    v = C.c_void_p(t.data_ptr())
+    v._keep = t
+    return v
+
+
+def _dense(t):
+    """A float32 contiguous device tensor for a kernel argument (a copy if t is
+    strided); anything else is refused rather than reinterpreted."""
+    if t is None:
+        return None
+    if not t.is_cuda or t.dtype != torch.float32:
+        raise ValueError("expected a float32 device tensor")
+    return t.contiguous()
 
 
 def _stream():
@@ -448,29 +466,32 @@ class Rasterizer:
         """Camera image [3][H][W] from the HEALPix image img [3][n_active] of
         `cam` (Interp_H over ring neighbours, renormalised over the active
         set); with want_valid also the uint8 validity map [H][W]."""
+        img = _dense(img)
         m = self.mask(cam)
         out = torch.empty((3, H, W), dtype=torch.float32, device=self.device)
         valid = torch.empty((H, W), dtype=torch.uint8, device=self.device) if want_valid else None
         v = cam.view()
         A.call("hp_sphere_to_image", _p(m.buf), C.byref(v), C.byref(self.prm), m.n_active,
-               _p(img.contiguous()), int(W), int(H), _p(out), _p(valid), _stream())
+               _p(img), int(W), int(H), _p(out), _p(valid), _stream())
         return (out, valid) if want_valid else out
 
     def image_to_sphere(self, img: torch.Tensor, cam: Camera, want_valid: bool = False):
         """Samples [3][n_active] of the camera image img [3][H][W] at the
         centres of cam's active HEALPix pixels (bilinear in the image)."""
+        img = _dense(img)
         m = self.mask(cam)
         H, W = int(img.shape[1]), int(img.shape[2])
         out = torch.empty((3, max(m.n_active, 1)), dtype=torch.float32, device=self.device)[:, :m.n_active]
         valid = torch.empty(max(m.n_active, 1), dtype=torch.uint8, device=self.device)[:m.n_active] if want_valid else None
         v = cam.view()
         A.call("hp_image_to_sphere", _p(m.buf), C.byref(v), C.byref(self.prm), m.n_active,
-               _p(img.contiguous()), W, H, _p(out), _p(valid), _stream())
+               _p(img), W, H, _p(out), _p(valid), _stream())
         return (out, valid) if want_valid else out
 
     # ---- loss ----------------------------------------------------------------
     def ssim_loss(self, img, ref, cam: Camera, sp: A.hp_ssim_params | None = None, dL_dloss=None, want_map=False):
         """Returns (out[3] = (mean SSIM, L1, loss), ssim_map or None, dL/dimg or None)."""
+        img, ref = _dense(img), _dense(ref)
         m = self.mask(cam)
         sp = sp or A.default_ssim_params()
         out = torch.zeros(3, dtype=torch.float32, device=self.device)
@@ -478,7 +499,7 @@ class Rasterizer:
         dimg = torch.empty_like(img) if dL_dloss is not None else None
         ws_n = A.lib().hp_ssim_workspace_bytes(cam.order, self.prm.tile_log2, m.n_active)
         ws = _bytes(ws_n, self.device)
-        A.call("hp_ssim", _p(img.contiguous()), _p(ref.contiguous()), m.n_active, m.n_tiles, cam.order,
+        A.call("hp_ssim", _p(img), _p(ref), m.n_active, m.n_tiles, cam.order,
                C.byref(self.prm), C.byref(sp), _p(m.buf), _p(out), _p(smap), _p(dL_dloss), _p(dimg), _p(ws), ws_n,
                _stream())
         return out, smap, dimg
@@ -486,6 +507,7 @@ class Rasterizer:
     def ssim_forward_saved(self, img, ref, cam: Camera, sp: A.hp_ssim_params | None = None, want_map=False):
         """Loss forward that keeps the backward's per-pixel partials: returns
         (out[3], ssim_map or None, saved workspace for ssim_backward_saved)."""
+        img, ref = _dense(img), _dense(ref)
         m = self.mask(cam)
         sp = sp or A.default_ssim_params()
         out = torch.zeros(3, dtype=torch.float32, device=self.device)
@@ -498,6 +520,7 @@ class Rasterizer:
 
     def ssim_backward_saved(self, img, ref, cam: Camera, sp: A.hp_ssim_params, ws, dL_dloss):
         """dL/dimg from the partials a previous ssim_forward_saved left in ws."""
+        img, ref, dL_dloss = _dense(img), _dense(ref), _dense(dL_dloss)
         m = self.mask(cam)
         dimg = torch.empty_like(img)
         A.call("hp_ssim_backward_saved", _p(img), _p(ref), m.n_active, m.n_tiles, cam.order, C.byref(self.prm),

@@ -43,7 +43,7 @@ def test_inverse_depth_forward_matches_oracle(R, case):
     g, cam, st = _forward(R, sc, camd)
     act = O.mask(camd)
     pr = O.preprocess(sc, camd)
-    rgb_o, T_o, nu, frag, D_o = O.render(sc, camd, pr, act, qtol=PT.qtol_for(), ttol=1e-3, want_depth=True)
+    rgb_o, T_o, nu, frag, D_o = O.render(sc, camd, pr, act, **PT.BANDS, want_depth=True)
     D_g = st.inv_depth.cpu().numpy().astype(np.float64)
     robust = frag == 0
     err = np.abs(D_g - D_o)
@@ -64,7 +64,7 @@ def test_inverse_depth_backward_matches_oracle(R, case):
     g, cam, st = _forward(R, sc, camd)
     act = O.mask(camd)
     pr = O.preprocess(sc, camd)
-    _, _, _, frag = O.render(sc, camd, pr, act, qtol=PT.qtol_for(), ttol=1e-3)
+    _, _, _, frag = O.render(sc, camd, pr, act, **PT.BANDS)
     rng = np.random.default_rng(23)
     dC = rng.normal(size=(3, act.size)) * 0.5
     dD = rng.normal(size=act.size)
@@ -90,7 +90,7 @@ def test_depth_only_gradient_reaches_means(R):
     g, cam, st = _forward(R, sc, camd)
     act = O.mask(camd)
     pr = O.preprocess(sc, camd)
-    _, _, _, frag = O.render(sc, camd, pr, act, qtol=PT.qtol_for(), ttol=1e-3)
+    _, _, _, frag = O.render(sc, camd, pr, act, **PT.BANDS)
     dD = np.random.default_rng(29).normal(size=act.size)
     dD[frag > 0] = 0
     z = torch.zeros_like
@@ -133,7 +133,7 @@ def test_density_stats_match_oracle_definition(R):
     g, cam, st = _forward(R, sc, camd)
     act = O.mask(camd)
     pr = O.preprocess(sc, camd)
-    _, _, _, frag = O.render(sc, camd, pr, act, qtol=PT.qtol_for(), ttol=1e-3)
+    _, _, _, frag = O.render(sc, camd, pr, act, **PT.BANDS)
     rng = np.random.default_rng(31)
     dC = rng.normal(size=(3, act.size)); dC[:, frag > 0] = 0
     acc = torch.zeros((10, g.P), dtype=torch.float32, device="cuda")

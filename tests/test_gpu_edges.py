@@ -32,7 +32,7 @@ def test_coarsest_orders_forward_and_backward(R, order):
     act = O.mask(cam)
     assert np.array_equal(st.mask.active_pix.cpu().numpy().astype(np.int64), act)
     pr = O.preprocess(sc, cam)
-    rgb_o, T_o, nu_o, frag = O.render(sc, cam, pr, act, qtol=PT.qtol_for(), ttol=1e-3)
+    rgb_o, T_o, nu_o, frag = O.render(sc, cam, pr, act, **PT.BANDS)
     worst, nfrag = PT.compare_render(st.rgb.cpu().numpy().astype(np.float64), st.T.cpu().numpy().astype(np.float64),
                                      rgb_o, T_o, frag)
     # backward over the robust pixels
@@ -62,7 +62,7 @@ def test_finest_order_narrow_pinhole(R):
     assert np.array_equal(st.mask.active_pix.cpu().numpy().astype(np.int64), act)
     idx = np.sort(rng.choice(act.size, size=min(400, act.size), replace=False))
     pr = O.preprocess(wl.scene, cam)
-    rgb_o, T_o, nu_o, frag = O.render(wl.scene, cam, pr, act[idx], qtol=PT.qtol_for(), ttol=1e-3)
+    rgb_o, T_o, nu_o, frag = O.render(wl.scene, cam, pr, act[idx], **PT.BANDS)
     worst, nfrag = PT.compare_render(st.rgb.cpu().numpy().astype(np.float64)[:, idx],
                                      st.T.cpu().numpy().astype(np.float64)[idx], rgb_o, T_o, frag)
     print("order 12 pinhole: active", act.size, "tiles", st.mask.n_tiles, "pairs", st.n_pairs, "max err", worst)
@@ -97,7 +97,7 @@ def test_wide_footprints_every_k2_range(R):
     s2 = np.sin(ang[ang <= pr.rs[None, :]]) ** 2
     assert np.mean((s2 >= 1 / 16) & (s2 < 1 / 4)) > 0.2 and np.mean(s2 < 1 / 16) > 0.05
     g, c, st = PT.gpu_forward(R, sc, cam)
-    rgb_o, T_o, nu_o, frag = O.render(sc, cam, pr, act, qtol=PT.qtol_for(), ttol=1e-3)
+    rgb_o, T_o, nu_o, frag = O.render(sc, cam, pr, act, **PT.BANDS)
     worst, nfrag = PT.compare_render(st.rgb.cpu().numpy().astype(np.float64), st.T.cpu().numpy().astype(np.float64),
                                      rgb_o, T_o, frag)
     dC = rng.normal(size=(3, act.size))

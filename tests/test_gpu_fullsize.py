@@ -1,4 +1,4 @@
-"""GPU parity at the full benchmark sizes, in the launch configuration the
+"""GPU parity at the full workload sizes, in the launch configuration the
 benchmark times, on outputs the oracle can compute one by one:
 
 * colours / T / composited counts at sampled active pixels of config 2
@@ -6,7 +6,12 @@ benchmark times, on outputs the oracle can compute one by one:
   Gaussians, 60-degree pinhole at Nside 2048);
 * complete per-Gaussian gradients for an upstream gradient that is non-zero
   only at sampled pixels: the oracle's backward over those pixels is then the
-  exact reference for every Gaussian."""
+  exact reference for every Gaussian (configs 1, 2 and 3);
+* the tile lists of 10,000 sampled Gaussians against the oracle's brute-force
+  tile sets, and the depth order of every whole list (configs 2 and 3);
+* the L1 + HEALPix-SSIM loss, its map and its gradient on whole images: the
+  config-1 render (180-degree fisheye at Nside 256) against its target, and a
+  full sphere at Nside 512."""
 import numpy as np
 import pytest
 
@@ -26,7 +31,7 @@ def R():
 
 
 def _workload(name):
-    return {"cfg2": SC.config2, "cfg3": SC.config3}[name]()
+    return {"cfg1": SC.config1, "cfg2": SC.config2, "cfg3": SC.config3}[name]()
 
 
 def _sample(act_size, n, seed):
@@ -43,7 +48,7 @@ def test_forward_sampled_full_size(R, name, n_pix):
     assert np.array_equal(act, O.mask(cam))
     idx = _sample(act.size, n_pix, 11)
     pr = O.preprocess(sc, cam)
-    rgb_o, T_o, nu_o, frag = O.render(sc, cam, pr, act[idx], qtol=PT.qtol_for(), ttol=1e-3)
+    rgb_o, T_o, nu_o, frag = O.render(sc, cam, pr, act[idx], **PT.BANDS)
     rgb_g = st.rgb.cpu().numpy().astype(np.float64)[:, idx]
     T_g = st.T.cpu().numpy().astype(np.float64)[idx]
     worst, nfrag = PT.compare_render(rgb_g, T_g, rgb_o, T_o, frag)
@@ -55,7 +60,7 @@ def test_forward_sampled_full_size(R, name, n_pix):
           "mean composited", float(nu_o.mean()))
 
 
-@pytest.mark.parametrize("name,n_pix", [("cfg2", 300), ("cfg3", 150)])
+@pytest.mark.parametrize("name,n_pix", [("cfg1", 300), ("cfg2", 300), ("cfg3", 150)])
 def test_backward_sparse_upstream_full_size(R, name, n_pix):
     import torch
     from paper_2606_29794_amd.raster import Gaussians
@@ -65,7 +70,7 @@ def test_backward_sparse_upstream_full_size(R, name, n_pix):
     act = st.mask.active_pix.cpu().numpy().astype(np.int64)
     idx = _sample(act.size, n_pix, 12)
     pr = O.preprocess(sc, cam)
-    _, _, _, frag = O.render(sc, cam, pr, act[idx], qtol=PT.qtol_for(), ttol=1e-3)
+    _, _, _, frag = O.render(sc, cam, pr, act[idx], **PT.BANDS)
     idx = idx[frag == 0]   # a fragile pixel carries a discontinuity
     rng = np.random.default_rng(13)
     dC_s = rng.normal(size=(3, idx.size))
@@ -82,6 +87,68 @@ def test_backward_sparse_upstream_full_size(R, name, n_pix):
     for k in ("mean", "scale", "rot", "opacity", "sh"):
         e = PT.grad_compare(f"{name}:{k}", getattr(gr, k).cpu().numpy(), getattr(go, k))
         print(name, k, "rel err", e)
+
+
+@pytest.mark.parametrize("name", ["cfg2", "cfg3"])
+def test_tile_lists_sampled_full_size(R, name):
+    """hp_bin_sorted's lists at full size (the path the benchmark times, with
+    its XCD-contiguous chunking and its task capacity): 10,000 random
+    Gaussians' tile memberships bit-exact against the oracle's tile sets up to
+    fragile pairs, in depth order inside every tile."""
+    wl = _workload(name)
+    sc, cam = wl.scene, wl.cameras[0]
+    g, c, st = PT.gpu_forward(R, sc, cam)
+    pr = O.preprocess(sc, cam)
+    gids = np.sort(np.random.default_rng(21).choice(sc.P, size=10_000, replace=False))
+    stats = PT.compare_tile_lists_sampled(st, pr, cam, cam["order"], gids)
+    print(name, stats, "list entries", st.n_pairs)
+    assert stats["pairs"] > 0
+
+
+def _loss_case(R, name):
+    import torch
+    from paper_2606_29794_amd.raster import Camera
+    if name == "cfg1":
+        # the config-1 render of its scene against its seeded target
+        wl = SC.config1()
+        camd = wl.cameras[0]
+        g, c, st = PT.gpu_forward(R, wl.scene, camd)
+        img = st.rgb
+        ref = torch.as_tensor(SC.target_image(wl.seed, 0, st.mask.n_active), device="cuda")
+        return camd, img, ref
+    rng = np.random.default_rng(9)
+    camd = SC.make_camera(rng, 9, SC.CAM_FULL)
+    n = R.mask(Camera.from_dict(camd)).n_active
+    img = torch.as_tensor(rng.random((3, n)), dtype=torch.float32, device="cuda")
+    ref = torch.as_tensor(0.5 * rng.random((3, n)), dtype=torch.float32, device="cuda") + 0.5 * img
+    return camd, img, ref
+
+
+@pytest.mark.parametrize("name", ["cfg1", "order9_full"])
+def test_hssim_loss_full_size(R, name):
+    """hp_ssim (mean SSIM, L1, loss, per-pixel map and dL/dimg) against the
+    oracle on whole images at the workloads' sizes: 393K active pixels of the
+    config-1 fisheye at Nside 256, and 3.1M pixels of the full sphere at Nside
+    512."""
+    import torch
+    from paper_2606_29794_amd.raster import Camera
+    camd, img, ref = _loss_case(R, name)
+    cam = Camera.from_dict(camd)
+    up = torch.tensor([1.3], dtype=torch.float32, device="cuda")
+    out, smap, dimg = R.ssim_loss(img, ref, cam, dL_dloss=up, want_map=True)
+    torch.cuda.synchronize()
+    act = O.mask(camd)
+    im = img.cpu().numpy().astype(np.float64)
+    rf = ref.cpu().numpy().astype(np.float64)
+    s_o, map_o, _ = O.hssim(camd["order"], act, im, rf, want_map=True)
+    L_o, gL_o = O.loss(camd["order"], act, im, rf, want_grad=True)
+    out = out.cpu().numpy()
+    assert abs(out[0] - s_o) < 1e-5 and abs(out[2] - L_o) < 1e-5, (out, s_o, L_o)
+    assert abs(out[1] - np.mean(np.abs(im - rf))) < 1e-5
+    err_map = np.abs(smap.cpu().numpy() - map_o).max()
+    assert err_map < 2e-5, err_map
+    e = PT.grad_compare(f"{name}: dL/dimg", dimg.cpu().numpy(), 1.3 * gL_o)
+    print(name, "pixels", act.size, "ssim", out[0], "map err", err_map, "grad rel err", e)
 
 
 def test_timed_step_equals_plain_views_full_size(R):

@@ -80,7 +80,7 @@ def test_render_forward_full_image(R, case):
     g, c, st = PT.gpu_forward(R, sc, cam)
     act = O.mask(cam)
     pr = O.preprocess(sc, cam)
-    rgb_o, T_o, nu, frag = O.render(sc, cam, pr, act, qtol=PT.qtol_for(), ttol=1e-3)
+    rgb_o, T_o, nu, frag = O.render(sc, cam, pr, act, **PT.BANDS)
     rgb_g = st.rgb.cpu().numpy().astype(np.float64)
     T_g = st.T.cpu().numpy().astype(np.float64)
     worst, nfrag = PT.compare_render(rgb_g, T_g, rgb_o, T_o, frag)
@@ -113,7 +113,7 @@ def test_render_forward_sampled_config1(R):
     rng = np.random.default_rng(0)
     idx = np.sort(rng.choice(act.size, size=3000, replace=False))
     pr = O.preprocess(sc, cam)
-    rgb_o, T_o, nu, frag = O.render(sc, cam, pr, act[idx], qtol=PT.qtol_for(), ttol=1e-3)
+    rgb_o, T_o, nu, frag = O.render(sc, cam, pr, act[idx], **PT.BANDS)
     rgb_g = st.rgb.cpu().numpy().astype(np.float64)[:, idx]
     T_g = st.T.cpu().numpy().astype(np.float64)[idx]
     worst, nfrag = PT.compare_render(rgb_g, T_g, rgb_o, T_o, frag)
@@ -142,7 +142,7 @@ def test_render_backward_matches_oracle(R, case):
     gg = _grads_gpu(R, g, st, dC, dT)
     pr = O.preprocess(sc, cam)
     # pixels with a fragile decision carry a discontinuity: leave them out on both sides
-    _, _, _, frag = O.render(sc, cam, pr, act, qtol=PT.qtol_for(), ttol=1e-3)
+    _, _, _, frag = O.render(sc, cam, pr, act, **PT.BANDS)
     dC[:, frag > 0] = 0
     dT[frag > 0] = 0
     gg = _grads_gpu(R, g, st, dC, dT)

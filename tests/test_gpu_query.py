@@ -218,7 +218,7 @@ def test_render_over_query_lists(R, case, mode, f):
                       set(lst[ranges[t, 0]:ranges[t, 1]].tolist()) for t in ptile])
     assert agree.mean() > 0.97
     sel = np.nonzero(agree)[0]
-    rgb_o, T_o, nu_o, frag = O.render_lists(sc, camd, pr, lst, ranges, act[sel], qtol=PT.qtol_for(), ttol=1e-3)
+    rgb_o, T_o, nu_o, frag = O.render_lists(sc, camd, pr, lst, ranges, act[sel], **PT.BANDS)
     rgb_g = st.rgb.cpu().numpy().astype(np.float64)[:, sel]
     T_g = st.T.cpu().numpy().astype(np.float64)[sel]
     worst, nfrag = PT.compare_render(rgb_g, T_g, rgb_o, T_o, frag)

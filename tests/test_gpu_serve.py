@@ -82,7 +82,7 @@ def test_served_results_equal_solo_renders():
     rng = np.random.default_rng(1)
     idx = np.sort(rng.choice(act.size, size=min(400, act.size), replace=False))
     pr = O.preprocess(sc, cams[k])
-    rgb_o, T_o, _, frag = O.render(sc, cams[k], pr, act[idx], qtol=PT.qtol_for(), ttol=1e-3)
+    rgb_o, T_o, _, frag = O.render(sc, cams[k], pr, act[idx], **PT.BANDS)
     res = stats.results[k]
     PT.compare_render(res.rgb.cpu().numpy()[:, idx].astype(np.float64), res.T.cpu().numpy()[idx].astype(np.float64),
                       rgb_o, T_o, frag)
