@@ -102,6 +102,9 @@ def main():
             rgb, T = render(*params, cam, R, fused_grad=True, query=query, prepared=pf.get(v) if pf else None)
             loss, _ = hssim_loss(rgb, targets[v], cam, 0.2, R)
             loss.backward()
+        # every view's list count against the capacity it ran with (raises if
+        # a list buffer was too small; the capacities settle in the warm-up)
+        R.verify()
         return tot
 
     query = None
@@ -168,17 +171,13 @@ def query_bench(R, params, cams, targets, torch, step, steps):
         for _ in range(3):
             e = [ev() for _ in range(6)]
             e[0].record()
-            if q is None:
-                vals, ranges, n = R.bin_sorted(proj, g.P, cam)
-                cand = n
-            else:
-                vals, ranges, cand, n = R.bin_query(proj, g.P, cam, q[0], q[1])
+            vals, ranges, cnt = R.bin_lists(proj, g.P, cam, q)
             e[1].record()
             e[2].record()
             rgb, T, nc = R.render_fwd(proj, g.P, vals, ranges, cam)
             e[3].record()
             _, _, dimg = R.ssim_loss(rgb, targets[0], cam, dL_dloss=up)
-            st = FwdState(cam, m, proj, vals, ranges, n, rgb, T, nc, g.P)
+            st = FwdState(cam, m, proj, vals, ranges, cnt, rgb, T, nc, g.P)
             acc = torch.zeros((10, g.P), dtype=torch.float32, device=g.mean.device)
             e[4].record()
             R.backward_pixels(st, dimg, None, acc)
@@ -187,6 +186,8 @@ def query_bench(R, params, cams, targets, torch, step, steps):
             tb.append(e[0].elapsed_time(e[1]))
             tf.append(e[2].elapsed_time(e[3]))
             tw.append(e[4].elapsed_time(e[5]))
+        cand = cnt.value(0)
+        n = cand if q is None else cnt.value(1)
         r = {"bin_ms": float(np.median(tb)), "render_fwd_ms": float(np.median(tf)),
              "render_bwd_ms": float(np.median(tw)), "pairs": int(n), "candidates": int(cand)}
         r["bin_render_ms"] = r["bin_ms"] + r["render_fwd_ms"] + r["render_bwd_ms"]
@@ -255,7 +256,7 @@ def kernel_breakdown(R, params, cams, targets, torch, A):
         proj = R.preprocess(g, cam)
         e[1].record()
         m = R.mask(cam)
-        vals, ranges, n = R.bin_sorted(proj, g.P, cam)
+        vals, ranges, cnt = R.bin_lists(proj, g.P, cam)
         e[2].record()
         e[3].record()
         rgb, T, nc, nu = R.render_fwd(proj, g.P, vals, ranges, cam, want_used=True)
@@ -264,7 +265,7 @@ def kernel_breakdown(R, params, cams, targets, torch, A):
         _, _, dimg = R.ssim_loss(rgb, targets[0], cam, dL_dloss=up)
         e[5].record()
         from paper_2606_29794_amd.raster import FwdState
-        st = FwdState(cam, m, proj, vals, ranges, n, rgb, T, nc, g.P)
+        st = FwdState(cam, m, proj, vals, ranges, cnt, rgb, T, nc, g.P)
         z = torch.zeros_like
         gr = Gaussians(z(g.mean), z(g.scale), z(g.rot), z(g.opacity), z(g.sh))
         acc = torch.zeros((10, g.P), dtype=torch.float32, device=g.mean.device)
@@ -278,6 +279,7 @@ def kernel_breakdown(R, params, cams, targets, torch, A):
             name = ["preprocess", "bin_and_sort", "render_fwd", "ssim_fwd_bwd", "render_bwd", "preprocess_bwd"][k]
             times.setdefault(name, []).append(e[a].elapsed_time(e[b]))
     med = {k: float(np.median(v)) for k, v in times.items()}
+    n = cnt.value(0)
     evals = int(nc.to(torch.int64).sum().item())
     used = int(nu.to(torch.int64).sum().item())
     P = g.P

@@ -11,8 +11,11 @@
  *    torch allocations are).
  *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
  *    Every call only enqueues work and returns without waiting, except the
- *    read-back helpers whose names end in _counts/_total, which wait for the
- *    stream.
+ *    read-back helpers hp_mask_counts, hp_read_total and hp_check_count,
+ *    which wait for the stream.  Counts that size later work (tasks, pairs)
+ *    stay in device memory; a count that exceeds a caller's capacity makes
+ *    the calls that depend on it write nothing (and leave every tile range
+ *    empty), and the caller learns it from the device count itself.
  *  - Arrays are float32 structure-of-arrays [component][count].
  *  - Argument checks happen on the host before anything is enqueued and
  *    return HP_ERR_INVALID_ARG / HP_ERR_UNSUPPORTED without side effects.
@@ -175,11 +178,11 @@ const float* hp_projected_radius(const void* projected, int64_t P);
  * tile key alone yields the per-tile front-to-back order of Alg. 1.
  * phase: HP_BIN_COUNT counts pairs (writes *n_pairs, device int64),
  *        HP_BIN_EMIT writes them (needs a previous COUNT on the same ws),
- *        HP_BIN_ALL does both.  If *n_pairs > capacity, EMIT writes nothing;
- *        the caller reads *n_pairs (hp_read_total) and calls EMIT again with
- *        larger buffers.  COUNT and EMIT each wait once for `stream` to read
- *        the task count; COUNT returns HP_ERR_CAPACITY if the tasks exceed the
- *        workspace (16 P + 2^20 of them).
+ *        HP_BIN_ALL does both.  Nothing waits for the host: if *n_pairs >
+ *        capacity when EMIT runs, EMIT writes nothing; the caller reads
+ *        *n_pairs (hp_read_total / hp_check_count) and calls EMIT again with
+ *        larger buffers.  If the tasks exceed the workspace (16 P + 2^20 of
+ *        them), *n_pairs is set to INT64_MAX, which no capacity admits.
  * keys/vals: device uint32 [capacity]; ws: hp_bin_workspace_bytes(P). */
 #define HP_BIN_COUNT 1
 #define HP_BIN_EMIT 2
@@ -196,11 +199,13 @@ hp_status hp_bin(int32_t phase, const void* projected, int64_t P, const hp_view*
  * scanned in (tile, chunk) order and each hit is written at its slot.
  * phase as for hp_bin (COUNT writes *n_pairs; EMIT fills vals [capacity] with
  * Gaussian ids grouped by tile and tile_ranges [n_tiles][2] with each active
- * tile's (start, end) in vals, n_tiles from hp_mask_counts).  If *n_pairs >
- * capacity, EMIT writes neither vals nor tile_ranges.  COUNT waits once for
- * `stream` (the task count sizes the task sort); EMIT does not wait.  Until
- * COUNT's work completes, *n_pairs holds INT64_MAX, so an EMIT after a COUNT
- * that returned an error writes nothing.
+ * tile's (start, end) in vals, n_tiles from hp_mask_counts).  No phase waits
+ * for the host: the task and chunk counts that size the steps are read on
+ * the device.  If *n_pairs > capacity (or is INT64_MAX: the tasks exceeded
+ * the workspace, or the COUNT before did not complete), EMIT writes no pair
+ * and sets every tile range to (0, 0), so a render over the result reads no
+ * list entry.  A typical caller passes HP_BIN_ALL with a capacity from an
+ * earlier view and checks *n_pairs afterwards (hp_check_count).
  * ws: hp_bin_sorted_workspace_bytes(P, order, tile_log2) bytes. */
 size_t hp_bin_sorted_workspace_bytes(int64_t P, int32_t order, int32_t tile_log2);
 hp_status hp_bin_sorted(int32_t phase, const void* projected, int64_t P, const hp_view* view, const hp_params* prm,
@@ -237,16 +242,25 @@ hp_status hp_bin_query(int32_t phase, int32_t mode, int32_t f, const void* proje
                        size_t ws_bytes, void* stream);
 /* Waits for `stream` and copies one device int64 to the host. */
 hp_status hp_read_total(const int64_t* dev_value, int64_t* host_value, void* stream);
+/* Synchronous form of the capacity check of an asynchronous count (the
+ * pairs of hp_bin / hp_bin_sorted / hp_bin_query): waits for `stream`,
+ * copies *dev_count to *host_count (nullable) and returns HP_ERR_CAPACITY
+ * when it is negative or exceeds `capacity` (the emission then wrote
+ * nothing), HP_OK otherwise. */
+hp_status hp_check_count(const int64_t* dev_count, int64_t capacity, int64_t* host_count, void* stream);
 
 /* ---- stage 2b: sort + tile ranges (Alg. 1: sort by tile then depth,
  * identify [start_t, end_t)) -------------------------------------------------
- * Stable LSD radix sort of (keys, vals) on the tile key; n_pairs is the host
- * count.  The sorted values are written back to vals (keys too).  tile_ranges
- * [n_tiles][2] receives (start, end) of each active tile's list in vals.
- * ws: hp_sort_workspace_bytes(n_pairs, n_tiles). */
-size_t hp_sort_workspace_bytes(int64_t n_pairs, int32_t n_tiles);
-hp_status hp_sort(uint32_t* keys, uint32_t* vals, int64_t n_pairs, int32_t n_tiles, uint32_t* tile_ranges, void* ws,
-                  size_t ws_bytes, void* stream);
+ * Stable LSD radix sort of the first *n_pairs (keys, vals) pairs on the tile
+ * key; n_pairs is a device int64 (as hp_bin writes it), read on the device,
+ * so the call does not wait for the binning.  The sorted values are written
+ * back to vals (keys too).  tile_ranges [n_tiles][2] receives (start, end)
+ * of each active tile's list in vals.  If *n_pairs exceeds capacity (the
+ * size of keys and vals) nothing is sorted and every range is (0, 0).
+ * ws: hp_sort_workspace_bytes(capacity, n_tiles). */
+size_t hp_sort_workspace_bytes(int64_t capacity, int32_t n_tiles);
+hp_status hp_sort(uint32_t* keys, uint32_t* vals, const int64_t* n_pairs, int64_t capacity, int32_t n_tiles,
+                  uint32_t* tile_ranges, void* ws, size_t ws_bytes, void* stream);
 
 /* ---- stage 3: rendering (Eq. unified_rendering; Alg. 1 rendering loop) ----
  * For each active pixel p, in its tile's list order: d = spherical offset of
@@ -318,16 +332,17 @@ hp_status hp_preprocess_bwd(const hp_gaussians* g, const hp_view* view, const hp
 
 /* ---- radian-space statistics for adaptive density control -----------------
  * (Sec. 4.2: r_s,max tracked across iterations, thresholds in radians.)
- * hp_mark_visible sets visible[i] = 1 for every Gaussian id in
- * vals[0 .. n_pairs) (the view's tile lists; visible [P] uint8 is zeroed by
- * the caller).  hp_density_stats then, for every Gaussian with visible[i],
+ * hp_mark_visible sets visible[i] = 1 for every Gaussian id in the view's
+ * tile lists (vals[start, end) of every tile_ranges entry, n_tiles of them;
+ * visible [P] uint8 is zeroed by the caller).  hp_density_stats then, for every Gaussian with visible[i],
  * sets rs_max[i] = max(rs_max[i], r_s,i), adds to grad_accum[i] the norm of
  * the loss gradient with respect to a displacement of its centre along the
  * sphere, |(dL/domega / cos phi, dL/dphi)| (rows 7 and 8 of the pixel pass's
  * acc [10][P], cos phi from the projected record), and increments count[i].
  * rs_max, grad_accum [P] float and count [P] int32 are device arrays owned by
  * the caller and updated in place. */
-hp_status hp_mark_visible(const uint32_t* vals, int64_t n_pairs, int64_t P, uint8_t* visible, void* stream);
+hp_status hp_mark_visible(const uint32_t* vals, const uint32_t* tile_ranges, int32_t n_tiles, int64_t P,
+                          uint8_t* visible, void* stream);
 hp_status hp_density_stats(const void* projected, int64_t P, const float* acc, const uint8_t* visible, float* rs_max,
                            float* grad_accum, int32_t* count, void* stream);
 

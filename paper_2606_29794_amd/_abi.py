@@ -81,7 +81,8 @@ _PROTOS = {
                            P_, P_, P_, SZ, P_]),
     "hp_read_total": (I32, [P_, C.POINTER(I64), P_]),
     "hp_sort_workspace_bytes": (SZ, [I64, I32]),
-    "hp_sort": (I32, [P_, P_, I64, I32, P_, P_, SZ, P_]),
+    "hp_sort": (I32, [P_, P_, P_, I64, I32, P_, P_, SZ, P_]),
+    "hp_check_count": (I32, [P_, I64, C.POINTER(I64), P_]),
     "hp_render_fwd": (I32, [P_, I64, P_, P_, I32, C.POINTER(hp_view), C.POINTER(hp_params), P_, I64, P_, P_, P_,
                             P_, P_, P_]),
     "hp_render_bwd_workspace_bytes": (SZ, [I64]),
@@ -89,7 +90,7 @@ _PROTOS = {
                             I64, P_, P_, P_, P_, P_, C.POINTER(hp_gaussians_grad), P_, SZ, P_]),
     "hp_render_bwd_pixels": (I32, [P_, I64, P_, P_, I32, C.POINTER(hp_view), C.POINTER(hp_params), P_, I64, P_, P_, P_,
                                    P_, P_, P_, P_]),
-    "hp_mark_visible": (I32, [P_, I64, I64, P_, P_]),
+    "hp_mark_visible": (I32, [P_, P_, I32, I64, P_, P_]),
     "hp_density_stats": (I32, [P_, I64, P_, P_, P_, P_, P_, P_]),
     "hp_preprocess_bwd": (I32, [C.POINTER(hp_gaussians), C.POINTER(hp_view), C.POINTER(hp_params), P_,
                                 C.POINTER(hp_gaussians_grad), P_]),

@@ -41,3 +41,11 @@ extern "C" hp_status hp_read_total(const int64_t* dev_value, int64_t* host_value
   *host_value = v;
   return HP_OK;
 }
+
+extern "C" hp_status hp_check_count(const int64_t* dev_count, int64_t capacity, int64_t* host_count, void* stream) {
+  if (!dev_count || capacity < 0) return HP_ERR_INVALID_ARG;
+  int64_t v = 0;
+  HP_TRY(hp_read_small(&v, dev_count, sizeof(v), (hipStream_t)stream));
+  if (host_count) *host_count = v;
+  return (v < 0 || v > capacity) ? HP_ERR_CAPACITY : HP_OK;
+}

@@ -71,21 +71,11 @@ static inline HpViewK hp_viewk(const hp_view* v) {
 
 static inline unsigned hp_blocks(int64_t n, int threads) { return (unsigned)((n + threads - 1) / threads); }
 
-// Small device-to-host read that waits for `s`: the copy goes through a
-// per-thread pinned buffer, so it is queued behind the stream's work like a
-// kernel (a pageable destination makes the runtime drain the stream first
-// and stage the copy, which costs a second host round trip).  The buffer is
-// allocated on a thread's first read and kept until the process ends.
+// Small device-to-host read that waits for `s`, straight into the caller's
+// host memory (no staging buffer is allocated).
 static inline hp_status hp_read_small(void* dst, const void* src, size_t n, hipStream_t s) {
-  static thread_local void* pin = nullptr;
-  if (n > 256) return HP_ERR_INVALID_ARG;
-  if (!pin && hipHostMalloc(&pin, 256, hipHostMallocDefault) != hipSuccess) {
-    pin = nullptr;
-    return HP_ERR_DEVICE;
-  }
-  if (hipMemcpyAsync(pin, src, n, hipMemcpyDeviceToHost, s) != hipSuccess) return HP_ERR_DEVICE;
+  if (hipMemcpyAsync(dst, src, n, hipMemcpyDeviceToHost, s) != hipSuccess) return HP_ERR_DEVICE;
   if (hipStreamSynchronize(s) != hipSuccess) return HP_ERR_DEVICE;
-  memcpy(dst, pin, n);
   return HP_OK;
 }
 

@@ -1,6 +1,13 @@
 // hp_sort_impl.h -- device-wide exclusive scan and stable LSD radix sort of
-// (uint32 key, uint32 value) pairs, used for the depth order of Gaussians and
-// the per-tile sort of (tile, Gaussian) pairs.
+// (uint32 key, uint32 value) pairs whose element count may live in device
+// memory: the binning sizes its later steps from counts it has just computed
+// on the GPU, so nothing here waits for the host.
+//
+// Both run on a grid fixed at launch from a capacity (an upper bound of the
+// count): block b of G takes the contiguous run of 4096-element tiles
+// [b T / G, (b + 1) T / G), T = ceil(n / 4096), with n read on the device.
+// Wave-level scans use DPP row shifts and row broadcasts; the sort ranks keys
+// with wave ballots on the digit bits.
 #pragma once
 
 #include "hp_common.h"
@@ -8,278 +15,368 @@
 namespace hpsort {
 namespace {  // internal linkage: each translation unit keeps its own kernels
 
-constexpr int kScanThreads = 1024;
-constexpr int kScanItems = 4;                       // per thread
-constexpr int kScanTile = kScanThreads * kScanItems;  // 4096 per block
-constexpr int kMaxScanBlocks = kScanThreads * 16;     // second level capacity
+constexpr int kThreads = 256;              // 4 waves
+constexpr int kItems = 16;                 // per thread and tile
+constexpr int kTile = kThreads * kItems;   // 4096 elements per tile
+constexpr int kMaxGrid = 1024;
 
-constexpr int kSortThreads = 256;
-constexpr int kSortItems = 16;
-constexpr int kSortTile = kSortThreads * kSortItems;  // 4096 pairs per block
-
-// ---------------------------------------------------------------------------
-// scan
-// ---------------------------------------------------------------------------
-template <class T>
-__device__ __forceinline__ T block_exclusive_scan(T v, T* total) {
-  // 1024 threads = 16 waves
-  __shared__ T s_w[16];
-  const int lane = hp_lane(), w = threadIdx.x >> 6;
-  T x = v;
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    T y = __shfl_up(x, off, 64);
-    if (lane >= off) x += y;
-  }
-  if (lane == 63) s_w[w] = x;
-  __syncthreads();
-  if (w == 0) {
-    T t = lane < (int)(blockDim.x >> 6) ? s_w[lane] : T(0);
-#pragma unroll
-    for (int off = 1; off < 16; off <<= 1) {
-      T y = __shfl_up(t, off, 64);
-      if (lane >= off) t += y;
-    }
-    if (lane < 16) s_w[lane] = t;
-  }
-  __syncthreads();
-  T wave_base = w > 0 ? s_w[w - 1] : T(0);
-  *total = s_w[(blockDim.x >> 6) - 1];
-  __syncthreads();
-  return wave_base + x - v;
+// element count: min(*n, cap) (cap when n is null)
+__device__ __forceinline__ int64_t dev_count(const uint64_t* n, int64_t cap) {
+  if (!n) return cap;
+  const uint64_t v = *n;
+  return v < (uint64_t)cap ? (int64_t)v : cap;
 }
 
-// per block: exclusive scan of its 4096 elements (in place into out) and the block sum
+inline unsigned grid_for(int64_t cap) {
+  const int64_t t = (cap + kTile - 1) / kTile;
+  return (unsigned)(t < 1 ? 1 : (t > kMaxGrid ? kMaxGrid : t));
+}
+
+// tiles of block b: [t0, t1)
+__device__ __forceinline__ void block_tiles(int64_t n, int64_t* t0, int64_t* t1) {
+  const int64_t T = (n + kTile - 1) / kTile, G = gridDim.x, b = blockIdx.x;
+  *t0 = T * b / G;
+  *t1 = T * (b + 1) / G;
+}
+
+// ---------------------------------------------------------------------------
+// wave and block scans
+// ---------------------------------------------------------------------------
+template <int CTRL, int ROW_MASK, bool BOUND>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROW_MASK, 0xf, BOUND);
+}
+template <int CTRL, int ROW_MASK, bool BOUND>
+__device__ __forceinline__ uint64_t dpp_u64(uint64_t v) {
+  const uint32_t lo = dpp_u32<CTRL, ROW_MASK, BOUND>((uint32_t)v);
+  const uint32_t hi = dpp_u32<CTRL, ROW_MASK, BOUND>((uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+template <int CTRL, int ROW_MASK, bool BOUND>
+__device__ __forceinline__ uint32_t dpp_any(uint32_t v) { return dpp_u32<CTRL, ROW_MASK, BOUND>(v); }
+template <int CTRL, int ROW_MASK, bool BOUND>
+__device__ __forceinline__ uint64_t dpp_any(uint64_t v) { return dpp_u64<CTRL, ROW_MASK, BOUND>(v); }
+
+// Inclusive scan over the 64 lanes (all active): Hillis-Steele inside each
+// 16-lane row with row_shr 1, 2, 4, 8 (lanes whose source lies before the row
+// start add 0), then row_bcast:15 adds the last lane of rows 0 and 2 into rows
+// 1 and 3, and row_bcast:31 adds lane 31 (rows 0 + 1) into rows 2 and 3.
+template <class T>
+__device__ __forceinline__ T wave_inclusive(T x) {
+  x += dpp_any<0x111, 0xf, true>(x);
+  x += dpp_any<0x112, 0xf, true>(x);
+  x += dpp_any<0x114, 0xf, true>(x);
+  x += dpp_any<0x118, 0xf, true>(x);
+  x += dpp_any<0x142, 0xa, false>(x);
+  x += dpp_any<0x143, 0xc, false>(x);
+  return x;
+}
+
+// Exclusive scan over the 256 threads of a block; *total gets the block's
+// sum.  s_w: 4 elements of LDS.
+template <class T>
+__device__ __forceinline__ T block_exclusive(T v, T* total, T* s_w) {
+  const int w = threadIdx.x >> 6;
+  const T inc = wave_inclusive<T>(v);
+  if (hp_lane() == 63) s_w[w] = inc;
+  __syncthreads();
+  const T w0 = s_w[0], w1 = s_w[1], w2 = s_w[2], w3 = s_w[3];
+  __syncthreads();  // s_w may be rewritten by the caller's next round
+  T base = 0;
+  if (w > 0) base += w0;
+  if (w > 1) base += w1;
+  if (w > 2) base += w2;
+  *total = w0 + w1 + w2 + w3;
+  return base + inc - v;
+}
+
+// ---------------------------------------------------------------------------
+// scan: out[i] = sum of in[0 .. i), *grand = sum of all (n from the device)
+// ---------------------------------------------------------------------------
 template <class T, class In>
-__global__ __launch_bounds__(kScanThreads) void k_scan_local(const In* __restrict__ in, T* __restrict__ out, int64_t n,
-                                                             T* __restrict__ sums) {
-  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
-  T v[kScanItems];
+__global__ __launch_bounds__(kThreads) void k_scan_reduce(const In* __restrict__ in, const uint64_t* __restrict__ cnt,
+                                                          int64_t cap, T* __restrict__ sums) {
+  __shared__ T s_w[4];
+  const int64_t n = dev_count(cnt, cap);
+  int64_t t0, t1;
+  block_tiles(n, &t0, &t1);
   T acc = 0;
+  for (int64_t t = t0; t < t1; ++t) {
+    const int64_t base = t * kTile + threadIdx.x;
 #pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
-    v[k] = base + k < n ? (T)in[base + k] : T(0);
-    acc += v[k];
+    for (int k = 0; k < kItems; ++k) {
+      const int64_t i = base + (int64_t)k * kThreads;
+      if (i < n) acc += (T)in[i];
+    }
   }
   T total;
-  T ex = block_exclusive_scan<T>(acc, &total);
-#pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
-    if (base + k < n) out[base + k] = ex;
-    ex += v[k];
-  }
+  block_exclusive<T>(acc, &total, s_w);
   if (threadIdx.x == 0) sums[blockIdx.x] = total;
 }
 
-// single block: exclusive scan of the block sums (up to kMaxScanBlocks), total to *grand
-template <class T>
-__global__ __launch_bounds__(kScanThreads) void k_scan_sums(T* sums, int64_t nb, T* grand) {
-  const int per = (int)((nb + kScanThreads - 1) / kScanThreads);
-  const int64_t lo = (int64_t)threadIdx.x * per;
-  T acc = 0;
-  for (int k = 0; k < per; ++k)
-    if (lo + k < nb) acc += sums[lo + k];
-  T total;
-  T ex = block_exclusive_scan<T>(acc, &total);
-  for (int k = 0; k < per; ++k)
-    if (lo + k < nb) {
-      T s = sums[lo + k];
-      sums[lo + k] = ex;
-      ex += s;
-    }
-  if (threadIdx.x == 0 && grand) *grand = total;
-}
-
-template <class T>
-__global__ __launch_bounds__(kScanThreads) void k_scan_add(T* __restrict__ out, int64_t n, const T* __restrict__ sums) {
-  const T add = sums[blockIdx.x];
-  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
-#pragma unroll
-  for (int k = 0; k < kScanItems; ++k)
-    if (base + k < n) out[base + k] += add;
-}
-
-template <class T>
-inline size_t scan_ws_bytes(int64_t n) {
-  return hp_align256((size_t)((n + kScanTile - 1) / kScanTile + 1) * sizeof(T));
-}
-
-// exclusive scan of n elements of `in` (converted to T) into `out`; *grand
-// (device, nullable) receives the total.  n <= kScanTile * kMaxScanBlocks.
+// every block adds the sums of the blocks before it, then scans its tiles
+// (16 consecutive elements per thread) with a running carry
 template <class T, class In>
-inline hp_status scan_exclusive(const In* in, T* out, int64_t n, T* grand, void* ws, hipStream_t s) {
-  if (n <= 0) return HP_OK;
-  const int64_t nb = (n + kScanTile - 1) / kScanTile;
-  if (nb > kMaxScanBlocks) return HP_ERR_UNSUPPORTED;
-  T* sums = (T*)ws;
-  hipLaunchKernelGGL((k_scan_local<T, In>), dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, out, n, sums);
-  HP_CHECK_LAUNCH();
-  hipLaunchKernelGGL((k_scan_sums<T>), dim3(1), dim3(kScanThreads), 0, s, sums, nb, grand);
-  HP_CHECK_LAUNCH();
-  if (nb > 1) {
-    hipLaunchKernelGGL((k_scan_add<T>), dim3((unsigned)nb), dim3(kScanThreads), 0, s, out, n, sums);
-    HP_CHECK_LAUNCH();
+__global__ __launch_bounds__(kThreads) void k_scan_down(const In* in, T* out, const uint64_t* __restrict__ cnt,
+                                                        int64_t cap, const T* __restrict__ sums, T* grand) {
+  __shared__ T s_w[4];
+  const int64_t n = dev_count(cnt, cap);
+  int64_t t0, t1;
+  block_tiles(n, &t0, &t1);
+  // prefix of the block sums before this block (and all of them)
+  T pre = 0, all = 0;
+  for (int j = threadIdx.x; j < (int)gridDim.x; j += kThreads) {
+    const T s = sums[j];
+    all += s;
+    if (j < (int)blockIdx.x) pre += s;
   }
+  T carry, tot_all;
+  block_exclusive<T>(pre, &carry, s_w);
+  block_exclusive<T>(all, &tot_all, s_w);
+  if (grand && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *grand = tot_all;
+  for (int64_t t = t0; t < t1; ++t) {
+    const int64_t base = t * kTile + (int64_t)threadIdx.x * kItems;
+    T v[kItems];
+    T acc = 0;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+      v[k] = base + k < n ? (T)in[base + k] : T(0);
+      acc += v[k];
+    }
+    T tile_total;
+    T ex = block_exclusive<T>(acc, &tile_total, s_w) + carry;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+      if (base + k < n) out[base + k] = ex;
+      ex += v[k];
+    }
+    carry += tile_total;
+  }
+}
+
+template <class T>
+inline size_t scan_ws_bytes(int64_t cap) {
+  return hp_align256((size_t)grid_for(cap) * sizeof(T));
+}
+
+// Exclusive scan of the first min(*cnt, cap) elements of `in` (converted to
+// T) into `out` (in place allowed); *grand (device, nullable) receives the
+// total.  cnt null: cap elements.
+template <class T, class In>
+inline hp_status scan_exclusive(const In* in, T* out, const uint64_t* cnt, int64_t cap, T* grand, void* ws,
+                                hipStream_t s) {
+  if (cap < 0) return HP_ERR_INVALID_ARG;
+  const unsigned G = grid_for(cap);
+  T* sums = (T*)ws;
+  hipLaunchKernelGGL((k_scan_reduce<T, In>), dim3(G), dim3(kThreads), 0, s, in, cnt, cap, sums);
+  HP_CHECK_LAUNCH();
+  hipLaunchKernelGGL((k_scan_down<T, In>), dim3(G), dim3(kThreads), 0, s, in, out, cnt, cap, (const T*)sums, grand);
+  HP_CHECK_LAUNCH();
   return HP_OK;
 }
 
 // ---------------------------------------------------------------------------
 // radix sort
 // ---------------------------------------------------------------------------
-// digit histogram of each block's 4096 keys: hist[d * nblocks + block]
-__global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t* __restrict__ keys, int64_t n, int shift,
-                                                             int bits, uint32_t* __restrict__ hist, int64_t nblocks) {
+// digit histogram of each block's tiles: hist[block * radix + digit]
+__global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t* __restrict__ keys,
+                                                         const uint64_t* __restrict__ cnt, int64_t cap, int shift,
+                                                         int bits, uint32_t* __restrict__ hist) {
   __shared__ uint32_t s_h[256];
   const int radix = 1 << bits;
-  for (int d = threadIdx.x; d < radix; d += kSortThreads) s_h[d] = 0;
-  __syncthreads();
-  const int64_t base = (int64_t)blockIdx.x * kSortTile;
   const uint32_t mask = (uint32_t)radix - 1;
-#pragma unroll 4
-  for (int k = 0; k < kSortItems; ++k) {
-    const int64_t i = base + (int64_t)k * kSortThreads + threadIdx.x;
-    if (i < n) atomicAdd(&s_h[(keys[i] >> shift) & mask], 1u);
-  }
+  for (int d = threadIdx.x; d < radix; d += kThreads) s_h[d] = 0;
   __syncthreads();
-  for (int d = threadIdx.x; d < radix; d += kSortThreads) hist[(int64_t)d * nblocks + blockIdx.x] = s_h[d];
+  const int64_t n = dev_count(cnt, cap);
+  int64_t t0, t1;
+  block_tiles(n, &t0, &t1);
+  const int64_t lo = t0 * kTile, hi = t1 * kTile < n ? t1 * kTile : n;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += kThreads) atomicAdd(&s_h[(keys[i] >> shift) & mask], 1u);
+  __syncthreads();
+  for (int d = threadIdx.x; d < radix; d += kThreads) hist[(int64_t)blockIdx.x * radix + d] = s_h[d];
 }
 
-// Stable scatter.  Wave w of a block owns the contiguous items
-// [w*1024, (w+1)*1024) of the block's 4096 and ranks them in 16 rounds of 64:
+// One block of 1024 threads turns the histograms into output offsets:
+// hist[b][d] <- start of digit d + count of digit d in blocks before b.
+// Thread (part p, digit d) sums its quarter of the blocks; the digit totals
+// are scanned over the digits; each quarter then rewrites its entries.
+__global__ __launch_bounds__(1024) void k_radix_offsets(uint32_t* __restrict__ hist, int nblocks, int bits) {
+  __shared__ uint32_t s_part[4][256];
+  __shared__ uint32_t s_w[4];
+  __shared__ uint32_t s_start[256];
+  const int radix = 1 << bits;
+  const int d = threadIdx.x & 255, p = threadIdx.x >> 8;
+  const int b0 = nblocks * p / 4, b1 = nblocks * (p + 1) / 4;
+  uint32_t sum = 0;
+  if (d < radix)
+    for (int b = b0; b < b1; ++b) sum += hist[(int64_t)b * radix + d];
+  s_part[p][d] = sum;
+  __syncthreads();
+  // digit totals and their exclusive scan over the digits: waves 0-3 (part
+  // 0) hold digits 0..255, one per lane; every barrier is reached by all
+  // threads
+  uint32_t tot = 0, inc = 0;
+  if (p == 0) {
+    tot = d < radix ? s_part[0][d] + s_part[1][d] + s_part[2][d] + s_part[3][d] : 0u;
+    inc = wave_inclusive<uint32_t>(tot);
+    if (hp_lane() == 63) s_w[threadIdx.x >> 6] = inc;
+  }
+  __syncthreads();
+  if (p == 0) {
+    const int w = threadIdx.x >> 6;
+    uint32_t base = 0;
+    for (int k = 0; k < w; ++k) base += s_w[k];
+    s_start[d] = base + inc - tot;
+  }
+  __syncthreads();
+  if (d < radix) {
+    uint32_t run = s_start[d];
+    for (int q = 0; q < p; ++q) run += s_part[q][d];
+    for (int b = b0; b < b1; ++b) {
+      const int64_t at = (int64_t)b * radix + d;
+      const uint32_t h = hist[at];
+      hist[at] = run;
+      run += h;
+    }
+  }
+}
+
+// Stable scatter of each block's tiles, in order.  Per tile, wave w owns the
+// contiguous items [w*1024, (w+1)*1024) and ranks them in 16 rounds of 64:
 // equal digits inside a round are matched by ballots on the digit bits, and a
 // running count per digit, private to the wave, carries the rank across
-// rounds.  After one barrier the per-wave counts become per-wave offsets and
-// the block's items are placed in LDS sorted by digit, so that the final
-// writes go out as contiguous runs per digit.
-__global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t* __restrict__ keys,
-                                                                const uint32_t* __restrict__ vals, int64_t n,
-                                                                int shift, int bits, const uint32_t* __restrict__ offs,
-                                                                int64_t nblocks, uint32_t* __restrict__ okeys,
-                                                                uint32_t* __restrict__ ovals) {
-  constexpr int kWaveItems = kSortTile / 4;  // 1024
-  constexpr int kRounds = kWaveItems / 64;   // 16
+// rounds.  The tile is then placed in LDS sorted by digit, so that the global
+// writes go out as contiguous runs per digit, and the block's running digit
+// offsets advance by the tile's digit counts.
+__global__ __launch_bounds__(kThreads) void k_radix_scatter(const uint32_t* __restrict__ keys,
+                                                            const uint32_t* __restrict__ vals,
+                                                            const uint64_t* __restrict__ cnt, int64_t cap, int shift,
+                                                            int bits, const uint32_t* __restrict__ offs,
+                                                            uint32_t* __restrict__ okeys, uint32_t* __restrict__ ovals) {
+  constexpr int kWaveItems = kTile / 4;     // 1024
+  constexpr int kRounds = kWaveItems / 64;  // 16
   __shared__ uint32_t s_cnt[4][256];
   __shared__ uint32_t s_loc[256];
   __shared__ uint32_t s_goff[256];
-  __shared__ uint32_t s_key[kSortTile];
-  __shared__ uint32_t s_val[kSortTile];
+  __shared__ uint32_t s_wsum[4];
+  __shared__ uint32_t s_key[kTile];
+  __shared__ uint32_t s_val[kTile];
   const int radix = 1 << bits;
   const uint32_t mask = (uint32_t)radix - 1;
   const int tid = threadIdx.x, lane = hp_lane(), w = tid >> 6;
-  for (int k = tid; k < 4 * 256; k += kSortThreads) (&s_cnt[0][0])[k] = 0;
-  for (int d = tid; d < radix; d += kSortThreads) s_goff[d] = offs[(int64_t)d * nblocks + blockIdx.x];
-  __syncthreads();
+  const int64_t n = dev_count(cnt, cap);
+  int64_t t0, t1;
+  block_tiles(n, &t0, &t1);
+  for (int d = tid; d < radix; d += kThreads) s_goff[d] = offs[(int64_t)blockIdx.x * radix + d];
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  const int64_t base = (int64_t)blockIdx.x * kSortTile;
-  uint32_t rk[kRounds], kk[kRounds], vv[kRounds];
-#pragma unroll
-  for (int r = 0; r < kRounds; ++r) {
-    const int64_t i = base + (int64_t)w * kWaveItems + r * 64 + lane;
-    const bool valid = i < n;
-    const uint32_t key = valid ? keys[i] : 0u;
-    kk[r] = key;
-    vv[r] = valid ? vals[i] : 0u;
-    const uint32_t d = (key >> shift) & mask;
-    uint64_t peers = __ballot(valid);
-    for (int b = 0; b < bits; ++b) {
-      const bool bit = (d >> b) & 1u;
-      const uint64_t m = __ballot(bit);
-      peers &= bit ? m : ~m;
-    }
-    uint32_t before = 0;
-    if (valid) before = s_cnt[w][d];
-    rk[r] = before + (uint32_t)__popcll(peers & lt);
-    const int leader = __ffsll((unsigned long long)peers) - 1;
-    if (valid && lane == leader) s_cnt[w][d] = before + (uint32_t)__popcll(peers);
-  }
-  __syncthreads();
-  // per digit: per-wave exclusive offsets and the block-local start of the digit
-  uint32_t tot = 0;
-  if (tid < radix) {
-    const uint32_t c0 = s_cnt[0][tid], c1 = s_cnt[1][tid], c2 = s_cnt[2][tid], c3 = s_cnt[3][tid];
-    s_cnt[0][tid] = 0;
-    s_cnt[1][tid] = c0;
-    s_cnt[2][tid] = c0 + c1;
-    s_cnt[3][tid] = c0 + c1 + c2;
-    tot = c0 + c1 + c2 + c3;
-  }
-  // exclusive scan of the digit totals over the (<= 256) digits
-  {
-    uint32_t x = tot;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-      const uint32_t y = __shfl_up(x, off, 64);
-      if (lane >= off) x += y;
-    }
-    __shared__ uint32_t s_wsum[4];
-    if (lane == 63) s_wsum[w] = x;
+  for (int64_t t = t0; t < t1; ++t) {
+    for (int k = tid; k < 4 * 256; k += kThreads) (&s_cnt[0][0])[k] = 0;
     __syncthreads();
-    uint32_t add = 0;
-    for (int k = 0; k < w; ++k) add += s_wsum[k];
-    if (tid < radix) s_loc[tid] = add + x - tot;
-  }
-  __syncthreads();
+    const int64_t base = t * kTile;
+    uint32_t rk[kRounds], kk[kRounds], vv[kRounds];
 #pragma unroll
-  for (int r = 0; r < kRounds; ++r) {
-    const int64_t i = base + (int64_t)w * kWaveItems + r * 64 + lane;
-    if (i < n) {
-      const uint32_t d = (kk[r] >> shift) & mask;
-      const uint32_t lp = s_loc[d] + s_cnt[w][d] + rk[r];
-      s_key[lp] = kk[r];
-      s_val[lp] = vv[r];
+    for (int r = 0; r < kRounds; ++r) {
+      const int64_t i = base + (int64_t)w * kWaveItems + r * 64 + lane;
+      const bool valid = i < n;
+      const uint32_t key = valid ? keys[i] : 0u;
+      kk[r] = key;
+      vv[r] = valid ? vals[i] : 0u;
+      const uint32_t d = (key >> shift) & mask;
+      uint64_t peers = __ballot(valid);
+      for (int b = 0; b < bits; ++b) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t m = __ballot(bit);
+        peers &= bit ? m : ~m;
+      }
+      uint32_t before = 0;
+      if (valid) before = s_cnt[w][d];
+      rk[r] = before + (uint32_t)__popcll(peers & lt);
+      const int leader = __ffsll((unsigned long long)peers) - 1;
+      if (valid && lane == leader) s_cnt[w][d] = before + (uint32_t)__popcll(peers);
     }
+    __syncthreads();
+    // per digit: per-wave exclusive offsets and the tile-local start of the digit
+    uint32_t tot = 0;
+    if (tid < radix) {
+      const uint32_t c0 = s_cnt[0][tid], c1 = s_cnt[1][tid], c2 = s_cnt[2][tid], c3 = s_cnt[3][tid];
+      s_cnt[0][tid] = 0;
+      s_cnt[1][tid] = c0;
+      s_cnt[2][tid] = c0 + c1;
+      s_cnt[3][tid] = c0 + c1 + c2;
+      tot = c0 + c1 + c2 + c3;
+    }
+    uint32_t all;
+    const uint32_t loc = block_exclusive<uint32_t>(tot, &all, s_wsum);
+    if (tid < radix) s_loc[tid] = loc;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+      const int64_t i = base + (int64_t)w * kWaveItems + r * 64 + lane;
+      if (i < n) {
+        const uint32_t d = (kk[r] >> shift) & mask;
+        const uint32_t lp = s_loc[d] + s_cnt[w][d] + rk[r];
+        s_key[lp] = kk[r];
+        s_val[lp] = vv[r];
+      }
+    }
+    __syncthreads();
+    const int nloc = (int)(n - base < kTile ? n - base : kTile);
+    for (int lp = tid; lp < nloc; lp += kThreads) {
+      const uint32_t key = s_key[lp];
+      const uint32_t d = (key >> shift) & mask;
+      const uint32_t g = s_goff[d] + ((uint32_t)lp - s_loc[d]);
+      okeys[g] = key;
+      ovals[g] = s_val[lp];
+    }
+    __syncthreads();
+    // the tile's digit counts move the block's offsets on
+    if (tid < radix) s_goff[tid] += tot;
   }
-  __syncthreads();
-  const int64_t nloc = n - base < kSortTile ? n - base : kSortTile;
-  for (int lp = tid; lp < nloc; lp += kSortThreads) {
-    const uint32_t key = s_key[lp];
-    const uint32_t d = (key >> shift) & mask;
-    const uint32_t g = s_goff[d] + ((uint32_t)lp - s_loc[d]);
-    okeys[g] = key;
-    ovals[g] = s_val[lp];
-  }
 }
 
-__global__ void k_copy_u32(const uint32_t* __restrict__ a, uint32_t* __restrict__ b, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) b[i] = a[i];
+__global__ void k_copy_u32(const uint32_t* __restrict__ a, uint32_t* __restrict__ b, const uint64_t* __restrict__ cnt,
+                           int64_t cap) {
+  const int64_t n = dev_count(cnt, cap);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    b[i] = a[i];
 }
 
-inline size_t radix_ws_bytes(int64_t n) {
-  const int64_t nb = (n + kSortTile - 1) / kSortTile;
-  const int64_t h = 256 * (nb > 0 ? nb : 1);
-  return 2 * hp_align256((size_t)n * 4) + hp_align256((size_t)h * 4) + scan_ws_bytes<uint32_t>(h);
+inline unsigned copy_grid(int64_t cap) {
+  const int64_t b = (cap + 255) / 256;
+  return (unsigned)(b < 1 ? 1 : (b > 4096 ? 4096 : b));
 }
 
-// Stable sort of (keys, vals) by the low `nbits` bits of the key; the result
-// ends in keys/vals.
-// Stable sort of n (key, value) pairs by the low nbits of the key.  The
-// result is left in (keys, vals), or, when out_keys / out_vals are given, in
-// whichever of (keys, vals) and the workspace's second buffer the last pass
-// wrote (returned through them; no copy back).
-inline hp_status radix_sort(uint32_t* keys, uint32_t* vals, int64_t n, int nbits, void* ws, hipStream_t s,
-                            uint32_t** out_keys = nullptr, uint32_t** out_vals = nullptr) {
+inline size_t radix_ws_bytes(int64_t cap) {
+  return 2 * hp_align256((size_t)(cap > 0 ? cap : 1) * 4) + hp_align256((size_t)grid_for(cap) * 256 * 4);
+}
+
+// Stable sort of the first min(*cnt, cap) (key, value) pairs by the low
+// `nbits` bits of the key (cnt null: cap pairs).  The result is left in
+// (keys, vals), or, when out_keys / out_vals are given, in whichever of
+// (keys, vals) and the workspace's second buffer the last pass wrote
+// (returned through them; no copy back).
+inline hp_status radix_sort(uint32_t* keys, uint32_t* vals, const uint64_t* cnt, int64_t cap, int nbits, void* ws,
+                            hipStream_t s, uint32_t** out_keys = nullptr, uint32_t** out_vals = nullptr) {
   if (out_keys) *out_keys = keys;
   if (out_vals) *out_vals = vals;
-  if (n <= 1 || nbits <= 0) return HP_OK;
+  if (cap <= 1 || nbits <= 0) return HP_OK;
   const int passes = (nbits + 7) / 8;
   const int bits = (nbits + passes - 1) / passes;
-  const int64_t nb = (n + kSortTile - 1) / kSortTile;
+  const unsigned G = grid_for(cap);
   char* p = (char*)ws;
-  uint32_t* k2 = (uint32_t*)p; p += hp_align256((size_t)n * 4);
-  uint32_t* v2 = (uint32_t*)p; p += hp_align256((size_t)n * 4);
-  uint32_t* hist = (uint32_t*)p; p += hp_align256((size_t)256 * nb * 4);
-  void* sws = p;
+  uint32_t* k2 = (uint32_t*)p; p += hp_align256((size_t)cap * 4);
+  uint32_t* v2 = (uint32_t*)p; p += hp_align256((size_t)cap * 4);
+  uint32_t* hist = (uint32_t*)p;
   uint32_t *ka = keys, *va = vals, *kb = k2, *vb = v2;
   for (int pass = 0; pass < passes; ++pass) {
     const int shift = pass * bits;
     const int b = (shift + bits <= nbits) ? bits : nbits - shift;
-    const int64_t nh = (int64_t)(1 << b) * nb;
-    hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(kSortThreads), 0, s, ka, n, shift, b, hist, nb);
+    hipLaunchKernelGGL(k_radix_hist, dim3(G), dim3(kThreads), 0, s, (const uint32_t*)ka, cnt, cap, shift, b, hist);
     HP_CHECK_LAUNCH();
-    HP_TRY((scan_exclusive<uint32_t, uint32_t>(hist, hist, nh, (uint32_t*)nullptr, sws, s)));
-    hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nb), dim3(kSortThreads), 0, s, ka, va, n, shift, b, hist, nb,
-                       kb, vb);
+    hipLaunchKernelGGL(k_radix_offsets, dim3(1), dim3(1024), 0, s, hist, (int)G, b);
+    HP_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_radix_scatter, dim3(G), dim3(kThreads), 0, s, (const uint32_t*)ka, (const uint32_t*)va, cnt,
+                       cap, shift, b, (const uint32_t*)hist, kb, vb);
     HP_CHECK_LAUNCH();
     uint32_t* t = ka; ka = kb; kb = t;
     t = va; va = vb; vb = t;
@@ -290,9 +387,9 @@ inline hp_status radix_sort(uint32_t* keys, uint32_t* vals, int64_t n, int nbits
     return HP_OK;
   }
   if (ka != keys) {
-    hipLaunchKernelGGL(k_copy_u32, dim3(hp_blocks(n, 256)), dim3(256), 0, s, ka, keys, n);
+    hipLaunchKernelGGL(k_copy_u32, dim3(copy_grid(cap)), dim3(256), 0, s, (const uint32_t*)ka, keys, cnt, cap);
     HP_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_copy_u32, dim3(hp_blocks(n, 256)), dim3(256), 0, s, va, vals, n);
+    hipLaunchKernelGGL(k_copy_u32, dim3(copy_grid(cap)), dim3(256), 0, s, (const uint32_t*)va, vals, cnt, cap);
     HP_CHECK_LAUNCH();
   }
   return HP_OK;

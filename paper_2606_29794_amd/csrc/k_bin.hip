@@ -19,14 +19,18 @@ struct BinWs {
   uint32_t* dkey;    // [P] depth bits, then sorted
   uint32_t* order;   // [P] Gaussian ids in depth order
   uint32_t* tcount;  // [P] tasks per Gaussian (depth order)
-  uint32_t* toff;    // [P] exclusive scan of tcount
+  uint64_t* toff;    // [P] exclusive scan of tcount (64-bit: the total may pass 2^32)
   uint32_t* task_g;  // [cap_t] Gaussian of each task
   uint32_t* task_n;  // [cap_t] node index at the split level
   uint32_t* pcount;  // [cap_t] pairs per task
   uint64_t* pmask;   // [cap_t] tiles hit below the task's node (bit per leaf)
   uint64_t* poff;    // [cap_t] exclusive scan of pcount
-  uint32_t* t_total; // device scalars: task total (u32), pair total (u64)
-  uint64_t* p_total;
+  // device scalars
+  uint64_t* t_total;  // tasks wanted (scan total)
+  uint64_t* nt;       // tasks kept: min(t_total, cap_t)
+  uint64_t* p_total;  // pairs
+  uint64_t* ncol;     // (chunk, leaf) count entries to scan (sorted emission)
+  uint32_t* over;     // 1 when the tasks exceeded cap_t
   void* sort_ws;
   void* scan_ws;
   int64_t cap_t;
@@ -36,7 +40,7 @@ static int64_t task_capacity(int64_t P) { return 16 * P + (1 << 20); }
 
 static size_t bin_ws_size(int64_t P) {
   const int64_t ct = task_capacity(P);
-  return 4 * hp_align256(P * 4) + 3 * hp_align256(ct * 4) + 2 * hp_align256(ct * 8) + 256 +
+  return 3 * hp_align256(P * 4) + hp_align256(P * 8) + 3 * hp_align256(ct * 4) + 2 * hp_align256(ct * 8) + 256 +
          hpsort::radix_ws_bytes(P) + hpsort::scan_ws_bytes<uint64_t>(ct > P ? ct : P);
 }
 
@@ -47,19 +51,30 @@ static BinWs bin_ws(void* base, int64_t P) {
   w.dkey = (uint32_t*)p; p += hp_align256(P * 4);
   w.order = (uint32_t*)p; p += hp_align256(P * 4);
   w.tcount = (uint32_t*)p; p += hp_align256(P * 4);
-  w.toff = (uint32_t*)p; p += hp_align256(P * 4);
+  w.toff = (uint64_t*)p; p += hp_align256(P * 8);
   w.task_g = (uint32_t*)p; p += hp_align256(ct * 4);
   w.task_n = (uint32_t*)p; p += hp_align256(ct * 4);
   w.pcount = (uint32_t*)p; p += hp_align256(ct * 4);
   w.pmask = (uint64_t*)p; p += hp_align256(ct * 8);
   w.poff = (uint64_t*)p; p += hp_align256(ct * 8);
-  w.t_total = (uint32_t*)p;
-  w.p_total = (uint64_t*)(p + 128);
+  w.t_total = (uint64_t*)p;
+  w.nt = (uint64_t*)(p + 8);
+  w.p_total = (uint64_t*)(p + 16);
+  w.ncol = (uint64_t*)(p + 24);
+  w.over = (uint32_t*)(p + 32);
   p += 256;
   w.sort_ws = p; p += hpsort::radix_ws_bytes(P);
   w.scan_ws = p;
   w.cap_t = ct;
   return w;
+}
+
+// tasks kept and the overflow flag, from the scanned task total
+__global__ void k_task_clamp(const uint64_t* __restrict__ t_total, int64_t cap_t, uint64_t* __restrict__ nt,
+                             uint32_t* __restrict__ over) {
+  const uint64_t t = *t_total;
+  *over = t > (uint64_t)cap_t ? 1u : 0u;
+  *nt = t > (uint64_t)cap_t ? (uint64_t)cap_t : t;
 }
 
 __global__ void k_depth_keys(int64_t P, const float* __restrict__ depth, uint32_t* __restrict__ key,
@@ -178,8 +193,9 @@ template <bool EMIT>
 __global__ __launch_bounds__(256) void k_bin_coarse(int64_t P, const uint32_t* __restrict__ order,
                                                     const float4* __restrict__ disc, const float* __restrict__ radius,
                                                     BinTables T, float guard, uint32_t* __restrict__ tcount,
-                                                    const uint32_t* __restrict__ toff, uint32_t* __restrict__ task_g,
-                                                    uint32_t* __restrict__ task_n, uint32_t* __restrict__ slots) {
+                                                    const uint64_t* __restrict__ toff, int64_t cap_t,
+                                                    uint32_t* __restrict__ task_g, uint32_t* __restrict__ task_n,
+                                                    uint32_t* __restrict__ slots) {
   // the quadtree's top levels (faces and two more: 252 nodes) in LDS; every
   // walk starts there
   __shared__ float4 s_cap[kTopNodes];
@@ -196,11 +212,16 @@ __global__ __launch_bounds__(256) void k_bin_coarse(int64_t P, const uint32_t* _
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= P) return;
   const uint32_t gid = order[k];
+  // the emit pass writes a Gaussian's tasks at its scanned offset, and none
+  // past the task capacity (the count pass then flagged the overflow)
+  const uint64_t base = EMIT ? toff[k] : 0ull;
+  const uint32_t room = EMIT ? (base >= (uint64_t)cap_t ? 0u
+                                : (uint32_t)min((uint64_t)tcount[k], (uint64_t)cap_t - base))
+                             : 0u;
   if (EMIT && slots) {
     const uint32_t cnt = tcount[k];
     if (cnt <= (uint32_t)kSlots) {
-      const uint32_t base = toff[k];
-      for (uint32_t j = 0; j < cnt; ++j) {
+      for (uint32_t j = 0; j < room; ++j) {
         task_g[base + j] = gid;
         task_n[base + j] = slots[(int64_t)j * P + k];
       }
@@ -215,9 +236,6 @@ __global__ __launch_bounds__(256) void k_bin_coarse(int64_t P, const uint32_t* _
     return;
   }
   uint32_t cnt = 0;
-  const uint32_t base = EMIT ? toff[k] : 0;
-  // the emit walk writes no more tasks than the count walk reserved
-  const uint32_t room = EMIT ? tcount[k] : 0;
   // node test: the top levels from the LDS copy, deeper ones from memory
   auto pass = [&](int64_t node) -> bool {
     if (node < ntop) {
@@ -284,7 +302,7 @@ __device__ __forceinline__ uint64_t hp_readlane64(uint64_t v, int i) {
   return ((uint64_t)hi << 32) | lo;
 }
 
-__global__ __launch_bounds__(256) void k_bin_fine_count(const uint32_t* __restrict__ n_tasks, int64_t cap_t,
+__global__ __launch_bounds__(256) void k_bin_fine_count(const uint64_t* __restrict__ n_tasks, int64_t cap_t,
                                                         const uint32_t* __restrict__ task_g,
                                                         const uint32_t* __restrict__ task_n,
                                                         const float4* __restrict__ disc, BinTables T,
@@ -345,7 +363,7 @@ __global__ __launch_bounds__(256) void k_bin_fine_count(const uint32_t* __restri
   }
 }
 
-__global__ __launch_bounds__(256) void k_bin_fine_emit(const uint32_t* __restrict__ n_tasks, int64_t cap_t,
+__global__ __launch_bounds__(256) void k_bin_fine_emit(const uint64_t* __restrict__ n_tasks, int64_t cap_t,
                                                        const uint32_t* __restrict__ task_g,
                                                        const uint32_t* __restrict__ task_n, BinTables T,
                                                        const uint64_t* __restrict__ pmask,
@@ -413,13 +431,15 @@ __global__ __launch_bounds__(256) void k_bin_fine_emit(const uint32_t* __restric
 // scanned, gives every (chunk, leaf) its first output slot; inside a chunk
 // the task at bit j writes at popcount(W_b below j).
 // ---------------------------------------------------------------------------
-__global__ void k_seg_ranges(const uint32_t* __restrict__ keys, int64_t n, uint32_t nn, uint32_t* __restrict__ seg) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const uint32_t k = keys[i];
-  if (k >= nn) return;
-  if (i == 0 || keys[i - 1] != k) seg[2 * (int64_t)k] = (uint32_t)i;
-  if (i == n - 1 || keys[i + 1] != k) seg[2 * (int64_t)k + 1] = (uint32_t)(i + 1);
+__global__ void k_seg_ranges(const uint32_t* __restrict__ keys, const uint64_t* __restrict__ n_dev, uint32_t nn,
+                             uint32_t* __restrict__ seg) {
+  const int64_t n = (int64_t)*n_dev;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t k = keys[i];
+    if (k >= nn) continue;
+    if (i == 0 || keys[i - 1] != k) seg[2 * (int64_t)k] = (uint32_t)i;
+    if (i == n - 1 || keys[i + 1] != k) seg[2 * (int64_t)k + 1] = (uint32_t)(i + 1);
+  }
 }
 
 __global__ void k_seg_chunks(const uint32_t* __restrict__ seg, uint32_t nn, uint32_t* __restrict__ nch) {
@@ -610,30 +630,69 @@ __global__ __launch_bounds__(256) void k_bin_emit_sorted(const uint32_t* __restr
   }
 }
 
-// (start, end) of every active tile from the scanned column counts
+// (start, end) of every active tile from the scanned column counts; the end
+// of the last tile of the last node is the total.  When nothing was emitted
+// (the pairs exceed the capacity, or the count has not completed) every
+// range is empty, so that a render over them reads no list entry.
 __global__ void k_bin_ranges(int32_t n_tiles, const int32_t* __restrict__ active_tiles, int depth,
                              const uint32_t* __restrict__ choff, const uint64_t* __restrict__ start,
+                             const uint64_t* __restrict__ ncol, const uint64_t* __restrict__ total,
                              const int64_t* __restrict__ n_pairs, int64_t capacity, uint32_t* __restrict__ ranges) {
-  if (*n_pairs > capacity) return;  // nothing was emitted (or the count did not complete)
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n_tiles) return;
+  if (*n_pairs > capacity) {
+    ranges[2 * k] = 0u;
+    ranges[2 * k + 1] = 0u;
+    return;
+  }
   const int t = active_tiles[k];
   const int nleaf = 1 << (2 * depth);
   const uint32_t n = (uint32_t)t >> (2 * depth), b = (uint32_t)t & (uint32_t)(nleaf - 1);
   const int64_t c0 = choff[n], nchn = (int64_t)choff[n + 1] - c0;
-  ranges[2 * k] = (uint32_t)start[c0 * nleaf + b * nchn];
-  ranges[2 * k + 1] = (uint32_t)start[c0 * nleaf + (b + 1) * nchn];
+  const uint64_t nc = *ncol;
+  const uint64_t i0 = (uint64_t)(c0 * nleaf + b * nchn), i1 = (uint64_t)(c0 * nleaf + (b + 1) * nchn);
+  ranges[2 * k] = (uint32_t)(i0 < nc ? start[i0] : *total);
+  ranges[2 * k + 1] = (uint32_t)(i1 < nc ? start[i1] : *total);
 }
 
-__global__ void k_store_total(const uint64_t* grand, int64_t* n_pairs) { *n_pairs = (int64_t)*grand; }
+// number of (chunk, leaf) count entries: chunks x leaves per node
+__global__ void k_col_count(const uint32_t* __restrict__ choff, uint32_t nn, int depth, uint64_t* __restrict__ ncol) {
+  *ncol = (uint64_t)choff[nn] << (2 * depth);
+}
+
+// the pair total, or a count no buffer holds when the tasks overflowed: the
+// emission kernels then write nothing
+__global__ void k_store_total(const uint64_t* grand, const uint32_t* over, int64_t* n_pairs) {
+  *n_pairs = *over ? INT64_MAX : (int64_t)*grand;
+}
 __global__ void k_store_zero(int64_t* n_pairs) { *n_pairs = 0; }
-// a pair count no buffer holds: the emission kernels then write nothing
 __global__ void k_store_unfinished(int64_t* n_pairs) { *n_pairs = INT64_MAX; }
 
 // one wave per 64 tasks, at most 8192 blocks of 4 waves that loop over them
 static unsigned fine_grid(int64_t nt) {
   const int64_t blocks = ((nt + 63) / 64 + 3) / 4;
   return (unsigned)(blocks < 8192 ? (blocks > 0 ? blocks : 1) : 8192);
+}
+
+// Depth order, coarse walk and task list (shared by both emissions): tasks
+// (Gaussian, node at the split level) in order of radial depth; *w.nt holds
+// their number and *w.over whether they exceeded the workspace's capacity.
+static hp_status bin_tasks(const HpProjView& pv, int64_t P, const BinTables& T, float guard, BinWs& w, uint32_t* slots,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_depth_keys, dim3(hp_blocks(P, 256)), dim3(256), 0, s, P, pv.depth, w.dkey, w.order);
+  HP_CHECK_LAUNCH();
+  HP_TRY(hpsort::radix_sort(w.dkey, w.order, nullptr, P, 32, w.sort_ws, s));
+  hipLaunchKernelGGL((k_bin_coarse<false>), dim3(hp_blocks(P, 256)), dim3(256), 0, s, P, w.order, pv.disc, pv.radius,
+                     T, guard, w.tcount, (const uint64_t*)nullptr, w.cap_t, (uint32_t*)nullptr, (uint32_t*)nullptr,
+                     slots);
+  HP_CHECK_LAUNCH();
+  HP_TRY((hpsort::scan_exclusive<uint64_t, uint32_t>(w.tcount, w.toff, nullptr, P, w.t_total, w.scan_ws, s)));
+  hipLaunchKernelGGL(k_task_clamp, dim3(1), dim3(1), 0, s, (const uint64_t*)w.t_total, w.cap_t, w.nt, w.over);
+  HP_CHECK_LAUNCH();
+  hipLaunchKernelGGL((k_bin_coarse<true>), dim3(hp_blocks(P, 256)), dim3(256), 0, s, P, w.order, pv.disc, pv.radius,
+                     T, guard, w.tcount, (const uint64_t*)w.toff, w.cap_t, w.task_g, w.task_n, slots);
+  HP_CHECK_LAUNCH();
+  return HP_OK;
 }
 
 extern "C" size_t hp_bin_workspace_bytes(int64_t P) { return P < 0 ? 0 : bin_ws_size(P) + 256; }
@@ -662,43 +721,24 @@ extern "C" hp_status hp_bin(int32_t phase, const void* projected, int64_t P, con
       HP_CHECK_LAUNCH();
       return HP_OK;
     }
-    hipLaunchKernelGGL(k_depth_keys, dim3(hp_blocks(P, 256)), dim3(256), 0, s, P, pv.depth, w.dkey, w.order);
+    hipLaunchKernelGGL(k_store_unfinished, dim3(1), dim3(1), 0, s, n_pairs);
     HP_CHECK_LAUNCH();
-    HP_TRY(hpsort::radix_sort(w.dkey, w.order, P, 32, w.sort_ws, s));
-    hipLaunchKernelGGL((k_bin_coarse<false>), dim3(hp_blocks(P, 256)), dim3(256), 0, s, P, w.order, pv.disc, pv.radius,
-                       T, prm->bin_guard, w.tcount, (const uint32_t*)nullptr, (uint32_t*)nullptr, (uint32_t*)nullptr,
-                       (uint32_t*)nullptr);
+    HP_TRY(bin_tasks(pv, P, T, prm->bin_guard, w, nullptr, s));
+    // per task: its 64-bit hit mask and count; the counts scanned into offsets
+    hipLaunchKernelGGL(k_bin_fine_count, dim3(fine_grid(w.cap_t)), dim3(256), 0, s, (const uint64_t*)w.nt, w.cap_t,
+                       w.task_g, w.task_n, pv.disc, T, w.pmask, w.pcount);
     HP_CHECK_LAUNCH();
-    HP_TRY((hpsort::scan_exclusive<uint32_t, uint32_t>(w.tcount, w.toff, P, w.t_total, w.scan_ws, s)));
-    // the number of tasks must fit the workspace: read it back once
-    uint32_t nt = 0;
-    HP_TRY(hp_read_small(&nt, w.t_total, 4, s));
-    if ((int64_t)nt > w.cap_t) return HP_ERR_CAPACITY;
-    hipLaunchKernelGGL((k_bin_coarse<true>), dim3(hp_blocks(P, 256)), dim3(256), 0, s, P, w.order, pv.disc, pv.radius,
-                       T, prm->bin_guard, w.tcount, w.toff, w.task_g, w.task_n, (uint32_t*)nullptr);
-    HP_CHECK_LAUNCH();
-    if (nt > 0) {
-      hipLaunchKernelGGL(k_bin_fine_count, dim3(fine_grid(nt)), dim3(256), 0, s, (const uint32_t*)w.t_total, w.cap_t,
-                         w.task_g, w.task_n, pv.disc, T, w.pmask, w.pcount);
-      HP_CHECK_LAUNCH();
-      HP_TRY((hpsort::scan_exclusive<uint64_t, uint32_t>(w.pcount, w.poff, nt, w.p_total, w.scan_ws, s)));
-      hipLaunchKernelGGL(k_store_total, dim3(1), dim3(1), 0, s, (const uint64_t*)w.p_total, n_pairs);
-    } else {
-      hipLaunchKernelGGL(k_store_zero, dim3(1), dim3(1), 0, s, n_pairs);
-    }
+    HP_TRY((hpsort::scan_exclusive<uint64_t, uint32_t>(w.pcount, w.poff, w.nt, w.cap_t, w.p_total, w.scan_ws, s)));
+    hipLaunchKernelGGL(k_store_total, dim3(1), dim3(1), 0, s, (const uint64_t*)w.p_total, (const uint32_t*)w.over,
+                       n_pairs);
     HP_CHECK_LAUNCH();
   }
   if ((phase & HP_BIN_EMIT) && P > 0) {
     // the task count is read on the device; the grid covers the capacity bound
-    // only up to the tasks present when the count phase ran on this stream
-    uint32_t nt = 0;
-    HP_TRY(hp_read_small(&nt, w.t_total, 4, s));
-    if (nt > 0) {
-      hipLaunchKernelGGL(k_bin_fine_emit, dim3(fine_grid(nt)), dim3(256), 0, s, (const uint32_t*)w.t_total, w.cap_t,
-                         w.task_g, w.task_n, T, (const uint64_t*)w.pmask, (const uint64_t*)w.poff, n_pairs, capacity,
-                         keys, vals);
-      HP_CHECK_LAUNCH();
-    }
+    hipLaunchKernelGGL(k_bin_fine_emit, dim3(fine_grid(w.cap_t)), dim3(256), 0, s, (const uint64_t*)w.nt, w.cap_t,
+                       w.task_g, w.task_n, T, (const uint64_t*)w.pmask, (const uint64_t*)w.poff, n_pairs, capacity,
+                       keys, vals);
+    HP_CHECK_LAUNCH();
   }
   return HP_OK;
 }
@@ -709,7 +749,7 @@ struct SortedWs {
   uint32_t* seg;     // [nn][2] task segment of every node
   uint32_t* nch;     // [nn] chunks per node
   uint32_t* choff;   // [nn + 1] first chunk of every node, total last
-  uint32_t* cnt;     // [L] hits per (chunk, leaf), tile-major, zero tail
+  uint32_t* cnt;     // [L] hits per (chunk, leaf), tile-major
   uint64_t* start;   // [L] exclusive scan of cnt: first output slot
   uint64_t* wcol;    // [nchunk_max][64] hit columns
   uint32_t* slots;   // [kSlots][P] first task nodes of every Gaussian (coarse walk)
@@ -722,7 +762,7 @@ static void sorted_dims(int64_t P, const HpGeom& g, int64_t* nn, int64_t* nchunk
   const int depth = g.kt - ls;
   *nn = 12ll << (2 * ls);
   *nchunk_max = task_capacity(P) / 64 + *nn + 1;
-  *L = *nchunk_max * (1ll << (2 * depth)) + 1;
+  *L = *nchunk_max * (1ll << (2 * depth));
 }
 
 static size_t sorted_ws_size(int64_t P, const HpGeom& g) {
@@ -762,7 +802,9 @@ static unsigned chunk_grid(int64_t nchunks) {
 }
 
 // The sorted emission with every Gaussian's test angle widened by `widen`
-// radians (0: the binning of hp_bin_sorted).
+// radians (0: the binning of hp_bin_sorted).  No step waits for the host:
+// every count that sizes a later step is read on the device, and the grids
+// are sized from the workspace's bounds.
 hp_status hp_bin_sorted_widened(int32_t phase, const void* projected, int64_t P, const hp_view* view,
                                 const hp_params* prm, const void* grid, const void* mask, uint32_t* vals,
                                 uint32_t* tile_ranges, int32_t n_tiles, int64_t capacity, int64_t* n_pairs, void* ws,
@@ -794,59 +836,41 @@ hp_status hp_bin_sorted_widened(int32_t phase, const void* projected, int64_t P,
       return HP_OK;
     }
     // until the count below completes, *n_pairs says that nothing may be
-    // emitted: an EMIT after a COUNT that failed (too many tasks) writes
-    // nothing, without reading the task count back
+    // emitted
     hipLaunchKernelGGL(k_store_unfinished, dim3(1), dim3(1), 0, s, n_pairs);
     HP_CHECK_LAUNCH();
-    // tasks (Gaussian, node at the split level) in depth order
-    hipLaunchKernelGGL(k_depth_keys, dim3(hp_blocks(P, 256)), dim3(256), 0, s, P, pv.depth, w.dkey, w.order);
-    HP_CHECK_LAUNCH();
-    HP_TRY(hpsort::radix_sort(w.dkey, w.order, P, 32, w.sort_ws, s));
-    hipLaunchKernelGGL((k_bin_coarse<false>), dim3(hp_blocks(P, 256)), dim3(256), 0, s, P, w.order, pv.disc, pv.radius,
-                       T, prm->bin_guard, w.tcount, (const uint32_t*)nullptr, (uint32_t*)nullptr, (uint32_t*)nullptr,
-                       sw.slots);
-    HP_CHECK_LAUNCH();
-    HP_TRY((hpsort::scan_exclusive<uint32_t, uint32_t>(w.tcount, w.toff, P, w.t_total, w.scan_ws, s)));
-    uint32_t nt = 0;
-    HP_TRY(hp_read_small(&nt, w.t_total, 4, s));
-    if ((int64_t)nt > w.cap_t) return HP_ERR_CAPACITY;
-    hipLaunchKernelGGL((k_bin_coarse<true>), dim3(hp_blocks(P, 256)), dim3(256), 0, s, P, w.order, pv.disc, pv.radius,
-                       T, prm->bin_guard, w.tcount, w.toff, w.task_g, w.task_n, sw.slots);
-    HP_CHECK_LAUNCH();
+    HP_TRY(bin_tasks(pv, P, T, prm->bin_guard, w, sw.slots, s));
     // stable sort of the tasks by node; segments and chunk offsets per node
     int nbits = 0;
     while (((int64_t)1 << nbits) < sw.nn) ++nbits;
     // the sorted node keys are only needed here: read them where the last
     // pass left them; the Gaussian ids go back to task_g for the emit phase
     uint32_t *snode = w.task_n, *sgid = w.task_g;
-    HP_TRY(hpsort::radix_sort(w.task_n, w.task_g, nt, nbits, sw.tsort_ws, s, &snode, &sgid));
-    if (sgid != w.task_g && nt > 0) {
-      hipLaunchKernelGGL(hpsort::k_copy_u32, dim3(hp_blocks(nt, 256)), dim3(256), 0, s, (const uint32_t*)sgid, w.task_g,
-                         (int64_t)nt);
+    HP_TRY(hpsort::radix_sort(w.task_n, w.task_g, w.nt, w.cap_t, nbits, sw.tsort_ws, s, &snode, &sgid));
+    if (sgid != w.task_g) {
+      hipLaunchKernelGGL(hpsort::k_copy_u32, dim3(hpsort::copy_grid(w.cap_t)), dim3(256), 0, s, (const uint32_t*)sgid,
+                         w.task_g, (const uint64_t*)w.nt, w.cap_t);
       HP_CHECK_LAUNCH();
     }
     hipLaunchKernelGGL(k_fill_zero_u32, dim3(hp_blocks(2 * sw.nn, 256)), dim3(256), 0, s, sw.seg, 2 * sw.nn);
     HP_CHECK_LAUNCH();
-    if (nt > 0) {
-      hipLaunchKernelGGL(k_seg_ranges, dim3(hp_blocks(nt, 256)), dim3(256), 0, s, (const uint32_t*)snode, (int64_t)nt,
-                         nn, sw.seg);
-      HP_CHECK_LAUNCH();
-    }
+    hipLaunchKernelGGL(k_seg_ranges, dim3(hpsort::copy_grid(w.cap_t)), dim3(256), 0, s, (const uint32_t*)snode,
+                       (const uint64_t*)w.nt, nn, sw.seg);
+    HP_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_seg_chunks, dim3(hp_blocks(sw.nn, 256)), dim3(256), 0, s, sw.seg, nn, sw.nch);
     HP_CHECK_LAUNCH();
-    HP_TRY((hpsort::scan_exclusive<uint32_t, uint32_t>(sw.nch, sw.choff, sw.nn, sw.choff + sw.nn, sw.scan_ws, s)));
-    // hit columns and their counts.  The chunks number at most nt/64 + nn;
-    // the counts beyond the last chunk stay zero, so the scan entry at the
-    // end of the last tile is the total.
-    const int64_t nchunk_bound = (int64_t)nt / 64 + sw.nn + 1;
-    const int64_t La = nchunk_bound * (1ll << (2 * depth)) + 1;
-    hipLaunchKernelGGL(k_fill_zero_u32, dim3(hp_blocks(La, 256)), dim3(256), 0, s, sw.cnt, La);
+    HP_TRY((hpsort::scan_exclusive<uint32_t, uint32_t>(sw.nch, sw.choff, nullptr, sw.nn, sw.choff + sw.nn, sw.scan_ws,
+                                                       s)));
+    // hit columns and their counts (every count entry of the chunks present
+    // is written), scanned in tile-major order into output slots
+    hipLaunchKernelGGL(k_col_count, dim3(1), dim3(1), 0, s, (const uint32_t*)sw.choff, nn, depth, w.ncol);
     HP_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_bin_cols, dim3(chunk_grid(nchunk_bound)), dim3(256), 0, s, (const uint32_t*)sw.choff, nn,
+    hipLaunchKernelGGL(k_bin_cols, dim3(chunk_grid(sw.nchunk_max)), dim3(256), 0, s, (const uint32_t*)sw.choff, nn,
                        (const uint32_t*)sw.seg, (const uint32_t*)w.task_g, pv.disc, T, sw.wcol, sw.cnt);
     HP_CHECK_LAUNCH();
-    HP_TRY((hpsort::scan_exclusive<uint64_t, uint32_t>(sw.cnt, sw.start, La, w.p_total, sw.scan_ws, s)));
-    hipLaunchKernelGGL(k_store_total, dim3(1), dim3(1), 0, s, (const uint64_t*)w.p_total, n_pairs);
+    HP_TRY((hpsort::scan_exclusive<uint64_t, uint32_t>(sw.cnt, sw.start, w.ncol, sw.L, w.p_total, sw.scan_ws, s)));
+    hipLaunchKernelGGL(k_store_total, dim3(1), dim3(1), 0, s, (const uint64_t*)w.p_total, (const uint32_t*)w.over,
+                       n_pairs);
     HP_CHECK_LAUNCH();
   }
   if ((phase & HP_BIN_EMIT) && P > 0) {
@@ -857,8 +881,8 @@ hp_status hp_bin_sorted_widened(int32_t phase, const void* projected, int64_t P,
     HP_CHECK_LAUNCH();
     if (n_tiles > 0) {
       hipLaunchKernelGGL(k_bin_ranges, dim3(hp_blocks(n_tiles, 256)), dim3(256), 0, s, n_tiles, mv.active_tiles, depth,
-                         (const uint32_t*)sw.choff, (const uint64_t*)sw.start, (const int64_t*)n_pairs, capacity,
-                         tile_ranges);
+                         (const uint32_t*)sw.choff, (const uint64_t*)sw.start, (const uint64_t*)w.ncol,
+                         (const uint64_t*)w.p_total, (const int64_t*)n_pairs, capacity, tile_ranges);
       HP_CHECK_LAUNCH();
     }
   } else if ((phase & HP_BIN_EMIT) && n_tiles > 0) {

@@ -596,11 +596,14 @@ extern "C" hp_status hp_preprocess_bwd(const hp_gaussians* gs, const hp_view* vi
 }
 
 // ---- radian-space statistics for adaptive density control -------------------
-__global__ void k_mark_visible(const uint32_t* __restrict__ vals, int64_t n, int64_t P, uint8_t* __restrict__ vis) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= n) return;
-  const uint32_t g = vals[k];
-  if ((int64_t)g < P) vis[g] = 1;
+// one block per active tile: every Gaussian of the tile's list [start, end)
+__global__ void k_mark_visible(const uint32_t* __restrict__ vals, const uint32_t* __restrict__ ranges, int64_t P,
+                               uint8_t* __restrict__ vis) {
+  const uint32_t s = ranges[2 * (int64_t)blockIdx.x], e = ranges[2 * (int64_t)blockIdx.x + 1];
+  for (uint32_t k = s + threadIdx.x; k < e; k += blockDim.x) {
+    const uint32_t g = vals[k];
+    if ((int64_t)g < P) vis[g] = 1;
+  }
 }
 
 // r_s,max and the norm of the gradient with respect to the centre's
@@ -620,11 +623,13 @@ __global__ void k_density_stats(HpProjView pv, int64_t P, const float* __restric
   cnt[i] += 1;
 }
 
-extern "C" hp_status hp_mark_visible(const uint32_t* vals, int64_t n_pairs, int64_t P, uint8_t* visible, void* stream) {
-  if (n_pairs < 0 || P < 0 || (n_pairs > 0 && !vals) || (P > 0 && !visible)) return HP_ERR_INVALID_ARG;
-  if (n_pairs == 0) return HP_OK;
-  hipLaunchKernelGGL(k_mark_visible, dim3(hp_blocks(n_pairs, 256)), dim3(256), 0, (hipStream_t)stream, vals, n_pairs,
-                     P, visible);
+extern "C" hp_status hp_mark_visible(const uint32_t* vals, const uint32_t* tile_ranges, int32_t n_tiles, int64_t P,
+                                     uint8_t* visible, void* stream) {
+  if (n_tiles < 0 || P < 0 || (n_tiles > 0 && (!vals || !tile_ranges)) || (P > 0 && !visible))
+    return HP_ERR_INVALID_ARG;
+  if (n_tiles == 0) return HP_OK;
+  hipLaunchKernelGGL(k_mark_visible, dim3((unsigned)n_tiles), dim3(256), 0, (hipStream_t)stream, vals, tile_ranges, P,
+                     visible);
   HP_CHECK_LAUNCH();
   return HP_OK;
 }

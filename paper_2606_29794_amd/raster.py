@@ -5,9 +5,7 @@ from __future__ import annotations
 
 import ctypes as C
 import math
-import queue
 import threading
-from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -104,12 +102,54 @@ class Gaussians:
                               self.rot.data_ptr(), self.opacity.data_ptr(), self.sh.data_ptr())
 
 
+def check_mask_counts(order: int, tile_log2: int, n_active: int, n_tiles: int) -> None:
+    """The header a mask computation left behind must describe a subset of
+    the grid: 0 <= n_active <= Npix, 0 <= n_tiles <= the tile count, every
+    active tile holding at least one and at most B^2 active pixels.  Buffers
+    are sized from these numbers, so anything else (a mask read before its
+    computation completed, a corrupted buffer) is refused here."""
+    b = min(tile_log2, order)
+    npix = 12 << (2 * order)
+    ntile = 12 << (2 * (order - b))
+    if not (0 <= n_active <= npix and 0 <= n_tiles <= ntile):
+        raise RuntimeError(f"inconsistent mask header: n_active {n_active}, n_tiles {n_tiles} at order {order}")
+    if not (n_tiles <= n_active <= n_tiles << (2 * b)):
+        raise RuntimeError(f"inconsistent mask header: {n_active} active pixels in {n_tiles} tiles of {1 << (2 * b)}")
+
+
 @dataclass
 class MaskInfo:
     buf: torch.Tensor
     n_active: int
     n_tiles: int
     active_pix: torch.Tensor   # int32 [n_active], sorted nested ids
+
+
+class PairCapacityError(RuntimeError):
+    """A binning wanted more list entries than the buffer it was given held:
+    its lists were left empty.  The capacity hints have been raised, so the
+    same work run again fits."""
+
+
+class PairCount:
+    """The pair count of one binning as the device wrote it (int64 [2]: the
+    entries the lists need, and the entries kept by a paper query), with the
+    capacity of the list buffer it was emitted into.  Reading it waits for
+    the binning; nothing on the render path reads it."""
+
+    def __init__(self, dev: torch.Tensor, capacity: int):
+        self.dev = dev
+        self.capacity = int(capacity)
+        self._host = None
+
+    def value(self, which: int = 0) -> int:
+        if self._host is None:
+            self._host = self.dev.cpu().tolist()
+        return int(self._host[which])
+
+    @property
+    def overflowed(self) -> bool:
+        return self.value(0) > self.capacity
 
 
 @dataclass
@@ -121,12 +161,17 @@ class FwdState:
     projected: torch.Tensor
     vals: torch.Tensor
     ranges: torch.Tensor
-    n_pairs: int
+    count: PairCount
     rgb: torch.Tensor
     T: torch.Tensor
     n_contrib: torch.Tensor
     P: int
     inv_depth: torch.Tensor | None = None
+
+    @property
+    def n_pairs(self) -> int:
+        """List entries (waits for the binning)."""
+        return self.count.value(0)
 
 
 @dataclass
@@ -137,18 +182,16 @@ class Prepared:
     projected: torch.Tensor
     vals: torch.Tensor
     ranges: torch.Tensor
-    n_pairs: int
+    count: PairCount
     event: torch.cuda.Event
     stream_id: int
 
 
 class Prefetch:
-    """Stages 1-2 of a sequence of views, made on side streams by host threads
-    of their own (each view on a stream no other view is using at the time),
-    so that they overlap the caller's rendering of the views before them.  The binning waits on its
-    stream for small counts, which then no longer stalls the caller, and its
-    many short kernels, which queue behind the caller's long render kernels,
-    progress for several views at once.  get(i) returns view i."""
+    """Stages 1-2 of a sequence of views, enqueued at once on side streams
+    (view i on stream i mod n), so that they overlap the caller's rendering
+    of the views before them.  Nothing in them waits for the host.  get(i)
+    returns view i."""
 
     def __init__(self, R: "Rasterizer", g: "Gaussians", cams, query=None, streams: int = 2):
         n = max(1, min(streams, len(cams)))
@@ -159,29 +202,13 @@ class Prefetch:
         start.record(torch.cuda.current_stream(R.device))
         for st in side:
             st.wait_event(start)
-
-        # a view takes whichever stream is free: views finish out of order,
-        # and two views on one stream would interleave their kernels and
-        # each wait for the other's at its read-backs
-        free = queue.SimpleQueue()
-        for st in side:
-            free.put(st)
-
-        def run(cam):
-            st = free.get()  # waits only if the pool has more threads than streams
-            try:
-                with torch.cuda.device(R.device), torch.cuda.stream(st):
-                    return R.prepare(g, cam, query)
-            finally:
-                free.put(st)
-
-        # n host threads: views 0 .. n-1 start at once, and each later view
-        # when an earlier one is done
-        pool = R.side_pool(n)
-        self._futures = [pool.submit(run, c) for c in cams]
+        self._views = []
+        for i, cam in enumerate(cams):
+            with torch.cuda.stream(side[i % n]):
+                self._views.append(R.prepare(g, cam, query))
 
     def get(self, i: int) -> Prepared:
-        return self._futures[i].result()
+        return self._views[i]
 
 
 class Rasterizer:
@@ -199,8 +226,14 @@ class Rasterizer:
         # the caches may be used from several host threads (serving workers)
         self._lock = threading.RLock()
         self._sides = []
-        self._pool = None
-        self._pool_n = 0
+        # list capacities per (P, camera model, order, query) from earlier
+        # counts, and the counts not yet compared with their capacity
+        self._cap_hint = {}
+        self._pending = []
+        self._overflows = []
+        # one binning workspace per stream (work on a stream is ordered, so
+        # the next binning there may reuse it)
+        self._ws = {}
 
     def side_streams(self, n: int) -> list:
         """The first n streams of prefetch() (default priority), created once."""
@@ -209,18 +242,8 @@ class Rasterizer:
                 self._sides.append(torch.cuda.Stream(device=self.device))
             return self._sides[:n]
 
-    def side_pool(self, n: int) -> ThreadPoolExecutor:
-        """Host threads of prefetch(), at least n."""
-        with self._lock:
-            if self._pool_n < n:
-                if self._pool is not None:
-                    self._pool.shutdown(wait=False)  # its queued work still runs
-                self._pool = ThreadPoolExecutor(max_workers=n, thread_name_prefix="hp-prefetch")
-                self._pool_n = n
-            return self._pool
-
     def prefetch(self, g: "Gaussians", cams, query=None, streams: int = 2) -> Prefetch:
-        """Start stages 1-2 of every camera in `cams` on up to `streams` side
+        """Enqueue stages 1-2 of every camera in `cams` on up to `streams` side
         streams (with the caller's stream, 4: the hardware queues a process
         gets by default); pass prefetch.get(i) as forward(..., prepared=) /
         render(..., prepared=)."""
@@ -271,6 +294,7 @@ class Rasterizer:
             A.call("hp_mask", C.byref(v), C.byref(self.prm), _p(self.grid(cam.order)), _p(buf), n, _stream())
             na, nt = C.c_int64(0), C.c_int32(0)
             A.call("hp_mask_counts", _p(buf), cam.order, self.prm.tile_log2, C.byref(na), C.byref(nt), _stream())
+            check_mask_counts(cam.order, self.prm.tile_log2, int(na.value), int(nt.value))
             ptr = A.lib().hp_mask_active_pix(_p(buf), cam.order, self.prm.tile_log2)
             off = ptr - buf.data_ptr()
             ap = buf[off: off + 4 * na.value].view(torch.int32)
@@ -300,7 +324,120 @@ class Rasterizer:
         return rec, depth, radius
 
     # ---- stage 2 ---------------------------------------------------------
+    def workspace(self, nbytes: int) -> torch.Tensor:
+        """A scratch buffer of at least nbytes for work on the current stream
+        (kept per stream and reused by the next call there)."""
+        sid = torch.cuda.current_stream(self.device).cuda_stream
+        with self._lock:
+            ws = self._ws.get(sid)
+            if ws is None or ws.numel() < nbytes:
+                ws = _bytes(nbytes, self.device)
+                self._ws[sid] = ws
+            return ws
+
+    def _bin_key(self, P: int, cam: Camera, query):
+        return (P, cam.mask_key(self.prm.tile_log2), query)
+
+    @staticmethod
+    def _grow(n: int) -> int:
+        return int(n * 1.25) + 65536
+
+    def _bin_call(self, phase, proj, P, cam, query, vals, ranges, cap, cnt, ws):
+        m = self.mask(cam)
+        v = cam.view()
+        grid = self.grid(cam.order)
+        if query is None:
+            A.call("hp_bin_sorted", phase, _p(proj), P, C.byref(v), C.byref(self.prm), _p(grid), _p(m.buf), _p(vals),
+                   _p(ranges), m.n_tiles, cap, _p(cnt), _p(ws), ws.numel(), _stream())
+        else:
+            code = {"ring": A.HP_QUERY_RING, "nested": A.HP_QUERY_NESTED}[query[0]]
+            A.call("hp_bin_query", phase, code, int(query[1]), _p(proj), P, C.byref(v), C.byref(self.prm), _p(grid),
+                   _p(m.buf), _p(vals), _p(ranges), m.n_tiles, cap, _p(cnt), C.c_void_p(cnt.data_ptr() + 8), _p(ws),
+                   ws.numel(), _stream())
+
+    def note_count(self, P: int, cam: Camera, query, n: int) -> None:
+        """Raise the list capacity hint of (P, camera model, query) to cover a
+        count of n entries."""
+        key = self._bin_key(P, cam, query)
+        with self._lock:
+            self._cap_hint[key] = max(self._cap_hint.get(key, 0), self._grow(n))
+
+    def bin_lists(self, proj: torch.Tensor, P: int, cam: Camera, query=None, track: bool = True):
+        """Tile lists of one view, in per-tile depth order: (vals, ranges,
+        PairCount).  query None: hp_bin_sorted's exact tile sets; (mode, f):
+        the paper's own query (mode "ring": Alg. 3 RING scan, "nested": Alg. 2
+        quadtree traversal) at search depth f, whose lists hold stale entries
+        past each tile's end.  The list buffer's capacity comes from earlier
+        counts of the same scene size, camera model and query; without one,
+        the count is read back once (the only wait).  A count beyond the
+        capacity leaves the lists empty and is reported by verify() (track
+        False: the caller checks the returned PairCount itself)."""
+        m = self.mask(cam)
+        key = self._bin_key(P, cam, query)
+        nbytes = (A.lib().hp_bin_sorted_workspace_bytes(P, cam.order, self.prm.tile_log2) if query is None else
+                  A.lib().hp_bin_query_workspace_bytes(P, cam.order, self.prm.tile_log2))
+        ws = self.workspace(nbytes)
+        cnt = torch.zeros(2, dtype=torch.int64, device=self.device)
+        ranges = torch.empty((max(m.n_tiles, 1), 2), dtype=torch.int32, device=self.device)
+        with self._lock:
+            cap = self._cap_hint.get(key)
+        if cap is None:
+            self._bin_call(A.HP_BIN_COUNT, proj, P, cam, query, None, None, 0, cnt, ws)
+            n = C.c_int64(0)
+            A.call("hp_read_total", _p(cnt), C.byref(n), _stream())
+            cap = max(int(n.value), 1)
+            with self._lock:
+                self._cap_hint[key] = max(self._cap_hint.get(key, 0), self._grow(cap))
+            vals = torch.empty(cap, dtype=torch.int32, device=self.device)
+            self._bin_call(A.HP_BIN_EMIT, proj, P, cam, query, vals, ranges, cap, cnt, ws)
+            return vals, ranges, PairCount(cnt, cap)
+        vals = torch.empty(cap, dtype=torch.int32, device=self.device)
+        self._bin_call(A.HP_BIN_ALL, proj, P, cam, query, vals, ranges, cap, cnt, ws)
+        if not track:
+            return vals, ranges, PairCount(cnt, cap)
+        # compared with the capacity later, without waiting now
+        host = torch.empty(2, dtype=torch.int64, pin_memory=True)
+        host.copy_(cnt, non_blocking=True)
+        ev = torch.cuda.Event()
+        ev.record(torch.cuda.current_stream(self.device))
+        with self._lock:
+            self._pending.append((key, host, ev, cap))
+            if len(self._pending) > 64:
+                self._settle(block=False)
+        return vals, ranges, PairCount(cnt, cap)
+
+    def _settle(self, block: bool) -> None:
+        """Compares the counts of finished binnings with their capacities
+        (all of them, waiting, when block): hints grow, overflows are kept
+        for verify().  Called with the lock held."""
+        keep = []
+        for key, host, ev, cap in self._pending:
+            if block:
+                ev.synchronize()
+            elif not ev.query():
+                keep.append((key, host, ev, cap))
+                continue
+            n = int(host[0])
+            self._cap_hint[key] = max(self._cap_hint.get(key, 0), self._grow(n))
+            if n > cap:
+                self._overflows.append((key, n, cap))
+        self._pending = keep
+
+    def verify(self) -> None:
+        """Waits for the binnings since the last verify() and compares their
+        counts with the capacities they ran with; raises PairCapacityError if
+        any list buffer was too small (its lists were left empty).  The
+        capacity hints grow from every count seen, so a repeat fits."""
+        with self._lock:
+            self._settle(block=True)
+            over, self._overflows = self._overflows, []
+        if over:
+            raise PairCapacityError(f"{len(over)} binning(s) needed more list entries than their buffers held "
+                                    f"(needed, capacity): {[(n, c) for _, n, c in over]}")
+
     def bin(self, proj: torch.Tensor, P: int, cam: Camera):
+        """Unsorted pairs of hp_bin (synchronous convenience: the count is
+        read back): (keys, vals, n)."""
         m = self.mask(cam)
         v = cam.view()
         ws_n = A.lib().hp_bin_workspace_bytes(P)
@@ -309,7 +446,7 @@ class Rasterizer:
         A.call("hp_bin", A.HP_BIN_COUNT, _p(proj), P, C.byref(v), C.byref(self.prm), _p(self.grid(cam.order)),
                _p(m.buf), None, None, 0, _p(npairs), _p(ws), ws_n, _stream())
         total = C.c_int64(0)
-        A.call("hp_read_total", _p(npairs), C.byref(total), _stream())
+        A.call("hp_check_count", _p(npairs), 1 << 40, C.byref(total), _stream())
         n = int(total.value)
         keys = torch.empty(max(n, 1), dtype=torch.int32, device=self.device)
         vals = torch.empty(max(n, 1), dtype=torch.int32, device=self.device)
@@ -318,55 +455,28 @@ class Rasterizer:
         return keys, vals, n
 
     def bin_sorted(self, proj: torch.Tensor, P: int, cam: Camera):
-        """Pairs emitted directly in per-tile depth order: (vals, ranges, n)."""
-        m = self.mask(cam)
-        v = cam.view()
-        ws_n = A.lib().hp_bin_sorted_workspace_bytes(P, cam.order, self.prm.tile_log2)
-        ws = _bytes(ws_n, self.device)
-        npairs = torch.zeros(1, dtype=torch.int64, device=self.device)
-        grid = self.grid(cam.order)
-        A.call("hp_bin_sorted", A.HP_BIN_COUNT, _p(proj), P, C.byref(v), C.byref(self.prm), _p(grid), _p(m.buf), None,
-               None, m.n_tiles, 0, _p(npairs), _p(ws), ws_n, _stream())
-        total = C.c_int64(0)
-        A.call("hp_read_total", _p(npairs), C.byref(total), _stream())
-        n = int(total.value)
-        vals = torch.empty(max(n, 1), dtype=torch.int32, device=self.device)
-        ranges = torch.empty((max(m.n_tiles, 1), 2), dtype=torch.int32, device=self.device)
-        A.call("hp_bin_sorted", A.HP_BIN_EMIT, _p(proj), P, C.byref(v), C.byref(self.prm), _p(grid), _p(m.buf),
-               _p(vals), _p(ranges), m.n_tiles, n, _p(npairs), _p(ws), ws_n, _stream())
-        return vals, ranges, n
+        """Pairs emitted directly in per-tile depth order (synchronous
+        convenience: waits for the count): (vals, ranges, n)."""
+        vals, ranges, cnt = self.bin_lists(proj, P, cam)
+        return vals, ranges, cnt.value(0)
 
     def bin_query(self, proj: torch.Tensor, P: int, cam: Camera, mode: str, f: int):
         """Tile lists of the paper's own queries (mode "ring": Alg. 3 RING scan,
         "nested": Alg. 2 quadtree traversal) at search depth f, in per-tile
-        depth order: (vals, ranges, n_candidates, n_kept).  A tile's list is
-        vals[ranges[k, 0]:ranges[k, 1]]; entries past a tile's end are stale."""
-        code = {"ring": A.HP_QUERY_RING, "nested": A.HP_QUERY_NESTED}[mode]
-        m = self.mask(cam)
-        v = cam.view()
-        ws_n = A.lib().hp_bin_query_workspace_bytes(P, cam.order, self.prm.tile_log2)
-        ws = _bytes(ws_n, self.device)
-        cnt = torch.zeros(2, dtype=torch.int64, device=self.device)
-        grid = self.grid(cam.order)
-        A.call("hp_bin_query", A.HP_BIN_COUNT, code, f, _p(proj), P, C.byref(v), C.byref(self.prm), _p(grid),
-               _p(m.buf), None, None, m.n_tiles, 0, _p(cnt), None, _p(ws), ws_n, _stream())
-        total = C.c_int64(0)
-        A.call("hp_read_total", _p(cnt), C.byref(total), _stream())
-        n = int(total.value)
-        vals = torch.empty(max(n, 1), dtype=torch.int32, device=self.device)
-        ranges = torch.empty((max(m.n_tiles, 1), 2), dtype=torch.int32, device=self.device)
-        A.call("hp_bin_query", A.HP_BIN_EMIT, code, f, _p(proj), P, C.byref(v), C.byref(self.prm), _p(grid),
-               _p(m.buf), _p(vals), _p(ranges), m.n_tiles, n, _p(cnt), C.c_void_p(cnt.data_ptr() + 8), _p(ws), ws_n,
-               _stream())
-        kept = C.c_int64(0)
-        A.call("hp_read_total", C.c_void_p(cnt.data_ptr() + 8), C.byref(kept), _stream())
-        return vals, ranges, n, int(kept.value)
+        depth order (synchronous convenience): (vals, ranges, n_candidates,
+        n_kept).  A tile's list is vals[ranges[k, 0]:ranges[k, 1]]; entries
+        past a tile's end are stale."""
+        vals, ranges, cnt = self.bin_lists(proj, P, cam, (mode, int(f)))
+        return vals, ranges, cnt.value(0), cnt.value(1)
 
-    def sort(self, keys, vals, n: int, n_tiles: int):
+    def sort(self, keys, vals, n, n_tiles: int):
+        """Stable tile sort of hp_bin's pairs; n: host count or device int64."""
         ranges = torch.zeros((max(n_tiles, 1), 2), dtype=torch.int32, device=self.device)
-        ws_n = A.lib().hp_sort_workspace_bytes(n, n_tiles)
+        cap = int(keys.numel())
+        n_dev = n if isinstance(n, torch.Tensor) else torch.tensor([int(n)], dtype=torch.int64, device=self.device)
+        ws_n = A.lib().hp_sort_workspace_bytes(cap, n_tiles)
         ws = _bytes(ws_n, self.device)
-        A.call("hp_sort", _p(keys), _p(vals), n, n_tiles, _p(ranges), _p(ws), ws_n, _stream())
+        A.call("hp_sort", _p(keys), _p(vals), _p(n_dev), cap, n_tiles, _p(ranges), _p(ws), ws_n, _stream())
         return ranges
 
     # ---- stage 3 ---------------------------------------------------------
@@ -391,14 +501,11 @@ class Rasterizer:
         (bin_query)."""
         self.mask(cam)
         proj = self.preprocess(g, cam)
-        if query is None:
-            vals, ranges, n = self.bin_sorted(proj, g.P, cam)
-        else:
-            vals, ranges, _, n = self.bin_query(proj, g.P, cam, query[0], query[1])
+        vals, ranges, cnt = self.bin_lists(proj, g.P, cam, None if query is None else (query[0], int(query[1])))
         cur = torch.cuda.current_stream(self.device)
         ev = torch.cuda.Event()
         ev.record(cur)
-        return Prepared(cam, proj, vals, ranges, n, ev, cur.cuda_stream)
+        return Prepared(cam, proj, vals, ranges, cnt, ev, cur.cuda_stream)
 
     def forward(self, g: Gaussians, cam: Camera, want_depth: bool = False, query=None,
                 prepared: Prepared | None = None) -> FwdState:
@@ -413,12 +520,12 @@ class Rasterizer:
             if cur.cuda_stream != prepared.stream_id:
                 cur.wait_event(prepared.event)
                 # made on another stream, used (and freed) on this one
-                for t in (prepared.projected, prepared.vals, prepared.ranges):
+                for t in (prepared.projected, prepared.vals, prepared.ranges, prepared.count.dev):
                     t.record_stream(cur)
-        proj, vals, ranges, n = prepared.projected, prepared.vals, prepared.ranges, prepared.n_pairs
+        proj, vals, ranges, cnt = prepared.projected, prepared.vals, prepared.ranges, prepared.count
         out = self.render_fwd(proj, g.P, vals, ranges, cam, want_depth=want_depth)
         rgb, T, nc = out[:3]
-        return FwdState(cam, m, proj, vals, ranges, n, rgb, T, nc, g.P, out[3] if want_depth else None)
+        return FwdState(cam, m, proj, vals, ranges, cnt, rgb, T, nc, g.P, out[3] if want_depth else None)
 
     def backward(self, g: Gaussians, st: FwdState, dL_drgb, dL_dT, grads: Gaussians, dL_dinv_depth=None) -> None:
         """Accumulates gradients into the tensors of `grads`."""
@@ -457,7 +564,7 @@ class Rasterizer:
         the Gaussians visible in this view (in any tile list), from the pixel
         pass's accumulators acc [10, P]."""
         vis = torch.zeros(max(st.P, 1), dtype=torch.uint8, device=self.device)
-        A.call("hp_mark_visible", _p(st.vals), st.n_pairs, st.P, _p(vis), _stream())
+        A.call("hp_mark_visible", _p(st.vals), _p(st.ranges), st.mask.n_tiles, st.P, _p(vis), _stream())
         A.call("hp_density_stats", _p(st.projected), st.P, _p(acc), _p(vis), _p(rs_max), _p(grad_accum), _p(count),
                _stream())
 

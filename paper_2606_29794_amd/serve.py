@@ -98,48 +98,30 @@ class Server:
         self.max_batch = min(max_batch, MAX_REQ_PER_RENDER)
         self.streams = [torch.cuda.Stream(device=self.g.mean.device) for _ in range(n_streams)]
         self.budget = hbm_budget_bytes
-        self._pairs_per_order = {}
-        self._mask_cache = collections.OrderedDict()
-        self._cache_lock = threading.Lock()
 
     # ---- memory accounting ---------------------------------------------------
     def _estimate(self, cam: Camera) -> int:
-        P = self.g.P
+        """Device bytes one request holds while it is in flight, from the
+        library's own sizes: its projected records (hp_projected_bytes), its
+        list buffer (the capacity the binning will use: the hint from earlier
+        counts of the camera model, else a first count's worth), its tile
+        ranges and its outputs (rgb, T, n_contrib).  The binning workspaces
+        are held per stream and reserved from the budget up front
+        (workspace_reserve)."""
+        R, P = self.R, self.g.P
+        m_key = R._bin_key(P, cam, None)
+        with R._lock:
+            cap = R._cap_hint.get(m_key)
         npix = 12 << (2 * cam.order)
-        pairs = self._pairs_per_order.get(cam.order, 8 * P)
-        return P * 72 + 24 * pairs + 24 * npix + A.lib().hp_mask_bytes(cam.order, self.R.prm.tile_log2)
+        ntile = 12 << (2 * max(0, cam.order - R.prm.tile_log2))
+        if cap is None:
+            cap = 64 * P   # before the first count of the model: a generous guess
+        return A.lib().hp_projected_bytes(P) + 4 * cap + 8 * ntile + 20 * npix
 
-    # ---- one batch ------------------------------------------------------------
-    def _mask_async(self, cam: Camera):
-        """Mask buffer for the camera model (cached; computed on the current
-        stream, counts read back later together with the pair counts)."""
-        with self._cache_lock:
-            return self._mask_async_locked(cam)
-
-    def _mask_async_locked(self, cam: Camera):
-        key = cam.mask_key(self.R.prm.tile_log2)
-        cur = torch.cuda.current_stream()
-        ent = self._mask_cache.get(key)
-        if ent is None:
-            n = A.lib().hp_mask_bytes(cam.order, self.R.prm.tile_log2)
-            buf = _bytes(n, self.g.mean.device)
-            v = cam.view()
-            A.call("hp_mask", C.byref(v), C.byref(self.R.prm), _p(self.R.grid(cam.order)), _p(buf), n,
-                   C.c_void_p(cur.cuda_stream))
-            ev = torch.cuda.Event()
-            ev.record(cur)
-            if len(self._mask_cache) > 64:
-                # in-flight batches keep their own references to the masks they
-                # read (released only after their completion event), so the
-                # cache can drop the oldest entry at once
-                self._mask_cache.popitem(last=False)
-            self._mask_cache[key] = (buf, ev, cur.cuda_stream)
-            return buf
-        buf, ev, sid = ent
-        if sid != cur.cuda_stream:
-            # written on another stream: order this stream after it
-            cur.wait_event(ev)
-        return buf
+    def workspace_reserve(self) -> int:
+        """Binning workspaces: one per stream slot, at the largest order."""
+        ws = max(A.lib().hp_bin_sorted_workspace_bytes(self.g.P, k, self.R.prm.tile_log2) for k in (7, 8, 9, 10))
+        return len(self.streams) * ws
 
     def _launch(self, reqs: list, stream: torch.cuda.Stream, keep: bool) -> _Batch:
         R, g = self.R, self.g
@@ -150,7 +132,7 @@ class Server:
             sptr = C.c_void_p(stream.cuda_stream)
             for r in reqs:
                 R.grid(r.camera.order)
-            masks = [self._mask_async(r.camera) for r in reqs]
+            masks = [R.mask(r.camera).buf for r in reqs]
             nproj = A.lib().hp_projected_bytes(P)
             projs = [_bytes(nproj, dev) for _ in reqs]
             gs = g.struct()
@@ -159,41 +141,28 @@ class Server:
                 views = (A.hp_view * len(chunk))(*[r.camera.view() for r in chunk])
                 ptrs = (C.c_void_p * len(chunk))(*[projs[s0 + k].data_ptr() for k in range(len(chunk))])
                 A.call("hp_preprocess_batch", C.byref(gs), len(chunk), views, C.byref(prm), ptrs, nproj, sptr)
-            # one binning workspace for the batch: each request counts, reads
-            # its sizes back and emits before the next one reuses it (stream order)
-            ws_n = max(A.lib().hp_bin_sorted_workspace_bytes(P, r.camera.order, prm.tile_log2) for r in reqs)
-            ws = _bytes(ws_n, dev)
-            npairs = torch.zeros(len(reqs), dtype=torch.int64, device=dev)
+            # tile lists per request, into buffers sized from earlier counts of
+            # the same camera model (the first request of a model reads its
+            # count back once); the binning workspace of the slot's stream is
+            # reused request after request (stream order)
             reqd = []
             outs = []
             keep = []
-            nbytes = ws_n
+            counts = []
+            nbytes = 0
             for k, r in enumerate(reqs):
-                v = r.camera.view()
-                grid = R.grid(r.camera.order)
-                A.call("hp_bin_sorted", A.HP_BIN_COUNT, _p(projs[k]), P, C.byref(v), C.byref(prm), _p(grid),
-                       _p(masks[k]), None, None, 0, 0, C.c_void_p(npairs.data_ptr() + 8 * k), _p(ws), ws_n, sptr)
-                # pair count and mask sizes (n_active int64, n_tiles int32) in one read-back
-                head = torch.cat([npairs[k:k + 1], masks[k][:16].view(torch.int64)]).cpu().numpy()
-                n, n_active, n_tiles = int(head[0]), int(head[1]), int(head[2] & 0xFFFFFFFF)
-                npix = 12 << (2 * r.camera.order)
-                if not (0 <= n_active <= npix and 0 <= n_tiles <= npix and n >= 0):
-                    raise RuntimeError(f"request {r.rid}: inconsistent mask header ({n_active}, {n_tiles}) or pair count {n}")
-                self._pairs_per_order[r.camera.order] = max(n, self._pairs_per_order.get(r.camera.order, 0) // 2)
-                vals = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
-                ranges = torch.zeros((max(n_tiles, 1), 2), dtype=torch.int32, device=dev)
-                A.call("hp_bin_sorted", A.HP_BIN_EMIT, _p(projs[k]), P, C.byref(v), C.byref(prm), _p(grid),
-                       _p(masks[k]), _p(vals), _p(ranges), n_tiles, n, C.c_void_p(npairs.data_ptr() + 8 * k), _p(ws),
-                       ws_n, sptr)
-                rgb = torch.empty((3, max(n_active, 1)), dtype=torch.float32, device=dev)
-                T = torch.empty(max(n_active, 1), dtype=torch.float32, device=dev)
-                nc = torch.empty(max(n_active, 1), dtype=torch.int32, device=dev)
-                reqd.append(A.hp_render_req(projs[k].data_ptr(), P, vals.data_ptr(), ranges.data_ptr(), n_tiles,
-                                            r.camera.order, masks[k].data_ptr(), n_active, rgb.data_ptr(),
+                m = R.mask(r.camera)
+                vals, ranges, cnt = R.bin_lists(projs[k], P, r.camera, track=False)
+                rgb = torch.empty((3, max(m.n_active, 1)), dtype=torch.float32, device=dev)
+                T = torch.empty(max(m.n_active, 1), dtype=torch.float32, device=dev)
+                nc = torch.empty(max(m.n_active, 1), dtype=torch.int32, device=dev)
+                reqd.append(A.hp_render_req(projs[k].data_ptr(), P, vals.data_ptr(), ranges.data_ptr(), m.n_tiles,
+                                            r.camera.order, m.buf.data_ptr(), m.n_active, rgb.data_ptr(),
                                             T.data_ptr(), nc.data_ptr()))
-                outs.append((rgb[:, :n_active], T[:n_active]))
+                outs.append((rgb[:, :m.n_active], T[:m.n_active]))
                 keep.append((vals, ranges, nc))
-                nbytes += nproj + 4 * n + 8 * n_tiles + 24 * n_active
+                counts.append(cnt)
+                nbytes += nproj + 4 * vals.numel() + 8 * m.n_tiles + 24 * m.n_active
             for s0 in range(0, len(reqd), MAX_REQ_PER_RENDER):
                 chunk = reqd[s0:s0 + MAX_REQ_PER_RENDER]
                 arr = (A.hp_render_req * len(chunk))(*chunk)
@@ -201,7 +170,30 @@ class Server:
             ev = torch.cuda.Event()
             ev.record(stream)
         b = _Batch(reqs, stream, ev, nbytes, outs=outs)
-        b.keep = [projs, ws, masks, npairs, keep]   # alive until the batch completes
+        b.counts = counts
+        b.keep = [projs, masks, keep]   # alive until the batch completes
+        return b
+
+    def _redo_overflowed(self, b: _Batch, stream: torch.cuda.Stream, keep: bool) -> _Batch:
+        """After a batch completed: requests whose lists needed more entries
+        than their buffers held rendered empty lists; their counts raise the
+        capacity hints and they run again (once more at most)."""
+        P = self.g.P
+        redo = []
+        for k, (r, cnt) in enumerate(zip(b.reqs, b.counts)):
+            n = cnt.value(0)
+            self.R.note_count(P, r.camera, None, n)
+            if n > cnt.capacity:
+                redo.append(k)
+        if not redo:
+            return b
+        b2 = self._launch([b.reqs[k] for k in redo], stream, keep)
+        b2.event.synchronize()
+        for j, k in enumerate(redo):
+            if b2.counts[j].overflowed:
+                raise RuntimeError(f"request {b.reqs[k].rid}: tile lists exceed their buffer after a recount")
+            b.outs[k] = b2.outs[j]
+        b.keep.append(b2.keep)
         return b
 
     # ---- the request loop -----------------------------------------------------
@@ -220,6 +212,7 @@ class Server:
         free = list(range(len(self.streams)))
         st = {"mem": 0, "error": None}
         inbox = [queue.SimpleQueue() for _ in self.streams]
+        reserve = self.workspace_reserve()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         clock = lambda: time.perf_counter() - t0
@@ -234,6 +227,7 @@ class Server:
                 try:
                     b = self._launch(batch, self.streams[slot], keep_outputs)
                     b.event.synchronize()
+                    b = self._redo_overflowed(b, self.streams[slot], keep_outputs)
                     t = clock()
                     with cv:
                         for k, r in enumerate(batch):
@@ -263,8 +257,8 @@ class Server:
                         pending.append(reqs[nxt])
                         nxt += 1
                     if pending and free:
-                        batch = select_batch(pending, lambda r: self._estimate(r.camera), st["mem"], self.budget,
-                                             self.max_batch, len(free) < len(self.streams))
+                        batch = select_batch(pending, lambda r: self._estimate(r.camera), st["mem"] + reserve,
+                                             self.budget, self.max_batch, len(free) < len(self.streams))
                         if batch:
                             est = sum(self._estimate(r.camera) for r in batch)
                             st["mem"] += est
@@ -298,6 +292,7 @@ class Server:
                     time.sleep(min(1e-3, max(0.0, r.arrival - (time.perf_counter() - t0))))
             st = self.R.forward(self.g, r.camera)
             torch.cuda.synchronize()
+            self.R.verify()
             t = time.perf_counter() - t0
             results.append(Result(r.rid, r.arrival if realtime else 0.0, t, st.rgb if keep_outputs else None,
                                   st.T if keep_outputs else None))

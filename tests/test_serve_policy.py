@@ -40,3 +40,18 @@ def test_oversize_request_runs_alone_when_idle():
 
 def test_empty_queue():
     assert select_batch(_q(), lambda r: 1, 0, 10, 4, False) == []
+
+
+def test_mask_header_check():
+    """Buffers are sized from a mask's (n_active, n_tiles); a header outside
+    the grid, or with more active pixels than its tiles hold (or tiles
+    without one), is refused."""
+    import pytest
+    from paper_2606_29794_amd.raster import check_mask_counts
+    check_mask_counts(9, 4, 12 << 18, 12 << 10)          # full sphere at Nside 512
+    check_mask_counts(2, 4, 192, 12)                     # order below the tile side: a tile is a face
+    check_mask_counts(6, 4, 0, 0)                        # empty
+    for bad in [(9, 4, (12 << 18) + 1, 12 << 10), (9, 4, 100, -1), (9, 4, -5, 0),
+                (9, 4, 300, 1), (9, 4, 3, 5), (6, 4, 10, (12 << 4) + 1)]:
+        with pytest.raises(RuntimeError):
+            check_mask_counts(*bad)
