@@ -178,7 +178,9 @@ inline hp_status scan_exclusive(const In* in, T* out, const uint64_t* cnt, int64
 // ---------------------------------------------------------------------------
 // radix sort
 // ---------------------------------------------------------------------------
-// digit histogram of each block's tiles: hist[block * radix + digit]
+// digit histogram of each block's tiles, digit-major: hist[digit * G + block]
+// (an exclusive scan of the whole array then gives every block's output
+// offset for every digit)
 __global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t* __restrict__ keys,
                                                          const uint64_t* __restrict__ cnt, int64_t cap, int shift,
                                                          int bits, uint32_t* __restrict__ hist) {
@@ -193,52 +195,7 @@ __global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t* __restr
   const int64_t lo = t0 * kTile, hi = t1 * kTile < n ? t1 * kTile : n;
   for (int64_t i = lo + threadIdx.x; i < hi; i += kThreads) atomicAdd(&s_h[(keys[i] >> shift) & mask], 1u);
   __syncthreads();
-  for (int d = threadIdx.x; d < radix; d += kThreads) hist[(int64_t)blockIdx.x * radix + d] = s_h[d];
-}
-
-// One block of 1024 threads turns the histograms into output offsets:
-// hist[b][d] <- start of digit d + count of digit d in blocks before b.
-// Thread (part p, digit d) sums its quarter of the blocks; the digit totals
-// are scanned over the digits; each quarter then rewrites its entries.
-__global__ __launch_bounds__(1024) void k_radix_offsets(uint32_t* __restrict__ hist, int nblocks, int bits) {
-  __shared__ uint32_t s_part[4][256];
-  __shared__ uint32_t s_w[4];
-  __shared__ uint32_t s_start[256];
-  const int radix = 1 << bits;
-  const int d = threadIdx.x & 255, p = threadIdx.x >> 8;
-  const int b0 = nblocks * p / 4, b1 = nblocks * (p + 1) / 4;
-  uint32_t sum = 0;
-  if (d < radix)
-    for (int b = b0; b < b1; ++b) sum += hist[(int64_t)b * radix + d];
-  s_part[p][d] = sum;
-  __syncthreads();
-  // digit totals and their exclusive scan over the digits: waves 0-3 (part
-  // 0) hold digits 0..255, one per lane; every barrier is reached by all
-  // threads
-  uint32_t tot = 0, inc = 0;
-  if (p == 0) {
-    tot = d < radix ? s_part[0][d] + s_part[1][d] + s_part[2][d] + s_part[3][d] : 0u;
-    inc = wave_inclusive<uint32_t>(tot);
-    if (hp_lane() == 63) s_w[threadIdx.x >> 6] = inc;
-  }
-  __syncthreads();
-  if (p == 0) {
-    const int w = threadIdx.x >> 6;
-    uint32_t base = 0;
-    for (int k = 0; k < w; ++k) base += s_w[k];
-    s_start[d] = base + inc - tot;
-  }
-  __syncthreads();
-  if (d < radix) {
-    uint32_t run = s_start[d];
-    for (int q = 0; q < p; ++q) run += s_part[q][d];
-    for (int b = b0; b < b1; ++b) {
-      const int64_t at = (int64_t)b * radix + d;
-      const uint32_t h = hist[at];
-      hist[at] = run;
-      run += h;
-    }
-  }
+  for (int d = threadIdx.x; d < radix; d += kThreads) hist[(int64_t)d * gridDim.x + blockIdx.x] = s_h[d];
 }
 
 // Stable scatter of each block's tiles, in order.  Per tile, wave w owns the
@@ -267,7 +224,7 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(const uint32_t* __re
   const int64_t n = dev_count(cnt, cap);
   int64_t t0, t1;
   block_tiles(n, &t0, &t1);
-  for (int d = tid; d < radix; d += kThreads) s_goff[d] = offs[(int64_t)blockIdx.x * radix + d];
+  for (int d = tid; d < radix; d += kThreads) s_goff[d] = offs[(int64_t)d * gridDim.x + blockIdx.x];
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   for (int64_t t = t0; t < t1; ++t) {
     for (int k = tid; k < 4 * 256; k += kThreads) (&s_cnt[0][0])[k] = 0;
@@ -347,7 +304,8 @@ inline unsigned copy_grid(int64_t cap) {
 }
 
 inline size_t radix_ws_bytes(int64_t cap) {
-  return 2 * hp_align256((size_t)(cap > 0 ? cap : 1) * 4) + hp_align256((size_t)grid_for(cap) * 256 * 4);
+  const int64_t h = (int64_t)grid_for(cap) * 256;
+  return 2 * hp_align256((size_t)(cap > 0 ? cap : 1) * 4) + hp_align256((size_t)h * 4) + scan_ws_bytes<uint32_t>(h);
 }
 
 // Stable sort of the first min(*cnt, cap) (key, value) pairs by the low
@@ -366,15 +324,15 @@ inline hp_status radix_sort(uint32_t* keys, uint32_t* vals, const uint64_t* cnt,
   char* p = (char*)ws;
   uint32_t* k2 = (uint32_t*)p; p += hp_align256((size_t)cap * 4);
   uint32_t* v2 = (uint32_t*)p; p += hp_align256((size_t)cap * 4);
-  uint32_t* hist = (uint32_t*)p;
+  uint32_t* hist = (uint32_t*)p; p += hp_align256((size_t)G * 256 * 4);
+  void* sws = p;
   uint32_t *ka = keys, *va = vals, *kb = k2, *vb = v2;
   for (int pass = 0; pass < passes; ++pass) {
     const int shift = pass * bits;
     const int b = (shift + bits <= nbits) ? bits : nbits - shift;
     hipLaunchKernelGGL(k_radix_hist, dim3(G), dim3(kThreads), 0, s, (const uint32_t*)ka, cnt, cap, shift, b, hist);
     HP_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_radix_offsets, dim3(1), dim3(1024), 0, s, hist, (int)G, b);
-    HP_CHECK_LAUNCH();
+    HP_TRY((scan_exclusive<uint32_t, uint32_t>(hist, hist, nullptr, (int64_t)G << b, nullptr, sws, s)));
     hipLaunchKernelGGL(k_radix_scatter, dim3(G), dim3(kThreads), 0, s, (const uint32_t*)ka, (const uint32_t*)va, cnt,
                        cap, shift, b, (const uint32_t*)hist, kb, vb);
     HP_CHECK_LAUNCH();
