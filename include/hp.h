@@ -330,6 +330,24 @@ hp_status hp_render_bwd_pixels(const void* projected, int64_t P, const uint32_t*
 hp_status hp_preprocess_bwd(const hp_gaussians* g, const hp_view* view, const hp_params* prm, const float* acc,
                             hp_gaussians_grad* grad, void* stream);
 
+/* hp_render_bwd_noalloc: hp_render_bwd for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  The same arguments without ws / ws_bytes and the
+ * same kernels; the per-Gaussian accumulators live in a fixed array of the
+ * library on each device (10 * HP_NOALLOC_MAX_P floats = 40 MiB, held until
+ * the process ends).  No memory is allocated by the call.  P above
+ * HP_NOALLOC_MAX_P returns HP_ERR_CAPACITY.  Every call on a device shares
+ * that device's array and leaves it holding its accumulators (the next call
+ * clears what it uses first): calls that overlap on one device, on different
+ * streams or from different threads, race and must be ordered by the caller.
+ * `stream` must belong to the current device. */
+#define HP_NOALLOC_MAX_P (1 << 20)
+hp_status hp_render_bwd_noalloc(const hp_gaussians* g, const void* projected, const uint32_t* vals,
+                                const uint32_t* tile_ranges, int32_t n_tiles, const hp_view* view,
+                                const hp_params* prm, const void* mask, int64_t n_active, const float* T,
+                                const int32_t* n_contrib, const float* dL_drgb, const float* dL_dT,
+                                const float* dL_dinv_depth, hp_gaussians_grad* grad, void* stream);
+
 /* ---- radian-space statistics for adaptive density control -----------------
  * (Sec. 4.2: r_s,max tracked across iterations, thresholds in radians.)
  * hp_mark_visible sets visible[i] = 1 for every Gaussian id in the view's

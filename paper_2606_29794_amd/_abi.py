@@ -13,6 +13,7 @@ HP_OK, HP_ERR_INVALID_ARG, HP_ERR_UNSUPPORTED, HP_ERR_CAPACITY, HP_ERR_DEVICE = 
 HP_CAM_FULL, HP_CAM_FISHEYE, HP_CAM_PINHOLE = 0, 1, 2
 HP_BIN_COUNT, HP_BIN_EMIT, HP_BIN_ALL = 1, 2, 3
 HP_QUERY_RING, HP_QUERY_NESTED = 1, 2
+HP_NOALLOC_MAX_P = 1 << 20   # largest scene of hp_render_bwd_noalloc
 
 
 class HPError(RuntimeError):
@@ -94,6 +95,8 @@ _PROTOS = {
     "hp_density_stats": (I32, [P_, I64, P_, P_, P_, P_, P_, P_]),
     "hp_preprocess_bwd": (I32, [C.POINTER(hp_gaussians), C.POINTER(hp_view), C.POINTER(hp_params), P_,
                                 C.POINTER(hp_gaussians_grad), P_]),
+    "hp_render_bwd_noalloc": (I32, [C.POINTER(hp_gaussians), P_, P_, P_, I32, C.POINTER(hp_view), C.POINTER(hp_params),
+                                    P_, I64, P_, P_, P_, P_, P_, C.POINTER(hp_gaussians_grad), P_]),
     "hp_ssim_workspace_bytes": (SZ, [I32, I32, I64]),
     "hp_ssim": (I32, [P_, P_, I64, I32, I32, C.POINTER(hp_params), C.POINTER(hp_ssim_params), P_, P_, P_, P_, P_, P_,
                       SZ, P_]),

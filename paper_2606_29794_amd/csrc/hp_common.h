@@ -85,3 +85,10 @@ hp_status hp_bin_sorted_widened(int32_t phase, const void* projected, int64_t P,
                                 const hp_params* prm, const void* grid, const void* mask, uint32_t* vals,
                                 uint32_t* tile_ranges, int32_t n_tiles, int64_t capacity, int64_t* n_pairs, void* ws,
                                 size_t ws_bytes, void* stream, double widen);
+
+// hp_render_bwd after its argument checks, accumulators [HP_NACC][P] at acc
+hp_status hp_render_bwd_acc(const hp_gaussians* gs, const void* projected, const uint32_t* vals,
+                            const uint32_t* tile_ranges, int32_t n_tiles, const hp_view* view, const hp_params* prm,
+                            const void* mask, int64_t n_active, const float* T, const int32_t* n_contrib,
+                            const float* dL_drgb, const float* dL_dT, const float* dL_dinv_depth,
+                            hp_gaussians_grad* grad, float* acc, void* stream);

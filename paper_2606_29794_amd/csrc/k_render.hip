@@ -549,11 +549,21 @@ extern "C" hp_status hp_render_bwd(const hp_gaussians* gs, const void* projected
     return HP_ERR_INVALID_ARG;
   if (n_active > 0 && n_tiles > 0 && (!T || !n_contrib || !dL_drgb || !tile_ranges || !vals)) return HP_ERR_INVALID_ARG;
   if (ws_bytes < hp_render_bwd_workspace_bytes(gs->P)) return HP_ERR_CAPACITY;
+  return hp_render_bwd_acc(gs, projected, vals, tile_ranges, n_tiles, view, prm, mask, n_active, T, n_contrib,
+                           dL_drgb, dL_dT, dL_dinv_depth, grad, (float*)ws, stream);
+}
+
+// hp_render_bwd after its argument checks, with the accumulators [HP_NACC][P]
+// at `acc` (zeroed here by a kernel)
+hp_status hp_render_bwd_acc(const hp_gaussians* gs, const void* projected, const uint32_t* vals,
+                            const uint32_t* tile_ranges, int32_t n_tiles, const hp_view* view, const hp_params* prm,
+                            const void* mask, int64_t n_active, const float* T, const int32_t* n_contrib,
+                            const float* dL_drgb, const float* dL_dT, const float* dL_dinv_depth,
+                            hp_gaussians_grad* grad, float* acc, void* stream) {
   if (gs->P == 0) return HP_OK;
   const HpGeom g = hp_geom(view->order, prm->tile_log2);
   if (n_tiles > g.ntile || n_active > g.npix) return HP_ERR_INVALID_ARG;
   hipStream_t s = (hipStream_t)stream;
-  float* acc = (float*)ws;
   hipLaunchKernelGGL(k_zero_f32, dim3(hp_blocks(gs->P * HP_NACC, 256)), dim3(256), 0, s, acc, gs->P * HP_NACC);
   HP_CHECK_LAUNCH();
   HP_TRY(hp_render_bwd_pixels(projected, gs->P, vals, tile_ranges, n_tiles, view, prm, mask, n_active, T, n_contrib,

@@ -83,3 +83,17 @@ def test_every_entry_point_checks_null_arguments_on_the_host():
     bad = {k: v for k, v in statuses.items() if v not in (0, 1, 3)}
     assert not bad, bad
     assert sum(v == 1 for v in statuses.values()) >= 15, statuses
+
+
+def test_noalloc_backward_rejects_oversized_scene():
+    """hp_render_bwd_noalloc's fixed accumulator array holds HP_NOALLOC_MAX_P
+    Gaussians; a larger scene is refused on the host (HP_ERR_CAPACITY)."""
+    W = np.eye(3, dtype=np.float32)
+    v = A.make_view(W, np.zeros(3, np.float32), np.zeros(3, np.float32), A.HP_CAM_FULL, 0.0, 0.0, 6)
+    g = A.hp_gaussians(A.HP_NOALLOC_MAX_P + 1, 0, 16, 16, 16, 16, 16)
+    gg = A.hp_gaussians_grad(16, 16, 16, 16, 16)
+    d = C.c_void_p(16)   # never dereferenced: the size check fails first
+    prm = A.default_params()
+    st = A.lib().hp_render_bwd_noalloc(C.byref(g), d, d, d, 1, C.byref(v), C.byref(prm), d, 1, d, d, d, None, None,
+                                       C.byref(gg), None)
+    assert st == A.HP_ERR_CAPACITY
