@@ -453,9 +453,13 @@ def render_bwd(scene, cam, proj: Projected, pix, dLdC, dLdT=None, prm=None, dLdD
     return (g, ang) if want_angles else g
 
 
-def hssim(order, active, img, ref, sigma=SSIM_SIGMA, c1=SSIM_C1, c2=SSIM_C2, want_map=False, want_grad=False):
+def hssim(order, active, img, ref, sigma=SSIM_SIGMA, c1=SSIM_C1, c2=SSIM_C2, want_map=False, want_grad=False,
+          zones=False):
     """Mean HEALPix-SSIM over active pixels and channels (Sec. 4.1, supp. eq.
-    for the masked average); optional map [3][n] and d mean / d img [3][n]."""
+    for the masked average); optional map [3][n] and d mean / d img [3][n].
+    zones: the zone-specific windows (isotropic chart window in the
+    equatorial belt, great-circle Gaussian of sigma pitches in the polar
+    caps); otherwise the isotropic chart window everywhere."""
     active = np.ascontiguousarray(active, np.int64)
     img = np.ascontiguousarray(img, np.float64)
     ref = np.ascontiguousarray(ref, np.float64)
@@ -463,16 +467,26 @@ def hssim(order, active, img, ref, sigma=SSIM_SIGMA, c1=SSIM_C1, c2=SSIM_C2, wan
     m = np.zeros((3, n)) if want_map else None
     g = np.zeros((3, n)) if want_grad else None
     mean = lib().or_hssim(order, C.c_int64(n), _p(active), _p(img), _p(ref), C.c_double(sigma), C.c_double(c1),
-                          C.c_double(c2), _p(m), _p(g))
+                          C.c_double(c2), int(bool(zones)), _p(m), _p(g))
     return mean, m, g
 
 
-def loss(order, active, img, ref, lam=LAMBDA, want_grad=False):
+def hssim_window(order, p, sigma=SSIM_SIGMA, zones=False):
+    """Raw window of nested pixel p: (neighbour ids [11, 11] with -1 in a
+    missing quadrant, weights [11, 11]), indexed by the chart offsets
+    (a + 5, b + 5)."""
+    q = np.zeros(121, np.int64)
+    w = np.zeros(121)
+    lib().or_hssim_window(int(order), C.c_int64(int(p)), C.c_double(sigma), int(bool(zones)), _p(q), _p(w))
+    return q.reshape(11, 11), w.reshape(11, 11)
+
+
+def loss(order, active, img, ref, lam=LAMBDA, want_grad=False, zones=False):
     """L = (1 - lambda) L1 + lambda (1 - HSSIM) (Sec. 4.1); L1 = mean |img - ref|.
     Returns (L, dL/dimg or None)."""
     img = np.asarray(img, np.float64); ref = np.asarray(ref, np.float64)
     l1 = float(np.mean(np.abs(img - ref)))
-    s, _, gs = hssim(order, active, img, ref, want_grad=want_grad)
+    s, _, gs = hssim(order, active, img, ref, want_grad=want_grad, zones=zones)
     L = (1 - lam) * l1 + lam * (1 - s)
     if not want_grad:
         return L, None

@@ -883,31 +883,78 @@ void or_render_bwd(const or_scene* S, const or_view* V, const or_params* prm, co
 }
 
 // --- HEALPix-SSIM and the training loss (Sec. 4.1; supp. HSSIM metric) ---
+// Zone-specific windows (Sec. 4.1: isotropic in the equatorial zone where the
+// pixels are roughly square, anisotropic in the polar zones where they are
+// compressed along the rings).  Reading: a pixel of the equatorial belt
+// (ring jr in [N, 3N], |z| <= 2/3) keeps the isotropic window of face-local
+// offsets, exp(-(a^2 + b^2) / (2 sigma^2)); a pixel of a polar cap (jr < N or
+// jr > 3N) weighs each chart neighbour q by its great-circle distance d,
+// exp(-d^2 / (2 sigma^2 Omega)) with Omega = 4 pi / Npix the pixel area, which
+// is the same Gaussian of width sigma pitches measured on the sphere instead
+// of in chart steps.  In (a, b) it is anisotropic and not separable.
+static bool polar_pixel(int order, i64 p) {
+  const i64 N = (i64)1 << order;
+  const RingPos r = xyf2ringpos(order, nest2xyf(order, p));
+  return r.jr < N || r.jr > 3 * N;
+}
+
+static double great_circle(const double u[3], const double v[3]) {
+  const double c[3] = {u[1] * v[2] - u[2] * v[1], u[2] * v[0] - u[0] * v[2], u[0] * v[1] - u[1] * v[0]};
+  return std::atan2(std::sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]), u[0] * v[0] + u[1] * v[1] + u[2] * v[2]);
+}
+
+// Raw window weights of nested pixel p over its 11 x 11 chart neighbourhood
+// (index (a + 5) * 11 + (b + 5) for offsets (a, b)); nbq receives the
+// neighbour's nested id or -1 in the missing quadrant (weight 0 there).
+static void hssim_window(int order, i64 p, double sigma, int zones, i64* nbq, double* w) {
+  const int R = 5, Wd = 11;
+  const XYF a = nest2xyf(order, p);
+  const bool polar = zones && polar_pixel(order, p);
+  double up[3];
+  if (polar) pix_vec(order, p, up);
+  const double omega = 4.0 * M_PI / (double)(12 * ((i64)1 << (2 * order)));
+  for (int da = -R; da <= R; ++da)
+    for (int db = -R; db <= R; ++db) {
+      const int j = (da + R) * Wd + (db + R);
+      const i64 q = chart_pixel(order, a.f, a.x + da, a.y + db);
+      nbq[j] = q;
+      if (q < 0) { w[j] = 0.0; continue; }
+      if (polar) {
+        double uq[3];
+        pix_vec(order, q, uq);
+        const double d = great_circle(up, uq);
+        w[j] = std::exp(-d * d / (2.0 * sigma * sigma * omega));
+      } else {
+        w[j] = std::exp(-(double)(da * da + db * db) / (2.0 * sigma * sigma));
+      }
+    }
+}
+
+// The raw window of one pixel (for the pins of the zone reading).
+void or_hssim_window(int order, i64 p, double sigma, int zones, i64* nbq, double* w) {
+  hssim_window(order, p, sigma, zones, nbq, w);
+}
+
 // img, ref: [3][n] over the active pixels; active: sorted nested ids.  Window
-// 11x11 (offsets -5..5) on the face-extended chart, raw weights
-// exp(-(a^2+b^2)/(2 sigma^2)); neighbours that are missing or inactive get
-// weight 0 and the rest are renormalised.  Returns mean SSIM over pixels and
-// channels; ssim_map [3][n] optional.  With grad != NULL also writes
-// d(mean SSIM)/d img  ([3][n]).
+// 11x11 (offsets -5..5) on the face-extended chart with the raw weights of
+// hssim_window (zones = 0: the isotropic chart window everywhere);
+// neighbours that are missing or inactive get weight 0 and the rest are
+// renormalised.  Returns mean SSIM over pixels and channels; ssim_map [3][n]
+// optional.  With grad != NULL also writes d(mean SSIM)/d img  ([3][n]).
 double or_hssim(int order, i64 n, const i64* active, const double* img, const double* ref, double sigma, double C1,
-                double C2, double* ssim_map, double* grad) {
+                double C2, int zones, double* ssim_map, double* grad) {
   i64 npix = 12 * ((i64)1 << (2 * order));
   std::vector<i64> idx(npix, -1);
   for (i64 k = 0; k < n; ++k) idx[active[k]] = k;
-  const int R = 5, Wd = 11;
-  double wr[Wd * Wd];
-  for (int a = -R; a <= R; ++a)
-    for (int b = -R; b <= R; ++b) wr[(a + R) * Wd + (b + R)] = std::exp(-(a * a + b * b) / (2 * sigma * sigma));
-  // neighbour lists
+  const int Wd = 11;
+  // neighbour lists (active slots) of every pixel
   std::vector<i64> nb((size_t)n * Wd * Wd);
 #pragma omp parallel for schedule(static)
   for (i64 k = 0; k < n; ++k) {
-    XYF a = nest2xyf(order, active[k]);
-    for (int da = -R; da <= R; ++da)
-      for (int db = -R; db <= R; ++db) {
-        i64 q = chart_pixel(order, a.f, a.x + da, a.y + db);
-        nb[(size_t)k * Wd * Wd + (da + R) * Wd + (db + R)] = q >= 0 ? idx[q] : -1;
-      }
+    i64 q[Wd * Wd];
+    double w[Wd * Wd];
+    hssim_window(order, active[k], sigma, 0, q, w);
+    for (int j = 0; j < Wd * Wd; ++j) nb[(size_t)k * Wd * Wd + j] = q[j] >= 0 ? idx[q[j]] : -1;
   }
   double total = 0;
   // per pixel/channel partials of SSIM w.r.t. the three x-dependent sums
@@ -915,6 +962,9 @@ double or_hssim(int order, i64 n, const i64* active, const double* img, const do
 #pragma omp parallel for schedule(static) reduction(+ : total)
   for (i64 k = 0; k < n; ++k) {
     const i64* nbk = &nb[(size_t)k * Wd * Wd];
+    i64 qk[Wd * Wd];
+    double wr[Wd * Wd];
+    hssim_window(order, active[k], sigma, zones, qk, wr);
     double Z = 0;
     for (int j = 0; j < Wd * Wd; ++j) if (nbk[j] >= 0) Z += wr[j];
     for (int ch = 0; ch < 3; ++ch) {
@@ -950,6 +1000,9 @@ double or_hssim(int order, i64 n, const i64* active, const double* img, const do
     std::fill(grad, grad + 3 * n, 0.0);
     for (i64 k = 0; k < n; ++k) {
       const i64* nbk = &nb[(size_t)k * Wd * Wd];
+      i64 qk[Wd * Wd];
+      double wr[Wd * Wd];
+      hssim_window(order, active[k], sigma, zones, qk, wr);
       for (int j = 0; j < Wd * Wd; ++j) {
         i64 p = nbk[j];
         if (p < 0) continue;
