@@ -99,9 +99,17 @@ typedef struct {
 
 /* HEALPix-SSIM constants (Sec. 4.1; window of Wang et al. 2004):
  * 11 x 11 window on face-local (x, y), Gaussian sigma, C1 = (0.01)^2,
- * C2 = (0.03)^2, loss weight lambda = 0.2. */
+ * C2 = (0.03)^2, loss weight lambda = 0.2.  zones = 1 selects the
+ * zone-specific windows of Sec. 4.1: pixels of the equatorial belt (|z| <=
+ * 2/3) keep the isotropic window exp(-(a^2 + b^2) / (2 sigma^2)) of chart
+ * offsets (a, b); pixels of the polar caps weigh each chart neighbour by its
+ * great-circle distance d, exp(-d^2 / (2 sigma^2 Omega)) with Omega = 4 pi /
+ * Npix, i.e. the same Gaussian measured on the sphere (anisotropic in the
+ * chart, where the rings compress the pixels).  zones = 0 (default): the
+ * isotropic chart window everywhere. */
 typedef struct {
   float sigma, C1, C2, lambda;
+  int32_t zones;
 } hp_ssim_params;
 
 void hp_default_params(hp_params* p);
@@ -375,26 +383,44 @@ hp_status hp_density_stats(const void* projected, int64_t P, const float* acc, c
  * out[2] = L = (1 - lambda) L1 + lambda (1 - mean SSIM).
  * img, ref: [3][n_active] in mask order; ssim_map [3][n_active] nullable.
  * If dL_dloss (device scalar) is non-null, dL_dimg [3][n_active] receives
- * dL_dloss * dL/dimg.  Requires order >= 3.  ws: hp_ssim_workspace_bytes. */
+ * dL_dloss * dL/dimg.  tables: from hp_ssim_tables for this mask (required).
+ * Requires order >= 3 and tiles of 8 or 16 pixels a side
+ * (tile_log2 = 4, or 3 at order 3) (HP_ERR_UNSUPPORTED otherwise).
+ * ws: hp_ssim_workspace_bytes. */
 size_t hp_ssim_workspace_bytes(int32_t order, int32_t tile_log2, int64_t n_active);
 hp_status hp_ssim(const float* img, const float* ref, int64_t n_active, int32_t n_tiles, int32_t order,
-                  const hp_params* prm, const hp_ssim_params* sp, const void* mask, float* out, float* ssim_map,
-                  const float* dL_dloss, float* dL_dimg, void* ws, size_t ws_bytes, void* stream);
+                  const hp_params* prm, const hp_ssim_params* sp, const void* mask, const int32_t* tables, float* out,
+                  float* ssim_map, const float* dL_dloss, float* dL_dimg, void* ws, size_t ws_bytes, void* stream);
+
+/* hp_ssim_tables: the image-independent part of the HSSIM gathers, built
+ * once per mask and passed to every hp_ssim call on that mask: for each
+ * active tile and each cell of its (B + 10)^2 patch (the tile and a 5-pixel
+ * halo on the face-extended chart), the compact slot of the neighbour pixel
+ * (-1 where it is missing or inactive) with bit 30 set when the neighbour
+ * lies in a polar cap.  tables: device int32 buffer of
+ * hp_ssim_tables_bytes(order, tile_log2, n_tiles) bytes (2,704 per active
+ * tile with 16 x 16 tiles). */
+size_t hp_ssim_tables_bytes(int32_t order, int32_t tile_log2, int32_t n_tiles);
+hp_status hp_ssim_tables(const hp_params* prm, const void* mask, int32_t order, int64_t n_active, int32_t n_tiles,
+                         int32_t* tables, size_t tables_bytes, void* stream);
 
 /* The same loss split at the point where the upstream gradient becomes known
  * (an autograd forward and its later backward).  hp_ssim_forward_saved does
  * what hp_ssim does without dL_dloss and also leaves the per-pixel SSIM
- * partials of the backward (9 floats per active pixel) in ws;
+ * partials of the backward (12 floats per active pixel) in ws;
  * hp_ssim_backward_saved then computes dL_dimg = dL_dloss * dL/dimg from them
  * with the gather pass alone.  Between the two calls the caller keeps ws, img
- * and ref unchanged; both calls take the same sizes, mask and parameters.
- * Errors as hp_ssim; the backward's dL_dloss and dL_dimg are required. */
+ * and ref unchanged; both calls take the same sizes, mask, tables and
+ * parameters.  Errors as hp_ssim; the backward's dL_dloss and dL_dimg are
+ * required. */
 hp_status hp_ssim_forward_saved(const float* img, const float* ref, int64_t n_active, int32_t n_tiles, int32_t order,
-                                const hp_params* prm, const hp_ssim_params* sp, const void* mask, float* out,
-                                float* ssim_map, void* ws, size_t ws_bytes, void* stream);
+                                const hp_params* prm, const hp_ssim_params* sp, const void* mask,
+                                const int32_t* tables, float* out, float* ssim_map, void* ws, size_t ws_bytes,
+                                void* stream);
 hp_status hp_ssim_backward_saved(const float* img, const float* ref, int64_t n_active, int32_t n_tiles, int32_t order,
-                                 const hp_params* prm, const hp_ssim_params* sp, const void* mask, const void* ws,
-                                 size_t ws_bytes, const float* dL_dloss, float* dL_dimg, void* stream);
+                                 const hp_params* prm, const hp_ssim_params* sp, const void* mask,
+                                 const int32_t* tables, const void* ws, size_t ws_bytes, const float* dL_dloss,
+                                 float* dL_dimg, void* stream);
 
 /* ---- image synthesis (Eq. camera_synthesis; supp. camera models) ----------
  * Camera images are planar float [3][H][W] (channel, row, column), row 0 at

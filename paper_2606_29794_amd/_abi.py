@@ -50,7 +50,7 @@ class hp_render_req(C.Structure):
 
 
 class hp_ssim_params(C.Structure):
-    _fields_ = [("sigma", C.c_float), ("C1", C.c_float), ("C2", C.c_float), ("lam", C.c_float)]
+    _fields_ = [("sigma", C.c_float), ("C1", C.c_float), ("C2", C.c_float), ("lam", C.c_float), ("zones", C.c_int32)]
 
 
 P_ = C.c_void_p
@@ -99,11 +99,13 @@ _PROTOS = {
                                     P_, I64, P_, P_, P_, P_, P_, C.POINTER(hp_gaussians_grad), P_]),
     "hp_ssim_workspace_bytes": (SZ, [I32, I32, I64]),
     "hp_ssim": (I32, [P_, P_, I64, I32, I32, C.POINTER(hp_params), C.POINTER(hp_ssim_params), P_, P_, P_, P_, P_, P_,
-                      SZ, P_]),
+                      P_, SZ, P_]),
+    "hp_ssim_tables_bytes": (SZ, [I32, I32, I32]),
+    "hp_ssim_tables": (I32, [C.POINTER(hp_params), P_, I32, I64, I32, P_, SZ, P_]),
     "hp_ssim_forward_saved": (I32, [P_, P_, I64, I32, I32, C.POINTER(hp_params), C.POINTER(hp_ssim_params), P_, P_,
-                                    P_, P_, SZ, P_]),
+                                    P_, P_, P_, SZ, P_]),
     "hp_ssim_backward_saved": (I32, [P_, P_, I64, I32, I32, C.POINTER(hp_params), C.POINTER(hp_ssim_params), P_,
-                                     P_, SZ, P_, P_, P_]),
+                                     P_, P_, SZ, P_, P_, P_]),
     "hp_sphere_to_image": (I32, [P_, C.POINTER(hp_view), C.POINTER(hp_params), I64, P_, I32, I32, P_, P_, P_]),
     "hp_image_to_sphere": (I32, [P_, C.POINTER(hp_view), C.POINTER(hp_params), I64, P_, I32, I32, P_, P_, P_]),
 }

@@ -20,6 +20,7 @@ extern "C" void hp_default_ssim_params(hp_ssim_params* p) {
   p->C1 = 0.01f * 0.01f;
   p->C2 = 0.03f * 0.03f;
   p->lambda = 0.2f;
+  p->zones = 0;
 }
 
 extern "C" const char* hp_status_string(hp_status s) {

@@ -3,18 +3,33 @@
 // One workgroup per active tile.  The tile's B x B pixels plus a 5-pixel halo
 // are gathered into LDS through the face-extended chart (neighbouring faces
 // with their axes turned to line up; the missing quadrant of a three-face
-// vertex and inactive pixels carry weight 0).  On that regular patch the 11x11
-// Gaussian window is separable, so the weighted sums of (1, x, y, x^2, y^2, xy)
-// are two 11-tap passes; dividing by the summed weight renormalises where
-// neighbours are missing.  The backward pass is the transposed convolution:
-// the chart neighbourhood relation is symmetric with equal offset lengths, so
-// the adjoint gathers the per-pixel SSIM partials over the same window.
+// vertex and inactive pixels carry weight 0).  Dividing the window sums by
+// the summed weight renormalises where neighbours are missing.
+//
+// Windows.  The isotropic chart window exp(-(a^2 + b^2) / (2 sigma^2)) is
+// separable on the patch: two 11-tap passes, each thread sliding the window
+// along a strip held in registers (one LDS read per input value, four or
+// eight outputs per strip).  With zone-specific windows, a pixel of a polar
+// cap weighs its neighbours by great-circle distance instead,
+// exp(-d^2 / (2 sigma^2 Omega)), Omega = 4 pi / Npix, which is not separable:
+// tiles holding such pixels take a direct 121-tap path with the pixel-centre
+// directions in LDS.
+//
+// The backward pass is the transposed window: the chart neighbourhood
+// relation is symmetric with equal offset lengths, so the adjoint gathers the
+// per-pixel SSIM partials over the same window, each neighbour's partials
+// weighted by that neighbour's own window at the pixel.
 #include "hp_common.h"
 
 #define SS_R 5
 #define SS_W 11
-#define SS_MAXB 16
-#define SS_MAXH (SS_MAXB + 2 * SS_R)  // 26
+
+// patch table entries: compact slot, bit 30 set for a polar-cap pixel, -1
+// for a missing or inactive neighbour
+constexpr int32_t kSsPolarBit = 1 << 30;
+constexpr int32_t kSsSlotMask = kSsPolarBit - 1;
+// the backward's per-pixel partials: 9 floats at a 12-float (48-byte) stride
+constexpr int kSsG = 12;
 
 struct SsimArgs {
   int order, b, kt;
@@ -24,7 +39,10 @@ struct SsimArgs {
   const uint32_t* tile_bits;
   int64_t n_active;
   float C1, C2, lam;
-  float g[SS_W];  // raw window weights exp(-a^2 / (2 sigma^2))
+  float g[SS_W];   // chart window taps exp(-a^2 / (2 sigma^2)), a = -5..5
+  float gsum;      // their sum, accumulated in the order of the passes
+  double wscale;   // 1 / (2 sigma^2 Omega): polar windows are exp(-d^2 wscale)
+  const int32_t* tables;  // [n_tiles][H*H] patch slots (see k_ssim_tables)
 };
 
 // compact slot of nested pixel q, or -1 when inactive / absent
@@ -43,23 +61,38 @@ __device__ __forceinline__ int64_t ss_slot(const SsimArgs& A, int64_t q) {
   return (int64_t)A.tile_start[t] + rank;
 }
 
-// Patch cell of gather index i (a bijection of [0, H*H)): the first B*B
-// indices are the tile's own pixels in NESTED order, which a fully active
-// tile stores contiguously (coalesced loads), the rest the halo row by row.
-__device__ __forceinline__ int ss_cell(int i, int B, int H) {
+// polar cap pixel: ring jr = jrll(f) N - x - y - 1 outside [N, 3N]
+__device__ __forceinline__ bool ss_polar(int order, int64_t q) {
+  int x, y, f;
+  hp_nest_xyf(order, q, &x, &y, &f);
+  const int N = 1 << order;
+  return f < 4 ? (x + y >= N) : (f >= 8 ? (x + y <= N - 2) : false);
+}
+
+// Patch cell (x, y) of gather index i (a bijection of [0, H*H)): the first
+// B*B indices are the tile's own pixels in NESTED order, which a fully
+// active tile stores contiguously (coalesced loads), the rest the halo row by
+// row.
+template <int B>
+__device__ __forceinline__ void ss_cell(int i, int* cx, int* cy) {
+  constexpr int H = B + 2 * SS_R;
   if (i < B * B) {
-    const int x = (int)hp_compact_bits((uint32_t)i), y = (int)hp_compact_bits((uint32_t)i >> 1);
-    return (y + SS_R) * H + x + SS_R;
+    *cx = (int)hp_compact_bits((uint32_t)i) + SS_R;
+    *cy = (int)hp_compact_bits((uint32_t)i >> 1) + SS_R;
+    return;
   }
   int h = i - B * B;
-  if (h < SS_R * H) return h;  // rows above the tile
+  if (h < SS_R * H) { *cy = h / H; *cx = h % H; return; }  // rows above the tile
   h -= SS_R * H;
   if (h < 2 * SS_R * B) {  // left and right of the tile's rows
-    const int row = SS_R + h / (2 * SS_R), c = h % (2 * SS_R);
-    return row * H + (c < SS_R ? c : c + B);
+    *cy = SS_R + h / (2 * SS_R);
+    const int c = h % (2 * SS_R);
+    *cx = c < SS_R ? c : c + B;
+    return;
   }
   h -= 2 * SS_R * B;
-  return (SS_R + B) * H + h;  // rows below
+  *cy = SS_R + B + h / H;  // rows below
+  *cx = h % H;
 }
 
 __device__ __forceinline__ void ss_tile_origin(const SsimArgs& A, int ct, int* f, int* x0, int* y0) {
@@ -70,134 +103,301 @@ __device__ __forceinline__ void ss_tile_origin(const SsimArgs& A, int ct, int* f
   *y0 = ty << A.b;
 }
 
+// squared great-circle distance between unit vectors u, v (double):
+// d = 2 asin(s), s = |u - v| / 2; d^2 = 4 s^2 (asin s / s)^2, the factor as
+// its series in s^2 below s^2 = 1/16 (truncation < 1e-9), asin beyond
+__device__ __forceinline__ double ss_dist2(const double* u, const double* v) {
+  const double dx = u[0] - v[0], dy = u[1] - v[1], dz = u[2] - v[2];
+  const double c2 = dx * dx + dy * dy + dz * dz;
+  const double s2 = 0.25 * c2;
+  if (s2 < 0.0625) {
+    const double k = 1.0 + s2 * (1.0 / 3.0 + s2 * (8.0 / 45.0 + s2 * (4.0 / 35.0 + s2 * (128.0 / 1575.0 +
+                     s2 * (128.0 / 2079.0 + s2 * (1024.0 / 21021.0))))));
+    return c2 * k;
+  }
+  const double d = 2.0 * asin(fmin(1.0, sqrt(s2)));
+  return d * d;
+}
+
+// SSIM of one pixel and channel from its normalised window moments, and the
+// partials of the backward: d SSIM / d (sum x, sum x^2, sum xy) / Z
+__device__ __forceinline__ float ss_index(float C1, float C2, float iZ, float Sx, float Sy, float Sxx, float Syy,
+                                          float Sxy, float* G0, float* G1, float* G2) {
+  const float mx = Sx * iZ, my = Sy * iZ;
+  const float vx = Sxx * iZ - mx * mx, vy = Syy * iZ - my * my;
+  const float cxy = Sxy * iZ - mx * my;
+  const float An = 2.f * mx * my + C1, Bn = 2.f * cxy + C2;
+  const float Ad = mx * mx + my * my + C1, Bd = vx + vy + C2;
+  // reciprocals to 1 ulp (v_rcp_f32) instead of IEEE divisions
+  const float iAd = __builtin_amdgcn_rcpf(Ad), iBd = __builtin_amdgcn_rcpf(Bd);
+  const float iden = iAd * iBd;
+  const float s = An * Bn * iden;
+  // s(sx, sxx, sxy) with the y sums fixed; sx = mx etc. (normalised)
+  const float ds_dmx = (2.f * my * Bn - An * 2.f * my) * iden - s * (2.f * mx * iAd - 2.f * mx * iBd);
+  *G0 = ds_dmx * iZ;
+  *G1 = (-s * iBd) * iZ;
+  *G2 = (2.f * An * iden) * iZ;
+  return s;
+}
+
+// nested index of patch-interior pixel (x, y) of a tile: x bits at even
+// positions, y bits at odd ones
+__device__ __forceinline__ int ss_nest_local(int x, int y) {
+  auto spread = [](uint32_t v) {
+    v = (v | (v << 8)) & 0x00FF00FFu;
+    v = (v | (v << 4)) & 0x0F0F0F0Fu;
+    v = (v | (v << 2)) & 0x33333333u;
+    v = (v | (v << 1)) & 0x55555555u;
+    return v;
+  };
+  return (int)(spread((uint32_t)x) | (spread((uint32_t)y) << 1));
+}
+
+// ---------------------------------------------------------------------------
+// forward
+// ---------------------------------------------------------------------------
+// LDS: the gathered patch (mask, x[3], y[3]), the first pass's output
+// [16][H][B] (or, on the direct path, the cells' directions), then the
+// second pass's output [16][B*B] over the patch's place.
+template <int B>
+struct SsFwdLds {
+  // row pitch HP: 16-byte aligned rows for the strip loads; P1S: the pass-1
+  // output's quantity stride, 16 mod 32 words so that the two quantities a
+  // half-wave reads in the second pass fall in different banks
+  static constexpr int H = B + 2 * SS_R, HP = (H + 3) & ~3, P1S = H * B + ((48 - (H * B) % 32) % 32);
+  float in[7][H][HP];
+  union {
+    float p1[16][P1S];
+    double dir[H * H][3];
+  };
+};
+
 // Forward: SSIM per active pixel and channel; per-block partial sums of SSIM
 // and |img - ref|; optionally the per-pixel partials needed by the backward,
 // G[m][n] = (d SSIM / d S_m) / Z for m in (sum x, sum x^2, sum xy) x channel.
+template <int B, bool ZONES>
 __global__ __launch_bounds__(256) void k_ssim_fwd(SsimArgs A, const float* __restrict__ img,
                                                   const float* __restrict__ ref, float* __restrict__ smap,
                                                   float* __restrict__ G, float2* __restrict__ part) {
-  // one LDS buffer serves first as the gathered patch [7][H*H] and then, once
-  // every thread holds its horizontal-pass sums in registers, as the pass
-  // output [16][B*H]: 26.6 KB instead of 45.5 KB, so twice the workgroups fit
-  constexpr int kIn = SS_MAXH * SS_MAXH, kH = SS_MAXB * SS_MAXH;
-  __shared__ float s_buf[16 * kH];
+  using L = SsFwdLds<B>;
+  constexpr int H = L::H;
+  __shared__ L s;
   __shared__ float s_red[2][4];
+  float(*S)[B * B] = reinterpret_cast<float(*)[B * B]>(&s.in[0][0][0]);  // after pass 1
   const int ct = hp_xcd_tile(blockIdx.x, gridDim.x), tid = threadIdx.x;
-  const int B = 1 << A.b, H = B + 2 * SS_R;
   int f, x0, y0;
   ss_tile_origin(A, ct, &f, &x0, &y0);
-  for (int i = tid; i < H * H; i += 256) {
-    const int cell = ss_cell(i, B, H);
-    const int cx = cell % H, cy = cell / H;
-    const int64_t slot = ss_slot(A, hp_chart_pixel(A.order, f, x0 + cx - SS_R, y0 + cy - SS_R));
-    float m = 0.f, v[6] = {0, 0, 0, 0, 0, 0};
-    if (slot >= 0) {
-      m = 1.f;
+  // zone windows: the tile takes the direct path when it holds a polar pixel
+  const int N = 1 << A.order;
+  const bool direct = ZONES && (f < 4 ? (x0 + y0 + 2 * B - 2 >= N) : (f >= 8 ? (x0 + y0 <= N - 2) : false));
+  // the patch from the tile's slot table: every load of the thread's cells
+  // goes out before the first LDS store
+  constexpr int NG = (H * H + 255) / 256;
+  const int32_t* tab = A.tables + (int64_t)ct * (H * H);
+  int32_t e[NG];
 #pragma unroll
-      for (int ch = 0; ch < 3; ++ch) {
-        v[ch] = img[ch * A.n_active + slot];
-        v[3 + ch] = ref[ch * A.n_active + slot];
-      }
-    }
-    s_buf[cell] = m;
-#pragma unroll
-    for (int k = 0; k < 6; ++k) s_buf[(1 + k) * kIn + cell] = v[k];
+  for (int gi = 0; gi < NG; ++gi) {
+    const int i = tid + 256 * gi;
+    e[gi] = i < H * H ? tab[i] : -1;
   }
-  __syncthreads();
-  // the centre values of this thread's pixel, for the L1 term
-  float xc[3] = {0.f, 0.f, 0.f}, yc[3] = {0.f, 0.f, 0.f};
-  const int px = tid % B, py = tid / B;
-  if (tid < B * B) {
-    const int cc = (py + SS_R) * H + px + SS_R;
+  float v[NG][6];
+#pragma unroll
+  for (int gi = 0; gi < NG; ++gi) {
+    const int64_t slot = e[gi] & kSsSlotMask;
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) {
-      xc[ch] = s_buf[(1 + ch) * kIn + cc];
-      yc[ch] = s_buf[(4 + ch) * kIn + cc];
+      v[gi][ch] = e[gi] >= 0 ? img[ch * A.n_active + slot] : 0.f;
+      v[gi][3 + ch] = e[gi] >= 0 ? ref[ch * A.n_active + slot] : 0.f;
     }
   }
-  // pass 1 along x: rows 0..H-1 of the patch, output columns 0..B-1; at most
-  // two outputs per thread (B * H <= 416)
-  float acc[2][16];
+  bool mine_full = true;
 #pragma unroll
-  for (int j = 0; j < 2; ++j) {
+  for (int gi = 0; gi < NG; ++gi) {
+    const int i = tid + 256 * gi;
+    if (i < H * H) {
+      int cx, cy;
+      ss_cell<B>(i, &cx, &cy);
+      mine_full &= e[gi] >= 0;
+      s.in[0][cy][cx] = e[gi] >= 0 ? 1.f : 0.f;
 #pragma unroll
-    for (int k = 0; k < 16; ++k) acc[j][k] = 0.f;
-    const int pos = tid + 256 * j;
-    if (pos < B * H) {
-      const int ox = pos % B, row = pos / B;
-      // partial unroll: a full one keeps every tap's loads live at once
-#pragma unroll 3
-      for (int a = 0; a < SS_W; ++a) {
-        const int cell = row * H + ox + a;
-        const float w = A.g[a] * s_buf[cell];
-        acc[j][0] += w;
+      for (int k = 0; k < 6; ++k) s.in[1 + k][cy][cx] = v[gi][k];
+      if (ZONES && direct) {
+        const int64_t q = hp_chart_pixel(A.order, f, x0 + cx - SS_R, y0 + cy - SS_R);
+        double d[3] = {0.0, 0.0, 0.0};
+        if (q >= 0) hp_pix_dir(A.order, q, d);
+        s.dir[cy * H + cx][0] = d[0];
+        s.dir[cy * H + cx][1] = d[1];
+        s.dir[cy * H + cx][2] = d[2];
+      }
+    }
+  }
+  // every cell of the patch active: the window weights need no mask and sum
+  // to (sum of taps)^2 everywhere
+  const bool full = __syncthreads_and(mine_full);
+  // this thread's pixel: nested local index tid (slot order of a full tile)
+  const int px = (int)hp_compact_bits((uint32_t)tid), py = (int)hp_compact_bits((uint32_t)tid >> 1);
+  const bool own = tid < B * B;
+  float xc[3] = {0.f, 0.f, 0.f}, yc[3] = {0.f, 0.f, 0.f};
+  if (own) {
 #pragma unroll
-        for (int ch = 0; ch < 3; ++ch) {
-          const float x = s_buf[(1 + ch) * kIn + cell], y = s_buf[(4 + ch) * kIn + cell];
-          acc[j][1 + ch] += w * x;
-          acc[j][4 + ch] += w * y;
-          acc[j][7 + ch] += w * x * x;
-          acc[j][10 + ch] += w * y * y;
-          acc[j][13 + ch] += w * x * y;
+    for (int ch = 0; ch < 3; ++ch) {
+      xc[ch] = s.in[1 + ch][py + SS_R][px + SS_R];
+      yc[ch] = s.in[4 + ch][py + SS_R][px + SS_R];
+    }
+  }
+  float Sm[16];
+  if (!direct) {
+    // pass 1 along x: item (row r, channel ch, quarter k) slides the window
+    // over the 14 cells behind its 4 outputs
+    constexpr int Q = B / 4, NI1 = H * 3 * Q;
+    for (int it = tid; it < NI1; it += 256) {
+      const int r = it / (3 * Q), rem = it % (3 * Q), ch = rem / Q, c0 = 4 * (rem % Q);
+      float m[16], x[16], y[16];
+#pragma unroll
+      for (int j = 0; j < 16; j += 4) {
+        const float4 a = *reinterpret_cast<const float4*>(&s.in[0][r][c0 + j]);
+        const float4 bx = *reinterpret_cast<const float4*>(&s.in[1 + ch][r][c0 + j]);
+        const float4 by = *reinterpret_cast<const float4*>(&s.in[4 + ch][r][c0 + j]);
+        m[j] = a.x; m[j + 1] = a.y; m[j + 2] = a.z; m[j + 3] = a.w;
+        x[j] = bx.x; x[j + 1] = bx.y; x[j + 2] = bx.z; x[j + 3] = bx.w;
+        y[j] = by.x; y[j + 1] = by.y; y[j + 2] = by.z; y[j + 3] = by.w;
+      }
+      float o[6][4];
+#pragma unroll
+      for (int k = 0; k < 6; ++k)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) o[k][u] = 0.f;
+      if (full) {
+        // m = 1 everywhere: no mask products, no weight sums
+#pragma unroll
+        for (int j = 0; j < 14; ++j) {
+          const float q5[5] = {x[j], y[j], x[j] * x[j], y[j] * y[j], x[j] * y[j]};
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int a = j - u;
+            if (a >= 0 && a < SS_W) {
+#pragma unroll
+              for (int k = 0; k < 5; ++k) o[1 + k][u] = fmaf(A.g[a], q5[k], o[1 + k][u]);
+            }
+          }
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < 14; ++j) {
+          const float wx = m[j] * x[j], wy = m[j] * y[j];
+          const float q5[6] = {m[j], wx, wy, wx * x[j], wy * y[j], wx * y[j]};
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int a = j - u;
+            if (a >= 0 && a < SS_W) {
+#pragma unroll
+              for (int k = 0; k < 6; ++k) o[k][u] = fmaf(A.g[a], q5[k], o[k][u]);
+            }
+          }
+        }
+      }
+      // quantity index: 0 weight, 1+ch x, 4+ch y, 7+ch xx, 10+ch yy, 13+ch xy
+      if (ch == 0 && !full)
+        *reinterpret_cast<float4*>(&s.p1[0][r * B + c0]) = make_float4(o[0][0], o[0][1], o[0][2], o[0][3]);
+#pragma unroll
+      for (int k = 1; k < 6; ++k)
+        *reinterpret_cast<float4*>(&s.p1[1 + 3 * (k - 1) + ch][r * B + c0]) =
+            make_float4(o[k][0], o[k][1], o[k][2], o[k][3]);
+    }
+    __syncthreads();
+    // pass 2 along y: item (column c, quantity k, half hh) slides over the
+    // B/2 + 10 rows behind its B/2 outputs
+    constexpr int RO = B / 2, NI2 = B * 16 * 2;
+    for (int it = tid; it < NI2; it += 256) {
+      const int c = it % B, k = (it / B) % 16, hh = it / (16 * B);
+      if (full && k == 0) continue;
+      float w[RO + 2 * SS_R];
+#pragma unroll
+      for (int j = 0; j < RO + 2 * SS_R; ++j) w[j] = s.p1[k][(hh * RO + j) * B + c];
+#pragma unroll
+      for (int u = 0; u < RO; ++u) {
+        float acc = 0.f;
+#pragma unroll
+        for (int a = 0; a < SS_W; ++a) acc = fmaf(A.g[a], w[u + a], acc);
+        S[k][ss_nest_local(c, hh * RO + u)] = acc;   // nested order: read back by pixel tid
+      }
+    }
+    __syncthreads();
+    if (own) {
+#pragma unroll
+      for (int k = 0; k < 16; ++k) Sm[k] = S[k][tid];
+      if (full) Sm[0] = A.gsum * A.gsum;
+    }
+  } else if (ZONES) {
+    // direct 121-tap sums: polar pixels weigh by great-circle distance,
+    // equatorial ones (in a mixed tile) by the chart window
+#pragma unroll
+    for (int k = 0; k < 16; ++k) Sm[k] = 0.f;
+    if (own) {
+      const bool polar = ss_polar(A.order, hp_xyf_nest(A.order, x0 + px, y0 + py, f));
+      const double* up = s.dir[(py + SS_R) * H + px + SS_R];
+      for (int b = 0; b < SS_W; ++b) {
+        for (int a = 0; a < SS_W; ++a) {
+          const int cy = py + b, cx = px + a;
+          const float m = s.in[0][cy][cx];
+          if (m == 0.f) continue;
+          const float w = polar ? m * __expf(-(float)(ss_dist2(up, s.dir[cy * H + cx]) * A.wscale))
+                                : m * (A.g[a] * A.g[b]);
+          Sm[0] += w;
+#pragma unroll
+          for (int ch = 0; ch < 3; ++ch) {
+            const float x = s.in[1 + ch][cy][cx], y = s.in[4 + ch][cy][cx];
+            const float wx = w * x, wy = w * y;
+            Sm[1 + ch] += wx;
+            Sm[4 + ch] += wy;
+            Sm[7 + ch] = fmaf(wx, x, Sm[7 + ch]);
+            Sm[10 + ch] = fmaf(wy, y, Sm[10 + ch]);
+            Sm[13 + ch] = fmaf(wx, y, Sm[13 + ch]);
+          }
         }
       }
     }
   }
-  __syncthreads();
-#pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    const int pos = tid + 256 * j;
-    if (pos < B * H) {
-#pragma unroll
-      for (int k = 0; k < 16; ++k) s_buf[k * kH + pos] = acc[j][k];  // pos = row * B + ox
-    }
-  }
-  __syncthreads();
   float ssum = 0.f, lsum = 0.f;
-  if (tid < B * B) {
-    float S[16];
-#pragma unroll
-    for (int k = 0; k < 16; ++k) S[k] = 0.f;
-#pragma unroll 3
-    for (int bb = 0; bb < SS_W; ++bb) {
-      const int idx = (py + bb) * B + px;
-#pragma unroll
-      for (int k = 0; k < 16; ++k) S[k] += A.g[bb] * s_buf[k * kH + idx];
-    }
-    const int64_t slot = ss_slot(A, hp_xyf_nest(A.order, x0 + px, y0 + py, f));
+  int64_t slot = -1;
+  float gl[kSsG] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  if (own) {
+    slot = ss_slot(A, hp_xyf_nest(A.order, x0 + px, y0 + py, f));
     if (slot >= 0) {
-      const float iZ = 1.f / S[0];
+      const float iZ = __builtin_amdgcn_rcpf(Sm[0]);
 #pragma unroll
       for (int ch = 0; ch < 3; ++ch) {
-        const float mx = S[1 + ch] * iZ, my = S[4 + ch] * iZ;
-        const float vx = S[7 + ch] * iZ - mx * mx, vy = S[10 + ch] * iZ - my * my;
-        const float cxy = S[13 + ch] * iZ - mx * my;
-        const float An = 2.f * mx * my + A.C1, Bn = 2.f * cxy + A.C2;
-        const float Ad = mx * mx + my * my + A.C1, Bd = vx + vy + A.C2;
-        const float iden = 1.f / (Ad * Bd);
-        const float s = An * Bn * iden;
-        ssum += s;
+        const float sv = ss_index(A.C1, A.C2, iZ, Sm[1 + ch], Sm[4 + ch], Sm[7 + ch], Sm[10 + ch], Sm[13 + ch],
+                                  &gl[ch], &gl[3 + ch], &gl[6 + ch]);
+        ssum += sv;
         lsum += fabsf(xc[ch] - yc[ch]);
-        if (smap) smap[ch * A.n_active + slot] = s;
-        if (G) {
-          // s(sx, sxx, sxy) with the y sums fixed; sx = mx etc. (normalised)
-          const float ds_dmx = (2.f * my * Bn - An * 2.f * my) * iden - s * (2.f * mx / Ad - 2.f * mx / Bd);
-          const float ds_dvxx = -s / Bd;
-          const float ds_dcxy = 2.f * An * iden;
-          G[(0 * 3 + ch) * A.n_active + slot] = ds_dmx * iZ;
-          G[(1 * 3 + ch) * A.n_active + slot] = ds_dvxx * iZ;
-          G[(2 * 3 + ch) * A.n_active + slot] = ds_dcxy * iZ;
-        }
+        if (smap) smap[ch * A.n_active + slot] = sv;
       }
     }
   }
-  // block reduction of (ssum, lsum)
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) {
-    ssum += __shfl_xor(ssum, off, 64);
-    lsum += __shfl_xor(lsum, off, 64);
+  if (G) {
+    // the tile's partials leave as one contiguous run: its active pixels
+    // hold the slots [start, start + count) (staged in LDS over the first
+    // pass's place, once every thread is done reading it)
+    const int t = A.active_tiles[ct];
+    const int64_t start = A.tile_start[t];
+    const int cnt = A.tile_count[t];
+    float4* stage = reinterpret_cast<float4*>(&s.p1[0][0]);
+    __syncthreads();
+    if (slot >= 0) {
+      const int loc = (int)(slot - start);
+      stage[3 * loc] = make_float4(gl[0], gl[1], gl[2], gl[3]);
+      stage[3 * loc + 1] = make_float4(gl[4], gl[5], gl[6], gl[7]);
+      stage[3 * loc + 2] = make_float4(gl[8], 0.f, 0.f, 0.f);
+    }
+    __syncthreads();
+    float4* out = reinterpret_cast<float4*>(G + start * kSsG);
+    for (int i = tid; i < 3 * cnt; i += 256) out[i] = stage[i];
   }
-  if (hp_lane() == 0) { s_red[0][tid >> 6] = ssum; s_red[1][tid >> 6] = lsum; }
+  // block reduction of (ssum, lsum)
+  float red[2] = {ssum, lsum};
+  hp_wave_totals<2>(red);
+  if (hp_lane() == 0) { s_red[0][tid >> 6] = red[0]; s_red[1][tid >> 6] = red[1]; }
   __syncthreads();
   if (tid == 0)
     part[ct] = make_float2(s_red[0][0] + s_red[0][1] + s_red[0][2] + s_red[0][3],
@@ -228,79 +428,192 @@ __global__ __launch_bounds__(1024) void k_ssim_reduce(const float2* __restrict__
   }
 }
 
-// Backward: dL/dimg_p = dL/dloss * [ (1 - lam) sign(img - ref) / (3n)
-//   - lam / (3n) * sum_{q in W(p)} g(q - p) (G0_q + 2 x_p G1_q + y_p G2_q) ]
+// ---------------------------------------------------------------------------
+// backward
+// ---------------------------------------------------------------------------
+template <int B>
+struct SsBwdLds {
+  static constexpr int H = B + 2 * SS_R, HP = (H + 3) & ~3, P1S = H * B + ((48 - (H * B) % 32) % 32);
+  float in[9][H][HP];
+  union {
+    float p1[9][P1S];
+    double dir[H * H][3];
+  };
+  uint8_t polar[H * H];
+};
+
+// dL/dimg_p = dL/dloss * [ (1 - lam) sign(img - ref) / (3n)
+//   - lam / (3n) * sum_{q in W(p)} w_q(p) (G0_q + 2 x_p G1_q + y_p G2_q) ]
+// with w_q(p) the raw weight of q's window at p
+template <int B, bool ZONES>
 __global__ __launch_bounds__(256) void k_ssim_bwd(SsimArgs A, const float* __restrict__ img,
                                                   const float* __restrict__ ref, const float* __restrict__ G,
                                                   const float* __restrict__ dL_dloss, float* __restrict__ dimg) {
-  // the gathered patch [9][H*H] and the horizontal-pass output [9][B*H]
-  // share one buffer (pass-1 sums wait in registers across a barrier)
-  constexpr int kIn = SS_MAXH * SS_MAXH, kH = SS_MAXB * SS_MAXH;
-  __shared__ float s_buf[9 * kIn];
+  using L = SsBwdLds<B>;
+  constexpr int H = L::H;
+  __shared__ L s;
+  float(*S)[B * B] = reinterpret_cast<float(*)[B * B]>(&s.in[0][0][0]);  // after pass 1
   const int ct = hp_xcd_tile(blockIdx.x, gridDim.x), tid = threadIdx.x;
-  const int B = 1 << A.b, H = B + 2 * SS_R;
   int f, x0, y0;
   ss_tile_origin(A, ct, &f, &x0, &y0);
-  for (int i = tid; i < H * H; i += 256) {
-    const int cell = ss_cell(i, B, H);
-    const int cx = cell % H, cy = cell / H;
-    const int64_t slot = ss_slot(A, hp_chart_pixel(A.order, f, x0 + cx - SS_R, y0 + cy - SS_R));
+  bool any_polar = false;
+  constexpr int NG = (H * H + 255) / 256;
+  const int32_t* tab = A.tables + (int64_t)ct * (H * H);
+  int32_t e[NG];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) s_buf[k * kIn + cell] = slot >= 0 ? G[k * A.n_active + slot] : 0.f;
+  for (int gi = 0; gi < NG; ++gi) {
+    const int i = tid + 256 * gi;
+    e[gi] = i < H * H ? tab[i] : -1;
   }
-  __syncthreads();
-  float acc[2][9];
+  float v[NG][9];
 #pragma unroll
-  for (int j = 0; j < 2; ++j) {
+  for (int gi = 0; gi < NG; ++gi) {
+    const int64_t slot = e[gi] & kSsSlotMask;
+    float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = a, c = a;
+    if (e[gi] >= 0) {
+      const float4* gp = reinterpret_cast<const float4*>(G + slot * kSsG);
+      a = gp[0]; b = gp[1]; c = gp[2];
+    }
+    v[gi][0] = a.x; v[gi][1] = a.y; v[gi][2] = a.z; v[gi][3] = a.w;
+    v[gi][4] = b.x; v[gi][5] = b.y; v[gi][6] = b.z; v[gi][7] = b.w;
+    v[gi][8] = c.x;
+  }
 #pragma unroll
-    for (int k = 0; k < 9; ++k) acc[j][k] = 0.f;
-    const int pos = tid + 256 * j;
-    if (pos < B * H) {
-      const int ox = pos % B, row = pos / B;
+  for (int gi = 0; gi < NG; ++gi) {
+    const int i = tid + 256 * gi;
+    if (i < H * H) {
+      int cx, cy;
+      ss_cell<B>(i, &cx, &cy);
 #pragma unroll
-      for (int a = 0; a < SS_W; ++a) {
-        const int cell = row * H + ox + a;
-#pragma unroll
-        for (int k = 0; k < 9; ++k) acc[j][k] += A.g[a] * s_buf[k * kIn + cell];
+      for (int k = 0; k < 9; ++k) s.in[k][cy][cx] = v[gi][k];
+      if (ZONES) {
+        const bool pq = e[gi] >= 0 && (e[gi] & kSsPolarBit) != 0;
+        s.polar[cy * H + cx] = pq ? 1 : 0;
+        any_polar |= pq;
       }
     }
   }
-  __syncthreads();
+  // the separable pass needs every neighbour's window to be the chart one
+  const bool direct = ZONES && __syncthreads_or(any_polar);
+  if (!ZONES) __syncthreads();
+  const int px = (int)hp_compact_bits((uint32_t)tid), py = (int)hp_compact_bits((uint32_t)tid >> 1);
+  float Sm[9];
+  if (!direct) {
+    constexpr int Q = B / 4, NI1 = H * 9 * Q;
+    float o[4][4];  // up to 4 items per thread, 4 outputs each
+    int kk[4], rr[4], cc[4];
 #pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    const int pos = tid + 256 * j;
-    if (pos < B * H) {
+    for (int t = 0; t < 4; ++t) {
+      const int it = tid + 256 * t;
+      kk[t] = -1;
+      if (it < NI1) {
+        const int r = it / (9 * Q), rem = it % (9 * Q), k = rem / Q, c0 = 4 * (rem % Q);
+        float v[16];
 #pragma unroll
-      for (int k = 0; k < 9; ++k) s_buf[k * kH + pos] = acc[j][k];
+        for (int j = 0; j < 16; j += 4) {
+          const float4 a = *reinterpret_cast<const float4*>(&s.in[k][r][c0 + j]);
+          v[j] = a.x; v[j + 1] = a.y; v[j + 2] = a.z; v[j + 3] = a.w;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          float acc = 0.f;
+#pragma unroll
+          for (int a = 0; a < SS_W; ++a) acc = fmaf(A.g[a], v[u + a], acc);
+          o[t][u] = acc;
+        }
+        kk[t] = k; rr[t] = r; cc[t] = c0;
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+      if (kk[t] >= 0)
+        *reinterpret_cast<float4*>(&s.p1[kk[t]][rr[t] * B + cc[t]]) = make_float4(o[t][0], o[t][1], o[t][2], o[t][3]);
+    __syncthreads();
+    constexpr int RO = B / 2, NI2 = B * 9 * 2;
+    for (int it = tid; it < NI2; it += 256) {
+      const int c = it % B, k = (it / B) % 9, hh = it / (9 * B);
+      float w[RO + 2 * SS_R];
+#pragma unroll
+      for (int j = 0; j < RO + 2 * SS_R; ++j) w[j] = s.p1[k][(hh * RO + j) * B + c];
+#pragma unroll
+      for (int u = 0; u < RO; ++u) {
+        float acc = 0.f;
+#pragma unroll
+        for (int a = 0; a < SS_W; ++a) acc = fmaf(A.g[a], w[u + a], acc);
+        S[k][ss_nest_local(c, hh * RO + u)] = acc;
+      }
+    }
+    __syncthreads();
+    if (tid < B * B) {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) Sm[k] = S[k][tid];
+    }
+  } else if (ZONES) {
+    // directions of the patch cells (over the first pass's place)
+    for (int i = tid; i < H * H; i += 256) {
+      const int cx = i % H, cy = i / H;
+      const int64_t q = hp_chart_pixel(A.order, f, x0 + cx - SS_R, y0 + cy - SS_R);
+      double d[3] = {0.0, 0.0, 0.0};
+      if (q >= 0) hp_pix_dir(A.order, q, d);
+      s.dir[i][0] = d[0];
+      s.dir[i][1] = d[1];
+      s.dir[i][2] = d[2];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 9; ++k) Sm[k] = 0.f;
+    if (tid < B * B) {
+      const double* up = s.dir[(py + SS_R) * H + px + SS_R];
+      for (int b = 0; b < SS_W; ++b) {
+        for (int a = 0; a < SS_W; ++a) {
+          const int cy = py + b, cx = px + a;
+          // q's own window at p: the great-circle Gaussian for a polar q,
+          // the (symmetric) chart taps otherwise
+          const float w = s.polar[cy * H + cx] ? __expf(-(float)(ss_dist2(up, s.dir[cy * H + cx]) * A.wscale))
+                                               : A.g[a] * A.g[b];
+#pragma unroll
+          for (int k = 0; k < 9; ++k) Sm[k] = fmaf(w, s.in[k][cy][cx], Sm[k]);
+        }
+      }
     }
   }
-  __syncthreads();
   if (tid >= B * B) return;
-  const int px = tid % B, py = tid / B;
   const int64_t slot = ss_slot(A, hp_xyf_nest(A.order, x0 + px, y0 + py, f));
   if (slot < 0) return;
-  float S[9];
-#pragma unroll
-  for (int k = 0; k < 9; ++k) S[k] = 0.f;
-#pragma unroll
-  for (int bb = 0; bb < SS_W; ++bb) {
-    const int idx = (py + bb) * B + px;
-#pragma unroll
-    for (int k = 0; k < 9; ++k) S[k] += A.g[bb] * s_buf[k * kH + idx];
-  }
   const float up = *dL_dloss;
   const float inv3n = 1.f / (3.f * (float)A.n_active);
 #pragma unroll
   for (int ch = 0; ch < 3; ++ch) {
     const float x = img[ch * A.n_active + slot], y = ref[ch * A.n_active + slot];
-    const float dssim = S[0 * 3 + ch] + 2.f * x * S[1 * 3 + ch] + y * S[2 * 3 + ch];
+    const float dssim = Sm[0 * 3 + ch] + 2.f * x * Sm[1 * 3 + ch] + y * Sm[2 * 3 + ch];
     const float sgn = (float)((x > y) - (x < y));
     dimg[ch * A.n_active + slot] = up * inv3n * ((1.f - A.lam) * sgn - A.lam * dssim);
   }
 }
 
+// Patch tables: for every active tile and patch cell (in gather order), the
+// compact slot of the chart neighbour (-1: missing or inactive), with bit 30
+// set when that neighbour lies in a polar cap.  Image independent: built once
+// per mask and reused by every forward and backward.
+template <int B>
+__global__ __launch_bounds__(256) void k_ssim_tables(SsimArgs A, int32_t* __restrict__ tables) {
+  constexpr int H = B + 2 * SS_R;
+  const int ct = blockIdx.x;
+  int f, x0, y0;
+  ss_tile_origin(A, ct, &f, &x0, &y0);
+  for (int i = threadIdx.x; i < H * H; i += 256) {
+    int cx, cy;
+    ss_cell<B>(i, &cx, &cy);
+    const int64_t q = hp_chart_pixel(A.order, f, x0 + cx - SS_R, y0 + cy - SS_R);
+    const int64_t slot = ss_slot(A, q);
+    tables[(int64_t)ct * H * H + i] = slot < 0 ? -1 : ((int32_t)slot | (ss_polar(A.order, q) ? kSsPolarBit : 0));
+  }
+}
+
+static int ss_patch(int b) { const int H = (1 << b) + 2 * SS_R; return H * H; }
+
 static size_t ssim_ws_size(int64_t n_active, int64_t ntile) {
-  return hp_align256((size_t)9 * n_active * 4) + hp_align256((size_t)ntile * sizeof(float2));
+  return hp_align256((size_t)kSsG * n_active * 4) + hp_align256((size_t)ntile * sizeof(float2));
 }
 
 extern "C" size_t hp_ssim_workspace_bytes(int32_t order, int32_t tile_log2, int64_t n_active) {
@@ -308,84 +621,146 @@ extern "C" size_t hp_ssim_workspace_bytes(int32_t order, int32_t tile_log2, int6
   return ssim_ws_size(n_active, hp_geom(order, tile_log2).ntile);
 }
 
-// shared argument checks and set-up of the three entry points
-static hp_status ssim_setup(const float* img, const float* ref, int64_t n_active, int32_t n_tiles, int32_t order,
-                            const hp_params* prm, const hp_ssim_params* sp, const void* mask, const void* ws,
-                            size_t ws_bytes, SsimArgs* A, float** Gm, float2** part) {
+extern "C" size_t hp_ssim_tables_bytes(int32_t order, int32_t tile_log2, int32_t n_tiles) {
+  if (order < 0 || order > HP_MAX_ORDER || tile_log2 < 0 || tile_log2 > 4 || n_tiles < 0) return 0;
+  return hp_align256((size_t)n_tiles * ss_patch(hp_geom(order, tile_log2).b) * 4);
+}
+
+static hp_status ssim_mask_args(int32_t order, const hp_params* prm, const void* mask, int64_t n_active,
+                                int32_t n_tiles, SsimArgs* A) {
   HP_TRY(hp_check_params(prm));
-  if (!sp || !mask || !ws) return HP_ERR_INVALID_ARG;
+  if (!mask) return HP_ERR_INVALID_ARG;
   if (order < 3 || order > HP_MAX_ORDER) return order < 0 || order > HP_MAX_ORDER ? HP_ERR_INVALID_ARG : HP_ERR_UNSUPPORTED;
-  if (n_active <= 0 || n_tiles <= 0 || !img || !ref) return HP_ERR_INVALID_ARG;
-  if (!(sp->sigma > 0) || !(sp->C1 > 0) || !(sp->C2 > 0) || !(sp->lambda >= 0 && sp->lambda <= 1))
-    return HP_ERR_INVALID_ARG;
   const HpGeom g = hp_geom(order, prm->tile_log2);
-  if (n_tiles > g.ntile || n_active > g.npix) return HP_ERR_INVALID_ARG;
-  if (ws_bytes < ssim_ws_size(n_active, g.ntile)) return HP_ERR_CAPACITY;
+  // the patch layout holds tiles of 8 or 16 pixels a side
+  if (g.b != 3 && g.b != 4) return HP_ERR_UNSUPPORTED;
+  if (n_tiles <= 0 || n_tiles > g.ntile || n_active <= 0 || n_active > g.npix) return HP_ERR_INVALID_ARG;
   const HpMaskView mv = hp_mask_view((const char*)mask, g);
   A->order = order; A->b = g.b; A->kt = g.kt;
   A->active_tiles = mv.active_tiles; A->tile_start = mv.tile_start; A->tile_count = mv.tile_count;
   A->tile_bits = mv.tile_bits; A->n_active = n_active;
-  A->C1 = sp->C1; A->C2 = sp->C2; A->lam = sp->lambda;
-  for (int a = 0; a < SS_W; ++a) {
-    const double d = a - SS_R;
-    A->g[a] = (float)exp(-d * d / (2.0 * (double)sp->sigma * (double)sp->sigma));
-  }
-  *Gm = (float*)ws;
-  *part = (float2*)((char*)ws + hp_align256((size_t)9 * n_active * 4));
   return HP_OK;
 }
 
-static hp_status ssim_fwd_launch(const SsimArgs& A, const float* img, const float* ref, int32_t n_tiles, float lam,
-                                 float* out, float* ssim_map, float* Gm, float2* part, hipStream_t s) {
-  hipLaunchKernelGGL(k_ssim_fwd, dim3((unsigned)n_tiles), dim3(256), 0, s, A, img, ref, ssim_map, Gm, part);
+extern "C" hp_status hp_ssim_tables(const hp_params* prm, const void* mask, int32_t order, int64_t n_active,
+                                    int32_t n_tiles, int32_t* tables, size_t tables_bytes, void* stream) {
+  SsimArgs A;
+  HP_TRY(ssim_mask_args(order, prm, mask, n_active, n_tiles, &A));
+  if (!tables) return HP_ERR_INVALID_ARG;
+  if (tables_bytes < hp_ssim_tables_bytes(order, prm->tile_log2, n_tiles)) return HP_ERR_CAPACITY;
+  hipStream_t s = (hipStream_t)stream;
+  if (A.b == 4)
+    hipLaunchKernelGGL(k_ssim_tables<16>, dim3((unsigned)n_tiles), dim3(256), 0, s, A, tables);
+  else
+    hipLaunchKernelGGL(k_ssim_tables<8>, dim3((unsigned)n_tiles), dim3(256), 0, s, A, tables);
   HP_CHECK_LAUNCH();
+  return HP_OK;
+}
+
+// shared argument checks and set-up of the three entry points
+static hp_status ssim_setup(const float* img, const float* ref, int64_t n_active, int32_t n_tiles, int32_t order,
+                            const hp_params* prm, const hp_ssim_params* sp, const void* mask, const int32_t* tables,
+                            const void* ws, size_t ws_bytes, SsimArgs* A, float** Gm, float2** part) {
+  HP_TRY(ssim_mask_args(order, prm, mask, n_active, n_tiles, A));
+  if (!sp || !ws || !tables || !img || !ref) return HP_ERR_INVALID_ARG;
+  if (!(sp->sigma > 0) || !(sp->C1 > 0) || !(sp->C2 > 0) || !(sp->lambda >= 0 && sp->lambda <= 1) ||
+      (sp->zones != 0 && sp->zones != 1))
+    return HP_ERR_INVALID_ARG;
+  const HpGeom g = hp_geom(order, prm->tile_log2);
+  if (ws_bytes < ssim_ws_size(n_active, g.ntile)) return HP_ERR_CAPACITY;
+  A->tables = tables;
+  A->C1 = sp->C1; A->C2 = sp->C2; A->lam = sp->lambda;
+  A->gsum = 0.f;
+  for (int a = 0; a < SS_W; ++a) {
+    const double d = a - SS_R;
+    A->g[a] = (float)exp(-d * d / (2.0 * (double)sp->sigma * (double)sp->sigma));
+    A->gsum += A->g[a];
+  }
+  const double omega = 4.0 * M_PI / (double)g.npix;
+  A->wscale = 1.0 / (2.0 * (double)sp->sigma * (double)sp->sigma * omega);
+  *Gm = (float*)ws;
+  *part = (float2*)((char*)ws + hp_align256((size_t)kSsG * n_active * 4));
+  return HP_OK;
+}
+
+template <int B>
+static hp_status ssim_fwd_launch_b(const SsimArgs& A, bool zones, const float* img, const float* ref,
+                                   int32_t n_tiles, float* ssim_map, float* Gm, float2* part, hipStream_t s) {
+  if (zones)
+    hipLaunchKernelGGL((k_ssim_fwd<B, true>), dim3((unsigned)n_tiles), dim3(256), 0, s, A, img, ref, ssim_map, Gm, part);
+  else
+    hipLaunchKernelGGL((k_ssim_fwd<B, false>), dim3((unsigned)n_tiles), dim3(256), 0, s, A, img, ref, ssim_map, Gm,
+                       part);
+  HP_CHECK_LAUNCH();
+  return HP_OK;
+}
+
+static hp_status ssim_fwd_launch(const SsimArgs& A, bool zones, const float* img, const float* ref, int32_t n_tiles,
+                                 float lam, float* out, float* ssim_map, float* Gm, float2* part, hipStream_t s) {
+  if (A.b == 4) HP_TRY(ssim_fwd_launch_b<16>(A, zones, img, ref, n_tiles, ssim_map, Gm, part, s));
+  else HP_TRY(ssim_fwd_launch_b<8>(A, zones, img, ref, n_tiles, ssim_map, Gm, part, s));
   hipLaunchKernelGGL(k_ssim_reduce, dim3(1), dim3(1024), 0, s, (const float2*)part, (int)n_tiles, A.n_active, lam, out);
   HP_CHECK_LAUNCH();
   return HP_OK;
 }
 
+template <int B>
+static hp_status ssim_bwd_launch_b(const SsimArgs& A, bool zones, const float* img, const float* ref,
+                                   int32_t n_tiles, const float* Gm, const float* dL_dloss, float* dL_dimg,
+                                   hipStream_t s) {
+  if (zones)
+    hipLaunchKernelGGL((k_ssim_bwd<B, true>), dim3((unsigned)n_tiles), dim3(256), 0, s, A, img, ref, Gm, dL_dloss,
+                       dL_dimg);
+  else
+    hipLaunchKernelGGL((k_ssim_bwd<B, false>), dim3((unsigned)n_tiles), dim3(256), 0, s, A, img, ref, Gm, dL_dloss,
+                       dL_dimg);
+  HP_CHECK_LAUNCH();
+  return HP_OK;
+}
+
+static hp_status ssim_bwd_launch(const SsimArgs& A, bool zones, const float* img, const float* ref, int32_t n_tiles,
+                                 const float* Gm, const float* dL_dloss, float* dL_dimg, hipStream_t s) {
+  if (A.b == 4) return ssim_bwd_launch_b<16>(A, zones, img, ref, n_tiles, Gm, dL_dloss, dL_dimg, s);
+  return ssim_bwd_launch_b<8>(A, zones, img, ref, n_tiles, Gm, dL_dloss, dL_dimg, s);
+}
+
 extern "C" hp_status hp_ssim(const float* img, const float* ref, int64_t n_active, int32_t n_tiles, int32_t order,
-                             const hp_params* prm, const hp_ssim_params* sp, const void* mask, float* out,
-                             float* ssim_map, const float* dL_dloss, float* dL_dimg, void* ws, size_t ws_bytes,
-                             void* stream) {
+                             const hp_params* prm, const hp_ssim_params* sp, const void* mask, const int32_t* tables,
+                             float* out, float* ssim_map, const float* dL_dloss, float* dL_dimg, void* ws,
+                             size_t ws_bytes, void* stream) {
   SsimArgs A;
   float* Gm;
   float2* part;
-  HP_TRY(ssim_setup(img, ref, n_active, n_tiles, order, prm, sp, mask, ws, ws_bytes, &A, &Gm, &part));
+  HP_TRY(ssim_setup(img, ref, n_active, n_tiles, order, prm, sp, mask, tables, ws, ws_bytes, &A, &Gm, &part));
   if (!out || (dL_dloss && !dL_dimg)) return HP_ERR_INVALID_ARG;
   hipStream_t s = (hipStream_t)stream;
-  HP_TRY(ssim_fwd_launch(A, img, ref, n_tiles, sp->lambda, out, ssim_map, dL_dloss ? Gm : nullptr, part, s));
-  if (dL_dloss) {
-    hipLaunchKernelGGL(k_ssim_bwd, dim3((unsigned)n_tiles), dim3(256), 0, s, A, img, ref, (const float*)Gm, dL_dloss,
-                       dL_dimg);
-    HP_CHECK_LAUNCH();
-  }
+  const bool zones = sp->zones != 0;
+  HP_TRY(ssim_fwd_launch(A, zones, img, ref, n_tiles, sp->lambda, out, ssim_map, dL_dloss ? Gm : nullptr, part, s));
+  if (dL_dloss) HP_TRY(ssim_bwd_launch(A, zones, img, ref, n_tiles, Gm, dL_dloss, dL_dimg, s));
   return HP_OK;
 }
 
 extern "C" hp_status hp_ssim_forward_saved(const float* img, const float* ref, int64_t n_active, int32_t n_tiles,
                                            int32_t order, const hp_params* prm, const hp_ssim_params* sp,
-                                           const void* mask, float* out, float* ssim_map, void* ws, size_t ws_bytes,
-                                           void* stream) {
+                                           const void* mask, const int32_t* tables, float* out, float* ssim_map,
+                                           void* ws, size_t ws_bytes, void* stream) {
   SsimArgs A;
   float* Gm;
   float2* part;
-  HP_TRY(ssim_setup(img, ref, n_active, n_tiles, order, prm, sp, mask, ws, ws_bytes, &A, &Gm, &part));
+  HP_TRY(ssim_setup(img, ref, n_active, n_tiles, order, prm, sp, mask, tables, ws, ws_bytes, &A, &Gm, &part));
   if (!out) return HP_ERR_INVALID_ARG;
-  return ssim_fwd_launch(A, img, ref, n_tiles, sp->lambda, out, ssim_map, Gm, part, (hipStream_t)stream);
+  return ssim_fwd_launch(A, sp->zones != 0, img, ref, n_tiles, sp->lambda, out, ssim_map, Gm, part,
+                         (hipStream_t)stream);
 }
 
 extern "C" hp_status hp_ssim_backward_saved(const float* img, const float* ref, int64_t n_active, int32_t n_tiles,
                                             int32_t order, const hp_params* prm, const hp_ssim_params* sp,
-                                            const void* mask, const void* ws, size_t ws_bytes,
+                                            const void* mask, const int32_t* tables, const void* ws, size_t ws_bytes,
                                             const float* dL_dloss, float* dL_dimg, void* stream) {
   SsimArgs A;
   float* Gm;
   float2* part;
-  HP_TRY(ssim_setup(img, ref, n_active, n_tiles, order, prm, sp, mask, ws, ws_bytes, &A, &Gm, &part));
+  HP_TRY(ssim_setup(img, ref, n_active, n_tiles, order, prm, sp, mask, tables, ws, ws_bytes, &A, &Gm, &part));
   if (!dL_dloss || !dL_dimg) return HP_ERR_INVALID_ARG;
-  hipLaunchKernelGGL(k_ssim_bwd, dim3((unsigned)n_tiles), dim3(256), 0, (hipStream_t)stream, A, img, ref,
-                     (const float*)Gm, dL_dloss, dL_dimg);
-  HP_CHECK_LAUNCH();
-  return HP_OK;
+  return ssim_bwd_launch(A, sp->zones != 0, img, ref, n_tiles, Gm, dL_dloss, dL_dimg, (hipStream_t)stream);
 }

@@ -234,6 +234,8 @@ class Rasterizer:
         # one binning workspace per stream (work on a stream is ordered, so
         # the next binning there may reuse it)
         self._ws = {}
+        # HSSIM patch tables per camera model (hp_ssim_tables)
+        self._ssim_tables = {}
 
     def side_streams(self, n: int) -> list:
         """The first n streams of prefetch() (default priority), created once."""
@@ -596,6 +598,23 @@ class Rasterizer:
         return (out, valid) if want_valid else out
 
     # ---- loss ----------------------------------------------------------------
+    def ssim_tables(self, cam: Camera) -> torch.Tensor:
+        """HSSIM patch tables of the camera model (built once, cached)."""
+        with self._lock:
+            key = cam.mask_key(self.prm.tile_log2)
+            t = self._ssim_tables.get(key)
+            if t is None:
+                m = self._mask(cam)
+                n = A.lib().hp_ssim_tables_bytes(cam.order, self.prm.tile_log2, m.n_tiles)
+                t = _bytes(n, self.device)
+                A.call("hp_ssim_tables", C.byref(self.prm), _p(m.buf), cam.order, m.n_active, m.n_tiles, _p(t), n,
+                       _stream())
+                self._ssim_tables[key] = t
+                self._created(("ssim_tables",) + key)
+            else:
+                self._await(("ssim_tables",) + key)
+            return t
+
     def ssim_loss(self, img, ref, cam: Camera, sp: A.hp_ssim_params | None = None, dL_dloss=None, want_map=False):
         """Returns (out[3] = (mean SSIM, L1, loss), ssim_map or None, dL/dimg or None)."""
         img, ref = _dense(img), _dense(ref)
@@ -606,9 +625,10 @@ class Rasterizer:
         dimg = torch.empty_like(img) if dL_dloss is not None else None
         ws_n = A.lib().hp_ssim_workspace_bytes(cam.order, self.prm.tile_log2, m.n_active)
         ws = _bytes(ws_n, self.device)
+        tab = self.ssim_tables(cam)
         A.call("hp_ssim", _p(img), _p(ref), m.n_active, m.n_tiles, cam.order,
-               C.byref(self.prm), C.byref(sp), _p(m.buf), _p(out), _p(smap), _p(dL_dloss), _p(dimg), _p(ws), ws_n,
-               _stream())
+               C.byref(self.prm), C.byref(sp), _p(m.buf), _p(tab), _p(out), _p(smap), _p(dL_dloss), _p(dimg), _p(ws),
+               ws_n, _stream())
         return out, smap, dimg
 
     def ssim_forward_saved(self, img, ref, cam: Camera, sp: A.hp_ssim_params | None = None, want_map=False):
@@ -622,7 +642,7 @@ class Rasterizer:
         ws_n = A.lib().hp_ssim_workspace_bytes(cam.order, self.prm.tile_log2, m.n_active)
         ws = _bytes(ws_n, self.device)
         A.call("hp_ssim_forward_saved", _p(img), _p(ref), m.n_active, m.n_tiles, cam.order, C.byref(self.prm),
-               C.byref(sp), _p(m.buf), _p(out), _p(smap), _p(ws), ws_n, _stream())
+               C.byref(sp), _p(m.buf), _p(self.ssim_tables(cam)), _p(out), _p(smap), _p(ws), ws_n, _stream())
         return out, smap, ws
 
     def ssim_backward_saved(self, img, ref, cam: Camera, sp: A.hp_ssim_params, ws, dL_dloss):
@@ -631,5 +651,6 @@ class Rasterizer:
         m = self.mask(cam)
         dimg = torch.empty_like(img)
         A.call("hp_ssim_backward_saved", _p(img), _p(ref), m.n_active, m.n_tiles, cam.order, C.byref(self.prm),
-               C.byref(sp), _p(m.buf), _p(ws), ws.numel(), _p(dL_dloss), _p(dimg), _stream())
+               C.byref(sp), _p(m.buf), _p(self.ssim_tables(cam)), _p(ws), ws.numel(), _p(dL_dloss), _p(dimg),
+               _stream())
         return dimg

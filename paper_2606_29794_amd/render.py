@@ -102,8 +102,8 @@ def render(mean, scale, rot, opacity, sh, camera: Camera, rasterizer: Rasterizer
 
 class _HSSIMLoss(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, img, ref, rasterizer, camera, lam):
-        sp = A.default_ssim_params(lam=float(lam))
+    def forward(ctx, img, ref, rasterizer, camera, lam, zones):
+        sp = A.default_ssim_params(lam=float(lam), zones=int(bool(zones)))
         img_d, ref_d = img.detach().contiguous(), ref.detach().contiguous()
         if ctx.needs_input_grad[0]:
             # keep the backward's per-pixel partials: the backward is then one gather pass
@@ -126,11 +126,14 @@ class _HSSIMLoss(torch.autograd.Function):
             ctx.ws = None
         else:
             _, _, dimg = ctx.R.ssim_loss(img, ref, ctx.cam, ctx.sp, dL_dloss=up)
-        return dimg, None, None, None, None
+        return dimg, None, None, None, None, None
 
 
-def hssim_loss(img, ref, camera: Camera, lam: float = 0.2, rasterizer: Rasterizer | None = None):
+def hssim_loss(img, ref, camera: Camera, lam: float = 0.2, rasterizer: Rasterizer | None = None,
+               zones: bool = False):
     """L = (1 - lam) mean|img - ref| + lam (1 - mean HSSIM); img, ref [3, n_active].
-    Returns (L, stats) with stats = (mean HSSIM, L1, L) (no gradient)."""
+    Returns (L, stats) with stats = (mean HSSIM, L1, L) (no gradient).
+    zones: the zone-specific windows of Sec. 4.1 (isotropic chart window in
+    the equatorial belt, great-circle Gaussian in the polar caps)."""
     R = rasterizer or default_rasterizer(img.device)
-    return _HSSIMLoss.apply(img, ref, R, camera, lam)
+    return _HSSIMLoss.apply(img, ref, R, camera, lam, zones)

@@ -124,8 +124,8 @@ def _loss_case(R, name):
     return camd, img, ref
 
 
-@pytest.mark.parametrize("name", ["cfg1", "order9_full"])
-def test_hssim_loss_full_size(R, name):
+@pytest.mark.parametrize("name,zones", [("cfg1", False), ("order9_full", False), ("order9_full", True)])
+def test_hssim_loss_full_size(R, name, zones):
     """hp_ssim (mean SSIM, L1, loss, per-pixel map and dL/dimg) against the
     oracle on whole images at the workloads' sizes: 393K active pixels of the
     config-1 fisheye at Nside 256, and 3.1M pixels of the full sphere at Nside
@@ -134,14 +134,16 @@ def test_hssim_loss_full_size(R, name):
     from paper_2606_29794_amd.raster import Camera
     camd, img, ref = _loss_case(R, name)
     cam = Camera.from_dict(camd)
+    from paper_2606_29794_amd import _abi as A
     up = torch.tensor([1.3], dtype=torch.float32, device="cuda")
-    out, smap, dimg = R.ssim_loss(img, ref, cam, dL_dloss=up, want_map=True)
+    out, smap, dimg = R.ssim_loss(img, ref, cam, sp=A.default_ssim_params(zones=int(zones)), dL_dloss=up,
+                                  want_map=True)
     torch.cuda.synchronize()
     act = O.mask(camd)
     im = img.cpu().numpy().astype(np.float64)
     rf = ref.cpu().numpy().astype(np.float64)
-    s_o, map_o, _ = O.hssim(camd["order"], act, im, rf, want_map=True)
-    L_o, gL_o = O.loss(camd["order"], act, im, rf, want_grad=True)
+    s_o, map_o, _ = O.hssim(camd["order"], act, im, rf, want_map=True, zones=zones)
+    L_o, gL_o = O.loss(camd["order"], act, im, rf, want_grad=True, zones=zones)
     out = out.cpu().numpy()
     assert abs(out[0] - s_o) < 1e-5 and abs(out[2] - L_o) < 1e-5, (out, s_o, L_o)
     assert abs(out[1] - np.mean(np.abs(im - rf))) < 1e-5

@@ -152,8 +152,12 @@ def test_render_backward_matches_oracle(R, case):
         print(case, k, "rel err", e)
 
 
-@pytest.mark.parametrize("order,masked", [(3, False), (4, False), (5, True), (6, True)])
-def test_hssim_and_loss(R, order, masked):
+@pytest.mark.parametrize("zones", [False, True])
+@pytest.mark.parametrize("order,masked", [(3, False), (4, False), (5, True), (6, True), (3, True), (7, False)])
+def test_hssim_and_loss(R, order, masked, zones):
+    """hp_ssim (mean, L1, loss, map, dL/dimg) and its split entry points
+    against the oracle, with the isotropic chart window and with the
+    zone-specific windows (polar caps weighted by great-circle distance)."""
     import torch
     from paper_2606_29794_amd.raster import Camera
     rng = np.random.default_rng(order)
@@ -167,10 +171,11 @@ def test_hssim_and_loss(R, order, masked):
     ref = (0.6 * img + 0.4 * rng.random((3, act.size))).astype(np.float32)
     ti = torch.as_tensor(img, device="cuda"); tr_ = torch.as_tensor(ref, device="cuda")
     up = torch.tensor([1.7], dtype=torch.float32, device="cuda")
-    out, smap, dimg = R.ssim_loss(ti, tr_, Camera.from_dict(cam), dL_dloss=up, want_map=True)
+    sp = A_default_ssim(zones=int(zones))
+    out, smap, dimg = R.ssim_loss(ti, tr_, Camera.from_dict(cam), sp=sp, dL_dloss=up, want_map=True)
     torch.cuda.synchronize()
-    s_o, map_o, g_o = O.hssim(order, act, img, ref, want_map=True, want_grad=True)
-    L_o, gL_o = O.loss(order, act, img, ref, want_grad=True)
+    s_o, map_o, g_o = O.hssim(order, act, img, ref, want_map=True, want_grad=True, zones=zones)
+    L_o, gL_o = O.loss(order, act, img, ref, want_grad=True, zones=zones)
     out = out.cpu().numpy()
     assert abs(out[0] - s_o) < 2e-6 and abs(out[2] - L_o) < 2e-6
     assert abs(out[1] - np.mean(np.abs(img.astype(np.float64) - ref))) < 1e-6
@@ -178,13 +183,13 @@ def test_hssim_and_loss(R, order, masked):
     PT.grad_compare("hssim-loss grad", dimg.cpu().numpy(), 1.7 * gL_o)
     # the split entry points (partials kept between forward and backward)
     # run the same kernels: identical results
-    out2, smap2, ws = R.ssim_forward_saved(ti, tr_, Camera.from_dict(cam), want_map=True)
-    dimg2 = R.ssim_backward_saved(ti, tr_, Camera.from_dict(cam), A_default_ssim(), ws, up)
+    out2, smap2, ws = R.ssim_forward_saved(ti, tr_, Camera.from_dict(cam), sp=sp, want_map=True)
+    dimg2 = R.ssim_backward_saved(ti, tr_, Camera.from_dict(cam), sp, ws, up)
     torch.cuda.synchronize()
     assert np.array_equal(out2.cpu().numpy(), out)
     assert torch.equal(smap2, smap) and torch.equal(dimg2, dimg)
 
 
-def A_default_ssim():
+def A_default_ssim(**kw):
     from paper_2606_29794_amd import _abi as A
-    return A.default_ssim_params()
+    return A.default_ssim_params(**kw)
