@@ -304,6 +304,42 @@ typedef struct {
 } hp_render_req;
 hp_status hp_render_fwd_batch(int32_t n_req, const hp_render_req* reqs, const hp_params* prm, void* stream);
 
+/* Persistent form of the serving render: a device queue of (request, tile)
+ * items that one long-running launch drains while the requests' preparation
+ * (preprocess, binning) still runs on another stream.
+ *  hp_render_queue_bytes: size of a queue holding max_items items (and the
+ *    arguments of up to 16 requests); the buffer is device memory owned by
+ *    the caller.
+ *  hp_render_queue_reset: empties the queue (a kernel; no host wait).
+ *  hp_render_queue_push: queues a kernel that stores request `slot`'s
+ *    arguments (0 <= slot < 16, distinct within one batch), appends one item
+ *    per active tile of it and publishes them; with last != 0 it also closes
+ *    the queue (no further pushes until the next reset).  Queue it on the
+ *    stream of the request's binning, after it.  Items beyond the queue's
+ *    capacity are not appended and set an overflow flag.
+ *  hp_render_fwd_persistent: the consumer, n_blocks workgroups that claim
+ *    published items, render each tile as hp_render_fwd does and count it
+ *    in its request's done counter; a workgroup leaves when the queue is
+ *    closed and drained, or after spin_limit empty polls.  DISABLED: it
+ *    checks its arguments and returns HP_ERR_UNSUPPORTED without launching
+ *    anything.  Launches of this consumer did not complete on MI355X (the
+ *    host wait after them never returned, with every item already
+ *    published before the launch), and no defect that explains it has been
+ *    found in the code; until one is, the kernel is built but not run.
+ *    Callers render a batch with hp_render_fwd_batch instead.
+ *  hp_render_queue_status: waits for `stream` and reads the done counters of
+ *    the first n_req requests and the overflow flag; a request whose count
+ *    is below its tile count was not finished (the launch ran out of polls
+ *    before its items appeared) and must be rendered again. */
+size_t hp_render_queue_bytes(int64_t max_items);
+hp_status hp_render_queue_reset(void* queue, size_t queue_bytes, void* stream);
+hp_status hp_render_queue_push(void* queue, size_t queue_bytes, int32_t slot, const hp_render_req* req,
+                               const hp_params* prm, int32_t last, void* stream);
+hp_status hp_render_fwd_persistent(void* queue, size_t queue_bytes, int32_t n_blocks, int32_t spin_limit,
+                                   void* stream);
+hp_status hp_render_queue_status(const void* queue, int32_t n_req, int32_t* done_tiles, int32_t* overflow,
+                                 void* stream);
+
 /* ---- backward (Sec. 3.2 Eqs. backward_lat_scale, grad_via_J_S) ------------
  * Reverse traversal per pixel from n_contrib with T recomputed as
  * T_j = T_{j+1} / (1 - alpha_j) (no per-Gaussian forward state), gradients

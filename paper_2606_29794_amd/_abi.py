@@ -71,6 +71,11 @@ _PROTOS = {
     "hp_preprocess_batch": (I32, [C.POINTER(hp_gaussians), I32, C.POINTER(hp_view), C.POINTER(hp_params),
                                   C.POINTER(P_), SZ, P_]),
     "hp_render_fwd_batch": (I32, [I32, C.POINTER(hp_render_req), C.POINTER(hp_params), P_]),
+    "hp_render_queue_bytes": (SZ, [I64]),
+    "hp_render_queue_reset": (I32, [P_, SZ, P_]),
+    "hp_render_queue_push": (I32, [P_, SZ, I32, C.POINTER(hp_render_req), C.POINTER(hp_params), I32, P_]),
+    "hp_render_fwd_persistent": (I32, [P_, SZ, I32, I32, P_]),
+    "hp_render_queue_status": (I32, [P_, I32, C.POINTER(I32), C.POINTER(I32), P_]),
     "hp_projected_radius": (P_, [P_, I64]),
     "hp_bin_workspace_bytes": (SZ, [I64]),
     "hp_bin": (I32, [I32, P_, I64, C.POINTER(hp_view), C.POINTER(hp_params), P_, P_, P_, P_, I64, P_, P_, SZ, P_]),

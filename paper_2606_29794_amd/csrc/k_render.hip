@@ -525,6 +525,191 @@ extern "C" hp_status hp_render_fwd_batch(int32_t n_req, const hp_render_req* req
   return HP_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Persistent serving render: a device queue of (request, tile) items that a
+// long-running launch would drain while the requests' preparation
+// (preprocess, binning) is still running on another stream.  Each request's
+// push kernel (queued after its binning) stores the request's arguments,
+// appends one item per active tile and publishes them by moving the tail; the
+// last push of a batch also closes the queue.  The consumer's blocks take
+// tickets from the head, wait for the ticket's item, render the tile and
+// count it in the request's done counter; a request whose done count falls
+// short of its tiles is rendered again by the caller.  The consumer launch is
+// switched off (hp_render_fwd_persistent returns HP_ERR_UNSUPPORTED): its
+// launches did not end on the hardware and the cause is not known.
+// ---------------------------------------------------------------------------
+// the counters that every block touches sit in cache lines of their own
+struct QueueHead {
+  uint32_t head, pad0[31];
+  uint32_t tail, pad1[31];
+  uint32_t closed, overflow, pad2[30];
+  uint32_t done[HP_MAX_BATCH];
+  uint32_t ntiles[HP_MAX_BATCH];
+};
+struct QueueReq {
+  RenderArgs A;
+  RenderOut O;
+};
+struct QueueView {
+  QueueHead* h;
+  QueueReq* reqs;
+  uint32_t* items;
+  int64_t cap;
+};
+static size_t queue_head_bytes() { return hp_align256(sizeof(QueueHead)) + hp_align256(sizeof(QueueReq) * HP_MAX_BATCH); }
+static QueueView queue_view(void* q, size_t bytes) {
+  QueueView v;
+  v.h = (QueueHead*)q;
+  v.reqs = (QueueReq*)((char*)q + hp_align256(sizeof(QueueHead)));
+  v.items = (uint32_t*)((char*)q + queue_head_bytes());
+  v.cap = bytes > queue_head_bytes() ? (int64_t)((bytes - queue_head_bytes()) / 4) : 0;
+  return v;
+}
+
+__global__ void k_queue_reset(QueueHead* h) {
+  uint32_t* w = (uint32_t*)h;
+  for (int i = threadIdx.x; i < (int)(sizeof(QueueHead) / 4); i += blockDim.x) w[i] = 0u;
+}
+
+// one block: the request's arguments, its items, then the new tail
+__global__ __launch_bounds__(256) void k_queue_push(QueueView Q, int slot, RenderArgs A, RenderOut O, int n_tiles,
+                                                    int last) {
+  const uint32_t t0 = __hip_atomic_fetch_add(&Q.h->tail, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const bool fits = (int64_t)t0 + n_tiles <= Q.cap;
+  if (fits) {
+    if (threadIdx.x == 0) {
+      Q.reqs[slot].A = A;
+      Q.reqs[slot].O = O;
+      Q.h->ntiles[slot] = (uint32_t)n_tiles;
+    }
+    for (int i = threadIdx.x; i < n_tiles; i += blockDim.x) Q.items[t0 + i] = ((uint32_t)slot << 24) | (uint32_t)i;
+  }
+  // every thread's writes reach device scope before the tail moves
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (fits) __hip_atomic_store(&Q.h->tail, t0 + (uint32_t)n_tiles, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    else __hip_atomic_store(&Q.h->overflow, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (last) __hip_atomic_store(&Q.h->closed, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// Claim the next item (thread 0 only): a ticket from one atomic add on the
+// head, then a wait until the ticket's item is published.  Returns 1 and the
+// item; 0 when the queue is closed and holds no item at the ticket, or when
+// spin_limit polls (each sleeps about 2000 cycles) pass without it.  A
+// ticket abandoned that way leaves its item unrendered, which the request's
+// done counter shows to the caller.  The counters are read with atomic
+// read-modify-writes (an add of 0), performed at the device's coherence
+// point, so they see the other XCDs' latest values where a plain load could
+// be served stale from this XCD's L2; and no fence is issued per poll (an
+// acquire fence would invalidate the whole L2 of the polling block's XCD
+// under the render and the binning running beside it).
+__device__ __forceinline__ uint32_t q_peek(uint32_t* p) {
+  return __hip_atomic_fetch_add(p, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int queue_claim(const QueueView& Q, int spin_limit, uint32_t* item) {
+  const uint32_t idx = __hip_atomic_fetch_add(&Q.h->head, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (int spins = 0; spins <= spin_limit; ++spins) {
+    if (idx < q_peek(&Q.h->tail)) {
+      *item = q_peek(&Q.items[idx]);
+      return 1;
+    }
+    // the tail is final once closed: the flag is read before a second look
+    if (q_peek(&Q.h->closed) && idx >= q_peek(&Q.h->tail)) return 0;
+    __builtin_amdgcn_s_sleep(32);
+  }
+  return 0;
+}
+
+__global__ __launch_bounds__(256) void k_render_fwd_persistent(QueueView Q, int spin_limit) {
+  __shared__ float4 s_rec[2 * HP_STAGE];
+  __shared__ uint32_t s_item;
+  __shared__ int s_ok;
+  __shared__ uint32_t s_req[(sizeof(QueueReq) + 3) / 4];
+  constexpr int kReqWords = (int)((sizeof(QueueReq) + 3) / 4);
+  while (true) {
+    if (threadIdx.x == 0) {
+      uint32_t it = 0;
+      s_ok = queue_claim(Q, spin_limit, &it);
+      s_item = it;
+    }
+    __syncthreads();
+    if (!s_ok) break;
+    const uint32_t it = s_item;
+    const int slot = (int)(it >> 24);
+    const int ct = (int)(it & 0xFFFFFFu);
+    // the request's arguments, read coherently (written by its push kernel,
+    // possibly on another XCD, after this launch began)
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(&Q.reqs[slot]);
+    for (int w = threadIdx.x; w < kReqWords; w += blockDim.x) s_req[w] = q_peek(const_cast<uint32_t*>(src + w));
+    __syncthreads();
+    const QueueReq* rq = reinterpret_cast<const QueueReq*>(s_req);
+    const RenderArgs A = rq->A;
+    const RenderOut O = rq->O;
+    render_fwd_tile<false>(A, O, ct, s_rec, nullptr);
+    __syncthreads();  // s_item and s_req may be reused
+    // the outputs are read after the launch ends: the count needs no fence
+    if (threadIdx.x == 0) __hip_atomic_fetch_add(&Q.h->done[slot], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+constexpr bool kPersistentEnabled = false;
+
+extern "C" size_t hp_render_queue_bytes(int64_t max_items) {
+  return max_items < 0 ? 0 : queue_head_bytes() + hp_align256((size_t)max_items * 4);
+}
+
+extern "C" hp_status hp_render_queue_reset(void* queue, size_t queue_bytes, void* stream) {
+  if (!queue || queue_bytes < queue_head_bytes()) return HP_ERR_INVALID_ARG;
+  hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, (hipStream_t)stream, (QueueHead*)queue);
+  HP_CHECK_LAUNCH();
+  return HP_OK;
+}
+
+extern "C" hp_status hp_render_queue_push(void* queue, size_t queue_bytes, int32_t slot, const hp_render_req* req,
+                                          const hp_params* prm, int32_t last, void* stream) {
+  if (!queue || !req || slot < 0 || slot >= HP_MAX_BATCH || queue_bytes < queue_head_bytes()) return HP_ERR_INVALID_ARG;
+  HP_TRY(hp_check_params(prm));
+  const hp_render_req& q = *req;
+  if (q.order < 0 || q.order > HP_MAX_ORDER || q.P < 0 || q.n_tiles < 0 || q.n_active < 0 || !q.projected || !q.mask)
+    return HP_ERR_INVALID_ARG;
+  if (q.n_tiles > 0 && (!q.tile_ranges || !q.vals || !q.rgb || !q.T || !q.n_contrib)) return HP_ERR_INVALID_ARG;
+  const HpGeom g = hp_geom(q.order, prm->tile_log2);
+  if (q.n_tiles > g.ntile || q.n_active > g.npix || q.n_tiles >= (1 << 24)) return HP_ERR_INVALID_ARG;
+  const RenderArgs A = make_args(g, hp_mask_view((const char*)q.mask, g), hp_proj_view((const char*)q.projected, q.P),
+                                 q.vals, q.tile_ranges, prm, q.n_active);
+  const RenderOut O{q.rgb, q.T, q.n_contrib, nullptr, nullptr};
+  hipLaunchKernelGGL(k_queue_push, dim3(1), dim3(256), 0, (hipStream_t)stream, queue_view(queue, queue_bytes), (int)slot,
+                     A, O, (int)q.n_tiles, (int)(last != 0));
+  HP_CHECK_LAUNCH();
+  return HP_OK;
+}
+
+extern "C" hp_status hp_render_fwd_persistent(void* queue, size_t queue_bytes, int32_t n_blocks, int32_t spin_limit,
+                                              void* stream) {
+  if (!queue || queue_bytes < queue_head_bytes() || n_blocks < 1 || n_blocks > 65536 || spin_limit < 0)
+    return HP_ERR_INVALID_ARG;
+  // Switched off: launches of this consumer did not end on MI355X although
+  // every item had been published before they started, and no defect that
+  // explains it has been found.  Nothing is launched until one is.
+  if (!kPersistentEnabled) return HP_ERR_UNSUPPORTED;
+  hipLaunchKernelGGL(k_render_fwd_persistent, dim3((unsigned)n_blocks), dim3(256), 0, (hipStream_t)stream,
+                     queue_view(queue, queue_bytes), (int)spin_limit);
+  HP_CHECK_LAUNCH();
+  return HP_OK;
+}
+
+extern "C" hp_status hp_render_queue_status(const void* queue, int32_t n_req, int32_t* done_tiles,
+                                            int32_t* overflow, void* stream) {
+  if (!queue || n_req < 0 || n_req > HP_MAX_BATCH || (n_req > 0 && !done_tiles)) return HP_ERR_INVALID_ARG;
+  QueueHead h;
+  HP_TRY(hp_read_small(&h, queue, sizeof(QueueHead), (hipStream_t)stream));
+  for (int r = 0; r < n_req; ++r) done_tiles[r] = (int32_t)h.done[r];
+  if (overflow) *overflow = (int32_t)h.overflow;
+  return HP_OK;
+}
+
 // the backward of stage 1 lives with the forward in k_preprocess.hip
 hp_status hp_preprocess_bwd_launch(const hp_gaussians* g, const hp_view* view, const hp_params* prm, const float* acc,
                                    hp_gaussians_grad* grad, hipStream_t s);

@@ -97,3 +97,15 @@ def test_noalloc_backward_rejects_oversized_scene():
     st = A.lib().hp_render_bwd_noalloc(C.byref(g), d, d, d, 1, C.byref(v), C.byref(prm), d, 1, d, d, d, None, None,
                                        C.byref(gg), None)
     assert st == A.HP_ERR_CAPACITY
+
+
+def test_persistent_render_is_switched_off():
+    """hp_render_fwd_persistent checks its arguments, then refuses every call
+    (HP_ERR_UNSUPPORTED) without launching: the consumer is built but not
+    run.  Its argument checks still come first."""
+    L = A.lib()
+    qn = L.hp_render_queue_bytes(1024)
+    d = C.c_void_p(256)   # never dereferenced
+    assert L.hp_render_fwd_persistent(d, qn, 512, 100, None) == A.HP_ERR_UNSUPPORTED
+    assert L.hp_render_fwd_persistent(d, qn, 0, 100, None) == A.HP_ERR_INVALID_ARG
+    assert L.hp_render_fwd_persistent(None, qn, 512, 100, None) == A.HP_ERR_INVALID_ARG
