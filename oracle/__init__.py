@@ -42,14 +42,31 @@ SSIM_C2 = 0.03 ** 2
 LAMBDA = 0.2
 
 
-def build(force: bool = False) -> str:
-    """Compile hp_oracle.cpp into libhp_oracle.so (g++, -O2, OpenMP)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp%d" % os.getpid()
-        cmd = ["g++", "-O2", "-std=c++17", "-fopenmp", "-fPIC", "-shared", "-o", tmp, _SRC]
+_LIB_SAN = os.path.join(_HERE, "libhp_oracle_san.so")
+# checking build: AddressSanitizer + UBSan (g++); a process that loads it
+# must preload g++'s ASan runtime (asan_runtime) and set HP_ORACLE_SANITIZED=1
+_SAN_FLAGS = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined"]
+
+
+def build(force: bool = False, sanitize: bool = False) -> str:
+    """Compile hp_oracle.cpp into libhp_oracle.so (g++, -O2, OpenMP), or
+    with sanitize into libhp_oracle_san.so."""
+    lib = _LIB_SAN if sanitize else _LIB
+    if force or not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(_SRC):
+        tmp = lib + ".tmp%d" % os.getpid()
+        opt = _SAN_FLAGS if sanitize else ["-O2"]
+        cmd = ["g++", *opt, "-std=c++17", "-fopenmp", "-fPIC", "-shared", "-o", tmp, _SRC]
         subprocess.check_call(cmd)
-        os.replace(tmp, _LIB)
-    return _LIB
+        os.replace(tmp, lib)
+    return lib
+
+
+def asan_runtime() -> str:
+    """g++'s ASan runtime, which a process loading libhp_oracle_san.so preloads."""
+    path = subprocess.run(["g++", "-print-file-name=libasan.so"], capture_output=True, text=True).stdout.strip()
+    if not os.path.isabs(path) or not os.path.exists(path):
+        raise RuntimeError("g++'s ASan runtime was not found")
+    return path
 
 
 class _Scene(C.Structure):
@@ -75,7 +92,7 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        _lib = C.CDLL(build())
+        _lib = C.CDLL(build(sanitize=os.environ.get("HP_ORACLE_SANITIZED") == "1"))
         _lib.or_mask.restype = C.c_int64
         _lib.or_tile_sets.restype = C.c_int64
         _lib.or_chart_pixel.restype = C.c_int64

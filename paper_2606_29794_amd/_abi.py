@@ -7,7 +7,9 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libhp.so")
+# HP_SANITIZED=1 selects the host-sanitized build (build.py, sanitize=True),
+# for host-only checks in a process that preloads the ASan runtime
+LIB_PATH = os.path.join(HERE, "libhp_san.so" if os.environ.get("HP_SANITIZED") == "1" else "libhp.so")
 
 HP_OK, HP_ERR_INVALID_ARG, HP_ERR_UNSUPPORTED, HP_ERR_CAPACITY, HP_ERR_DEVICE = 0, 1, 2, 3, 4
 HP_CAM_FULL, HP_CAM_FISHEYE, HP_CAM_PINHOLE = 0, 1, 2

@@ -57,8 +57,9 @@ __device__ __forceinline__ float hp_k2_series_deriv(float s2) {  // d k2 / d s2
 
 // atan2(s, c) for s > 0 (angles in (0, pi)): reduced to t = min / max of
 // (s, |c|) in [0, 1], atan t = t P(t^2) with P a degree-8 polynomial fitted
-// to atan(t) / t on [0, 1] in relative error (fit error 1.5e-8; the float
-// evaluation stays within a few ulp), then reflected about pi/4 and pi/2.
+// to atan(t) / t on [0, 1] for least maximum relative error by Lawson's
+// algorithm (fit_atan.py; fit error 1.5e-8, 5.1e-8 with the coefficients
+// rounded to float, under one ulp at 1), then reflected about pi/4 and pi/2.
 __device__ __forceinline__ float hp_atan2_pos(float s, float c) {
   const float ac = fabsf(c);
   const bool steep = s > ac;

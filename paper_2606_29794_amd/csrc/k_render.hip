@@ -1,11 +1,18 @@
 // k_render.hip -- stage 3 of Alg. 1 (front-to-back compositing on the
 // HEALPix grid, Eq. unified_rendering) and its per-pixel backward pass.
 //
-// One 256-thread workgroup per active tile; each of its four waves owns 64
-// consecutive active pixels of the tile and walks the tile's depth-sorted
-// Gaussian list on its own (no barriers): the list index is wave-uniform, so
-// the Gaussian id and its 64-byte record are scalar loads shared by all lanes,
-// and a wave leaves the list as soon as all its pixels are saturated.
+// One 256-thread workgroup per active tile, one pixel per lane; the four
+// waves each own 64 consecutive active pixels of the tile.  The tile's
+// depth-sorted list is walked in chunks of 64 entries: all 256 threads stage
+// a chunk's 64-byte records into LDS (one 16-byte quarter each, the next
+// chunk's records requested before the current one is evaluated), a barrier
+// publishes it, and every wave reads the records as LDS broadcasts.  Per
+// chunk, a wave first tests every entry against its 64 pixels as a whole and
+// visits only the entries that can reach one of them.  The forward stops a
+// wave once its pixels are saturated and the block once all four waves are
+// (a vote taken with the chunk's barrier); the backward walks the chunks
+// from the back, reduces each entry's gradients across the wave and the
+// block, and adds them to per-Gaussian accumulators with global atomics.
 #include "hp_common.h"
 #include "hp_offset.h"
 

@@ -40,8 +40,20 @@ MAX_REQ_PER_RENDER = 16
 @dataclass
 class Request:
     rid: int
-    arrival: float          # seconds from the start of the trace
+    arrival: float                  # seconds from the start of the trace
     camera: Camera
+    deadline: float | None = None   # longest wait for admission, seconds after arrival
+    cancelled: bool = False         # set by cancel(), from any thread
+
+    def cancel(self) -> None:
+        """Withdraw the request.  Before admission it is dropped; after, its
+        render still runs (launched work is not recalled) but its output is
+        discarded."""
+        self.cancelled = True
+
+
+# outcome of a request
+OK, ERROR, CANCELLED, TIMEOUT = "ok", "error", "cancelled", "timeout"
 
 
 @dataclass
@@ -51,6 +63,8 @@ class Result:
     done: float
     rgb: torch.Tensor | None = None
     T: torch.Tensor | None = None
+    status: str = OK
+    error: str | None = None
 
     @property
     def latency(self) -> float:
@@ -85,6 +99,156 @@ def select_batch(pending, estimate, mem_in_use: int, budget: int, max_batch: int
         if mem_in_use + est > budget:
             break
     return batch
+
+
+class BatchTimeout(RuntimeError):
+    """A batch did not complete within the serving loop's batch_timeout."""
+
+
+def device_error(e: BaseException) -> bool:
+    """Errors after which the device cannot be trusted and serving stops:
+    the library's HP_ERR_DEVICE, a HIP runtime error surfaced by torch, and
+    anything that is not an Exception (interrupts).  Other errors (a refused
+    argument, a capacity the retry could not meet) fail only the batch that
+    raised them."""
+    if not isinstance(e, Exception):
+        return True
+    if isinstance(e, A.HPError):
+        return e.status == A.HP_ERR_DEVICE
+    msg = str(e)
+    return isinstance(e, RuntimeError) and ("HIP error" in msg or "hipError" in msg)
+
+
+def run_continuous(requests: list, n_slots: int, estimate, reserve: int, budget: int, max_batch: int, run_batch,
+                   realtime: bool = True, fatal=device_error, batch_timeout: float | None = None,
+                   worker_init=None):
+    """The continuous-batching loop, independent of the device.
+
+    A dispatcher admits arrived requests (select_batch: FIFO, HBM budget)
+    into a batch whenever one of n_slots worker threads is free; the worker
+    calls run_batch(batch, slot), which returns one (rgb, T) pair per request
+    once the batch has completed.  `estimate(request)` gives a request's
+    bytes in flight and `reserve` the bytes held for the whole run.
+
+    Failure handling:
+    * a batch whose run_batch raises an error that `fatal` does not call
+      fatal fails its own requests (status ERROR, with the message), its
+      slot and bytes are released, and serving goes on;
+    * a fatal error ends the loop and is raised;
+    * a request cancelled before admission is dropped (CANCELLED); one
+      cancelled while in flight is rendered but its output is discarded;
+    * a request still waiting for admission `deadline` seconds after its
+      arrival is dropped (TIMEOUT);
+    * a batch in flight for longer than batch_timeout seconds ends the loop
+      with BatchTimeout: the device is presumed hung, and its worker thread
+      is left behind (daemon) rather than waited for.
+
+    Returns (results in request order, makespan in seconds)."""
+    reqs = sorted(requests, key=lambda r: r.arrival)
+    n = len(reqs)
+    cv = threading.Condition()
+    results = {}
+    free = list(range(n_slots))
+    busy = {}                      # slot -> time its batch was handed over
+    st = {"mem": 0, "error": None}
+    inbox = [queue.SimpleQueue() for _ in range(n_slots)]
+    t0 = time.perf_counter()
+    clock = lambda: time.perf_counter() - t0
+    arrival = (lambda r: r.arrival) if realtime else (lambda r: 0.0)
+
+    def finish(r, status, t, rgb=None, T=None, error=None):
+        # without real-time replay every request is queued at t = 0
+        results[r.rid] = Result(r.rid, arrival(r), t, rgb, T, status, error)
+
+    def worker(slot):
+        if worker_init is not None:
+            worker_init()
+        while True:
+            item = inbox[slot].get()
+            if item is None:
+                return
+            batch, est = item
+            try:
+                outs = run_batch(batch, slot)
+                err = None
+            except BaseException as e:
+                if fatal(e):
+                    with cv:
+                        st["error"] = e
+                        cv.notify_all()
+                    return
+                outs, err = None, f"{type(e).__name__}: {e}"
+            t = clock()
+            with cv:
+                for k, r in enumerate(batch):
+                    if err is not None:
+                        finish(r, ERROR, t, error=err)
+                    elif r.cancelled:
+                        finish(r, CANCELLED, t)
+                    else:
+                        finish(r, OK, t, *outs[k])
+                outs = None
+                st["mem"] -= est
+                busy.pop(slot, None)
+                free.append(slot)
+                cv.notify_all()
+
+    threads = [threading.Thread(target=worker, args=(k,), daemon=True) for k in range(n_slots)]
+    for th in threads:
+        th.start()
+    pending = collections.deque()
+    nxt = 0
+    hung = False
+    try:
+        with cv:
+            while len(results) < n and st["error"] is None:
+                now = clock()
+                while nxt < n and (not realtime or reqs[nxt].arrival <= now):
+                    pending.append(reqs[nxt])
+                    nxt += 1
+                # withdrawn and expired requests leave the queue
+                keep = collections.deque()
+                for r in pending:
+                    if r.cancelled:
+                        finish(r, CANCELLED, now)
+                    elif r.deadline is not None and now - arrival(r) > r.deadline:
+                        finish(r, TIMEOUT, now)
+                    else:
+                        keep.append(r)
+                pending = keep
+                if batch_timeout is not None:
+                    late = [k for k, ts in busy.items() if now - ts > batch_timeout]
+                    if late:
+                        hung = True
+                        st["error"] = BatchTimeout(f"batch on slot {late[0]} still running after {batch_timeout} s")
+                        break
+                if pending and free:
+                    batch = select_batch(pending, estimate, st["mem"] + reserve, budget, max_batch,
+                                         len(free) < n_slots)
+                    if batch:
+                        est = sum(estimate(r) for r in batch)
+                        st["mem"] += est
+                        slot = free.pop(0)
+                        busy[slot] = now
+                        inbox[slot].put((batch, est))
+                        continue
+                # sleep until a batch completes or the next request arrives
+                wait = 0.05
+                if realtime and nxt < n:
+                    wait = min(wait, max(0.0, reqs[nxt].arrival - clock()))
+                if batch_timeout is not None and busy:
+                    wait = min(wait, max(0.0, min(busy.values()) + batch_timeout - clock()) + 1e-3)
+                cv.wait(timeout=wait)
+    finally:
+        for q in inbox:
+            q.put(None)
+        if not hung:
+            for th in threads:
+                th.join()
+    if st["error"] is not None:
+        raise st["error"]
+    makespan = max((r.done for r in results.values()), default=0.0)
+    return [results[r.rid] for r in reqs], makespan
 
 
 def _percentile(x, q):
@@ -208,90 +372,29 @@ class Server:
         return b
 
     # ---- the request loop -----------------------------------------------------
-    def serve(self, requests: list, realtime: bool = True, keep_outputs: bool = False):
-        """Continuous batching.  One worker thread per stream slot launches
-        its batch (the pair-count read-backs inside block only that worker),
-        waits for the batch's completion event and records the results; the
-        dispatcher admits arrived requests into a batch whenever a slot is
-        free and the HBM budget allows.  Host waits release the interpreter
+    def serve(self, requests: list, realtime: bool = True, keep_outputs: bool = False,
+              batch_timeout: float | None = None):
+        """Continuous batching (run_continuous) with one worker thread per
+        stream slot: a worker launches its batch (the pair-count read-backs
+        inside block only that worker), waits for the batch's completion
+        event and hands back its images.  Host waits release the interpreter
         lock, so while one worker waits the others keep the GPU fed."""
-        reqs = sorted(requests, key=lambda r: r.arrival)
-        n = len(reqs)
         dev = self.g.mean.device
-        cv = threading.Condition()
-        results = {}
-        free = list(range(len(self.streams)))
-        st = {"mem": 0, "error": None}
-        inbox = [queue.SimpleQueue() for _ in self.streams]
-        reserve = self.workspace_reserve()
+
+        def run(batch, slot):
+            b = self._launch(batch, slot, keep_outputs)
+            b.event.synchronize()
+            b = self._redo_overflowed(b, keep_outputs)
+            # the batch's buffers go with this frame, before its bytes leave
+            # the account
+            return b.outs if keep_outputs else [(None, None)] * len(batch)
+
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        clock = lambda: time.perf_counter() - t0
-
-        def worker(slot):
-            torch.cuda.set_device(dev)
-            while True:
-                item = inbox[slot].get()
-                if item is None:
-                    return
-                batch, est = item
-                try:
-                    b = self._launch(batch, slot, keep_outputs)
-                    b.event.synchronize()
-                    b = self._redo_overflowed(b, keep_outputs)
-                    outs = b.outs if keep_outputs else [(None, None)] * len(batch)
-                    # the batch's buffers are released before its bytes leave
-                    # the account (the next batch of this slot must not find
-                    # them still held)
-                    b = None
-                    t = clock()
-                    with cv:
-                        for r, (rgb, T) in zip(batch, outs):
-                            # without real-time replay every request is queued at t = 0
-                            results[r.rid] = Result(r.rid, r.arrival if realtime else 0.0, t, rgb, T)
-                        st["mem"] -= est
-                        free.append(slot)
-                        cv.notify_all()
-                except BaseException as e:  # surfaced by the dispatcher
-                    with cv:
-                        st["error"] = e
-                        cv.notify_all()
-                    return
-
-        threads = [threading.Thread(target=worker, args=(k,), daemon=True) for k in range(len(self.streams))]
-        for th in threads:
-            th.start()
-        pending = collections.deque()
-        nxt = 0
-        try:
-            with cv:
-                while len(results) < n and st["error"] is None:
-                    now = clock()
-                    while nxt < n and (not realtime or reqs[nxt].arrival <= now):
-                        pending.append(reqs[nxt])
-                        nxt += 1
-                    if pending and free:
-                        batch = select_batch(pending, lambda r: self._estimate(r.camera), st["mem"] + reserve,
-                                             self.budget, self.max_batch, len(free) < len(self.streams))
-                        if batch:
-                            est = sum(self._estimate(r.camera) for r in batch)
-                            st["mem"] += est
-                            inbox[free.pop(0)].put((batch, est))
-                            continue
-                    # sleep until a batch completes or the next request arrives
-                    wait = 0.05
-                    if realtime and nxt < n:
-                        wait = min(wait, max(0.0, reqs[nxt].arrival - clock()))
-                    cv.wait(timeout=wait)
-        finally:
-            for q in inbox:
-                q.put(None)
-            for th in threads:
-                th.join()
-        if st["error"] is not None:
-            raise st["error"]
-        makespan = max(r.done for r in results.values())
-        return ServeStats.of([results[r.rid] for r in reqs], makespan)
+        results, makespan = run_continuous(
+            requests, len(self.streams), lambda r: self._estimate(r.camera), self.workspace_reserve(), self.budget,
+            self.max_batch, run, realtime=realtime, batch_timeout=batch_timeout,
+            worker_init=lambda: torch.cuda.set_device(dev))
+        return ServeStats.of(results, makespan)
 
     def serve_sequential(self, requests: list, realtime: bool = True, keep_outputs: bool = False):
         """Baseline: one request at a time, FIFO, the plain per-request
@@ -316,6 +419,8 @@ class Server:
 
 @dataclass
 class ServeStats:
+    """Throughput and latency over the requests that rendered (status OK);
+    the other outcomes are counted."""
     n: int
     makespan_s: float
     renders_per_s: float
@@ -323,16 +428,26 @@ class ServeStats:
     p99_ms: float
     mean_ms: float
     results: list
+    failed: int = 0
+    cancelled: int = 0
+    timed_out: int = 0
 
     @staticmethod
     def of(results, makespan):
-        lat = [r.latency * 1e3 for r in results]
-        return ServeStats(len(results), makespan, len(results) / makespan, _percentile(lat, 50), _percentile(lat, 99),
-                          float(np.mean(lat)), results)
+        ok = [r for r in results if r.status == OK]
+        lat = [r.latency * 1e3 for r in ok]
+        count = lambda s: sum(r.status == s for r in results)
+        return ServeStats(len(results), makespan, len(ok) / makespan if makespan > 0 else float("nan"),
+                          _percentile(lat, 50), _percentile(lat, 99), float(np.mean(lat)) if lat else float("nan"),
+                          results, count(ERROR), count(CANCELLED), count(TIMEOUT))
 
     def summary(self) -> dict:
-        return dict(n=self.n, makespan_s=self.makespan_s, renders_per_s=self.renders_per_s, p50_ms=self.p50_ms,
-                    p99_ms=self.p99_ms, mean_ms=self.mean_ms)
+        d = dict(n=self.n, makespan_s=self.makespan_s, renders_per_s=self.renders_per_s, p50_ms=self.p50_ms,
+                 p99_ms=self.p99_ms, mean_ms=self.mean_ms)
+        for k in ("failed", "cancelled", "timed_out"):
+            if getattr(self, k):
+                d[k] = getattr(self, k)
+        return d
 
 
 def requests_from_workload(wl, limit: int | None = None) -> list:
