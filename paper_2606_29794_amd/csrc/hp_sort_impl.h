@@ -115,11 +115,15 @@ __global__ __launch_bounds__(kThreads) void k_scan_reduce(const In* __restrict__
 }
 
 // every block adds the sums of the blocks before it, then scans its tiles
-// (16 consecutive elements per thread) with a running carry
+// with a running carry: a tile is loaded striped (coalesced) into LDS, each
+// thread scans 16 consecutive elements of it, and the results leave striped
+// again.  LDS element i sits at i + i / 16, so that the 16-element runs of
+// neighbouring threads start in different banks.
 template <class T, class In>
 __global__ __launch_bounds__(kThreads) void k_scan_down(const In* in, T* out, const uint64_t* __restrict__ cnt,
                                                         int64_t cap, const T* __restrict__ sums, T* grand) {
   __shared__ T s_w[4];
+  __shared__ T s_x[kTile + kTile / kItems];
   const int64_t n = dev_count(cnt, cap);
   int64_t t0, t1;
   block_tiles(n, &t0, &t1);
@@ -134,22 +138,36 @@ __global__ __launch_bounds__(kThreads) void k_scan_down(const In* in, T* out, co
   block_exclusive<T>(pre, &carry, s_w);
   block_exclusive<T>(all, &tot_all, s_w);
   if (grand && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *grand = tot_all;
+  const int run = (int)threadIdx.x * (kItems + 1);
   for (int64_t t = t0; t < t1; ++t) {
-    const int64_t base = t * kTile + (int64_t)threadIdx.x * kItems;
+    const int64_t tb = t * kTile;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+      const int i = k * kThreads + (int)threadIdx.x;
+      s_x[i + i / kItems] = tb + i < n ? (T)in[tb + i] : T(0);
+    }
+    __syncthreads();
     T v[kItems];
     T acc = 0;
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
-      v[k] = base + k < n ? (T)in[base + k] : T(0);
+      v[k] = s_x[run + k];
       acc += v[k];
     }
     T tile_total;
     T ex = block_exclusive<T>(acc, &tile_total, s_w) + carry;
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
-      if (base + k < n) out[base + k] = ex;
+      s_x[run + k] = ex;
       ex += v[k];
     }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+      const int i = k * kThreads + (int)threadIdx.x;
+      if (tb + i < n) out[tb + i] = s_x[i + i / kItems];
+    }
+    __syncthreads();  // the next tile's loads reuse s_x
     carry += tile_total;
   }
 }

@@ -189,6 +189,69 @@ __device__ __forceinline__ void gauss_dir(const float4* disc, const float* radiu
 constexpr int kSlots = 16;
 constexpr int kTopNodes = 252;  // quadtree levels 0..2
 
+// The quadtree's top levels (faces and two more: 252 nodes) in LDS, where
+// every walk starts.  Returns how many are there.  The caller synchronises.
+struct TopNodes {
+  float4 cap[kTopNodes];
+  float2 sc[kTopNodes];
+  uint8_t act[kTopNodes];
+};
+__device__ __forceinline__ int load_top_nodes(const BinTables& T, TopNodes& S) {
+  const int64_t nlev = hp_level_offset(T.ls + 1);  // nodes of levels 0..ls
+  const int ntop = (int)(nlev < kTopNodes ? nlev : kTopNodes);
+  for (int t = threadIdx.x; t < ntop; t += blockDim.x) {
+    S.cap[t] = T.cap[t];
+    S.sc[t] = T.sc[t];
+    S.act[t] = T.node_active ? T.node_active[t] : (uint8_t)1;
+  }
+  return ntop;
+}
+
+// Calls emit(i) for the passing nodes i at level T.ls, in increasing order,
+// of the Gaussian with direction u and half test angle (sg, cg): the top
+// levels are tested from the LDS copy, deeper ones from memory.  Level 1 (48
+// nodes) is tested by every lane in the same order, which keeps the wave
+// converged where a walk from the 12 faces would diverge at once; below a
+// passing level-1 node the children are tested in order (level 2) and deeper
+// levels are walked depth-first.
+template <class Emit>
+__device__ __forceinline__ void coarse_nodes(const BinTables& T, const TopNodes& S, int ntop, const float* u, float sg,
+                                             float cg, Emit&& emit) {
+  auto pass = [&](int64_t node) -> bool {
+    if (node < ntop) {
+      if (!S.act[node]) return false;
+      const float4 c = S.cap[node];
+      const float2 h = S.sc[node];
+      return hp_cap_test(c.x, c.y, c.z, h.x, h.y, u[0], u[1], u[2], sg, cg);
+    }
+    return node_pass(T, node, u[0], u[1], u[2], sg, cg);
+  };
+  if (T.ls == 0) {
+    for (int f = 0; f < 12; ++f)
+      if (pass(f)) emit(f);
+    return;
+  }
+  uint64_t m1 = 0;
+#pragma unroll 4
+  for (int j = 0; j < 48; ++j) m1 |= pass(12 + j) ? (1ull << j) : 0ull;
+  while (m1 != 0) {
+    const int j = __builtin_ctzll(m1);
+    m1 &= m1 - 1;
+    if (T.ls == 1) {
+      emit(j);
+      continue;
+    }
+    for (int c = 0; c < 4; ++c) {
+      const int64_t i2 = 4 * (int64_t)j + c;
+      if (T.ls == 2) {
+        if (pass(60 + i2)) emit(i2);
+      } else {
+        quad_walk(2, i2, T.ls, pass, emit);
+      }
+    }
+  }
+}
+
 template <bool EMIT>
 __global__ __launch_bounds__(256) void k_bin_coarse(int64_t P, const uint32_t* __restrict__ order,
                                                     const float4* __restrict__ disc, const float* __restrict__ radius,
@@ -196,18 +259,8 @@ __global__ __launch_bounds__(256) void k_bin_coarse(int64_t P, const uint32_t* _
                                                     const uint64_t* __restrict__ toff, int64_t cap_t,
                                                     uint32_t* __restrict__ task_g, uint32_t* __restrict__ task_n,
                                                     uint32_t* __restrict__ slots) {
-  // the quadtree's top levels (faces and two more: 252 nodes) in LDS; every
-  // walk starts there
-  __shared__ float4 s_cap[kTopNodes];
-  __shared__ float2 s_sc[kTopNodes];
-  __shared__ uint8_t s_act[kTopNodes];
-  const int64_t nlev = hp_level_offset(T.ls + 1);  // nodes of levels 0..ls
-  const int ntop = (int)(nlev < kTopNodes ? nlev : kTopNodes);
-  for (int t = threadIdx.x; t < ntop; t += blockDim.x) {
-    s_cap[t] = T.cap[t];
-    s_sc[t] = T.sc[t];
-    s_act[t] = T.node_active ? T.node_active[t] : (uint8_t)1;
-  }
+  __shared__ TopNodes S;
+  const int ntop = load_top_nodes(T, S);
   __syncthreads();
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= P) return;
@@ -236,54 +289,201 @@ __global__ __launch_bounds__(256) void k_bin_coarse(int64_t P, const uint32_t* _
     return;
   }
   uint32_t cnt = 0;
-  // node test: the top levels from the LDS copy, deeper ones from memory
-  auto pass = [&](int64_t node) -> bool {
-    if (node < ntop) {
-      if (!s_act[node]) return false;
-      const float4 c = s_cap[node];
-      const float2 h = s_sc[node];
-      return hp_cap_test(c.x, c.y, c.z, h.x, h.y, u[0], u[1], u[2], sg, cg);
-    }
-    return node_pass(T, node, u[0], u[1], u[2], sg, cg);
-  };
-  auto emit = [&](int64_t i) {
+  coarse_nodes(T, S, ntop, u, sg, cg, [&](int64_t i) {
     if (EMIT && cnt < room) {
       task_g[base + cnt] = gid;
       task_n[base + cnt] = (uint32_t)i;
     }
     if (!EMIT && slots && cnt < (uint32_t)kSlots) slots[(int64_t)cnt * P + k] = (uint32_t)i;
     ++cnt;
+  });
+  if (!EMIT) tcount[k] = cnt;
+}
+
+// ---- task list in node order without a sort --------------------------------
+// For split levels of at most kHistNodes nodes.  The count walk also counts
+// each workgroup's tasks per node into a node-major histogram [nn][G] (G
+// workgroups of 256 Gaussians in depth order).  An exclusive scan of the
+// histogram gives every (node, workgroup) its first slot, and the scatter
+// pass writes each task straight to its place: that slot plus the number of
+// the workgroup's earlier Gaussians with a task at the node.  A Gaussian has
+// at most one task per node, so this is the order a stable sort of the
+// depth-ordered tasks by node gives.
+constexpr int kHistNodes = 768;
+
+__global__ __launch_bounds__(256) void k_task_count(int64_t P, const uint32_t* __restrict__ order,
+                                                    const float4* __restrict__ disc, const float* __restrict__ radius,
+                                                    BinTables T, uint32_t* __restrict__ tcount,
+                                                    uint32_t* __restrict__ slots, int nn, uint32_t* __restrict__ hist) {
+  __shared__ TopNodes S;
+  __shared__ uint32_t s_cnt[kHistNodes];
+  const int ntop = load_top_nodes(T, S);
+  for (int n = threadIdx.x; n < nn; n += blockDim.x) s_cnt[n] = 0u;
+  __syncthreads();
+  const int gb = blockIdx.x;
+  const int64_t k = (int64_t)gb * blockDim.x + threadIdx.x;
+  if (k < P) {
+    const uint32_t gid = order[k];
+    float u[3], sg, cg;
+    bool ok;
+    gauss_dir(disc, radius, gid, T, u, &sg, &cg, &ok);
+    uint32_t cnt = 0;
+    if (ok) {
+      coarse_nodes(T, S, ntop, u, sg, cg, [&](int64_t i) {
+        if (cnt < (uint32_t)kSlots) slots[(int64_t)cnt * P + k] = (uint32_t)i;
+        atomicAdd(&s_cnt[i], 1u);
+        ++cnt;
+      });
+    }
+    tcount[k] = cnt;
+  }
+  __syncthreads();
+  const int64_t G = gridDim.x;
+  for (int n = threadIdx.x; n < nn; n += blockDim.x) hist[(int64_t)n * G + gb] = s_cnt[n];
+}
+
+// Dynamic LDS per node: the workgroup's first slot (8 B), 256 membership
+// bits (which of the workgroup's Gaussians have a task at the node), the
+// node's first place in the workgroup's staging run (4 B) and the bit counts
+// before each of the 8 words (8 x 1 B): 52 B.
+constexpr int kScatterLdsPerNode = 52;
+// tasks of one workgroup staged in LDS in node order, then written out in
+// runs; a workgroup with more writes its tasks directly
+constexpr int kStage = 2048;
+
+__global__ __launch_bounds__(256) void k_task_scatter(int64_t P, const uint32_t* __restrict__ order,
+                                                      const float4* __restrict__ disc,
+                                                      const float* __restrict__ radius, BinTables T,
+                                                      const uint32_t* __restrict__ tcount,
+                                                      const uint32_t* __restrict__ slots, int nn,
+                                                      const uint64_t* __restrict__ hoff, int64_t cap_t,
+                                                      uint32_t* __restrict__ task_g) {
+  extern __shared__ uint64_t s_dyn[];
+  uint64_t* s_off = s_dyn;                            // [nn]
+  uint32_t* s_bits = (uint32_t*)(s_dyn + nn);         // [nn][8]
+  uint32_t* s_start = s_bits + 8 * nn;                // [nn]
+  uint8_t* s_pre = (uint8_t*)(s_start + nn);          // [nn][8]
+  __shared__ TopNodes S;
+  __shared__ uint32_t s_gid[kStage];
+  __shared__ uint16_t s_node[kStage];
+  __shared__ uint32_t s_w[4];
+  const int ntop = load_top_nodes(T, S);
+  const int64_t G = gridDim.x;
+  for (int n = threadIdx.x; n < nn; n += blockDim.x) s_off[n] = hoff[(int64_t)n * G + blockIdx.x];
+  for (int i = threadIdx.x; i < 8 * nn; i += blockDim.x) s_bits[i] = 0u;
+  __syncthreads();
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool live = k < P;
+  const uint32_t cnt = live ? tcount[k] : 0u;
+  const uint32_t gid = live ? order[k] : 0u;
+  const int w = threadIdx.x >> 5;
+  const uint32_t bit = 1u << (threadIdx.x & 31);
+  // the Gaussian's nodes: from the count walk's slots, or walked again when
+  // it had more than kSlots
+  auto each_node = [&](auto&& f) {
+    if (cnt <= (uint32_t)kSlots) {
+      for (uint32_t j = 0; j < cnt; ++j) f((int64_t)slots[(int64_t)j * P + k]);
+      return;
+    }
+    float u[3], sg, cg;
+    bool ok;
+    gauss_dir(disc, radius, gid, T, u, &sg, &cg, &ok);
+    if (ok) coarse_nodes(T, S, ntop, u, sg, cg, f);
   };
-  // Passing nodes at level ls in increasing order.  Level 1 (48 nodes) is
-  // tested by every lane in the same order, which keeps the wave converged
-  // where a walk from the 12 faces would diverge at once; below a passing
-  // level-1 node the children are tested in order (level 2) and deeper
-  // levels are walked depth-first.
-  if (T.ls == 0) {
-    for (int f = 0; f < 12; ++f)
-      if (pass(f)) emit(f);
-  } else {
-    uint64_t m1 = 0;
-#pragma unroll 4
-    for (int j = 0; j < 48; ++j) m1 |= pass(12 + j) ? (1ull << j) : 0ull;
-    while (m1 != 0) {
-      const int j = __builtin_ctzll(m1);
-      m1 &= m1 - 1;
-      if (T.ls == 1) {
-        emit(j);
-        continue;
-      }
-      for (int c = 0; c < 4; ++c) {
-        const int64_t i2 = 4 * (int64_t)j + c;
-        if (T.ls == 2) {
-          if (pass(60 + i2)) emit(i2);
-        } else {
-          quad_walk(2, i2, T.ls, pass, emit);
-        }
+  if (cnt) each_node([&](int64_t i) { atomicOr(&s_bits[8 * i + w], bit); });
+  __syncthreads();
+  // per node (thread t: nodes 4t .. 4t + 3): counts before each word, and
+  // the node's place in the workgroup's node-ordered run
+  uint32_t tot[4], sum = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int n = 4 * (int)threadIdx.x + q;
+    uint32_t a = 0;
+    if (n < nn) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        s_pre[8 * n + j] = (uint8_t)a;
+        a += (uint32_t)__popc(s_bits[8 * n + j]);
       }
     }
+    tot[q] = a;
+    sum += a;
   }
-  if (!EMIT) tcount[k] = cnt;
+  uint32_t total;
+  uint32_t ex = hpsort::block_exclusive<uint32_t>(sum, &total, s_w);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int n = 4 * (int)threadIdx.x + q;
+    if (n < nn) s_start[n] = ex;
+    ex += tot[q];
+  }
+  __syncthreads();
+  const bool staged = total <= (uint32_t)kStage;
+  if (cnt) {
+    each_node([&](int64_t i) {
+      const uint32_t r = (uint32_t)s_pre[8 * i + w] + (uint32_t)__popc(s_bits[8 * i + w] & (bit - 1u));
+      if (staged) {
+        const uint32_t lp = s_start[i] + r;
+        s_gid[lp] = gid;
+        s_node[lp] = (uint16_t)i;
+      } else {
+        const uint64_t pos = s_off[i] + r;
+        if (pos < (uint64_t)cap_t) task_g[pos] = gid;
+      }
+    });
+  }
+  if (staged) {
+    __syncthreads();
+    // consecutive threads write consecutive places of each node's run
+    for (uint32_t t = threadIdx.x; t < total; t += blockDim.x) {
+      const int n = s_node[t];
+      const uint64_t pos = s_off[n] + (t - s_start[n]);
+      if (pos < (uint64_t)cap_t) task_g[pos] = s_gid[t];
+    }
+  }
+}
+
+// One workgroup: the task total and overflow flag, every node's task segment
+// (clamped to the capacity), its chunks of 64 tasks and their offsets, and
+// the number of (chunk, leaf) columns.  After an overflow no chunk is made.
+__global__ __launch_bounds__(256) void k_task_segments(int nn, int64_t G, const uint64_t* __restrict__ hoff,
+                                                       const uint64_t* __restrict__ t_total, int64_t cap_t, int depth,
+                                                       uint64_t* __restrict__ nt, uint32_t* __restrict__ over,
+                                                       uint32_t* __restrict__ seg, uint32_t* __restrict__ choff,
+                                                       uint64_t* __restrict__ ncol) {
+  __shared__ uint32_t s_w[4];
+  const uint64_t tot = *t_total;
+  const bool ov = tot > (uint64_t)cap_t;
+  const uint64_t lim = ov ? (uint64_t)cap_t : tot;
+  uint32_t nch[4], sum = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int n = 4 * (int)threadIdx.x + q;
+    nch[q] = 0u;
+    if (n < nn) {
+      uint64_t s0 = hoff[(int64_t)n * G], s1 = n + 1 < nn ? hoff[(int64_t)(n + 1) * G] : tot;
+      s0 = s0 < lim ? s0 : lim;
+      s1 = s1 < lim ? s1 : lim;
+      seg[2 * n] = (uint32_t)s0;
+      seg[2 * n + 1] = (uint32_t)s1;
+      nch[q] = ov ? 0u : (uint32_t)((s1 - s0 + 63) / 64);
+    }
+    sum += nch[q];
+  }
+  uint32_t total;
+  uint32_t ex = hpsort::block_exclusive<uint32_t>(sum, &total, s_w);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int n = 4 * (int)threadIdx.x + q;
+    if (n < nn) choff[n] = ex;
+    ex += nch[q];
+  }
+  if (threadIdx.x == 0) {
+    choff[nn] = total;
+    *ncol = (uint64_t)total << (2 * depth);
+    *nt = lim;
+    *over = ov ? 1u : 0u;
+  }
 }
 
 // fine stage: one lane per tile below a task's node (64 tiles three levels
@@ -452,23 +652,19 @@ __global__ void k_fill_zero_u32(uint32_t* __restrict__ p, int64_t n) {
   if (i < n) p[i] = 0u;
 }
 
-// chunk c -> its node: the last n with choff[n] <= c (choff non-decreasing,
-// choff[0] = 0, c < choff[nn]); wave-uniform
-__device__ __forceinline__ uint32_t chunk_node(const uint32_t* __restrict__ choff, uint32_t nn, uint32_t c) {
-  uint32_t lo = 0, hi = nn;  // choff[lo] <= c < choff[hi]
-  while (hi - lo > 1) {
-    const uint32_t mid = (lo + hi) >> 1;
-    if (hp_uniform(((hp_cu32p)choff)[mid]) <= c) lo = mid; else hi = mid;
-  }
-  return lo;
+// node of every chunk: workgroup n fills the chunks [choff[n], choff[n+1])
+__global__ void k_chunk_nodes(const uint32_t* __restrict__ choff, uint32_t* __restrict__ cnode) {
+  const uint32_t n = blockIdx.x, c1 = choff[n + 1];
+  for (uint32_t c = choff[n] + threadIdx.x; c < c1; c += blockDim.x) cnode[c] = n;
 }
 
 struct ChunkInfo {
   uint32_t node, local, nchn, t0, ntask;
 };
-__device__ __forceinline__ ChunkInfo chunk_info(const uint32_t* choff, uint32_t nn, const uint32_t* seg, uint32_t c) {
+__device__ __forceinline__ ChunkInfo chunk_info(const uint32_t* choff, const uint32_t* seg, const uint32_t* cnode,
+                                                uint32_t c) {
   ChunkInfo ci;
-  ci.node = chunk_node(choff, nn, c);
+  ci.node = hp_uniform(((hp_cu32p)cnode)[c]);
   const uint32_t c0 = hp_uniform(((hp_cu32p)choff)[ci.node]);
   ci.nchn = hp_uniform(((hp_cu32p)choff)[ci.node + 1]) - c0;
   ci.local = c - c0;
@@ -509,7 +705,8 @@ __device__ __forceinline__ ChunkRange xcd_chunks(uint32_t n) {
 
 // per chunk: the hit columns W_b (kept) and their popcounts, tile-major
 __global__ __launch_bounds__(256) void k_bin_cols(const uint32_t* __restrict__ choff, uint32_t nn,
-                                                  const uint32_t* __restrict__ seg, const uint32_t* __restrict__ tgid,
+                                                  const uint32_t* __restrict__ seg, const uint32_t* __restrict__ cnode,
+                                                  const uint32_t* __restrict__ tgid,
                                                   const float4* __restrict__ disc, BinTables T,
                                                   uint64_t* __restrict__ wcol, uint32_t* __restrict__ cnt) {
   const uint32_t nchunks = hp_uniform(((hp_cu32p)choff)[nn]);
@@ -525,7 +722,7 @@ __global__ __launch_bounds__(256) void k_bin_cols(const uint32_t* __restrict__ c
   const int wv = threadIdx.x >> 6;
   const ChunkRange cr = xcd_chunks(nchunks);
   for (uint32_t c = cr.first; c < cr.end; c += cr.stride) {
-    const ChunkInfo ci = chunk_info(choff, nn, seg, c);
+    const ChunkInfo ci = chunk_info(choff, seg, cnode, c);
     const uint32_t ntask = hp_uniform(ci.ntask);
     // this lane's leaf below the chunk's node (lanes past the leaves test a
     // valid leaf and drop the result)
@@ -579,27 +776,69 @@ __global__ __launch_bounds__(256) void k_bin_cols(const uint32_t* __restrict__ c
   }
 }
 
-// per chunk: every hit of leaf b's column goes to its slot in tile (node, b).
-// Lane b holds column W_b and its first slot; the wave walks the leaves, and
-// for leaf b the lanes j of the tasks with bit j set write consecutive slots,
-// so each store instruction covers one contiguous run.
+// Inclusive max over the 64 lanes (all active): the DPP pattern of the
+// sorting's wave scan with max in place of the sum (0, what lanes outside a
+// row read, is the identity of an unsigned max).
+__device__ __forceinline__ uint32_t wave_inclusive_max(uint32_t x) {
+  x = max(x, hpsort::dpp_u32<0x111, 0xf, true>(x));
+  x = max(x, hpsort::dpp_u32<0x112, 0xf, true>(x));
+  x = max(x, hpsort::dpp_u32<0x114, 0xf, true>(x));
+  x = max(x, hpsort::dpp_u32<0x118, 0xf, true>(x));
+  x = max(x, hpsort::dpp_u32<0x142, 0xa, false>(x));
+  x = max(x, hpsort::dpp_u32<0x143, 0xc, false>(x));
+  return x;
+}
+
+// index of the r-th set bit (from 0) of w; r < popcount(w)
+__device__ __forceinline__ uint32_t select_bit64(uint64_t w, uint32_t r) {
+  uint32_t pos = 0, v = (uint32_t)w, c = (uint32_t)__popc(v);
+  if (r >= c) {
+    r -= c;
+    v = (uint32_t)(w >> 32);
+    pos = 32;
+  }
+#pragma unroll
+  for (int h = 16; h >= 1; h >>= 1) {
+    c = (uint32_t)__popc(v & ((1u << h) - 1u));
+    if (r >= c) {
+      r -= c;
+      v >>= h;
+      pos += (uint32_t)h;
+    }
+  }
+  return pos;
+}
+
+// Per chunk: every hit of leaf b's column goes to its slot in tile (node, b).
+// The chunk's hits are numbered in (leaf, task) order and the wave writes 64
+// of them per store, lane k taking hit o + k: the column that holds it is
+// found by a running maximum over marks placed at every column's first
+// number, its rank in the column gives the slot and, through the column's
+// bits, the task.  So each store instruction is full (the slots of one
+// column are consecutive), where a store per column would carry ~10 lanes.
+constexpr int kMaxChunkHits = 64 * 64;
+
 __global__ __launch_bounds__(256) void k_bin_emit_sorted(const uint32_t* __restrict__ choff, uint32_t nn,
                                                          const uint32_t* __restrict__ seg,
+                                                         const uint32_t* __restrict__ cnode,
                                                          const uint32_t* __restrict__ tgid, int depth,
                                                          const uint64_t* __restrict__ wcol,
                                                          const uint64_t* __restrict__ start,
                                                          const int64_t* __restrict__ n_pairs, int64_t capacity,
                                                          uint32_t* __restrict__ vals) {
   if (*n_pairs > capacity) return;
+  __shared__ uint64_t s_W[4][64], s_base[4][64];
+  __shared__ uint32_t s_g[4][64], s_off[4][64];
+  __shared__ uint8_t s_mark[4][kMaxChunkHits];
   const uint32_t nchunks = hp_uniform(((hp_cu32p)choff)[nn]);
   const int lane = hp_lane();
+  const int wv = threadIdx.x >> 6;
   const int nleaf = 1 << (2 * depth);
   const bool leaf_lane = lane < nleaf;
-  const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   const ChunkRange cr = xcd_chunks(nchunks);
   // a chunk's columns, output slots and Gaussian ids
   auto fetch = [&](uint32_t c, uint64_t* W, uint64_t* base, uint32_t* g) {
-    const ChunkInfo ci = chunk_info(choff, nn, seg, c);
+    const ChunkInfo ci = chunk_info(choff, seg, cnode, c);
     *W = leaf_lane ? wcol[(int64_t)c * 64 + lane] : 0ull;
     *base = leaf_lane ? start[(int64_t)(c - ci.local) * nleaf + (int64_t)lane * ci.nchn + ci.local] : 0ull;
     *g = (uint32_t)lane < ci.ntask ? tgid[ci.t0 + lane] : 0u;
@@ -610,18 +849,39 @@ __global__ __launch_bounds__(256) void k_bin_emit_sorted(const uint32_t* __restr
   uint32_t g;
   fetch(c, &W, &base, &g);
   while (true) {
-    // the next chunk's loads go out before this chunk's stores, so their
-    // latency overlaps the store loop instead of following it
+    // the next chunk's loads go out before this chunk's stores
     const uint32_t cn = c + cr.stride;
     const bool more = cn < cr.end;
     uint64_t Wn = 0ull, basen = 0ull;
     uint32_t gn = 0u;
     if (more) fetch(cn, &Wn, &basen, &gn);
-    for (int b = 0; b < nleaf; ++b) {
-      const uint64_t Wb = hp_readlane64(W, b);
-      if (Wb == 0) continue;
-      if ((Wb >> lane) & 1ull) vals[hp_readlane64(base, b) + (uint64_t)__popcll(Wb & below)] = g;
+    const uint32_t cnt = (uint32_t)__popcll(W);
+    const uint32_t incl = hpsort::wave_inclusive<uint32_t>(cnt);
+    const uint32_t off = incl - cnt;
+    const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+    // the previous chunk's marks within [0, tot) go, then this chunk's
+    // columns mark their first number (distinct for non-empty columns)
+    for (uint32_t o = (uint32_t)lane; o < tot; o += 64) s_mark[wv][o] = 0;
+    __builtin_amdgcn_wave_barrier();
+    if (cnt) s_mark[wv][off] = (uint8_t)(lane + 1);
+    s_W[wv][lane] = W;
+    s_base[wv][lane] = base;
+    s_g[wv][lane] = g;
+    s_off[wv][lane] = off;
+    __builtin_amdgcn_wave_barrier();
+    uint32_t carry = 0;
+    for (uint32_t o = 0; o < tot; o += 64) {
+      const uint32_t k = o + (uint32_t)lane;
+      const uint32_t m = max(wave_inclusive_max(k < tot ? (uint32_t)s_mark[wv][k] : 0u), carry);
+      carry = (uint32_t)__builtin_amdgcn_readlane((int)m, 63);
+      if (k < tot) {
+        const uint32_t b = m - 1u;
+        const uint32_t r = k - s_off[wv][b];
+        const uint32_t j = select_bit64(s_W[wv][b], r);
+        vals[s_base[wv][b] + r] = s_g[wv][j];
+      }
     }
+    __builtin_amdgcn_wave_barrier();  // this chunk's LDS reads are done
     if (!more) break;
     c = cn;
     W = Wn;
@@ -677,11 +937,15 @@ static unsigned fine_grid(int64_t nt) {
 // Depth order, coarse walk and task list (shared by both emissions): tasks
 // (Gaussian, node at the split level) in order of radial depth; *w.nt holds
 // their number and *w.over whether they exceeded the workspace's capacity.
-static hp_status bin_tasks(const HpProjView& pv, int64_t P, const BinTables& T, float guard, BinWs& w, uint32_t* slots,
-                           hipStream_t s) {
+static hp_status depth_order(const HpProjView& pv, int64_t P, BinWs& w, hipStream_t s) {
   hipLaunchKernelGGL(k_depth_keys, dim3(hp_blocks(P, 256)), dim3(256), 0, s, P, pv.depth, w.dkey, w.order);
   HP_CHECK_LAUNCH();
-  HP_TRY(hpsort::radix_sort(w.dkey, w.order, nullptr, P, 32, w.sort_ws, s));
+  return hpsort::radix_sort(w.dkey, w.order, nullptr, P, 32, w.sort_ws, s);
+}
+
+static hp_status bin_tasks(const HpProjView& pv, int64_t P, const BinTables& T, float guard, BinWs& w, uint32_t* slots,
+                           hipStream_t s) {
+  HP_TRY(depth_order(pv, P, w, s));
   hipLaunchKernelGGL((k_bin_coarse<false>), dim3(hp_blocks(P, 256)), dim3(256), 0, s, P, w.order, pv.disc, pv.radius,
                      T, guard, w.tcount, (const uint64_t*)nullptr, w.cap_t, (uint32_t*)nullptr, (uint32_t*)nullptr,
                      slots);
@@ -753,6 +1017,7 @@ struct SortedWs {
   uint64_t* start;   // [L] exclusive scan of cnt: first output slot
   uint64_t* wcol;    // [nchunk_max][64] hit columns
   uint32_t* slots;   // [kSlots][P] first task nodes of every Gaussian (coarse walk)
+  uint32_t* cnode;   // [nchunk_max] node of every chunk
   void* scan_ws;
   int64_t nn, nchunk_max, L;
 };
@@ -770,7 +1035,8 @@ static size_t sorted_ws_size(int64_t P, const HpGeom& g) {
   sorted_dims(P, g, &nn, &ncm, &L);
   return hpsort::radix_ws_bytes(task_capacity(P)) + hp_align256(nn * 8) + hp_align256(nn * 4) +
          hp_align256((nn + 1) * 4) + hp_align256(L * 4) + hp_align256(L * 8) + hp_align256(ncm * 64 * 8) +
-         hp_align256((size_t)kSlots * P * 4) + hpsort::scan_ws_bytes<uint64_t>(L > nn ? L : nn);
+         hp_align256((size_t)kSlots * P * 4) + hp_align256((size_t)ncm * 4) +
+         hpsort::scan_ws_bytes<uint64_t>(L > nn ? L : nn);
 }
 
 static SortedWs sorted_ws(void* base, int64_t P, const HpGeom& g) {
@@ -785,6 +1051,7 @@ static SortedWs sorted_ws(void* base, int64_t P, const HpGeom& g) {
   w.start = (uint64_t*)p; p += hp_align256(w.L * 8);
   w.wcol = (uint64_t*)p; p += hp_align256(w.nchunk_max * 64 * 8);
   w.slots = (uint32_t*)p; p += hp_align256((size_t)kSlots * P * 4);
+  w.cnode = (uint32_t*)p; p += hp_align256((size_t)w.nchunk_max * 4);
   w.scan_ws = p;
   return w;
 }
@@ -795,10 +1062,12 @@ extern "C" size_t hp_bin_sorted_workspace_bytes(int64_t P, int32_t order, int32_
   return bin_ws_size(P) + sorted_ws_size(P, g) + 512;
 }
 
-// one wave per chunk, at most 8192 blocks of 4 waves looping over the chunks
+// one wave per chunk, at most kChunkBlocks blocks of 4 waves looping over the
+// chunks (measured on config 2: 8192 blocks beat one resident round of 2048)
+constexpr int64_t kChunkBlocks = 8192;
 static unsigned chunk_grid(int64_t nchunks) {
   const int64_t blocks = (nchunks + 3) / 4;
-  return (unsigned)(blocks < 8192 ? (blocks > 0 ? blocks : 1) : 8192);
+  return (unsigned)(blocks < kChunkBlocks ? (blocks > 0 ? blocks : 1) : kChunkBlocks);
 }
 
 // The sorted emission with every Gaussian's test angle widened by `widen`
@@ -839,34 +1108,60 @@ hp_status hp_bin_sorted_widened(int32_t phase, const void* projected, int64_t P,
     // emitted
     hipLaunchKernelGGL(k_store_unfinished, dim3(1), dim3(1), 0, s, n_pairs);
     HP_CHECK_LAUNCH();
-    HP_TRY(bin_tasks(pv, P, T, prm->bin_guard, w, sw.slots, s));
-    // stable sort of the tasks by node; segments and chunk offsets per node
-    int nbits = 0;
-    while (((int64_t)1 << nbits) < sw.nn) ++nbits;
-    // the sorted node keys are only needed here: read them where the last
-    // pass left them; the Gaussian ids go back to task_g for the emit phase
-    uint32_t *snode = w.task_n, *sgid = w.task_g;
-    HP_TRY(hpsort::radix_sort(w.task_n, w.task_g, w.nt, w.cap_t, nbits, sw.tsort_ws, s, &snode, &sgid));
-    if (sgid != w.task_g) {
-      hipLaunchKernelGGL(hpsort::k_copy_u32, dim3(hpsort::copy_grid(w.cap_t)), dim3(256), 0, s, (const uint32_t*)sgid,
-                         w.task_g, (const uint64_t*)w.nt, w.cap_t);
+    if (sw.nn <= kHistNodes) {
+      // tasks written in node order straight from the walk (no task sort);
+      // the histogram lives in task_n and its scan in poff, which this path
+      // does not otherwise use (nn x G <= 4 (P + 255) <= task capacity)
+      HP_TRY(depth_order(pv, P, w, s));
+      const unsigned G = hp_blocks(P, 256);
+      const int nni = (int)sw.nn;
+      uint32_t* hist = w.task_n;
+      uint64_t* hoff = w.poff;
+      hipLaunchKernelGGL(k_task_count, dim3(G), dim3(256), 0, s, P, (const uint32_t*)w.order, pv.disc, pv.radius, T,
+                         w.tcount, sw.slots, nni, hist);
+      HP_CHECK_LAUNCH();
+      HP_TRY((hpsort::scan_exclusive<uint64_t, uint32_t>(hist, hoff, nullptr, (int64_t)nni * G, w.t_total, w.scan_ws,
+                                                         s)));
+      hipLaunchKernelGGL(k_task_scatter, dim3(G), dim3(256), (size_t)nni * kScatterLdsPerNode, s, P,
+                         (const uint32_t*)w.order, pv.disc, pv.radius, T, (const uint32_t*)w.tcount,
+                         (const uint32_t*)sw.slots, nni, (const uint64_t*)hoff, w.cap_t, w.task_g);
+      HP_CHECK_LAUNCH();
+      hipLaunchKernelGGL(k_task_segments, dim3(1), dim3(256), 0, s, nni, (int64_t)G, (const uint64_t*)hoff,
+                         (const uint64_t*)w.t_total, w.cap_t, depth, w.nt, w.over, sw.seg, sw.choff, w.ncol);
+      HP_CHECK_LAUNCH();
+    } else {
+      HP_TRY(bin_tasks(pv, P, T, prm->bin_guard, w, sw.slots, s));
+      // stable sort of the tasks by node; segments and chunk offsets per node
+      int nbits = 0;
+      while (((int64_t)1 << nbits) < sw.nn) ++nbits;
+      // the sorted node keys are only needed here: read them where the last
+      // pass left them; the Gaussian ids go back to task_g for the emit phase
+      uint32_t *snode = w.task_n, *sgid = w.task_g;
+      HP_TRY(hpsort::radix_sort(w.task_n, w.task_g, w.nt, w.cap_t, nbits, sw.tsort_ws, s, &snode, &sgid));
+      if (sgid != w.task_g) {
+        hipLaunchKernelGGL(hpsort::k_copy_u32, dim3(hpsort::copy_grid(w.cap_t)), dim3(256), 0, s, (const uint32_t*)sgid,
+                           w.task_g, (const uint64_t*)w.nt, w.cap_t);
+        HP_CHECK_LAUNCH();
+      }
+      hipLaunchKernelGGL(k_fill_zero_u32, dim3(hp_blocks(2 * sw.nn, 256)), dim3(256), 0, s, sw.seg, 2 * sw.nn);
+      HP_CHECK_LAUNCH();
+      hipLaunchKernelGGL(k_seg_ranges, dim3(hpsort::copy_grid(w.cap_t)), dim3(256), 0, s, (const uint32_t*)snode,
+                         (const uint64_t*)w.nt, nn, sw.seg);
+      HP_CHECK_LAUNCH();
+      hipLaunchKernelGGL(k_seg_chunks, dim3(hp_blocks(sw.nn, 256)), dim3(256), 0, s, sw.seg, nn, sw.nch);
+      HP_CHECK_LAUNCH();
+      HP_TRY((hpsort::scan_exclusive<uint32_t, uint32_t>(sw.nch, sw.choff, nullptr, sw.nn, sw.choff + sw.nn, sw.scan_ws,
+                                                         s)));
+      // hit columns and their counts (every count entry of the chunks present
+      // is written), scanned in tile-major order into output slots
+      hipLaunchKernelGGL(k_col_count, dim3(1), dim3(1), 0, s, (const uint32_t*)sw.choff, nn, depth, w.ncol);
       HP_CHECK_LAUNCH();
     }
-    hipLaunchKernelGGL(k_fill_zero_u32, dim3(hp_blocks(2 * sw.nn, 256)), dim3(256), 0, s, sw.seg, 2 * sw.nn);
-    HP_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_seg_ranges, dim3(hpsort::copy_grid(w.cap_t)), dim3(256), 0, s, (const uint32_t*)snode,
-                       (const uint64_t*)w.nt, nn, sw.seg);
-    HP_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_seg_chunks, dim3(hp_blocks(sw.nn, 256)), dim3(256), 0, s, sw.seg, nn, sw.nch);
-    HP_CHECK_LAUNCH();
-    HP_TRY((hpsort::scan_exclusive<uint32_t, uint32_t>(sw.nch, sw.choff, nullptr, sw.nn, sw.choff + sw.nn, sw.scan_ws,
-                                                       s)));
-    // hit columns and their counts (every count entry of the chunks present
-    // is written), scanned in tile-major order into output slots
-    hipLaunchKernelGGL(k_col_count, dim3(1), dim3(1), 0, s, (const uint32_t*)sw.choff, nn, depth, w.ncol);
+    hipLaunchKernelGGL(k_chunk_nodes, dim3(nn), dim3(256), 0, s, (const uint32_t*)sw.choff, sw.cnode);
     HP_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_bin_cols, dim3(chunk_grid(sw.nchunk_max)), dim3(256), 0, s, (const uint32_t*)sw.choff, nn,
-                       (const uint32_t*)sw.seg, (const uint32_t*)w.task_g, pv.disc, T, sw.wcol, sw.cnt);
+                       (const uint32_t*)sw.seg, (const uint32_t*)sw.cnode, (const uint32_t*)w.task_g, pv.disc, T,
+                       sw.wcol, sw.cnt);
     HP_CHECK_LAUNCH();
     HP_TRY((hpsort::scan_exclusive<uint64_t, uint32_t>(sw.cnt, sw.start, w.ncol, sw.L, w.p_total, sw.scan_ws, s)));
     hipLaunchKernelGGL(k_store_total, dim3(1), dim3(1), 0, s, (const uint64_t*)w.p_total, (const uint32_t*)w.over,
@@ -876,7 +1171,7 @@ hp_status hp_bin_sorted_widened(int32_t phase, const void* projected, int64_t P,
   if ((phase & HP_BIN_EMIT) && P > 0) {
     // the chunk count is read on the device: launch for the workspace's bound
     hipLaunchKernelGGL(k_bin_emit_sorted, dim3(chunk_grid(sw.nchunk_max)), dim3(256), 0, s, (const uint32_t*)sw.choff,
-                       nn, (const uint32_t*)sw.seg, (const uint32_t*)w.task_g, depth, (const uint64_t*)sw.wcol,
+                       nn, (const uint32_t*)sw.seg, (const uint32_t*)sw.cnode, (const uint32_t*)w.task_g, depth, (const uint64_t*)sw.wcol,
                        (const uint64_t*)sw.start, (const int64_t*)n_pairs, capacity, vals);
     HP_CHECK_LAUNCH();
     if (n_tiles > 0) {
