@@ -33,10 +33,20 @@ inline unsigned grid_for(int64_t cap) {
 }
 
 // tiles of block b: [t0, t1)
-__device__ __forceinline__ void block_tiles(int64_t n, int64_t* t0, int64_t* t1) {
-  const int64_t T = (n + kTile - 1) / kTile, G = gridDim.x, b = blockIdx.x;
+__device__ __forceinline__ void block_tiles(int64_t n, int64_t* t0, int64_t* t1, int64_t tile = kTile) {
+  const int64_t T = (n + tile - 1) / tile, G = gridDim.x, b = blockIdx.x;
   *t0 = T * b / G;
   *t1 = T * (b + 1) / G;
+}
+
+// The radix passes work on tiles of 1024 keys (4 per thread): a million keys
+// make ~1000 workgroups, enough to keep every CU busy, where 4096-key tiles
+// left one 4-wave workgroup per CU.
+constexpr int kRadixTile = 1024;
+
+inline unsigned radix_grid(int64_t cap) {
+  const int64_t t = (cap + kRadixTile - 1) / kRadixTile;
+  return (unsigned)(t < 1 ? 1 : (t > kMaxGrid ? kMaxGrid : t));
 }
 
 // ---------------------------------------------------------------------------
@@ -209,15 +219,15 @@ __global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t* __restr
   __syncthreads();
   const int64_t n = dev_count(cnt, cap);
   int64_t t0, t1;
-  block_tiles(n, &t0, &t1);
-  const int64_t lo = t0 * kTile, hi = t1 * kTile < n ? t1 * kTile : n;
+  block_tiles(n, &t0, &t1, kRadixTile);
+  const int64_t lo = t0 * kRadixTile, hi = t1 * kRadixTile < n ? t1 * kRadixTile : n;
   for (int64_t i = lo + threadIdx.x; i < hi; i += kThreads) atomicAdd(&s_h[(keys[i] >> shift) & mask], 1u);
   __syncthreads();
   for (int d = threadIdx.x; d < radix; d += kThreads) hist[(int64_t)d * gridDim.x + blockIdx.x] = s_h[d];
 }
 
 // Stable scatter of each block's tiles, in order.  Per tile, wave w owns the
-// contiguous items [w*1024, (w+1)*1024) and ranks them in 16 rounds of 64:
+// contiguous items [w*256, (w+1)*256) and ranks them in 4 rounds of 64:
 // equal digits inside a round are matched by ballots on the digit bits, and a
 // running count per digit, private to the wave, carries the rank across
 // rounds.  The tile is then placed in LDS sorted by digit, so that the global
@@ -228,26 +238,26 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(const uint32_t* __re
                                                             const uint64_t* __restrict__ cnt, int64_t cap, int shift,
                                                             int bits, const uint32_t* __restrict__ offs,
                                                             uint32_t* __restrict__ okeys, uint32_t* __restrict__ ovals) {
-  constexpr int kWaveItems = kTile / 4;     // 1024
-  constexpr int kRounds = kWaveItems / 64;  // 16
+  constexpr int kWaveItems = kRadixTile / 4;  // 256
+  constexpr int kRounds = kWaveItems / 64;     // 4
   __shared__ uint32_t s_cnt[4][256];
   __shared__ uint32_t s_loc[256];
   __shared__ uint32_t s_goff[256];
   __shared__ uint32_t s_wsum[4];
-  __shared__ uint32_t s_key[kTile];
-  __shared__ uint32_t s_val[kTile];
+  __shared__ uint32_t s_key[kRadixTile];
+  __shared__ uint32_t s_val[kRadixTile];
   const int radix = 1 << bits;
   const uint32_t mask = (uint32_t)radix - 1;
   const int tid = threadIdx.x, lane = hp_lane(), w = tid >> 6;
   const int64_t n = dev_count(cnt, cap);
   int64_t t0, t1;
-  block_tiles(n, &t0, &t1);
+  block_tiles(n, &t0, &t1, kRadixTile);
   for (int d = tid; d < radix; d += kThreads) s_goff[d] = offs[(int64_t)d * gridDim.x + blockIdx.x];
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   for (int64_t t = t0; t < t1; ++t) {
     for (int k = tid; k < 4 * 256; k += kThreads) (&s_cnt[0][0])[k] = 0;
     __syncthreads();
-    const int64_t base = t * kTile;
+    const int64_t base = t * kRadixTile;
     uint32_t rk[kRounds], kk[kRounds], vv[kRounds];
 #pragma unroll
     for (int r = 0; r < kRounds; ++r) {
@@ -295,7 +305,7 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(const uint32_t* __re
       }
     }
     __syncthreads();
-    const int nloc = (int)(n - base < kTile ? n - base : kTile);
+    const int nloc = (int)(n - base < kRadixTile ? n - base : kRadixTile);
     for (int lp = tid; lp < nloc; lp += kThreads) {
       const uint32_t key = s_key[lp];
       const uint32_t d = (key >> shift) & mask;
@@ -322,7 +332,7 @@ inline unsigned copy_grid(int64_t cap) {
 }
 
 inline size_t radix_ws_bytes(int64_t cap) {
-  const int64_t h = (int64_t)grid_for(cap) * 256;
+  const int64_t h = (int64_t)radix_grid(cap) * 256;
   return 2 * hp_align256((size_t)(cap > 0 ? cap : 1) * 4) + hp_align256((size_t)h * 4) + scan_ws_bytes<uint32_t>(h);
 }
 
@@ -338,7 +348,7 @@ inline hp_status radix_sort(uint32_t* keys, uint32_t* vals, const uint64_t* cnt,
   if (cap <= 1 || nbits <= 0) return HP_OK;
   const int passes = (nbits + 7) / 8;
   const int bits = (nbits + passes - 1) / passes;
-  const unsigned G = grid_for(cap);
+  const unsigned G = radix_grid(cap);
   char* p = (char*)ws;
   uint32_t* k2 = (uint32_t*)p; p += hp_align256((size_t)cap * 4);
   uint32_t* v2 = (uint32_t*)p; p += hp_align256((size_t)cap * 4);
