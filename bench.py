@@ -390,9 +390,25 @@ def cpu_baseline(wl, n_pix):
     t3 = time.perf_counter()
     per_px = (t3 - t1) / n_pix
     full = (t1 - t0) + per_px * npix
+    # the same on one core, over a sample 16x smaller (about as long)
+    n1 = max(16, n_pix // 16)
+    O.set_threads(1)
+    try:
+        s0 = time.perf_counter()
+        pr1 = O.preprocess(sc, cam)
+        s1 = time.perf_counter()
+        O.render(sc, cam, pr1, pix[:n1])
+        O.render_bwd(sc, cam, pr1, pix[:n1], np.ones((3, n1)), None)
+        s2 = time.perf_counter()
+    finally:
+        O.set_threads(threads)
+    full1 = (s1 - s0) + (s2 - s1) / n1 * npix
     return {"value": 1.0 / full, "unit": "renders/s", "cores": threads, "kind": "oracle",
             "sample": f"view 0: preprocess of all {sc.P} Gaussians ({t1 - t0:.2f} s) + brute-force fwd+bwd at "
-                      f"{n_pix} random pixels ({t3 - t1:.2f} s), extrapolated to {npix} pixels"}
+                      f"{n_pix} random pixels ({t3 - t1:.2f} s), extrapolated to {npix} pixels",
+            "single_core": {"value": 1.0 / full1, "unit": "renders/s", "cores": 1,
+                            "sample": f"the same on one thread: preprocess ({s1 - s0:.2f} s) + fwd+bwd at the first "
+                                      f"{n1} of those pixels ({s2 - s1:.2f} s), extrapolated"}}
 
 
 if __name__ == "__main__":
