@@ -227,8 +227,12 @@ class Rasterizer:
         self._lock = threading.RLock()
         self._sides = []
         # list capacities per (P, camera model, order, query) from earlier
-        # counts, and the counts not yet compared with their capacity
+        # counts; per (P, order, camera type, query) the largest count per
+        # active tile seen, which sizes the lists of a camera model not seen
+        # before (a new field of view) without a count read-back; and the
+        # counts not yet compared with their capacity
         self._cap_hint = {}
+        self._tile_ratio = {}
         self._pending = []
         self._overflows = []
         # one binning workspace per stream (work on a stream is ordered, so
@@ -250,6 +254,20 @@ class Rasterizer:
         gets by default); pass prefetch.get(i) as forward(..., prepared=) /
         render(..., prepared=)."""
         return Prefetch(self, g, cams, query, streams)
+
+    # camera models kept (masks and HSSIM tables): a serving trace with a
+    # field of view per request would otherwise grow the caches without end
+    CACHE_MODELS = 256
+
+    def _evict(self, cache: dict, ready_prefix) -> None:
+        """Drops the oldest entries of a per-camera-model cache beyond
+        CACHE_MODELS (and their ready events).  Work in flight keeps its own
+        references to the tensors.  Lock held."""
+        while len(cache) > self.CACHE_MODELS:
+            old = next(iter(cache))
+            del cache[old]
+            if ready_prefix is not None:
+                self._ready.pop(ready_prefix + old, None)
 
     def _created(self, key):
         ev = torch.cuda.Event()
@@ -302,6 +320,7 @@ class Rasterizer:
             ap = buf[off: off + 4 * na.value].view(torch.int32)
             m = MaskInfo(buf, int(na.value), int(nt.value), ap)
             self._masks[key] = m
+            self._evict(self._masks, ("mask",))
             self._created(("mask",) + key)
         else:
             self._await(("mask",) + key)
@@ -341,8 +360,29 @@ class Rasterizer:
         return (P, cam.mask_key(self.prm.tile_log2), query)
 
     @staticmethod
+    def _ratio_key(P: int, cam: Camera, query):
+        return (P, cam.order, cam.cam_type, query)
+
+    @staticmethod
     def _grow(n: int) -> int:
         return int(n * 1.25) + 65536
+
+    def capacity_hint(self, P: int, cam: Camera, query, n_tiles: int):
+        """List capacity for a binning of this view: the hint of its camera
+        model, else the largest count per active tile seen for its order and
+        camera type times its n_tiles (grown like a hint), else None (the
+        count has to be read back).  Called with the lock held or not."""
+        with self._lock:
+            cap = self._cap_hint.get(self._bin_key(P, cam, query))
+            if cap is not None:
+                return cap
+            r = self._tile_ratio.get(self._ratio_key(P, cam, query))
+        return None if r is None else self._grow(int(math.ceil(r * max(n_tiles, 1))))
+
+    def _note(self, key, rkey, n: int, n_tiles: int) -> None:
+        """A count seen: the hints grow to cover it.  Lock held."""
+        self._cap_hint[key] = max(self._cap_hint.get(key, 0), self._grow(n))
+        self._tile_ratio[rkey] = max(self._tile_ratio.get(rkey, 0.0), n / max(n_tiles, 1))
 
     def _bin_call(self, phase, proj, P, cam, query, vals, ranges, cap, cnt, ws):
         m = self.mask(cam)
@@ -358,11 +398,11 @@ class Rasterizer:
                    ws.numel(), _stream())
 
     def note_count(self, P: int, cam: Camera, query, n: int) -> None:
-        """Raise the list capacity hint of (P, camera model, query) to cover a
-        count of n entries."""
-        key = self._bin_key(P, cam, query)
+        """Raise the list capacity hints of (P, camera model, query) and of its
+        order and camera type to cover a count of n entries."""
+        n_tiles = self.mask(cam).n_tiles
         with self._lock:
-            self._cap_hint[key] = max(self._cap_hint.get(key, 0), self._grow(n))
+            self._note(self._bin_key(P, cam, query), self._ratio_key(P, cam, query), n, n_tiles)
 
     def bin_lists(self, proj: torch.Tensor, P: int, cam: Camera, query=None, track: bool = True):
         """Tile lists of one view, in per-tile depth order: (vals, ranges,
@@ -375,21 +415,20 @@ class Rasterizer:
         capacity leaves the lists empty and is reported by verify() (track
         False: the caller checks the returned PairCount itself)."""
         m = self.mask(cam)
-        key = self._bin_key(P, cam, query)
+        key, rkey = self._bin_key(P, cam, query), self._ratio_key(P, cam, query)
         nbytes = (A.lib().hp_bin_sorted_workspace_bytes(P, cam.order, self.prm.tile_log2) if query is None else
                   A.lib().hp_bin_query_workspace_bytes(P, cam.order, self.prm.tile_log2))
         ws = self.workspace(nbytes)
         cnt = torch.zeros(2, dtype=torch.int64, device=self.device)
         ranges = torch.empty((max(m.n_tiles, 1), 2), dtype=torch.int32, device=self.device)
-        with self._lock:
-            cap = self._cap_hint.get(key)
+        cap = self.capacity_hint(P, cam, query, m.n_tiles)
         if cap is None:
             self._bin_call(A.HP_BIN_COUNT, proj, P, cam, query, None, None, 0, cnt, ws)
             n = C.c_int64(0)
             A.call("hp_read_total", _p(cnt), C.byref(n), _stream())
             cap = max(int(n.value), 1)
             with self._lock:
-                self._cap_hint[key] = max(self._cap_hint.get(key, 0), self._grow(cap))
+                self._note(key, rkey, cap, m.n_tiles)
             vals = torch.empty(cap, dtype=torch.int32, device=self.device)
             self._bin_call(A.HP_BIN_EMIT, proj, P, cam, query, vals, ranges, cap, cnt, ws)
             return vals, ranges, PairCount(cnt, cap)
@@ -403,7 +442,7 @@ class Rasterizer:
         ev = torch.cuda.Event()
         ev.record(torch.cuda.current_stream(self.device))
         with self._lock:
-            self._pending.append((key, host, ev, cap))
+            self._pending.append((key, rkey, m.n_tiles, host, ev, cap))
             if len(self._pending) > 64:
                 self._settle(block=False)
         return vals, ranges, PairCount(cnt, cap)
@@ -413,14 +452,15 @@ class Rasterizer:
         (all of them, waiting, when block): hints grow, overflows are kept
         for verify().  Called with the lock held."""
         keep = []
-        for key, host, ev, cap in self._pending:
+        for item in self._pending:
+            key, rkey, n_tiles, host, ev, cap = item
             if block:
                 ev.synchronize()
             elif not ev.query():
-                keep.append((key, host, ev, cap))
+                keep.append(item)
                 continue
             n = int(host[0])
-            self._cap_hint[key] = max(self._cap_hint.get(key, 0), self._grow(n))
+            self._note(key, rkey, n, n_tiles)
             if n > cap:
                 self._overflows.append((key, n, cap))
         self._pending = keep
@@ -610,6 +650,7 @@ class Rasterizer:
                 A.call("hp_ssim_tables", C.byref(self.prm), _p(m.buf), cam.order, m.n_active, m.n_tiles, _p(t), n,
                        _stream())
                 self._ssim_tables[key] = t
+                self._evict(self._ssim_tables, None)
                 self._created(("ssim_tables",) + key)
             else:
                 self._await(("ssim_tables",) + key)

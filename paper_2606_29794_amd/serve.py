@@ -121,7 +121,7 @@ def device_error(e: BaseException) -> bool:
 
 def run_continuous(requests: list, n_slots: int, estimate, reserve: int, budget: int, max_batch: int, run_batch,
                    realtime: bool = True, fatal=device_error, batch_timeout: float | None = None,
-                   worker_init=None):
+                   worker_init=None, inline_idle: bool = False):
     """The continuous-batching loop, independent of the device.
 
     A dispatcher admits arrived requests (select_batch: FIFO, HBM budget)
@@ -143,6 +143,11 @@ def run_continuous(requests: list, n_slots: int, estimate, reserve: int, budget:
       with BatchTimeout: the device is presumed hung, and its worker thread
       is left behind (daemon) rather than waited for.
 
+    With inline_idle (and no batch_timeout), a batch of one request formed
+    while nothing else is in flight runs on the dispatcher's own thread:
+    under light load a request then starts as soon as it arrives, as in
+    one-at-a-time serving, with no hand-over to a worker thread.
+
     Returns (results in request order, makespan in seconds)."""
     reqs = sorted(requests, key=lambda r: r.arrival)
     n = len(reqs)
@@ -160,38 +165,41 @@ def run_continuous(requests: list, n_slots: int, estimate, reserve: int, budget:
         # without real-time replay every request is queued at t = 0
         results[r.rid] = Result(r.rid, arrival(r), t, rgb, T, status, error)
 
+    def execute(batch, est, slot) -> bool:
+        """Runs one batch and records its results; False after a fatal error."""
+        try:
+            outs = run_batch(batch, slot)
+            err = None
+        except BaseException as e:
+            if fatal(e):
+                with cv:
+                    st["error"] = e
+                    cv.notify_all()
+                return False
+            outs, err = None, f"{type(e).__name__}: {e}"
+        t = clock()
+        with cv:
+            for k, r in enumerate(batch):
+                if err is not None:
+                    finish(r, ERROR, t, error=err)
+                elif r.cancelled:
+                    finish(r, CANCELLED, t)
+                else:
+                    finish(r, OK, t, *outs[k])
+            outs = None
+            st["mem"] -= est
+            busy.pop(slot, None)
+            free.append(slot)
+            cv.notify_all()
+        return True
+
     def worker(slot):
         if worker_init is not None:
             worker_init()
         while True:
             item = inbox[slot].get()
-            if item is None:
+            if item is None or not execute(*item, slot):
                 return
-            batch, est = item
-            try:
-                outs = run_batch(batch, slot)
-                err = None
-            except BaseException as e:
-                if fatal(e):
-                    with cv:
-                        st["error"] = e
-                        cv.notify_all()
-                    return
-                outs, err = None, f"{type(e).__name__}: {e}"
-            t = clock()
-            with cv:
-                for k, r in enumerate(batch):
-                    if err is not None:
-                        finish(r, ERROR, t, error=err)
-                    elif r.cancelled:
-                        finish(r, CANCELLED, t)
-                    else:
-                        finish(r, OK, t, *outs[k])
-                outs = None
-                st["mem"] -= est
-                busy.pop(slot, None)
-                free.append(slot)
-                cv.notify_all()
 
     threads = [threading.Thread(target=worker, args=(k,), daemon=True) for k in range(n_slots)]
     for th in threads:
@@ -230,7 +238,16 @@ def run_continuous(requests: list, n_slots: int, estimate, reserve: int, budget:
                         st["mem"] += est
                         slot = free.pop(0)
                         busy[slot] = now
-                        inbox[slot].put((batch, est))
+                        if inline_idle and batch_timeout is None and len(batch) == 1 and len(busy) == 1:
+                            # nothing else in flight: the lone request runs
+                            # here, without a hand-over to a worker thread
+                            cv.release()
+                            try:
+                                execute(batch, est, slot)
+                            finally:
+                                cv.acquire()
+                        else:
+                            inbox[slot].put((batch, est))
                         continue
                 # sleep until a batch completes or the next request arrives
                 wait = 0.05
@@ -257,7 +274,8 @@ def _percentile(x, q):
 
 class Server:
     def __init__(self, gaussians: Gaussians, rasterizer: Rasterizer | None = None, max_batch: int = 8,
-                 n_streams: int = 3, hbm_budget_bytes: int = 48 << 30, persistent: bool = False):
+                 n_streams: int = 2, hbm_budget_bytes: int = 48 << 30, persistent: bool = False,
+                 inline_idle: bool = False):
         if persistent:
             # hp_render_fwd_persistent is switched off in the library: its
             # launches did not end on MI355X and the cause is not known
@@ -268,24 +286,27 @@ class Server:
         dev = self.g.mean.device
         self.streams = [torch.cuda.Stream(device=dev) for _ in range(n_streams)]
         self.budget = hbm_budget_bytes
+        self.inline_idle = inline_idle
 
     # ---- memory accounting ---------------------------------------------------
     def _estimate(self, cam: Camera) -> int:
         """Device bytes one request holds while it is in flight, from the
         library's own sizes: its projected records (hp_projected_bytes), its
-        list buffer (the capacity the binning will use: the hint from earlier
-        counts of the camera model, else a first count's worth), its tile
-        ranges and its outputs (rgb, T, n_contrib).  The binning workspaces
-        are held per stream and reserved from the budget up front
-        (workspace_reserve)."""
+        list buffer (at most the capacity the binning will use: the hint of
+        the camera model, else the largest count per active tile seen for
+        its order and camera type over every tile of the sphere when its mask
+        is not made yet), its tile ranges and its outputs (rgb, T,
+        n_contrib).  The binning workspaces are held per stream and reserved
+        from the budget up front (workspace_reserve)."""
         R, P = self.R, self.g.P
-        m_key = R._bin_key(P, cam, None)
-        with R._lock:
-            cap = R._cap_hint.get(m_key)
         npix = 12 << (2 * cam.order)
         ntile = 12 << (2 * max(0, cam.order - R.prm.tile_log2))
+        with R._lock:
+            m = R._masks.get(cam.mask_key(R.prm.tile_log2))
+        # the mask's tile count when the camera model has one, else every tile
+        cap = R.capacity_hint(P, cam, None, m.n_tiles if m is not None else ntile)
         if cap is None:
-            cap = 64 * P   # before the first count of the model: a generous guess
+            cap = 64 * P   # before the first count of the order and camera type: a generous guess
         # + the allocator's rounding of the request's seven buffers (512 B each)
         return A.lib().hp_projected_bytes(P) + 4 * cap + 8 * ntile + 20 * npix + 7 * 512
 
@@ -355,8 +376,9 @@ class Server:
         capacity hints and they run again (once more at most)."""
         P = self.g.P
         redo = []
-        for k, (r, cnt) in enumerate(zip(b.reqs, b.counts)):
-            n = cnt.value(0)
+        # every count of the batch in one read-back
+        ns = torch.stack([c.dev[0] for c in b.counts]).cpu().tolist()
+        for k, (r, cnt, n) in enumerate(zip(b.reqs, b.counts, ns)):
             self.R.note_count(P, r.camera, None, n)
             if n > cnt.capacity:
                 redo.append(k)
@@ -393,7 +415,7 @@ class Server:
         results, makespan = run_continuous(
             requests, len(self.streams), lambda r: self._estimate(r.camera), self.workspace_reserve(), self.budget,
             self.max_batch, run, realtime=realtime, batch_timeout=batch_timeout,
-            worker_init=lambda: torch.cuda.set_device(dev))
+            worker_init=lambda: torch.cuda.set_device(dev), inline_idle=self.inline_idle)
         return ServeStats.of(results, makespan)
 
     def serve_sequential(self, requests: list, realtime: bool = True, keep_outputs: bool = False):

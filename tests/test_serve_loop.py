@@ -152,3 +152,27 @@ def test_device_error_classification():
     assert device_error(RuntimeError("HIP error: an illegal memory access was encountered"))
     assert not device_error(RuntimeError("tile lists exceed their buffer after a recount"))
     assert device_error(KeyboardInterrupt())
+
+
+def test_lone_request_runs_inline_when_idle():
+    """With inline_idle, a batch of one formed while nothing is in flight runs
+    on the dispatcher's thread; a burst still goes to the workers."""
+    main = threading.get_ident()
+    where = {}
+
+    class Where(Fake):
+        def run(self, batch, slot):
+            for r in batch:
+                where[r.rid] = threading.get_ident()
+            return super().run(batch, slot)
+
+    f = Where(dt=0.01)
+    reqs = [Request(k, 0.05 * k, camera=None) for k in range(4)]        # spaced: each alone
+    res, _ = run_continuous(reqs, 2, f.estimate, 0, 10**9, 4, f.run, realtime=True, inline_idle=True)
+    assert all(r.status == OK for r in res)
+    assert all(where[k] == main for k in range(4))
+    where.clear()
+    f = Where(dt=0.05)
+    res, _ = run_continuous(_reqs(9), 2, f.estimate, 0, 10**9, 4, f.run, realtime=False, inline_idle=True)
+    assert all(r.status == OK for r in res)
+    assert any(t != main for t in where.values())
