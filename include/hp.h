@@ -420,8 +420,9 @@ hp_status hp_density_stats(const void* projected, int64_t P, const float* acc, c
  * img, ref: [3][n_active] in mask order; ssim_map [3][n_active] nullable.
  * If dL_dloss (device scalar) is non-null, dL_dimg [3][n_active] receives
  * dL_dloss * dL/dimg.  tables: from hp_ssim_tables for this mask (required).
- * Requires order >= 3 and tiles of 8 or 16 pixels a side
- * (tile_log2 = 4, or 3 at order 3) (HP_ERR_UNSUPPORTED otherwise).
+ * Orders 0-12, tiles of 1 to 16 pixels a side; tiles narrower than 8
+ * pixels (orders 0-2), where the window is wider than a face, sum the 121
+ * taps directly instead of in two separable passes.
  * ws: hp_ssim_workspace_bytes. */
 size_t hp_ssim_workspace_bytes(int32_t order, int32_t tile_log2, int64_t n_active);
 hp_status hp_ssim(const float* img, const float* ref, int64_t n_active, int32_t n_tiles, int32_t order,

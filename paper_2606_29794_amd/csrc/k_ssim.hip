@@ -189,7 +189,10 @@ __global__ __launch_bounds__(256) void k_ssim_fwd(SsimArgs A, const float* __res
   ss_tile_origin(A, ct, &f, &x0, &y0);
   // zone windows: the tile takes the direct path when it holds a polar pixel
   const int N = 1 << A.order;
-  const bool direct = ZONES && (f < 4 ? (x0 + y0 + 2 * B - 2 >= N) : (f >= 8 ? (x0 + y0 <= N - 2) : false));
+  // tiles narrower than 8 pixels (orders 0-2) always take the direct path
+  constexpr bool kSmall = B < 8;
+  const bool direct =
+      kSmall || (ZONES && (f < 4 ? (x0 + y0 + 2 * B - 2 >= N) : (f >= 8 ? (x0 + y0 <= N - 2) : false)));
   // the patch from the tile's slot table: every load of the thread's cells
   // goes out before the first LDS store
   constexpr int NG = (H * H + 255) / 256;
@@ -246,7 +249,7 @@ __global__ __launch_bounds__(256) void k_ssim_fwd(SsimArgs A, const float* __res
     }
   }
   float Sm[16];
-  if (!direct) {
+  if constexpr (!kSmall) if (!direct) {
     // pass 1 along x: item (row r, channel ch, quarter k) slides the window
     // over the 14 cells behind its 4 outputs
     constexpr int Q = B / 4, NI1 = H * 3 * Q;
@@ -328,13 +331,14 @@ __global__ __launch_bounds__(256) void k_ssim_fwd(SsimArgs A, const float* __res
       for (int k = 0; k < 16; ++k) Sm[k] = S[k][tid];
       if (full) Sm[0] = A.gsum * A.gsum;
     }
-  } else if (ZONES) {
-    // direct 121-tap sums: polar pixels weigh by great-circle distance,
-    // equatorial ones (in a mixed tile) by the chart window
+  }
+  if (direct) {
+    // direct 121-tap sums: polar pixels (zone windows) weigh by great-circle
+    // distance, the others by the chart window
 #pragma unroll
     for (int k = 0; k < 16; ++k) Sm[k] = 0.f;
     if (own) {
-      const bool polar = ss_polar(A.order, hp_xyf_nest(A.order, x0 + px, y0 + py, f));
+      const bool polar = ZONES && ss_polar(A.order, hp_xyf_nest(A.order, x0 + px, y0 + py, f));
       const double* up = s.dir[(py + SS_R) * H + px + SS_R];
       for (int b = 0; b < SS_W; ++b) {
         for (int a = 0; a < SS_W; ++a) {
@@ -493,12 +497,15 @@ __global__ __launch_bounds__(256) void k_ssim_bwd(SsimArgs A, const float* __res
       }
     }
   }
-  // the separable pass needs every neighbour's window to be the chart one
-  const bool direct = ZONES && __syncthreads_or(any_polar);
-  if (!ZONES) __syncthreads();
+  // the separable pass needs every neighbour's window to be the chart one;
+  // tiles narrower than 8 pixels always take the direct path
+  constexpr bool kSmall = B < 8;
+  bool direct = kSmall;
+  if (ZONES) direct = __syncthreads_or(any_polar) || kSmall;
+  else __syncthreads();
   const int px = (int)hp_compact_bits((uint32_t)tid), py = (int)hp_compact_bits((uint32_t)tid >> 1);
   float Sm[9];
-  if (!direct) {
+  if constexpr (!kSmall) if (!direct) {
     constexpr int Q = B / 4, NI1 = H * 9 * Q;
     float o[4][4];  // up to 4 items per thread, 4 outputs each
     int kk[4], rr[4], cc[4];
@@ -548,18 +555,22 @@ __global__ __launch_bounds__(256) void k_ssim_bwd(SsimArgs A, const float* __res
 #pragma unroll
       for (int k = 0; k < 9; ++k) Sm[k] = S[k][tid];
     }
-  } else if (ZONES) {
-    // directions of the patch cells (over the first pass's place)
-    for (int i = tid; i < H * H; i += 256) {
-      const int cx = i % H, cy = i / H;
-      const int64_t q = hp_chart_pixel(A.order, f, x0 + cx - SS_R, y0 + cy - SS_R);
-      double d[3] = {0.0, 0.0, 0.0};
-      if (q >= 0) hp_pix_dir(A.order, q, d);
-      s.dir[i][0] = d[0];
-      s.dir[i][1] = d[1];
-      s.dir[i][2] = d[2];
+  }
+  if (direct) {
+    // directions of the patch cells (over the first pass's place), for the
+    // polar windows
+    if (ZONES) {
+      for (int i = tid; i < H * H; i += 256) {
+        const int cx = i % H, cy = i / H;
+        const int64_t q = hp_chart_pixel(A.order, f, x0 + cx - SS_R, y0 + cy - SS_R);
+        double d[3] = {0.0, 0.0, 0.0};
+        if (q >= 0) hp_pix_dir(A.order, q, d);
+        s.dir[i][0] = d[0];
+        s.dir[i][1] = d[1];
+        s.dir[i][2] = d[2];
+      }
+      __syncthreads();
     }
-    __syncthreads();
 #pragma unroll
     for (int k = 0; k < 9; ++k) Sm[k] = 0.f;
     if (tid < B * B) {
@@ -569,8 +580,9 @@ __global__ __launch_bounds__(256) void k_ssim_bwd(SsimArgs A, const float* __res
           const int cy = py + b, cx = px + a;
           // q's own window at p: the great-circle Gaussian for a polar q,
           // the (symmetric) chart taps otherwise
-          const float w = s.polar[cy * H + cx] ? __expf(-(float)(ss_dist2(up, s.dir[cy * H + cx]) * A.wscale))
-                                               : A.g[a] * A.g[b];
+          const float w = (ZONES && s.polar[cy * H + cx])
+                              ? __expf(-(float)(ss_dist2(up, s.dir[cy * H + cx]) * A.wscale))
+                              : A.g[a] * A.g[b];
 #pragma unroll
           for (int k = 0; k < 9; ++k) Sm[k] = fmaf(w, s.in[k][cy][cx], Sm[k]);
         }
@@ -630,10 +642,10 @@ static hp_status ssim_mask_args(int32_t order, const hp_params* prm, const void*
                                 int32_t n_tiles, SsimArgs* A) {
   HP_TRY(hp_check_params(prm));
   if (!mask) return HP_ERR_INVALID_ARG;
-  if (order < 3 || order > HP_MAX_ORDER) return order < 0 || order > HP_MAX_ORDER ? HP_ERR_INVALID_ARG : HP_ERR_UNSUPPORTED;
+  if (order < 0 || order > HP_MAX_ORDER) return HP_ERR_INVALID_ARG;
   const HpGeom g = hp_geom(order, prm->tile_log2);
-  // the patch layout holds tiles of 8 or 16 pixels a side
-  if (g.b != 3 && g.b != 4) return HP_ERR_UNSUPPORTED;
+  // tiles of 1 to 16 pixels a side (tiles under 8 pixels take the direct path)
+  if (g.b < 0 || g.b > 4) return HP_ERR_UNSUPPORTED;
   if (n_tiles <= 0 || n_tiles > g.ntile || n_active <= 0 || n_active > g.npix) return HP_ERR_INVALID_ARG;
   const HpMaskView mv = hp_mask_view((const char*)mask, g);
   A->order = order; A->b = g.b; A->kt = g.kt;
@@ -649,10 +661,13 @@ extern "C" hp_status hp_ssim_tables(const hp_params* prm, const void* mask, int3
   if (!tables) return HP_ERR_INVALID_ARG;
   if (tables_bytes < hp_ssim_tables_bytes(order, prm->tile_log2, n_tiles)) return HP_ERR_CAPACITY;
   hipStream_t s = (hipStream_t)stream;
-  if (A.b == 4)
-    hipLaunchKernelGGL(k_ssim_tables<16>, dim3((unsigned)n_tiles), dim3(256), 0, s, A, tables);
-  else
-    hipLaunchKernelGGL(k_ssim_tables<8>, dim3((unsigned)n_tiles), dim3(256), 0, s, A, tables);
+  switch (A.b) {
+    case 4: hipLaunchKernelGGL(k_ssim_tables<16>, dim3((unsigned)n_tiles), dim3(256), 0, s, A, tables); break;
+    case 3: hipLaunchKernelGGL(k_ssim_tables<8>, dim3((unsigned)n_tiles), dim3(256), 0, s, A, tables); break;
+    case 2: hipLaunchKernelGGL(k_ssim_tables<4>, dim3((unsigned)n_tiles), dim3(256), 0, s, A, tables); break;
+    case 1: hipLaunchKernelGGL(k_ssim_tables<2>, dim3((unsigned)n_tiles), dim3(256), 0, s, A, tables); break;
+    default: hipLaunchKernelGGL(k_ssim_tables<1>, dim3((unsigned)n_tiles), dim3(256), 0, s, A, tables); break;
+  }
   HP_CHECK_LAUNCH();
   return HP_OK;
 }
@@ -697,8 +712,13 @@ static hp_status ssim_fwd_launch_b(const SsimArgs& A, bool zones, const float* i
 
 static hp_status ssim_fwd_launch(const SsimArgs& A, bool zones, const float* img, const float* ref, int32_t n_tiles,
                                  float lam, float* out, float* ssim_map, float* Gm, float2* part, hipStream_t s) {
-  if (A.b == 4) HP_TRY(ssim_fwd_launch_b<16>(A, zones, img, ref, n_tiles, ssim_map, Gm, part, s));
-  else HP_TRY(ssim_fwd_launch_b<8>(A, zones, img, ref, n_tiles, ssim_map, Gm, part, s));
+  switch (A.b) {
+    case 4: HP_TRY(ssim_fwd_launch_b<16>(A, zones, img, ref, n_tiles, ssim_map, Gm, part, s)); break;
+    case 3: HP_TRY(ssim_fwd_launch_b<8>(A, zones, img, ref, n_tiles, ssim_map, Gm, part, s)); break;
+    case 2: HP_TRY(ssim_fwd_launch_b<4>(A, zones, img, ref, n_tiles, ssim_map, Gm, part, s)); break;
+    case 1: HP_TRY(ssim_fwd_launch_b<2>(A, zones, img, ref, n_tiles, ssim_map, Gm, part, s)); break;
+    default: HP_TRY(ssim_fwd_launch_b<1>(A, zones, img, ref, n_tiles, ssim_map, Gm, part, s)); break;
+  }
   hipLaunchKernelGGL(k_ssim_reduce, dim3(1), dim3(1024), 0, s, (const float2*)part, (int)n_tiles, A.n_active, lam, out);
   HP_CHECK_LAUNCH();
   return HP_OK;
@@ -720,8 +740,13 @@ static hp_status ssim_bwd_launch_b(const SsimArgs& A, bool zones, const float* i
 
 static hp_status ssim_bwd_launch(const SsimArgs& A, bool zones, const float* img, const float* ref, int32_t n_tiles,
                                  const float* Gm, const float* dL_dloss, float* dL_dimg, hipStream_t s) {
-  if (A.b == 4) return ssim_bwd_launch_b<16>(A, zones, img, ref, n_tiles, Gm, dL_dloss, dL_dimg, s);
-  return ssim_bwd_launch_b<8>(A, zones, img, ref, n_tiles, Gm, dL_dloss, dL_dimg, s);
+  switch (A.b) {
+    case 4: return ssim_bwd_launch_b<16>(A, zones, img, ref, n_tiles, Gm, dL_dloss, dL_dimg, s);
+    case 3: return ssim_bwd_launch_b<8>(A, zones, img, ref, n_tiles, Gm, dL_dloss, dL_dimg, s);
+    case 2: return ssim_bwd_launch_b<4>(A, zones, img, ref, n_tiles, Gm, dL_dloss, dL_dimg, s);
+    case 1: return ssim_bwd_launch_b<2>(A, zones, img, ref, n_tiles, Gm, dL_dloss, dL_dimg, s);
+    default: return ssim_bwd_launch_b<1>(A, zones, img, ref, n_tiles, Gm, dL_dloss, dL_dimg, s);
+  }
 }
 
 extern "C" hp_status hp_ssim(const float* img, const float* ref, int64_t n_active, int32_t n_tiles, int32_t order,

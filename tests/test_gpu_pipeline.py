@@ -153,11 +153,14 @@ def test_render_backward_matches_oracle(R, case):
 
 
 @pytest.mark.parametrize("zones", [False, True])
-@pytest.mark.parametrize("order,masked", [(3, False), (4, False), (5, True), (6, True), (3, True), (7, False)])
+@pytest.mark.parametrize("order,masked", [(0, False), (1, False), (2, False), (2, True), (3, False), (4, False),
+                                          (5, True), (6, True), (3, True), (7, False)])
 def test_hssim_and_loss(R, order, masked, zones):
     """hp_ssim (mean, L1, loss, map, dL/dimg) and its split entry points
     against the oracle, with the isotropic chart window and with the
-    zone-specific windows (polar caps weighted by great-circle distance)."""
+    zone-specific windows (polar caps weighted by great-circle distance).
+    Orders 0-2 (tiles narrower than 8 pixels, windows wider than a face)
+    take the direct path."""
     import torch
     from paper_2606_29794_amd.raster import Camera
     rng = np.random.default_rng(order)
