@@ -170,13 +170,16 @@ __device__ __forceinline__ void widen_half(float wsin, float wcos, float* sg, fl
 
 // direction and (sin, cos) of half the test angle r_s + guard (the sine is
 // precomputed in the Gaussian's disc entry; the half angle is at most pi/2,
-// so the cosine is the non-negative root), widened by the table's margin
+// so the cosine is the non-negative root), widened by the table's margin.
+// A culled Gaussian (r_s = 0) has an all-zero disc entry, so the sine alone
+// tells it apart (a kept one has r_s > 0 and a positive sine): one gather
+// per Gaussian, not two.
 __device__ __forceinline__ void gauss_dir(const float4* disc, const float* radius, uint32_t gid, const BinTables& T,
                                           float* u, float* sg, float* cg, bool* ok) {
-  const float rs = radius[gid];
-  *ok = rs > 0.f;
-  if (!*ok) return;
+  (void)radius;
   const hp_cfloatp r = (hp_cfloatp)disc + 4 * (int64_t)gid;
+  *ok = r[3] > 0.f;
+  if (!*ok) return;
   u[0] = r[0]; u[1] = r[1]; u[2] = r[2];
   *sg = r[3];
   *cg = sqrtf(fmaxf(0.f, 1.f - *sg * *sg));
