@@ -246,43 +246,46 @@ def serve_bench(n_requests):
 
 
 def kernel_breakdown(R, params, cams, targets, torch, A):
-    """One instrumented step: HIP events (torch's current stream, the stream
-    every call is issued on) around each stage; algorithmic work per stage."""
-    from paper_2606_29794_amd.raster import Gaussians
-    from paper_2606_29794_amd.render import hssim_loss
+    """One instrumented view: HIP events (torch's current stream, the stream
+    every call is issued on) around each stage; algorithmic work per stage.
+    Each stage runs REPS times back to back between its two events, behind
+    a ~0.1 ms fill kernel queued first, so that the timed span holds the
+    stage's GPU work and not the host's launch latency (which the GPU would
+    otherwise sit idle through)."""
+    from paper_2606_29794_amd.raster import FwdState, Gaussians
     g = Gaussians(*[p.detach() for p in params])
     cam = cams[0]
+    dev = g.mean.device
     ev = lambda: torch.cuda.Event(enable_timing=True)
+    filler = torch.empty(128 << 20, dtype=torch.float32, device=dev)
     times = {}
-    reps = 3
-    for _ in range(reps):
-        e = [ev() for _ in range(9)]
-        e[0].record()
-        proj = R.preprocess(g, cam)
-        e[1].record()
-        m = R.mask(cam)
-        vals, ranges, cnt = R.bin_lists(proj, g.P, cam)
-        e[2].record()
-        e[3].record()
-        rgb, T, nc, nu = R.render_fwd(proj, g.P, vals, ranges, cam, want_used=True)
-        e[4].record()
-        up = torch.ones(1, device=rgb.device)
-        _, _, dimg = R.ssim_loss(rgb, targets[0], cam, dL_dloss=up)
-        e[5].record()
-        from paper_2606_29794_amd.raster import FwdState
-        st = FwdState(cam, m, proj, vals, ranges, cnt, rgb, T, nc, g.P)
-        z = torch.zeros_like
-        gr = Gaussians(z(g.mean), z(g.scale), z(g.rot), z(g.opacity), z(g.sh))
-        acc = torch.zeros((10, g.P), dtype=torch.float32, device=g.mean.device)
-        e[6].record()
-        R.backward_pixels(st, dimg, None, acc)  # k_render_bwd alone
-        e[7].record()
-        R.backward_preprocess(g, cam, acc, gr)
-        e[8].record()
+    REPS = 4
+
+    def timed(name, fn):
+        filler.fill_(0.0)
+        e0, e1 = ev(), ev()
+        e0.record()
+        for _ in range(REPS):
+            out = fn()
+        e1.record()
         torch.cuda.synchronize()
-        for k, (a, b) in enumerate([(0, 1), (1, 2), (3, 4), (4, 5), (6, 7), (7, 8)]):
-            name = ["preprocess", "bin_and_sort", "render_fwd", "ssim_fwd_bwd", "render_bwd", "preprocess_bwd"][k]
-            times.setdefault(name, []).append(e[a].elapsed_time(e[b]))
+        times.setdefault(name, []).append(e0.elapsed_time(e1) / REPS)
+        return out
+
+    up = torch.ones(1, device=dev)
+    z = torch.zeros_like
+    for _ in range(3):
+        proj = timed("preprocess", lambda: R.preprocess(g, cam))
+        m = R.mask(cam)
+        vals, ranges, cnt = timed("bin_and_sort", lambda: R.bin_lists(proj, g.P, cam))
+        rgb, T, nc, nu = timed("render_fwd", lambda: R.render_fwd(proj, g.P, vals, ranges, cam, want_used=True))
+        _, _, dimg = timed("ssim_fwd_bwd", lambda: R.ssim_loss(rgb, targets[0], cam, dL_dloss=up))
+        st = FwdState(cam, m, proj, vals, ranges, cnt, rgb, T, nc, g.P)
+        gr = Gaussians(z(g.mean), z(g.scale), z(g.rot), z(g.opacity), z(g.sh))
+        acc = torch.zeros((10, g.P), dtype=torch.float32, device=dev)
+        timed("render_bwd", lambda: R.backward_pixels(st, dimg, None, acc))  # k_render_bwd alone
+        timed("preprocess_bwd", lambda: R.backward_preprocess(g, cam, acc, gr))
+    R.verify()
     med = {k: float(np.median(v)) for k, v in times.items()}
     n = cnt.value(0)
     evals = int(nc.to(torch.int64).sum().item())
