@@ -6,6 +6,7 @@
 // active pixel.  Gaussians are processed in order of radial depth so that the
 // pair list is depth-ordered, which the stable tile sort then preserves.
 #include "hp_sort_impl.h"
+#include <type_traits>
 
 // Work is split in two so that no lane walks a large Gaussian alone:
 //  coarse: each Gaussian walks the quadtree from the 12 faces down to the
@@ -113,6 +114,26 @@ __device__ __forceinline__ bool hp_cap_test(float cx, float cy, float cz, float 
   return (ch <= 0.f) | (chord2 <= sh2 * sh2);
 }
 
+// The same test without the cos((R + theta) / 2) <= 0 branch, for callers
+// that know R + theta < pi: when cos(theta / 2) > sin(R / 2) + 1e-5 the
+// half-angle sum is below pi / 2 by a margin far beyond the rounding of ch,
+// so the branch cannot fire and both forms decide alike.
+__device__ __forceinline__ bool hp_cap_test_near(float cx, float cy, float cz, float sR, float cR, float ux, float uy,
+                                                 float uz, float sg, float cg) {
+  const float dx = cx - ux, dy = cy - uy, dz = cz - uz;
+  const float chord2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+  const float sh2 = fmaf(2.f * sR, cg, (2.f * cR) * sg);
+  return chord2 <= sh2 * sh2;
+}
+constexpr float kNearMargin = 1e-5f;
+
+// largest value of v over the wave (all lanes active)
+__device__ __forceinline__ float hp_wave_max(float v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
 // cap test of node `node` (inactive nodes fail)
 __device__ __forceinline__ bool node_pass(const BinTables& T, int64_t node, float ux, float uy, float uz, float sg,
                                           float cg) {
@@ -210,6 +231,14 @@ __device__ __forceinline__ int load_top_nodes(const BinTables& T, TopNodes& S) {
   return ntop;
 }
 
+// largest sin(R/2) over the LDS copy's nodes below the faces (levels 1-2), for
+// the near-test guard; called by every lane after the copy is synchronised
+__device__ __forceinline__ float top_srmax(const TopNodes& S, int ntop) {
+  float m = 0.f;
+  for (int t = 12 + hp_lane(); t < ntop; t += 64) m = fmaxf(m, S.sc[t].x);
+  return hp_wave_max(m);
+}
+
 // Calls emit(i) for the passing nodes i at level T.ls, in increasing order,
 // of the Gaussian with direction u and half test angle (sg, cg): the top
 // levels are tested from the LDS copy, deeper ones from memory.  Level 1 (48
@@ -217,15 +246,19 @@ __device__ __forceinline__ int load_top_nodes(const BinTables& T, TopNodes& S) {
 // converged where a walk from the 12 faces would diverge at once; below a
 // passing level-1 node the children are tested in order (level 2) and deeper
 // levels are walked depth-first.
+// srmax: top_srmax of the LDS copy.  When every walking lane of the wave has
+// cos(theta / 2) > srmax + margin, the LDS nodes take the near test.
 template <class Emit>
-__device__ __forceinline__ void coarse_nodes(const BinTables& T, const TopNodes& S, int ntop, const float* u, float sg,
-                                             float cg, Emit&& emit) {
+__device__ __forceinline__ void coarse_nodes(const BinTables& T, const TopNodes& S, int ntop, float srmax,
+                                             const float* u, float sg, float cg, Emit&& emit) {
+  const bool near = __builtin_amdgcn_ballot_w64(!(cg > srmax + kNearMargin)) == 0;
   auto pass = [&](int64_t node) -> bool {
     if (node < ntop) {
       if (!S.act[node]) return false;
       const float4 c = S.cap[node];
       const float2 h = S.sc[node];
-      return hp_cap_test(c.x, c.y, c.z, h.x, h.y, u[0], u[1], u[2], sg, cg);
+      return near && node >= 12 ? hp_cap_test_near(c.x, c.y, c.z, h.x, h.y, u[0], u[1], u[2], sg, cg)
+                                : hp_cap_test(c.x, c.y, c.z, h.x, h.y, u[0], u[1], u[2], sg, cg);
     }
     return node_pass(T, node, u[0], u[1], u[2], sg, cg);
   };
@@ -265,6 +298,7 @@ __global__ __launch_bounds__(256) void k_bin_coarse(int64_t P, const uint32_t* _
   __shared__ TopNodes S;
   const int ntop = load_top_nodes(T, S);
   __syncthreads();
+  const float srmax = top_srmax(S, ntop);
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= P) return;
   const uint32_t gid = order[k];
@@ -292,7 +326,7 @@ __global__ __launch_bounds__(256) void k_bin_coarse(int64_t P, const uint32_t* _
     return;
   }
   uint32_t cnt = 0;
-  coarse_nodes(T, S, ntop, u, sg, cg, [&](int64_t i) {
+  coarse_nodes(T, S, ntop, srmax, u, sg, cg, [&](int64_t i) {
     if (EMIT && cnt < room) {
       task_g[base + cnt] = gid;
       task_n[base + cnt] = (uint32_t)i;
@@ -323,6 +357,7 @@ __global__ __launch_bounds__(256) void k_task_count(int64_t P, const uint32_t* _
   const int ntop = load_top_nodes(T, S);
   for (int n = threadIdx.x; n < nn; n += blockDim.x) s_cnt[n] = 0u;
   __syncthreads();
+  const float srmax = top_srmax(S, ntop);
   const int gb = blockIdx.x;
   const int64_t k = (int64_t)gb * blockDim.x + threadIdx.x;
   if (k < P) {
@@ -332,7 +367,7 @@ __global__ __launch_bounds__(256) void k_task_count(int64_t P, const uint32_t* _
     gauss_dir(disc, radius, gid, T, u, &sg, &cg, &ok);
     uint32_t cnt = 0;
     if (ok) {
-      coarse_nodes(T, S, ntop, u, sg, cg, [&](int64_t i) {
+      coarse_nodes(T, S, ntop, srmax, u, sg, cg, [&](int64_t i) {
         if (cnt < (uint32_t)kSlots) slots[(int64_t)cnt * P + k] = (uint32_t)i;
         atomicAdd(&s_cnt[i], 1u);
         ++cnt;
@@ -375,6 +410,7 @@ __global__ __launch_bounds__(256) void k_task_scatter(int64_t P, const uint32_t*
   for (int n = threadIdx.x; n < nn; n += blockDim.x) s_off[n] = hoff[(int64_t)n * G + blockIdx.x];
   for (int i = threadIdx.x; i < 8 * nn; i += blockDim.x) s_bits[i] = 0u;
   __syncthreads();
+  const float srmax = top_srmax(S, ntop);
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool live = k < P;
   const uint32_t cnt = live ? tcount[k] : 0u;
@@ -391,7 +427,7 @@ __global__ __launch_bounds__(256) void k_task_scatter(int64_t P, const uint32_t*
     float u[3], sg, cg;
     bool ok;
     gauss_dir(disc, radius, gid, T, u, &sg, &cg, &ok);
-    if (ok) coarse_nodes(T, S, ntop, u, sg, cg, f);
+    if (ok) coarse_nodes(T, S, ntop, srmax, u, sg, cg, f);
   };
   if (cnt) each_node([&](int64_t i) { atomicOr(&s_bits[8 * i + w], bit); });
   __syncthreads();
@@ -746,6 +782,12 @@ __global__ __launch_bounds__(256) void k_bin_cols(const uint32_t* __restrict__ c
     s_disc[wv][lane] = make_float4(dl.x, dl.y, dl.z, sgl);
     s_cg[wv][lane] = cgl;
     __builtin_amdgcn_wave_barrier();
+    // tasks far from the antipodal case for every leaf of the node, as a wave
+    // mask: groups of such tasks take the near test (hp_cap_test_near),
+    // which decides alike; a Gaussian whose disc covers nearly the whole
+    // sphere keeps the full test
+    const float srl = hp_wave_max(h.x);
+    const uint64_t nearmask = __builtin_amdgcn_ballot_w64(!((uint32_t)lane < ntask) || cgl > srl + kNearMargin);
     // bits of tasks 0..31 and 32..63 are kept apart so that every set is a
     // 32-bit select-or
     uint32_t Wh[2] = {0u, 0u};
@@ -753,21 +795,29 @@ __global__ __launch_bounds__(256) void k_bin_cols(const uint32_t* __restrict__ c
     for (int half = 0; half < 2; ++half) {
       const uint32_t jend = ntask < 32u * (half + 1) ? ntask : 32u * (half + 1);
       for (uint32_t j0 = 32u * half; j0 < jend; j0 += kFineGroup) {
-        float ux[kFineGroup], uy[kFineGroup], uz[kFineGroup], sg[kFineGroup], cg[kFineGroup];
+        // entries past the chunk's end are read too (stale or zero LDS, in
+        // bounds) and their bits dropped, so the reads take fixed offsets
+        auto group = [&](auto near_tag) {
+          constexpr bool NEAR = decltype(near_tag)::value;
+          float ux[kFineGroup], uy[kFineGroup], uz[kFineGroup], sg[kFineGroup], cg[kFineGroup];
 #pragma unroll
-        for (int q = 0; q < kFineGroup; ++q) {
-          // past the chunk's end the last task is read again and its bit dropped
-          const uint32_t j = j0 + q < ntask ? j0 + q : ntask - 1;
-          const float4 d = s_disc[wv][j];  // same address on every lane: a broadcast
-          ux[q] = d.x; uy[q] = d.y; uz[q] = d.z; sg[q] = d.w;
-          cg[q] = s_cg[wv][j];
-        }
+          for (int q = 0; q < kFineGroup; ++q) {
+            const float4 d = s_disc[wv][j0 + q];  // same address on every lane: a broadcast
+            ux[q] = d.x; uy[q] = d.y; uz[q] = d.z; sg[q] = d.w;
+            cg[q] = s_cg[wv][j0 + q];
+          }
 #pragma unroll
-        for (int q = 0; q < kFineGroup; ++q) {
-          const bool in = hp_cap_test(cx, cy, cz, h.x, h.y, ux[q], uy[q], uz[q], sg[q], cg[q]);
-          const uint32_t bit = j0 + q < jend ? (1u << ((j0 + q) & 31u)) : 0u;
-          Wh[half] |= in ? bit : 0u;
-        }
+          for (int q = 0; q < kFineGroup; ++q) {
+            const bool in = NEAR ? hp_cap_test_near(cx, cy, cz, h.x, h.y, ux[q], uy[q], uz[q], sg[q], cg[q])
+                                 : hp_cap_test(cx, cy, cz, h.x, h.y, ux[q], uy[q], uz[q], sg[q], cg[q]);
+            const uint32_t bit = j0 + q < jend ? (1u << ((j0 + q) & 31u)) : 0u;
+            Wh[half] |= in ? bit : 0u;
+          }
+        };
+        if (((nearmask >> j0) & 0xffull) == 0xffull)
+          group(std::true_type{});
+        else
+          group(std::false_type{});
       }
     }
     const uint64_t W = act ? ((uint64_t)Wh[1] << 32) | Wh[0] : 0ull;
