@@ -178,234 +178,269 @@ struct SsFwdLds {
 template <int B, bool ZONES>
 __global__ __launch_bounds__(256) void k_ssim_fwd(SsimArgs A, const float* __restrict__ img,
                                                   const float* __restrict__ ref, float* __restrict__ smap,
-                                                  float* __restrict__ G, float2* __restrict__ part) {
+                                                  float* __restrict__ G, float2* __restrict__ part, int n_tiles) {
   using L = SsFwdLds<B>;
   constexpr int H = L::H;
   __shared__ L s;
   __shared__ float s_red[2][4];
   float(*S)[B * B] = reinterpret_cast<float(*)[B * B]>(&s.in[0][0][0]);  // after pass 1
-  const int ct = hp_xcd_tile(blockIdx.x, gridDim.x), tid = threadIdx.x;
-  int f, x0, y0;
-  ss_tile_origin(A, ct, &f, &x0, &y0);
-  // zone windows: the tile takes the direct path when it holds a polar pixel
-  const int N = 1 << A.order;
-  // tiles narrower than 8 pixels (orders 0-2) always take the direct path
-  constexpr bool kSmall = B < 8;
-  const bool direct =
-      kSmall || (ZONES && (f < 4 ? (x0 + y0 + 2 * B - 2 >= N) : (f >= 8 ? (x0 + y0 <= N - 2) : false)));
-  // the patch from the tile's slot table: every load of the thread's cells
-  // goes out before the first LDS store
+  const int tid = threadIdx.x;
   constexpr int NG = (H * H + 255) / 256;
-  const int32_t* tab = A.tables + (int64_t)ct * (H * H);
-  int32_t e[NG];
+  // The workgroup renders tiles l = blockIdx.x, + gridDim.x, ... (a multiple
+  // of 8 workgroups, so every l of a workgroup maps to the XCD it runs on),
+  // and fetches the next tile's slot table and patch cells while the passes
+  // of the current one run, so their latency is not waited out.
+  auto load_table = [&](int l, int32_t* e) {
+    const int32_t* tab = A.tables + (int64_t)hp_xcd_tile(l, n_tiles) * (H * H);
 #pragma unroll
-  for (int gi = 0; gi < NG; ++gi) {
-    const int i = tid + 256 * gi;
-    e[gi] = i < H * H ? tab[i] : -1;
-  }
-  float v[NG][6];
-#pragma unroll
-  for (int gi = 0; gi < NG; ++gi) {
-    const int64_t slot = e[gi] & kSsSlotMask;
-#pragma unroll
-    for (int ch = 0; ch < 3; ++ch) {
-      v[gi][ch] = e[gi] >= 0 ? img[ch * A.n_active + slot] : 0.f;
-      v[gi][3 + ch] = e[gi] >= 0 ? ref[ch * A.n_active + slot] : 0.f;
+    for (int gi = 0; gi < NG; ++gi) {
+      const int i = tid + 256 * gi;
+      e[gi] = i < H * H ? tab[i] : -1;
     }
-  }
-  bool mine_full = true;
+  };
+  auto load_cells = [&](const int32_t* e, float (*v)[6]) {
 #pragma unroll
-  for (int gi = 0; gi < NG; ++gi) {
-    const int i = tid + 256 * gi;
-    if (i < H * H) {
-      int cx, cy;
-      ss_cell<B>(i, &cx, &cy);
-      mine_full &= e[gi] >= 0;
-      s.in[0][cy][cx] = e[gi] >= 0 ? 1.f : 0.f;
-#pragma unroll
-      for (int k = 0; k < 6; ++k) s.in[1 + k][cy][cx] = v[gi][k];
-      if (ZONES && direct) {
-        const int64_t q = hp_chart_pixel(A.order, f, x0 + cx - SS_R, y0 + cy - SS_R);
-        double d[3] = {0.0, 0.0, 0.0};
-        if (q >= 0) hp_pix_dir(A.order, q, d);
-        s.dir[cy * H + cx][0] = d[0];
-        s.dir[cy * H + cx][1] = d[1];
-        s.dir[cy * H + cx][2] = d[2];
-      }
-    }
-  }
-  // every cell of the patch active: the window weights need no mask and sum
-  // to (sum of taps)^2 everywhere
-  const bool full = __syncthreads_and(mine_full);
-  // this thread's pixel: nested local index tid (slot order of a full tile)
-  const int px = (int)hp_compact_bits((uint32_t)tid), py = (int)hp_compact_bits((uint32_t)tid >> 1);
-  const bool own = tid < B * B;
-  float xc[3] = {0.f, 0.f, 0.f}, yc[3] = {0.f, 0.f, 0.f};
-  if (own) {
-#pragma unroll
-    for (int ch = 0; ch < 3; ++ch) {
-      xc[ch] = s.in[1 + ch][py + SS_R][px + SS_R];
-      yc[ch] = s.in[4 + ch][py + SS_R][px + SS_R];
-    }
-  }
-  float Sm[16];
-  if constexpr (!kSmall) if (!direct) {
-    // pass 1 along x: item (row r, channel ch, quarter k) slides the window
-    // over the 14 cells behind its 4 outputs
-    constexpr int Q = B / 4, NI1 = H * 3 * Q;
-    for (int it = tid; it < NI1; it += 256) {
-      const int r = it / (3 * Q), rem = it % (3 * Q), ch = rem / Q, c0 = 4 * (rem % Q);
-      float m[16], x[16], y[16];
-#pragma unroll
-      for (int j = 0; j < 16; j += 4) {
-        const float4 a = *reinterpret_cast<const float4*>(&s.in[0][r][c0 + j]);
-        const float4 bx = *reinterpret_cast<const float4*>(&s.in[1 + ch][r][c0 + j]);
-        const float4 by = *reinterpret_cast<const float4*>(&s.in[4 + ch][r][c0 + j]);
-        m[j] = a.x; m[j + 1] = a.y; m[j + 2] = a.z; m[j + 3] = a.w;
-        x[j] = bx.x; x[j + 1] = bx.y; x[j + 2] = bx.z; x[j + 3] = bx.w;
-        y[j] = by.x; y[j + 1] = by.y; y[j + 2] = by.z; y[j + 3] = by.w;
-      }
-      float o[6][4];
-#pragma unroll
-      for (int k = 0; k < 6; ++k)
-#pragma unroll
-        for (int u = 0; u < 4; ++u) o[k][u] = 0.f;
-      if (full) {
-        // m = 1 everywhere: no mask products, no weight sums
-#pragma unroll
-        for (int j = 0; j < 14; ++j) {
-          const float q5[5] = {x[j], y[j], x[j] * x[j], y[j] * y[j], x[j] * y[j]};
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const int a = j - u;
-            if (a >= 0 && a < SS_W) {
-#pragma unroll
-              for (int k = 0; k < 5; ++k) o[1 + k][u] = fmaf(A.g[a], q5[k], o[1 + k][u]);
-            }
-          }
-        }
-      } else {
-#pragma unroll
-        for (int j = 0; j < 14; ++j) {
-          const float wx = m[j] * x[j], wy = m[j] * y[j];
-          const float q5[6] = {m[j], wx, wy, wx * x[j], wy * y[j], wx * y[j]};
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const int a = j - u;
-            if (a >= 0 && a < SS_W) {
-#pragma unroll
-              for (int k = 0; k < 6; ++k) o[k][u] = fmaf(A.g[a], q5[k], o[k][u]);
-            }
-          }
-        }
-      }
-      // quantity index: 0 weight, 1+ch x, 4+ch y, 7+ch xx, 10+ch yy, 13+ch xy
-      if (ch == 0 && !full)
-        *reinterpret_cast<float4*>(&s.p1[0][r * B + c0]) = make_float4(o[0][0], o[0][1], o[0][2], o[0][3]);
-#pragma unroll
-      for (int k = 1; k < 6; ++k)
-        *reinterpret_cast<float4*>(&s.p1[1 + 3 * (k - 1) + ch][r * B + c0]) =
-            make_float4(o[k][0], o[k][1], o[k][2], o[k][3]);
-    }
-    __syncthreads();
-    // pass 2 along y: item (column c, quantity k, half hh) slides over the
-    // B/2 + 10 rows behind its B/2 outputs
-    constexpr int RO = B / 2, NI2 = B * 16 * 2;
-    for (int it = tid; it < NI2; it += 256) {
-      const int c = it % B, k = (it / B) % 16, hh = it / (16 * B);
-      if (full && k == 0) continue;
-      float w[RO + 2 * SS_R];
-#pragma unroll
-      for (int j = 0; j < RO + 2 * SS_R; ++j) w[j] = s.p1[k][(hh * RO + j) * B + c];
-#pragma unroll
-      for (int u = 0; u < RO; ++u) {
-        float acc = 0.f;
-#pragma unroll
-        for (int a = 0; a < SS_W; ++a) acc = fmaf(A.g[a], w[u + a], acc);
-        S[k][ss_nest_local(c, hh * RO + u)] = acc;   // nested order: read back by pixel tid
-      }
-    }
-    __syncthreads();
-    if (own) {
-#pragma unroll
-      for (int k = 0; k < 16; ++k) Sm[k] = S[k][tid];
-      if (full) Sm[0] = A.gsum * A.gsum;
-    }
-  }
-  if (direct) {
-    // direct 121-tap sums: polar pixels (zone windows) weigh by great-circle
-    // distance, the others by the chart window
-#pragma unroll
-    for (int k = 0; k < 16; ++k) Sm[k] = 0.f;
-    if (own) {
-      const bool polar = ZONES && ss_polar(A.order, hp_xyf_nest(A.order, x0 + px, y0 + py, f));
-      const double* up = s.dir[(py + SS_R) * H + px + SS_R];
-      for (int b = 0; b < SS_W; ++b) {
-        for (int a = 0; a < SS_W; ++a) {
-          const int cy = py + b, cx = px + a;
-          const float m = s.in[0][cy][cx];
-          if (m == 0.f) continue;
-          const float w = polar ? m * __expf(-(float)(ss_dist2(up, s.dir[cy * H + cx]) * A.wscale))
-                                : m * (A.g[a] * A.g[b]);
-          Sm[0] += w;
-#pragma unroll
-          for (int ch = 0; ch < 3; ++ch) {
-            const float x = s.in[1 + ch][cy][cx], y = s.in[4 + ch][cy][cx];
-            const float wx = w * x, wy = w * y;
-            Sm[1 + ch] += wx;
-            Sm[4 + ch] += wy;
-            Sm[7 + ch] = fmaf(wx, x, Sm[7 + ch]);
-            Sm[10 + ch] = fmaf(wy, y, Sm[10 + ch]);
-            Sm[13 + ch] = fmaf(wx, y, Sm[13 + ch]);
-          }
-        }
-      }
-    }
-  }
-  float ssum = 0.f, lsum = 0.f;
-  int64_t slot = -1;
-  float gl[kSsG] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  if (own) {
-    slot = ss_slot(A, hp_xyf_nest(A.order, x0 + px, y0 + py, f));
-    if (slot >= 0) {
-      const float iZ = __builtin_amdgcn_rcpf(Sm[0]);
+    for (int gi = 0; gi < NG; ++gi) {
+      const int64_t slot = e[gi] & kSsSlotMask;
 #pragma unroll
       for (int ch = 0; ch < 3; ++ch) {
-        const float sv = ss_index(A.C1, A.C2, iZ, Sm[1 + ch], Sm[4 + ch], Sm[7 + ch], Sm[10 + ch], Sm[13 + ch],
-                                  &gl[ch], &gl[3 + ch], &gl[6 + ch]);
-        ssum += sv;
-        lsum += fabsf(xc[ch] - yc[ch]);
-        if (smap) smap[ch * A.n_active + slot] = sv;
+        v[gi][ch] = e[gi] >= 0 ? img[ch * A.n_active + slot] : 0.f;
+        v[gi][3 + ch] = e[gi] >= 0 ? ref[ch * A.n_active + slot] : 0.f;
+      }
+    }
+  };
+  int32_t e[NG], en[NG];
+  float v[NG][6], vn[NG][6];
+  if ((int)blockIdx.x >= n_tiles) return;
+  // one tile: the cells in e / v; with more, the next tile's (ln) are
+  // fetched into en / vn during the passes
+  auto tile = [&](int l, int ln, bool more) {
+    const int ct = hp_xcd_tile(l, n_tiles);
+    int f, x0, y0;
+    ss_tile_origin(A, ct, &f, &x0, &y0);
+    // zone windows: the tile takes the direct path when it holds a polar pixel
+    const int N = 1 << A.order;
+    // tiles narrower than 8 pixels (orders 0-2) always take the direct path
+    constexpr bool kSmall = B < 8;
+    const bool direct =
+        kSmall || (ZONES && (f < 4 ? (x0 + y0 + 2 * B - 2 >= N) : (f >= 8 ? (x0 + y0 <= N - 2) : false)));
+    __syncthreads();  // the previous tile's LDS reads are done
+    bool mine_full = true;
+  #pragma unroll
+    for (int gi = 0; gi < NG; ++gi) {
+      const int i = tid + 256 * gi;
+      if (i < H * H) {
+        int cx, cy;
+        ss_cell<B>(i, &cx, &cy);
+        mine_full &= e[gi] >= 0;
+        s.in[0][cy][cx] = e[gi] >= 0 ? 1.f : 0.f;
+  #pragma unroll
+        for (int k = 0; k < 6; ++k) s.in[1 + k][cy][cx] = v[gi][k];
+        if (ZONES && direct) {
+          const int64_t q = hp_chart_pixel(A.order, f, x0 + cx - SS_R, y0 + cy - SS_R);
+          double d[3] = {0.0, 0.0, 0.0};
+          if (q >= 0) hp_pix_dir(A.order, q, d);
+          s.dir[cy * H + cx][0] = d[0];
+          s.dir[cy * H + cx][1] = d[1];
+          s.dir[cy * H + cx][2] = d[2];
+        }
+      }
+    }
+    // every cell of the patch active: the window weights need no mask and sum
+    // to (sum of taps)^2 everywhere
+    const bool full = __syncthreads_and(mine_full);
+    if (more) load_table(ln, en);
+    // this thread's pixel: nested local index tid (slot order of a full tile)
+    const int px = (int)hp_compact_bits((uint32_t)tid), py = (int)hp_compact_bits((uint32_t)tid >> 1);
+    const bool own = tid < B * B;
+    float xc[3] = {0.f, 0.f, 0.f}, yc[3] = {0.f, 0.f, 0.f};
+    if (own) {
+  #pragma unroll
+      for (int ch = 0; ch < 3; ++ch) {
+        xc[ch] = s.in[1 + ch][py + SS_R][px + SS_R];
+        yc[ch] = s.in[4 + ch][py + SS_R][px + SS_R];
+      }
+    }
+    float Sm[16];
+    if constexpr (!kSmall) if (!direct) {
+      // pass 1 along x: item (row r, channel ch, quarter k) slides the window
+      // over the 14 cells behind its 4 outputs
+      constexpr int Q = B / 4, NI1 = H * 3 * Q;
+      for (int it = tid; it < NI1; it += 256) {
+        const int r = it / (3 * Q), rem = it % (3 * Q), ch = rem / Q, c0 = 4 * (rem % Q);
+        float m[16], x[16], y[16];
+  #pragma unroll
+        for (int j = 0; j < 16; j += 4) {
+          const float4 a = *reinterpret_cast<const float4*>(&s.in[0][r][c0 + j]);
+          const float4 bx = *reinterpret_cast<const float4*>(&s.in[1 + ch][r][c0 + j]);
+          const float4 by = *reinterpret_cast<const float4*>(&s.in[4 + ch][r][c0 + j]);
+          m[j] = a.x; m[j + 1] = a.y; m[j + 2] = a.z; m[j + 3] = a.w;
+          x[j] = bx.x; x[j + 1] = bx.y; x[j + 2] = bx.z; x[j + 3] = bx.w;
+          y[j] = by.x; y[j + 1] = by.y; y[j + 2] = by.z; y[j + 3] = by.w;
+        }
+        float o[6][4];
+  #pragma unroll
+        for (int k = 0; k < 6; ++k)
+  #pragma unroll
+          for (int u = 0; u < 4; ++u) o[k][u] = 0.f;
+        if (full) {
+          // m = 1 everywhere: no mask products, no weight sums
+  #pragma unroll
+          for (int j = 0; j < 14; ++j) {
+            const float q5[5] = {x[j], y[j], x[j] * x[j], y[j] * y[j], x[j] * y[j]};
+  #pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const int a = j - u;
+              if (a >= 0 && a < SS_W) {
+  #pragma unroll
+                for (int k = 0; k < 5; ++k) o[1 + k][u] = fmaf(A.g[a], q5[k], o[1 + k][u]);
+              }
+            }
+          }
+        } else {
+  #pragma unroll
+          for (int j = 0; j < 14; ++j) {
+            const float wx = m[j] * x[j], wy = m[j] * y[j];
+            const float q5[6] = {m[j], wx, wy, wx * x[j], wy * y[j], wx * y[j]};
+  #pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const int a = j - u;
+              if (a >= 0 && a < SS_W) {
+  #pragma unroll
+                for (int k = 0; k < 6; ++k) o[k][u] = fmaf(A.g[a], q5[k], o[k][u]);
+              }
+            }
+          }
+        }
+        // quantity index: 0 weight, 1+ch x, 4+ch y, 7+ch xx, 10+ch yy, 13+ch xy
+        if (ch == 0 && !full)
+          *reinterpret_cast<float4*>(&s.p1[0][r * B + c0]) = make_float4(o[0][0], o[0][1], o[0][2], o[0][3]);
+  #pragma unroll
+        for (int k = 1; k < 6; ++k)
+          *reinterpret_cast<float4*>(&s.p1[1 + 3 * (k - 1) + ch][r * B + c0]) =
+              make_float4(o[k][0], o[k][1], o[k][2], o[k][3]);
+      }
+      if (more) load_cells(en, vn);
+      __syncthreads();
+      // pass 2 along y: item (column c, quantity k, half hh) slides over the
+      // B/2 + 10 rows behind its B/2 outputs
+      constexpr int RO = B / 2, NI2 = B * 16 * 2;
+      for (int it = tid; it < NI2; it += 256) {
+        const int c = it % B, k = (it / B) % 16, hh = it / (16 * B);
+        if (full && k == 0) continue;
+        float w[RO + 2 * SS_R];
+  #pragma unroll
+        for (int j = 0; j < RO + 2 * SS_R; ++j) w[j] = s.p1[k][(hh * RO + j) * B + c];
+  #pragma unroll
+        for (int u = 0; u < RO; ++u) {
+          float acc = 0.f;
+  #pragma unroll
+          for (int a = 0; a < SS_W; ++a) acc = fmaf(A.g[a], w[u + a], acc);
+          S[k][ss_nest_local(c, hh * RO + u)] = acc;   // nested order: read back by pixel tid
+        }
+      }
+      __syncthreads();
+      if (own) {
+  #pragma unroll
+        for (int k = 0; k < 16; ++k) Sm[k] = S[k][tid];
+        if (full) Sm[0] = A.gsum * A.gsum;
+      }
+    }
+    if (direct) {
+      // direct 121-tap sums: polar pixels (zone windows) weigh by great-circle
+      // distance, the others by the chart window
+      if (more) load_cells(en, vn);
+  #pragma unroll
+      for (int k = 0; k < 16; ++k) Sm[k] = 0.f;
+      if (own) {
+        const bool polar = ZONES && ss_polar(A.order, hp_xyf_nest(A.order, x0 + px, y0 + py, f));
+        const double* up = s.dir[(py + SS_R) * H + px + SS_R];
+        for (int b = 0; b < SS_W; ++b) {
+          for (int a = 0; a < SS_W; ++a) {
+            const int cy = py + b, cx = px + a;
+            const float m = s.in[0][cy][cx];
+            if (m == 0.f) continue;
+            const float w = polar ? m * __expf(-(float)(ss_dist2(up, s.dir[cy * H + cx]) * A.wscale))
+                                  : m * (A.g[a] * A.g[b]);
+            Sm[0] += w;
+  #pragma unroll
+            for (int ch = 0; ch < 3; ++ch) {
+              const float x = s.in[1 + ch][cy][cx], y = s.in[4 + ch][cy][cx];
+              const float wx = w * x, wy = w * y;
+              Sm[1 + ch] += wx;
+              Sm[4 + ch] += wy;
+              Sm[7 + ch] = fmaf(wx, x, Sm[7 + ch]);
+              Sm[10 + ch] = fmaf(wy, y, Sm[10 + ch]);
+              Sm[13 + ch] = fmaf(wx, y, Sm[13 + ch]);
+            }
+          }
+        }
+      }
+    }
+    float ssum = 0.f, lsum = 0.f;
+    int64_t slot = -1;
+    float gl[kSsG] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (own) {
+      slot = ss_slot(A, hp_xyf_nest(A.order, x0 + px, y0 + py, f));
+      if (slot >= 0) {
+        const float iZ = __builtin_amdgcn_rcpf(Sm[0]);
+  #pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+          const float sv = ss_index(A.C1, A.C2, iZ, Sm[1 + ch], Sm[4 + ch], Sm[7 + ch], Sm[10 + ch], Sm[13 + ch],
+                                    &gl[ch], &gl[3 + ch], &gl[6 + ch]);
+          ssum += sv;
+          lsum += fabsf(xc[ch] - yc[ch]);
+          if (smap) smap[ch * A.n_active + slot] = sv;
+        }
+      }
+    }
+    if (G) {
+      // the tile's partials leave as one contiguous run: its active pixels
+      // hold the slots [start, start + count) (staged in LDS over the first
+      // pass's place, once every thread is done reading it)
+      const int t = A.active_tiles[ct];
+      const int64_t start = A.tile_start[t];
+      const int cnt = A.tile_count[t];
+      float4* stage = reinterpret_cast<float4*>(&s.p1[0][0]);
+      __syncthreads();
+      if (slot >= 0) {
+        const int loc = (int)(slot - start);
+        stage[3 * loc] = make_float4(gl[0], gl[1], gl[2], gl[3]);
+        stage[3 * loc + 1] = make_float4(gl[4], gl[5], gl[6], gl[7]);
+        stage[3 * loc + 2] = make_float4(gl[8], 0.f, 0.f, 0.f);
+      }
+      __syncthreads();
+      float4* out = reinterpret_cast<float4*>(G + start * kSsG);
+      for (int i = tid; i < 3 * cnt; i += 256) out[i] = stage[i];
+    }
+    // block reduction of (ssum, lsum)
+    float red[2] = {ssum, lsum};
+    hp_wave_totals<2>(red);
+    if (hp_lane() == 0) { s_red[0][tid >> 6] = red[0]; s_red[1][tid >> 6] = red[1]; }
+    __syncthreads();
+    if (tid == 0)
+      part[ct] = make_float2(s_red[0][0] + s_red[0][1] + s_red[0][2] + s_red[0][3],
+                             s_red[1][0] + s_red[1][1] + s_red[1][2] + s_red[1][3]);
+  };
+  if constexpr (ZONES) {
+    // with zone windows every workgroup has one tile (ssim_grid)
+    load_table(blockIdx.x, e);
+    load_cells(e, v);
+    tile(blockIdx.x, 0, false);
+  } else {
+    load_table(blockIdx.x, e);
+    load_cells(e, v);
+    for (int l = blockIdx.x; l < n_tiles; l += gridDim.x) {
+      const int ln = l + (int)gridDim.x;
+      tile(l, ln, ln < n_tiles);
+#pragma unroll
+      for (int gi = 0; gi < NG; ++gi) {
+        e[gi] = en[gi];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) v[gi][k] = vn[gi][k];
       }
     }
   }
-  if (G) {
-    // the tile's partials leave as one contiguous run: its active pixels
-    // hold the slots [start, start + count) (staged in LDS over the first
-    // pass's place, once every thread is done reading it)
-    const int t = A.active_tiles[ct];
-    const int64_t start = A.tile_start[t];
-    const int cnt = A.tile_count[t];
-    float4* stage = reinterpret_cast<float4*>(&s.p1[0][0]);
-    __syncthreads();
-    if (slot >= 0) {
-      const int loc = (int)(slot - start);
-      stage[3 * loc] = make_float4(gl[0], gl[1], gl[2], gl[3]);
-      stage[3 * loc + 1] = make_float4(gl[4], gl[5], gl[6], gl[7]);
-      stage[3 * loc + 2] = make_float4(gl[8], 0.f, 0.f, 0.f);
-    }
-    __syncthreads();
-    float4* out = reinterpret_cast<float4*>(G + start * kSsG);
-    for (int i = tid; i < 3 * cnt; i += 256) out[i] = stage[i];
-  }
-  // block reduction of (ssum, lsum)
-  float red[2] = {ssum, lsum};
-  hp_wave_totals<2>(red);
-  if (hp_lane() == 0) { s_red[0][tid >> 6] = red[0]; s_red[1][tid >> 6] = red[1]; }
-  __syncthreads();
-  if (tid == 0)
-    part[ct] = make_float2(s_red[0][0] + s_red[0][1] + s_red[0][2] + s_red[0][3],
-                           s_red[1][0] + s_red[1][1] + s_red[1][2] + s_red[1][3]);
 }
 
 // single block: mean SSIM, mean L1, loss
@@ -452,154 +487,190 @@ struct SsBwdLds {
 template <int B, bool ZONES>
 __global__ __launch_bounds__(256) void k_ssim_bwd(SsimArgs A, const float* __restrict__ img,
                                                   const float* __restrict__ ref, const float* __restrict__ G,
-                                                  const float* __restrict__ dL_dloss, float* __restrict__ dimg) {
+                                                  const float* __restrict__ dL_dloss, float* __restrict__ dimg,
+                                                  int n_tiles) {
   using L = SsBwdLds<B>;
   constexpr int H = L::H;
   __shared__ L s;
   float(*S)[B * B] = reinterpret_cast<float(*)[B * B]>(&s.in[0][0][0]);  // after pass 1
-  const int ct = hp_xcd_tile(blockIdx.x, gridDim.x), tid = threadIdx.x;
-  int f, x0, y0;
-  ss_tile_origin(A, ct, &f, &x0, &y0);
-  bool any_polar = false;
+  const int tid = threadIdx.x;
   constexpr int NG = (H * H + 255) / 256;
-  const int32_t* tab = A.tables + (int64_t)ct * (H * H);
-  int32_t e[NG];
+  // tiles l = blockIdx.x, + gridDim.x, ... as in the forward; the next
+  // tile's slot table and partials are fetched during the current passes
+  auto load_table = [&](int l, int32_t* e) {
+    const int32_t* tab = A.tables + (int64_t)hp_xcd_tile(l, n_tiles) * (H * H);
 #pragma unroll
-  for (int gi = 0; gi < NG; ++gi) {
-    const int i = tid + 256 * gi;
-    e[gi] = i < H * H ? tab[i] : -1;
-  }
-  float v[NG][9];
-#pragma unroll
-  for (int gi = 0; gi < NG; ++gi) {
-    const int64_t slot = e[gi] & kSsSlotMask;
-    float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = a, c = a;
-    if (e[gi] >= 0) {
-      const float4* gp = reinterpret_cast<const float4*>(G + slot * kSsG);
-      a = gp[0]; b = gp[1]; c = gp[2];
+    for (int gi = 0; gi < NG; ++gi) {
+      const int i = tid + 256 * gi;
+      e[gi] = i < H * H ? tab[i] : -1;
     }
-    v[gi][0] = a.x; v[gi][1] = a.y; v[gi][2] = a.z; v[gi][3] = a.w;
-    v[gi][4] = b.x; v[gi][5] = b.y; v[gi][6] = b.z; v[gi][7] = b.w;
-    v[gi][8] = c.x;
-  }
+  };
+  auto load_cells = [&](const int32_t* e, float (*v)[9]) {
 #pragma unroll
-  for (int gi = 0; gi < NG; ++gi) {
-    const int i = tid + 256 * gi;
-    if (i < H * H) {
-      int cx, cy;
-      ss_cell<B>(i, &cx, &cy);
-#pragma unroll
-      for (int k = 0; k < 9; ++k) s.in[k][cy][cx] = v[gi][k];
-      if (ZONES) {
-        const bool pq = e[gi] >= 0 && (e[gi] & kSsPolarBit) != 0;
-        s.polar[cy * H + cx] = pq ? 1 : 0;
-        any_polar |= pq;
+    for (int gi = 0; gi < NG; ++gi) {
+      const int64_t slot = e[gi] & kSsSlotMask;
+      float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = a, c = a;
+      if (e[gi] >= 0) {
+        const float4* gp = reinterpret_cast<const float4*>(G + slot * kSsG);
+        a = gp[0]; b = gp[1]; c = gp[2];
+      }
+      v[gi][0] = a.x; v[gi][1] = a.y; v[gi][2] = a.z; v[gi][3] = a.w;
+      v[gi][4] = b.x; v[gi][5] = b.y; v[gi][6] = b.z; v[gi][7] = b.w;
+      v[gi][8] = c.x;
+    }
+  };
+  int32_t e[NG], en[NG];
+  float v[NG][9], vn[NG][9];
+  if ((int)blockIdx.x >= n_tiles) return;
+  // one tile: the cells in e / v; with more, the next tile's (ln) are
+  // fetched into en / vn during the passes
+  auto tile = [&](int l, int ln, bool more) {
+    const int ct = hp_xcd_tile(l, n_tiles);
+    int f, x0, y0;
+    ss_tile_origin(A, ct, &f, &x0, &y0);
+    bool any_polar = false;
+    __syncthreads();  // the previous tile's LDS reads are done
+  #pragma unroll
+    for (int gi = 0; gi < NG; ++gi) {
+      const int i = tid + 256 * gi;
+      if (i < H * H) {
+        int cx, cy;
+        ss_cell<B>(i, &cx, &cy);
+  #pragma unroll
+        for (int k = 0; k < 9; ++k) s.in[k][cy][cx] = v[gi][k];
+        if (ZONES) {
+          const bool pq = e[gi] >= 0 && (e[gi] & kSsPolarBit) != 0;
+          s.polar[cy * H + cx] = pq ? 1 : 0;
+          any_polar |= pq;
+        }
       }
     }
-  }
-  // the separable pass needs every neighbour's window to be the chart one;
-  // tiles narrower than 8 pixels always take the direct path
-  constexpr bool kSmall = B < 8;
-  bool direct = kSmall;
-  if (ZONES) direct = __syncthreads_or(any_polar) || kSmall;
-  else __syncthreads();
-  const int px = (int)hp_compact_bits((uint32_t)tid), py = (int)hp_compact_bits((uint32_t)tid >> 1);
-  float Sm[9];
-  if constexpr (!kSmall) if (!direct) {
-    constexpr int Q = B / 4, NI1 = H * 9 * Q;
-    float o[4][4];  // up to 4 items per thread, 4 outputs each
-    int kk[4], rr[4], cc[4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int it = tid + 256 * t;
-      kk[t] = -1;
-      if (it < NI1) {
-        const int r = it / (9 * Q), rem = it % (9 * Q), k = rem / Q, c0 = 4 * (rem % Q);
-        float v[16];
-#pragma unroll
-        for (int j = 0; j < 16; j += 4) {
-          const float4 a = *reinterpret_cast<const float4*>(&s.in[k][r][c0 + j]);
-          v[j] = a.x; v[j + 1] = a.y; v[j + 2] = a.z; v[j + 3] = a.w;
+    // the separable pass needs every neighbour's window to be the chart one;
+    // tiles narrower than 8 pixels always take the direct path
+    constexpr bool kSmall = B < 8;
+    bool direct = kSmall;
+    if (ZONES) direct = __syncthreads_or(any_polar) || kSmall;
+    else __syncthreads();
+    if (more) load_table(ln, en);
+    const int px = (int)hp_compact_bits((uint32_t)tid), py = (int)hp_compact_bits((uint32_t)tid >> 1);
+    float Sm[9];
+    if constexpr (!kSmall) if (!direct) {
+      constexpr int Q = B / 4, NI1 = H * 9 * Q;
+      float o[4][4];  // up to 4 items per thread, 4 outputs each
+      int kk[4], rr[4], cc[4];
+  #pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int it = tid + 256 * t;
+        kk[t] = -1;
+        if (it < NI1) {
+          const int r = it / (9 * Q), rem = it % (9 * Q), k = rem / Q, c0 = 4 * (rem % Q);
+          float v[16];
+  #pragma unroll
+          for (int j = 0; j < 16; j += 4) {
+            const float4 a = *reinterpret_cast<const float4*>(&s.in[k][r][c0 + j]);
+            v[j] = a.x; v[j + 1] = a.y; v[j + 2] = a.z; v[j + 3] = a.w;
+          }
+  #pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            float acc = 0.f;
+  #pragma unroll
+            for (int a = 0; a < SS_W; ++a) acc = fmaf(A.g[a], v[u + a], acc);
+            o[t][u] = acc;
+          }
+          kk[t] = k; rr[t] = r; cc[t] = c0;
         }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
+      }
+  #pragma unroll
+      for (int t = 0; t < 4; ++t)
+        if (kk[t] >= 0)
+          *reinterpret_cast<float4*>(&s.p1[kk[t]][rr[t] * B + cc[t]]) = make_float4(o[t][0], o[t][1], o[t][2], o[t][3]);
+      if (more) load_cells(en, vn);
+      __syncthreads();
+      constexpr int RO = B / 2, NI2 = B * 9 * 2;
+      for (int it = tid; it < NI2; it += 256) {
+        const int c = it % B, k = (it / B) % 9, hh = it / (9 * B);
+        float w[RO + 2 * SS_R];
+  #pragma unroll
+        for (int j = 0; j < RO + 2 * SS_R; ++j) w[j] = s.p1[k][(hh * RO + j) * B + c];
+  #pragma unroll
+        for (int u = 0; u < RO; ++u) {
           float acc = 0.f;
-#pragma unroll
-          for (int a = 0; a < SS_W; ++a) acc = fmaf(A.g[a], v[u + a], acc);
-          o[t][u] = acc;
+  #pragma unroll
+          for (int a = 0; a < SS_W; ++a) acc = fmaf(A.g[a], w[u + a], acc);
+          S[k][ss_nest_local(c, hh * RO + u)] = acc;
         }
-        kk[t] = k; rr[t] = r; cc[t] = c0;
-      }
-    }
-#pragma unroll
-    for (int t = 0; t < 4; ++t)
-      if (kk[t] >= 0)
-        *reinterpret_cast<float4*>(&s.p1[kk[t]][rr[t] * B + cc[t]]) = make_float4(o[t][0], o[t][1], o[t][2], o[t][3]);
-    __syncthreads();
-    constexpr int RO = B / 2, NI2 = B * 9 * 2;
-    for (int it = tid; it < NI2; it += 256) {
-      const int c = it % B, k = (it / B) % 9, hh = it / (9 * B);
-      float w[RO + 2 * SS_R];
-#pragma unroll
-      for (int j = 0; j < RO + 2 * SS_R; ++j) w[j] = s.p1[k][(hh * RO + j) * B + c];
-#pragma unroll
-      for (int u = 0; u < RO; ++u) {
-        float acc = 0.f;
-#pragma unroll
-        for (int a = 0; a < SS_W; ++a) acc = fmaf(A.g[a], w[u + a], acc);
-        S[k][ss_nest_local(c, hh * RO + u)] = acc;
-      }
-    }
-    __syncthreads();
-    if (tid < B * B) {
-#pragma unroll
-      for (int k = 0; k < 9; ++k) Sm[k] = S[k][tid];
-    }
-  }
-  if (direct) {
-    // directions of the patch cells (over the first pass's place), for the
-    // polar windows
-    if (ZONES) {
-      for (int i = tid; i < H * H; i += 256) {
-        const int cx = i % H, cy = i / H;
-        const int64_t q = hp_chart_pixel(A.order, f, x0 + cx - SS_R, y0 + cy - SS_R);
-        double d[3] = {0.0, 0.0, 0.0};
-        if (q >= 0) hp_pix_dir(A.order, q, d);
-        s.dir[i][0] = d[0];
-        s.dir[i][1] = d[1];
-        s.dir[i][2] = d[2];
       }
       __syncthreads();
+      if (tid < B * B) {
+  #pragma unroll
+        for (int k = 0; k < 9; ++k) Sm[k] = S[k][tid];
+      }
     }
-#pragma unroll
-    for (int k = 0; k < 9; ++k) Sm[k] = 0.f;
-    if (tid < B * B) {
-      const double* up = s.dir[(py + SS_R) * H + px + SS_R];
-      for (int b = 0; b < SS_W; ++b) {
-        for (int a = 0; a < SS_W; ++a) {
-          const int cy = py + b, cx = px + a;
-          // q's own window at p: the great-circle Gaussian for a polar q,
-          // the (symmetric) chart taps otherwise
-          const float w = (ZONES && s.polar[cy * H + cx])
-                              ? __expf(-(float)(ss_dist2(up, s.dir[cy * H + cx]) * A.wscale))
-                              : A.g[a] * A.g[b];
-#pragma unroll
-          for (int k = 0; k < 9; ++k) Sm[k] = fmaf(w, s.in[k][cy][cx], Sm[k]);
+    if (direct) {
+      if (more) load_cells(en, vn);
+      // directions of the patch cells (over the first pass's place), for the
+      // polar windows
+      if (ZONES) {
+        for (int i = tid; i < H * H; i += 256) {
+          const int cx = i % H, cy = i / H;
+          const int64_t q = hp_chart_pixel(A.order, f, x0 + cx - SS_R, y0 + cy - SS_R);
+          double d[3] = {0.0, 0.0, 0.0};
+          if (q >= 0) hp_pix_dir(A.order, q, d);
+          s.dir[i][0] = d[0];
+          s.dir[i][1] = d[1];
+          s.dir[i][2] = d[2];
+        }
+        __syncthreads();
+      }
+  #pragma unroll
+      for (int k = 0; k < 9; ++k) Sm[k] = 0.f;
+      if (tid < B * B) {
+        const double* up = s.dir[(py + SS_R) * H + px + SS_R];
+        for (int b = 0; b < SS_W; ++b) {
+          for (int a = 0; a < SS_W; ++a) {
+            const int cy = py + b, cx = px + a;
+            // q's own window at p: the great-circle Gaussian for a polar q,
+            // the (symmetric) chart taps otherwise
+            const float w = (ZONES && s.polar[cy * H + cx])
+                                ? __expf(-(float)(ss_dist2(up, s.dir[cy * H + cx]) * A.wscale))
+                                : A.g[a] * A.g[b];
+  #pragma unroll
+            for (int k = 0; k < 9; ++k) Sm[k] = fmaf(w, s.in[k][cy][cx], Sm[k]);
+          }
         }
       }
     }
-  }
-  if (tid >= B * B) return;
-  const int64_t slot = ss_slot(A, hp_xyf_nest(A.order, x0 + px, y0 + py, f));
-  if (slot < 0) return;
-  const float up = *dL_dloss;
-  const float inv3n = 1.f / (3.f * (float)A.n_active);
+    const int64_t slot = tid < B * B ? ss_slot(A, hp_xyf_nest(A.order, x0 + px, y0 + py, f)) : -1;
+    if (slot >= 0) {
+      const float up = *dL_dloss;
+      const float inv3n = 1.f / (3.f * (float)A.n_active);
+  #pragma unroll
+      for (int ch = 0; ch < 3; ++ch) {
+        const float x = img[ch * A.n_active + slot], y = ref[ch * A.n_active + slot];
+        const float dssim = Sm[0 * 3 + ch] + 2.f * x * Sm[1 * 3 + ch] + y * Sm[2 * 3 + ch];
+        const float sgn = (float)((x > y) - (x < y));
+        dimg[ch * A.n_active + slot] = up * inv3n * ((1.f - A.lam) * sgn - A.lam * dssim);
+      }
+    }
+  };
+  if constexpr (ZONES) {
+    // with zone windows every workgroup has one tile (ssim_grid)
+    load_table(blockIdx.x, e);
+    load_cells(e, v);
+    tile(blockIdx.x, 0, false);
+  } else {
+    load_table(blockIdx.x, e);
+    load_cells(e, v);
+    for (int l = blockIdx.x; l < n_tiles; l += gridDim.x) {
+      const int ln = l + (int)gridDim.x;
+      tile(l, ln, ln < n_tiles);
 #pragma unroll
-  for (int ch = 0; ch < 3; ++ch) {
-    const float x = img[ch * A.n_active + slot], y = ref[ch * A.n_active + slot];
-    const float dssim = Sm[0 * 3 + ch] + 2.f * x * Sm[1 * 3 + ch] + y * Sm[2 * 3 + ch];
-    const float sgn = (float)((x > y) - (x < y));
-    dimg[ch * A.n_active + slot] = up * inv3n * ((1.f - A.lam) * sgn - A.lam * dssim);
+      for (int gi = 0; gi < NG; ++gi) {
+        e[gi] = en[gi];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) v[gi][k] = vn[gi][k];
+      }
+    }
   }
 }
 
@@ -698,14 +769,24 @@ static hp_status ssim_setup(const float* img, const float* ref, int64_t n_active
   return HP_OK;
 }
 
+// Workgroups of the forward and backward: with the separable windows, three
+// per CU (what the LDS patch allows; a multiple of 8), each looping over
+// tiles; with zone windows one per tile, since their direct-path tiles cost
+// several times the others and a fixed share per workgroup would leave the
+// load uneven.
+static unsigned ssim_grid(int32_t n_tiles, bool zones) {
+  const int32_t g = 3 * 256;
+  return (unsigned)(zones || n_tiles <= g ? n_tiles : g);
+}
+
 template <int B>
 static hp_status ssim_fwd_launch_b(const SsimArgs& A, bool zones, const float* img, const float* ref,
                                    int32_t n_tiles, float* ssim_map, float* Gm, float2* part, hipStream_t s) {
+  const dim3 grid(ssim_grid(n_tiles, zones));
   if (zones)
-    hipLaunchKernelGGL((k_ssim_fwd<B, true>), dim3((unsigned)n_tiles), dim3(256), 0, s, A, img, ref, ssim_map, Gm, part);
+    hipLaunchKernelGGL((k_ssim_fwd<B, true>), grid, dim3(256), 0, s, A, img, ref, ssim_map, Gm, part, (int)n_tiles);
   else
-    hipLaunchKernelGGL((k_ssim_fwd<B, false>), dim3((unsigned)n_tiles), dim3(256), 0, s, A, img, ref, ssim_map, Gm,
-                       part);
+    hipLaunchKernelGGL((k_ssim_fwd<B, false>), grid, dim3(256), 0, s, A, img, ref, ssim_map, Gm, part, (int)n_tiles);
   HP_CHECK_LAUNCH();
   return HP_OK;
 }
@@ -728,12 +809,12 @@ template <int B>
 static hp_status ssim_bwd_launch_b(const SsimArgs& A, bool zones, const float* img, const float* ref,
                                    int32_t n_tiles, const float* Gm, const float* dL_dloss, float* dL_dimg,
                                    hipStream_t s) {
+  const dim3 grid(ssim_grid(n_tiles, zones));
   if (zones)
-    hipLaunchKernelGGL((k_ssim_bwd<B, true>), dim3((unsigned)n_tiles), dim3(256), 0, s, A, img, ref, Gm, dL_dloss,
-                       dL_dimg);
+    hipLaunchKernelGGL((k_ssim_bwd<B, true>), grid, dim3(256), 0, s, A, img, ref, Gm, dL_dloss, dL_dimg, (int)n_tiles);
   else
-    hipLaunchKernelGGL((k_ssim_bwd<B, false>), dim3((unsigned)n_tiles), dim3(256), 0, s, A, img, ref, Gm, dL_dloss,
-                       dL_dimg);
+    hipLaunchKernelGGL((k_ssim_bwd<B, false>), grid, dim3(256), 0, s, A, img, ref, Gm, dL_dloss, dL_dimg,
+                       (int)n_tiles);
   HP_CHECK_LAUNCH();
   return HP_OK;
 }
