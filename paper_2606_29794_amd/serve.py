@@ -362,10 +362,15 @@ class Server:
                 chunk = reqd[s0:s0 + MAX_REQ_PER_RENDER]
                 arr = (A.hp_render_req * len(chunk))(*chunk)
                 A.call("hp_render_fwd_batch", len(chunk), arr, C.byref(prm), sptr)
+            # the pair counts go to pinned host memory in the batch's stream
+            # order, so they are readable once the batch's event completes
+            host_counts = torch.empty(len(counts), dtype=torch.int64, pin_memory=True)
+            host_counts.copy_(torch.stack([c.dev[0] for c in counts]), non_blocking=True)
             ev = torch.cuda.Event()
             ev.record(stream)
         b = _Batch(reqs, stream, ev, nbytes, outs=outs)
         b.counts = counts
+        b.host_counts = host_counts
         b.slot = slot
         b.keep = [projs, masks, keep_t]   # alive until the batch completes
         return b
@@ -376,8 +381,8 @@ class Server:
         capacity hints and they run again (once more at most)."""
         P = self.g.P
         redo = []
-        # every count of the batch in one read-back
-        ns = torch.stack([c.dev[0] for c in b.counts]).cpu().tolist()
+        # every count of the batch, copied to the host with the batch
+        ns = b.host_counts.tolist()
         for k, (r, cnt, n) in enumerate(zip(b.reqs, b.counts, ns)):
             self.R.note_count(P, r.camera, None, n)
             if n > cnt.capacity:
