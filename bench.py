@@ -43,6 +43,7 @@ def parse():
     ap.add_argument("--cpu-pixels", type=int, default=3072)
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
     ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-only", action="store_true", help="only the serving measurement (one JSON line)")
     ap.add_argument("--profile-only", action="store_true", help="run warmup+steps without the extra passes")
     ap.add_argument("--no-queries", action="store_true", help="skip the paper-query (RING / NESTED x f) comparison")
     ap.add_argument("--prefetch-streams", type=int, default=2,
@@ -69,6 +70,11 @@ def main():
     args = parse()
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.serve_only:
+        import torch
+        torch.cuda.set_device(0)
+        print(json.dumps(serve_bench(args.serve_requests)), flush=True)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
@@ -142,10 +148,21 @@ def main():
         if not args.no_cpu_baseline:
             out["cpu_baseline"] = cpu_baseline(wl, args.cpu_pixels)
         if not args.no_serve:
-            del params, g0, targets
-            torch.cuda.empty_cache()
-            out["serve"] = serve_bench(args.serve_requests)
+            out["serve"] = serve_in_child(args.serve_requests)
     print(json.dumps(out), flush=True)
+
+
+def serve_in_child(n_requests):
+    """The serving measurement in a process of its own (started as a child,
+    so this process keeps its GPU state): it then starts from an empty
+    allocator and a cold cache of camera models, as a server would."""
+    import subprocess
+    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--serve-only", "--serve-requests",
+                        str(n_requests)], capture_output=True, text=True, timeout=900)
+    lines = [ln for ln in r.stdout.splitlines() if ln.startswith("{")]
+    if r.returncode != 0 or not lines:
+        raise RuntimeError(f"serving measurement failed (status {r.returncode}): {r.stderr[-2000:]}")
+    return json.loads(lines[-1])
 
 
 QUERIES = [("exact", None), ("ring_x1", ("ring", 1)), ("ring_x2", ("ring", 2)), ("ring_x4", ("ring", 4)),
