@@ -33,16 +33,29 @@ CASES = {
 }
 
 
-@pytest.mark.parametrize("case", list(CASES))
+def _big_discs():
+    """700 Gaussians 10-60 degrees across at order 9: a workgroup of 256 has
+    thousands of coarse tasks (more than the task scatter stages in LDS) and
+    many Gaussians have more than 16 (the count walk's slots), so both
+    fall-back paths of the node-order task list run."""
+    rng = np.random.default_rng(91)
+    sc = SC.make_scene(700, 0, "volume", 2.0, 6.0, 91, log_scale_mu=-0.9, log_scale_sigma=0.5, rgb_dc=True, rng=rng)
+    return sc, SC.make_camera(rng, 9, SC.CAM_FULL)
+
+
+LIST_CASES = dict(CASES, big_discs=_big_discs)
+
+
+@pytest.mark.parametrize("case", list(LIST_CASES))
 def test_tile_lists_and_order(R, case):
-    sc, cam = CASES[case]()
+    sc, cam = LIST_CASES[case]()
     g, c, st = PT.gpu_forward(R, sc, cam)
     stats = PT.compare_tile_lists(R, st, sc, cam, cam["order"])
     print(case, stats)
     assert stats["pairs"] > 0
 
 
-@pytest.mark.parametrize("case", list(CASES) + ["cfg1_fisheye", "cfg3_small"])
+@pytest.mark.parametrize("case", list(LIST_CASES) + ["cfg1_fisheye", "cfg3_small"])
 def test_sorted_bin_equals_bin_then_sort(R, case):
     """hp_bin_sorted emits exactly what hp_bin followed by the stable tile
     sort hp_sort gives: the same ids in the same order, the same ranges."""
@@ -55,7 +68,7 @@ def test_sorted_bin_equals_bin_then_sort(R, case):
         wl = SC.config3(P=50000, order=9)
         sc, camd = wl.scene, wl.cameras[0]
     else:
-        sc, camd = CASES[case]()
+        sc, camd = LIST_CASES[case]()
     g = Gaussians.from_scene(sc)
     cam = Camera.from_dict(camd)
     proj = R.preprocess(g, cam)
