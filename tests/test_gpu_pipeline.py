@@ -37,9 +37,12 @@ def _big_discs():
     """700 Gaussians 10-60 degrees across at order 9: a workgroup of 256 has
     thousands of coarse tasks (more than the task scatter stages in LDS) and
     many Gaussians have more than 16 (the count walk's slots), so both
-    fall-back paths of the node-order task list run."""
+    fall-back paths of the node-order task list run.  Four of them are
+    blown up to enclose the camera (r_s = pi): their discs reach the
+    antipode, which the binning's near cap test must not take."""
     rng = np.random.default_rng(91)
     sc = SC.make_scene(700, 0, "volume", 2.0, 6.0, 91, log_scale_mu=-0.9, log_scale_sigma=0.5, rgb_dc=True, rng=rng)
+    sc.scale[:, 100:104] *= 40.0
     return sc, SC.make_camera(rng, 9, SC.CAM_FULL)
 
 
