@@ -650,7 +650,7 @@ class Rasterizer:
                 A.call("hp_ssim_tables", C.byref(self.prm), _p(m.buf), cam.order, m.n_active, m.n_tiles, _p(t), n,
                        _stream())
                 self._ssim_tables[key] = t
-                self._evict(self._ssim_tables, None)
+                self._evict(self._ssim_tables, ("ssim_tables",))
                 self._created(("ssim_tables",) + key)
             else:
                 self._await(("ssim_tables",) + key)

@@ -55,3 +55,24 @@ def test_mask_header_check():
                 (9, 4, 300, 1), (9, 4, 3, 5), (6, 4, 10, (12 << 4) + 1)]:
         with pytest.raises(RuntimeError):
             check_mask_counts(*bad)
+
+
+def test_camera_model_caches_are_bounded():
+    """The per-camera-model caches drop their oldest entries (and those
+    entries' ready events) beyond CACHE_MODELS; what is in flight keeps its
+    own references."""
+    import threading
+    from paper_2606_29794_amd.raster import Rasterizer
+    R = Rasterizer.__new__(Rasterizer)      # the cache logic only: no device
+    R._ready = {}
+    R._lock = threading.RLock()
+    cache = {}
+    n = Rasterizer.CACHE_MODELS + 10
+    for k in range(n):
+        key = (7, 2, float(k), 0.0, 4)
+        cache[key] = object()
+        R._ready[("mask",) + key] = "event"
+        R._evict(cache, ("mask",))
+    assert len(cache) == Rasterizer.CACHE_MODELS
+    assert (7, 2, 0.0, 0.0, 4) not in cache and (7, 2, float(n - 1), 0.0, 4) in cache
+    assert len(R._ready) == Rasterizer.CACHE_MODELS
