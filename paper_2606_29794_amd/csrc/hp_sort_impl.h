@@ -19,6 +19,7 @@ constexpr int kThreads = 256;              // 4 waves
 constexpr int kItems = 16;                 // per thread and tile
 constexpr int kTile = kThreads * kItems;   // 4096 elements per tile
 constexpr int kMaxGrid = 1024;
+static_assert(kMaxGrid <= 4 * kThreads, "k_radix_digit_scan holds a row of at most 4 entries per thread");
 
 // element count: min(*n, cap) (cap when n is null)
 __device__ __forceinline__ int64_t dev_count(const uint64_t* n, int64_t cap) {
@@ -207,8 +208,8 @@ inline hp_status scan_exclusive(const In* in, T* out, const uint64_t* cnt, int64
 // radix sort
 // ---------------------------------------------------------------------------
 // digit histogram of each block's tiles, digit-major: hist[digit * G + block]
-// (an exclusive scan of the whole array then gives every block's output
-// offset for every digit)
+// (k_radix_digit_scan then turns every digit's row into the block offsets
+// within that digit)
 __global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t* __restrict__ keys,
                                                          const uint64_t* __restrict__ cnt, int64_t cap, int shift,
                                                          int bits, uint32_t* __restrict__ hist) {
@@ -226,6 +227,31 @@ __global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t* __restr
   for (int d = threadIdx.x; d < radix; d += kThreads) hist[(int64_t)d * gridDim.x + blockIdx.x] = s_h[d];
 }
 
+// One workgroup per digit d: the row hist[d * G .. d * G + G) becomes its
+// exclusive scan (where each block's keys of digit d start among all keys of
+// digit d) and dtot[d] the digit's total.  G <= kMaxGrid = 4 * kThreads, so
+// every thread holds four consecutive entries of the row.
+__global__ __launch_bounds__(kThreads) void k_radix_digit_scan(uint32_t* __restrict__ hist, int G,
+                                                               uint32_t* __restrict__ dtot) {
+  __shared__ uint32_t s_w[4];
+  uint32_t* row = hist + (int64_t)blockIdx.x * G;
+  const int j0 = 4 * (int)threadIdx.x;
+  uint32_t v[4], acc = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    v[k] = j0 + k < G ? row[j0 + k] : 0u;
+    acc += v[k];
+  }
+  uint32_t total;
+  uint32_t ex = block_exclusive<uint32_t>(acc, &total, s_w);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (j0 + k < G) row[j0 + k] = ex;
+    ex += v[k];
+  }
+  if (threadIdx.x == 0) dtot[blockIdx.x] = total;
+}
+
 // Stable scatter of each block's tiles, in order.  Per tile, wave w owns the
 // contiguous items [w*256, (w+1)*256) and ranks them in 4 rounds of 64:
 // equal digits inside a round are matched by ballots on the digit bits, and a
@@ -237,6 +263,7 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(const uint32_t* __re
                                                             const uint32_t* __restrict__ vals,
                                                             const uint64_t* __restrict__ cnt, int64_t cap, int shift,
                                                             int bits, const uint32_t* __restrict__ offs,
+                                                            const uint32_t* __restrict__ dtot,
                                                             uint32_t* __restrict__ okeys, uint32_t* __restrict__ ovals) {
   constexpr int kWaveItems = kRadixTile / 4;  // 256
   constexpr int kRounds = kWaveItems / 64;     // 4
@@ -252,7 +279,14 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(const uint32_t* __re
   const int64_t n = dev_count(cnt, cap);
   int64_t t0, t1;
   block_tiles(n, &t0, &t1, kRadixTile);
-  for (int d = tid; d < radix; d += kThreads) s_goff[d] = offs[(int64_t)d * gridDim.x + blockIdx.x];
+  // the block's first output position per digit: the keys of all smaller
+  // digits (an exclusive scan of the digit totals; radix <= kThreads) plus
+  // those of digit d in the blocks before this one
+  {
+    uint32_t all;
+    const uint32_t dpre = block_exclusive<uint32_t>(tid < radix ? dtot[tid] : 0u, &all, s_wsum);
+    if (tid < radix) s_goff[tid] = dpre + offs[(int64_t)tid * gridDim.x + blockIdx.x];
+  }
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   for (int64_t t = t0; t < t1; ++t) {
     for (int k = tid; k < 4 * 256; k += kThreads) (&s_cnt[0][0])[k] = 0;
@@ -333,7 +367,7 @@ inline unsigned copy_grid(int64_t cap) {
 
 inline size_t radix_ws_bytes(int64_t cap) {
   const int64_t h = (int64_t)radix_grid(cap) * 256;
-  return 2 * hp_align256((size_t)(cap > 0 ? cap : 1) * 4) + hp_align256((size_t)h * 4) + scan_ws_bytes<uint32_t>(h);
+  return 2 * hp_align256((size_t)(cap > 0 ? cap : 1) * 4) + hp_align256((size_t)h * 4) + hp_align256(256 * 4);
 }
 
 // Stable sort of the first min(*cnt, cap) (key, value) pairs by the low
@@ -353,16 +387,17 @@ inline hp_status radix_sort(uint32_t* keys, uint32_t* vals, const uint64_t* cnt,
   uint32_t* k2 = (uint32_t*)p; p += hp_align256((size_t)cap * 4);
   uint32_t* v2 = (uint32_t*)p; p += hp_align256((size_t)cap * 4);
   uint32_t* hist = (uint32_t*)p; p += hp_align256((size_t)G * 256 * 4);
-  void* sws = p;
+  uint32_t* dtot = (uint32_t*)p;
   uint32_t *ka = keys, *va = vals, *kb = k2, *vb = v2;
   for (int pass = 0; pass < passes; ++pass) {
     const int shift = pass * bits;
     const int b = (shift + bits <= nbits) ? bits : nbits - shift;
     hipLaunchKernelGGL(k_radix_hist, dim3(G), dim3(kThreads), 0, s, (const uint32_t*)ka, cnt, cap, shift, b, hist);
     HP_CHECK_LAUNCH();
-    HP_TRY((scan_exclusive<uint32_t, uint32_t>(hist, hist, nullptr, (int64_t)G << b, nullptr, sws, s)));
+    hipLaunchKernelGGL(k_radix_digit_scan, dim3(1u << b), dim3(kThreads), 0, s, hist, (int)G, dtot);
+    HP_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_radix_scatter, dim3(G), dim3(kThreads), 0, s, (const uint32_t*)ka, (const uint32_t*)va, cnt,
-                       cap, shift, b, (const uint32_t*)hist, kb, vb);
+                       cap, shift, b, (const uint32_t*)hist, (const uint32_t*)dtot, kb, vb);
     HP_CHECK_LAUNCH();
     uint32_t* t = ka; ka = kb; kb = t;
     t = va; va = vb; vb = t;
