@@ -97,10 +97,11 @@ def main():
 
     g_det = Gaussians(*[p.detach() for p in params])
 
+    inflight = []
+
     def step(query=None):
         for p in params:
             p.grad = None
-        tot = 0.0
         # preprocess + binning of every view on a side stream, overlapping the
         # rendering of the views before it
         pf = R.prefetch(g_det, cams, query, args.prefetch_streams) if args.prefetch_streams > 0 else None
@@ -108,10 +109,22 @@ def main():
             rgb, T = render(*params, cam, R, fused_grad=True, query=query, prepared=pf.get(v) if pf else None)
             loss, _ = hssim_loss(rgb, targets[v], cam, 0.2, R)
             loss.backward()
-        # every view's list count against the capacity it ran with (raises if
-        # a list buffer was too small; the capacities settle in the warm-up)
+        # at most two steps in flight: the host waits for the previous step,
+        # not this one, so the GPU has the next step queued when this one ends
+        done = torch.cuda.Event()
+        done.record()
+        inflight.append(done)
+        if len(inflight) > 1:
+            inflight.pop(0).synchronize()
+        # every finished view's list count against the capacity it ran with
+        # (raises if a list buffer was too small; the capacities settle in the
+        # warm-up); the rest are checked by the blocking verify after the loop
+        R.verify(block=False)
+
+    def drain():
+        torch.cuda.synchronize()
+        inflight.clear()
         R.verify()
-        return tot
 
     query = None
     if args.query:
@@ -119,12 +132,13 @@ def main():
         query = (mode, int(f))
     for _ in range(args.warmup):
         step(query)
-    torch.cuda.synchronize()
+    drain()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         step(query)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    drain()
     ms_per_step = dt * 1e3 / args.steps
     renders_per_s = args.steps * len(cams) / dt
 
@@ -144,7 +158,7 @@ def main():
         # Gaussian-pixel evaluations per second over the whole fwd+bwd step (view 0's counts)
         out["gaussian_pixel_evaluations_per_s"] = out["evaluated_pixel_pairs"] * renders_per_s
         if not args.no_queries:
-            out["tile_queries"] = query_bench(R, params, cams, targets, torch, step, args.steps)
+            out["tile_queries"] = query_bench(R, params, cams, targets, torch, step, drain, args.steps)
         if not args.no_cpu_baseline:
             out["cpu_baseline"] = cpu_baseline(wl, args.cpu_pixels)
         if not args.no_serve:
@@ -169,7 +183,7 @@ QUERIES = [("exact", None), ("ring_x1", ("ring", 1)), ("ring_x2", ("ring", 2)), 
            ("nested_x1", ("nested", 1)), ("nested_x2", ("nested", 2)), ("nested_x4", ("nested", 4))]
 
 
-def query_bench(R, params, cams, targets, torch, step, steps):
+def query_bench(R, params, cams, targets, torch, step, drain, steps):
     """The paper's own tile queries (RING scan, NESTED traversal at search
     depth f) against the exact binning on view 0: binning time, pairs kept,
     and forward / backward render time over each query's lists (HIP events,
@@ -213,12 +227,13 @@ def query_bench(R, params, cams, targets, torch, step, steps):
     whole = {}
     for name, q in (("ring_x4", ("ring", 4)), ("nested_x4", ("nested", 4)), ("exact", None)):
         step(q)
-        torch.cuda.synchronize()
+        drain()
         t0 = time.perf_counter()
         for _ in range(steps):
             step(q)
         torch.cuda.synchronize()
         whole[name] = (time.perf_counter() - t0) * 1e3 / steps
+        drain()
     res["step_ms"] = whole
     res["nested_x4_over_ring_x4_step"] = whole["nested_x4"] / whole["ring_x4"]
     return res

@@ -465,13 +465,14 @@ class Rasterizer:
                 self._overflows.append((key, n, cap))
         self._pending = keep
 
-    def verify(self) -> None:
-        """Waits for the binnings since the last verify() and compares their
-        counts with the capacities they ran with; raises PairCapacityError if
-        any list buffer was too small (its lists were left empty).  The
-        capacity hints grow from every count seen, so a repeat fits."""
+    def verify(self, block: bool = True) -> None:
+        """Waits for the binnings since the last verify() (block False: takes
+        only those already finished) and compares their counts with the
+        capacities they ran with; raises PairCapacityError if any list buffer
+        was too small (its lists were left empty).  The capacity hints grow
+        from every count seen, so a repeat fits."""
         with self._lock:
-            self._settle(block=True)
+            self._settle(block=block)
             over, self._overflows = self._overflows, []
         if over:
             raise PairCapacityError(f"{len(over)} binning(s) needed more list entries than their buffers held "

@@ -126,6 +126,13 @@ def test_capacity_hints_and_verify(R):
     R.verify()
     assert cnt.value(0) == n
     assert torch.equal(vals[:n], vals_ref[:n]) and torch.equal(ranges, ranges_ref)
+    # without waiting: an overflow is reported once its binning has finished
+    R._cap_hint[key] = n // 3
+    R.bin_lists(proj, g.P, cam)
+    torch.cuda.synchronize()
+    with pytest.raises(PairCapacityError):
+        R.verify(block=False)
+    R.verify()
 
 
 def _whole_sphere_scene(P):
