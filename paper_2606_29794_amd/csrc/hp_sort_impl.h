@@ -299,7 +299,7 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(const uint32_t* __re
       const bool valid = i < n;
       const uint32_t key = valid ? keys[i] : 0u;
       kk[r] = key;
-      vv[r] = valid ? vals[i] : 0u;
+      vv[r] = valid ? (vals ? vals[i] : (uint32_t)i) : 0u;  // no values: each key's index
       const uint32_t d = (key >> shift) & mask;
       uint64_t peers = __ballot(valid);
       for (int b = 0; b < bits; ++b) {
@@ -353,6 +353,16 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(const uint32_t* __re
   }
 }
 
+// keys[i] = src[i], vals[i] = i
+__global__ void k_keys_iota(const uint32_t* __restrict__ src, uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
+                            const uint64_t* __restrict__ cnt, int64_t cap) {
+  const int64_t n = dev_count(cnt, cap);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    keys[i] = src[i];
+    vals[i] = (uint32_t)i;
+  }
+}
+
 __global__ void k_copy_u32(const uint32_t* __restrict__ a, uint32_t* __restrict__ b, const uint64_t* __restrict__ cnt,
                            int64_t cap) {
   const int64_t n = dev_count(cnt, cap);
@@ -374,12 +384,22 @@ inline size_t radix_ws_bytes(int64_t cap) {
 // `nbits` bits of the key (cnt null: cap pairs).  The result is left in
 // (keys, vals), or, when out_keys / out_vals are given, in whichever of
 // (keys, vals) and the workspace's second buffer the last pass wrote
-// (returned through them; no copy back).
+// (returned through them; no copy back).  With first_keys, the input keys are
+// read from there and each element's value is its index: keys and vals are
+// then outputs only.
 inline hp_status radix_sort(uint32_t* keys, uint32_t* vals, const uint64_t* cnt, int64_t cap, int nbits, void* ws,
-                            hipStream_t s, uint32_t** out_keys = nullptr, uint32_t** out_vals = nullptr) {
+                            hipStream_t s, uint32_t** out_keys = nullptr, uint32_t** out_vals = nullptr,
+                            const uint32_t* first_keys = nullptr) {
   if (out_keys) *out_keys = keys;
   if (out_vals) *out_vals = vals;
-  if (cap <= 1 || nbits <= 0) return HP_OK;
+  if (cap <= 0) return HP_OK;
+  if (cap == 1 || nbits <= 0) {
+    if (first_keys) {
+      hipLaunchKernelGGL(k_keys_iota, dim3(copy_grid(cap)), dim3(256), 0, s, first_keys, keys, vals, cnt, cap);
+      HP_CHECK_LAUNCH();
+    }
+    return HP_OK;
+  }
   const int passes = (nbits + 7) / 8;
   const int bits = (nbits + passes - 1) / passes;
   const unsigned G = radix_grid(cap);
@@ -392,12 +412,14 @@ inline hp_status radix_sort(uint32_t* keys, uint32_t* vals, const uint64_t* cnt,
   for (int pass = 0; pass < passes; ++pass) {
     const int shift = pass * bits;
     const int b = (shift + bits <= nbits) ? bits : nbits - shift;
-    hipLaunchKernelGGL(k_radix_hist, dim3(G), dim3(kThreads), 0, s, (const uint32_t*)ka, cnt, cap, shift, b, hist);
+    const uint32_t* src_k = (pass == 0 && first_keys) ? first_keys : ka;
+    const uint32_t* src_v = (pass == 0 && first_keys) ? nullptr : va;
+    hipLaunchKernelGGL(k_radix_hist, dim3(G), dim3(kThreads), 0, s, src_k, cnt, cap, shift, b, hist);
     HP_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_radix_digit_scan, dim3(1u << b), dim3(kThreads), 0, s, hist, (int)G, dtot);
     HP_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_radix_scatter, dim3(G), dim3(kThreads), 0, s, (const uint32_t*)ka, (const uint32_t*)va, cnt,
-                       cap, shift, b, (const uint32_t*)hist, (const uint32_t*)dtot, kb, vb);
+    hipLaunchKernelGGL(k_radix_scatter, dim3(G), dim3(kThreads), 0, s, src_k, src_v, cnt, cap, shift, b,
+                       (const uint32_t*)hist, (const uint32_t*)dtot, kb, vb);
     HP_CHECK_LAUNCH();
     uint32_t* t = ka; ka = kb; kb = t;
     t = va; va = vb; vb = t;

@@ -78,14 +78,6 @@ __global__ void k_task_clamp(const uint64_t* __restrict__ t_total, int64_t cap_t
   *nt = t > (uint64_t)cap_t ? (uint64_t)cap_t : t;
 }
 
-__global__ void k_depth_keys(int64_t P, const float* __restrict__ depth, uint32_t* __restrict__ key,
-                             uint32_t* __restrict__ id) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= P) return;
-  key[i] = __float_as_uint(depth[i]);  // positive floats order as unsigned ints; +inf (culled) last
-  id[i] = (uint32_t)i;
-}
-
 struct BinTables {
   const float4* cap;
   const float2* sc;
@@ -991,9 +983,10 @@ static unsigned fine_grid(int64_t nt) {
 // (Gaussian, node at the split level) in order of radial depth; *w.nt holds
 // their number and *w.over whether they exceeded the workspace's capacity.
 static hp_status depth_order(const HpProjView& pv, int64_t P, BinWs& w, hipStream_t s) {
-  hipLaunchKernelGGL(k_depth_keys, dim3(hp_blocks(P, 256)), dim3(256), 0, s, P, pv.depth, w.dkey, w.order);
-  HP_CHECK_LAUNCH();
-  return hpsort::radix_sort(w.dkey, w.order, nullptr, P, 32, w.sort_ws, s);
+  // positive floats order as unsigned ints (+inf, a culled Gaussian, last):
+  // the sort reads the depths' bits as its keys
+  return hpsort::radix_sort(w.dkey, w.order, nullptr, P, 32, w.sort_ws, s, nullptr, nullptr,
+                            reinterpret_cast<const uint32_t*>(pv.depth));
 }
 
 static hp_status bin_tasks(const HpProjView& pv, int64_t P, const BinTables& T, float guard, BinWs& w, uint32_t* slots,
