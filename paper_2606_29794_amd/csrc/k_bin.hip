@@ -333,12 +333,14 @@ __global__ __launch_bounds__(256) void k_bin_coarse(int64_t P, const uint32_t* _
 // For split levels of at most kHistNodes nodes.  The count walk also counts
 // each workgroup's tasks per node into a node-major histogram [nn][G] (G
 // workgroups of 256 Gaussians in depth order).  An exclusive scan of the
-// histogram gives every (node, workgroup) its first slot, and the scatter
+// histogram (each node's row scanned by its own workgroup, then the node
+// offsets added) gives every (node, workgroup) its first slot, and the scatter
 // pass writes each task straight to its place: that slot plus the number of
 // the workgroup's earlier Gaussians with a task at the node.  A Gaussian has
 // at most one task per node, so this is the order a stable sort of the
 // depth-ordered tasks by node gives.
 constexpr int kHistNodes = 768;
+static_assert(kHistNodes <= 4 * 256, "k_task_segments takes four nodes per thread");
 
 __global__ __launch_bounds__(256) void k_task_count(int64_t P, const uint32_t* __restrict__ order,
                                                     const float4* __restrict__ disc, const float* __restrict__ radius,
@@ -372,6 +374,38 @@ __global__ __launch_bounds__(256) void k_task_count(int64_t P, const uint32_t* _
   for (int n = threadIdx.x; n < nn; n += blockDim.x) hist[(int64_t)n * G + gb] = s_cnt[n];
 }
 
+// One workgroup per node n: the histogram row hist[n][0..G) becomes its
+// exclusive scan hoff[n][0..G) (where workgroup b's tasks at node n start
+// among the node's tasks) and rowtot[n] the node's task count.  The node
+// offsets (an exclusive scan of rowtot) follow in k_task_segments.
+__global__ __launch_bounds__(256) void k_hist_rows(const uint32_t* __restrict__ hist, int64_t G,
+                                                   uint64_t* __restrict__ hoff, uint64_t* __restrict__ rowtot) {
+  __shared__ uint64_t s_w[4];
+  constexpr int kItems = 16;
+  const uint32_t* row = hist + (int64_t)blockIdx.x * G;
+  uint64_t* out = hoff + (int64_t)blockIdx.x * G;
+  uint64_t carry = 0;
+  for (int64_t t0 = 0; t0 < G; t0 += 256 * kItems) {
+    const int64_t j0 = t0 + (int64_t)kItems * threadIdx.x;
+    uint32_t v[kItems];
+    uint64_t acc = 0;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+      v[k] = j0 + k < G ? row[j0 + k] : 0u;
+      acc += v[k];
+    }
+    uint64_t tot;
+    uint64_t ex = hpsort::block_exclusive<uint64_t>(acc, &tot, s_w) + carry;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+      if (j0 + k < G) out[j0 + k] = ex;
+      ex += v[k];
+    }
+    carry += tot;
+  }
+  if (threadIdx.x == 0) rowtot[blockIdx.x] = carry;
+}
+
 // Dynamic LDS per node: the workgroup's first slot (8 B), 256 membership
 // bits (which of the workgroup's Gaussians have a task at the node), the
 // node's first place in the workgroup's staging run (4 B) and the bit counts
@@ -386,7 +420,8 @@ __global__ __launch_bounds__(256) void k_task_scatter(int64_t P, const uint32_t*
                                                       const float* __restrict__ radius, BinTables T,
                                                       const uint32_t* __restrict__ tcount,
                                                       const uint32_t* __restrict__ slots, int nn,
-                                                      const uint64_t* __restrict__ hoff, int64_t cap_t,
+                                                      const uint64_t* __restrict__ hoff,
+                                                      const uint64_t* __restrict__ node_off, int64_t cap_t,
                                                       uint32_t* __restrict__ task_g) {
   extern __shared__ uint64_t s_dyn[];
   uint64_t* s_off = s_dyn;                            // [nn]
@@ -399,7 +434,7 @@ __global__ __launch_bounds__(256) void k_task_scatter(int64_t P, const uint32_t*
   __shared__ uint32_t s_w[4];
   const int ntop = load_top_nodes(T, S);
   const int64_t G = gridDim.x;
-  for (int n = threadIdx.x; n < nn; n += blockDim.x) s_off[n] = hoff[(int64_t)n * G + blockIdx.x];
+  for (int n = threadIdx.x; n < nn; n += blockDim.x) s_off[n] = node_off[n] + hoff[(int64_t)n * G + blockIdx.x];
   for (int i = threadIdx.x; i < 8 * nn; i += blockDim.x) s_bits[i] = 0u;
   __syncthreads();
   const float srmax = top_srmax(S, ntop);
@@ -474,35 +509,49 @@ __global__ __launch_bounds__(256) void k_task_scatter(int64_t P, const uint32_t*
   }
 }
 
-// One workgroup: the task total and overflow flag, every node's task segment
-// (clamped to the capacity), its chunks of 64 tasks and their offsets, and
-// the number of (chunk, leaf) columns.  After an overflow no chunk is made.
-__global__ __launch_bounds__(256) void k_task_segments(int nn, int64_t G, const uint64_t* __restrict__ hoff,
-                                                       const uint64_t* __restrict__ t_total, int64_t cap_t, int depth,
-                                                       uint64_t* __restrict__ nt, uint32_t* __restrict__ over,
-                                                       uint32_t* __restrict__ seg, uint32_t* __restrict__ choff,
-                                                       uint64_t* __restrict__ ncol) {
+// One workgroup: every node's first task (an exclusive scan of the node task
+// counts, into node_off), the task total and overflow flag, every node's task
+// segment (clamped to the capacity), its chunks of 64 tasks and their
+// offsets, and the number of (chunk, leaf) columns.  After an overflow no
+// chunk is made.
+__global__ __launch_bounds__(256) void k_task_segments(int nn, const uint64_t* __restrict__ rowtot,
+                                                       uint64_t* __restrict__ node_off, int64_t cap_t, int depth,
+                                                       uint64_t* __restrict__ t_total, uint64_t* __restrict__ nt,
+                                                       uint32_t* __restrict__ over, uint32_t* __restrict__ seg,
+                                                       uint32_t* __restrict__ choff, uint64_t* __restrict__ ncol) {
+  __shared__ uint64_t s_w64[4];
   __shared__ uint32_t s_w[4];
-  const uint64_t tot = *t_total;
+  // nodes 4t .. 4t + 3 of thread t
+  uint64_t cnt[4], sum = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int n = 4 * (int)threadIdx.x + q;
+    cnt[q] = n < nn ? rowtot[n] : 0ull;
+    sum += cnt[q];
+  }
+  uint64_t tot;
+  uint64_t pre = hpsort::block_exclusive<uint64_t>(sum, &tot, s_w64);
   const bool ov = tot > (uint64_t)cap_t;
   const uint64_t lim = ov ? (uint64_t)cap_t : tot;
-  uint32_t nch[4], sum = 0;
+  uint32_t nch[4], csum = 0;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int n = 4 * (int)threadIdx.x + q;
     nch[q] = 0u;
     if (n < nn) {
-      uint64_t s0 = hoff[(int64_t)n * G], s1 = n + 1 < nn ? hoff[(int64_t)(n + 1) * G] : tot;
+      node_off[n] = pre;
+      uint64_t s0 = pre, s1 = pre + cnt[q];
       s0 = s0 < lim ? s0 : lim;
       s1 = s1 < lim ? s1 : lim;
       seg[2 * n] = (uint32_t)s0;
       seg[2 * n + 1] = (uint32_t)s1;
       nch[q] = ov ? 0u : (uint32_t)((s1 - s0 + 63) / 64);
     }
-    sum += nch[q];
+    pre += cnt[q];
+    csum += nch[q];
   }
   uint32_t total;
-  uint32_t ex = hpsort::block_exclusive<uint32_t>(sum, &total, s_w);
+  uint32_t ex = hpsort::block_exclusive<uint32_t>(csum, &total, s_w);
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int n = 4 * (int)threadIdx.x + q;
@@ -512,6 +561,7 @@ __global__ __launch_bounds__(256) void k_task_segments(int nn, int64_t G, const 
   if (threadIdx.x == 0) {
     choff[nn] = total;
     *ncol = (uint64_t)total << (2 * depth);
+    *t_total = tot;
     *nt = lim;
     *over = ov ? 1u : 0u;
   }
@@ -1156,8 +1206,9 @@ hp_status hp_bin_sorted_widened(int32_t phase, const void* projected, int64_t P,
     HP_CHECK_LAUNCH();
     if (sw.nn <= kHistNodes) {
       // tasks written in node order straight from the walk (no task sort);
-      // the histogram lives in task_n and its scan in poff, which this path
-      // does not otherwise use (nn x G <= 4 (P + 255) <= task capacity)
+      // the histogram lives in task_n and its row scans, node counts and node
+      // offsets in poff, which this path does not otherwise use
+      // (nn x G + 2 nn <= 3 (P + 255) + 1536 <= task capacity)
       HP_TRY(depth_order(pv, P, w, s));
       const unsigned G = hp_blocks(P, 256);
       const int nni = (int)sw.nn;
@@ -1166,14 +1217,19 @@ hp_status hp_bin_sorted_widened(int32_t phase, const void* projected, int64_t P,
       hipLaunchKernelGGL(k_task_count, dim3(G), dim3(256), 0, s, P, (const uint32_t*)w.order, pv.disc, pv.radius, T,
                          w.tcount, sw.slots, nni, hist);
       HP_CHECK_LAUNCH();
-      HP_TRY((hpsort::scan_exclusive<uint64_t, uint32_t>(hist, hoff, nullptr, (int64_t)nni * G, w.t_total, w.scan_ws,
-                                                         s)));
+      // per node: the row scan of the histogram and the node's task count
+      // (after the histogram in poff), then the node offsets
+      uint64_t* rowtot = hoff + (int64_t)nni * G;
+      uint64_t* node_off = rowtot + nni;
+      hipLaunchKernelGGL(k_hist_rows, dim3(nni), dim3(256), 0, s, (const uint32_t*)hist, (int64_t)G, hoff, rowtot);
+      HP_CHECK_LAUNCH();
+      hipLaunchKernelGGL(k_task_segments, dim3(1), dim3(256), 0, s, nni, (const uint64_t*)rowtot, node_off, w.cap_t,
+                         depth, w.t_total, w.nt, w.over, sw.seg, sw.choff, w.ncol);
+      HP_CHECK_LAUNCH();
       hipLaunchKernelGGL(k_task_scatter, dim3(G), dim3(256), (size_t)nni * kScatterLdsPerNode, s, P,
                          (const uint32_t*)w.order, pv.disc, pv.radius, T, (const uint32_t*)w.tcount,
-                         (const uint32_t*)sw.slots, nni, (const uint64_t*)hoff, w.cap_t, w.task_g);
-      HP_CHECK_LAUNCH();
-      hipLaunchKernelGGL(k_task_segments, dim3(1), dim3(256), 0, s, nni, (int64_t)G, (const uint64_t*)hoff,
-                         (const uint64_t*)w.t_total, w.cap_t, depth, w.nt, w.over, sw.seg, sw.choff, w.ncol);
+                         (const uint32_t*)sw.slots, nni, (const uint64_t*)hoff, (const uint64_t*)node_off, w.cap_t,
+                         w.task_g);
       HP_CHECK_LAUNCH();
     } else {
       HP_TRY(bin_tasks(pv, P, T, prm->bin_guard, w, sw.slots, s));
