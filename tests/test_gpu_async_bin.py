@@ -30,7 +30,9 @@ def _stream():
 
 
 @pytest.mark.parametrize("n,cap,n_tiles", [(0, 10, 5), (1, 1, 3), (4095, 5000, 300), (4096, 4096, 300),
-                                           (4097, 9000, 300), (300_001, 400_000, 70_000), (250_000, 250_000, 12)])
+                                           (4097, 9000, 300), (300_001, 400_000, 70_000), (250_000, 250_000, 12),
+                                           # 1024 workgroups of several 1024-key tiles each, 3 passes
+                                           (2_500_000, 3_000_000, 70_000)])
 def test_sort_matches_stable_numpy_sort(R, n, cap, n_tiles):
     """hp_sort with the count in device memory and a buffer of `cap` pairs:
     keys, values (stable order) and ranges equal numpy's stable argsort."""

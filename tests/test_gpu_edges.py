@@ -80,6 +80,22 @@ def test_empty_scene(R):
     assert float(st.T.min()) == 1.0 and float(st.rgb.abs().max()) == 0.0
 
 
+def test_single_visible_gaussian(R):
+    """One Gaussian in view (the depth sort of a single element takes its own
+    path: the key copied, the order written, no pass): image equal to the
+    oracle's."""
+    wl = SC.config0(P=1)
+    cam = wl.cameras[0]
+    g, c, st = PT.gpu_forward(R, wl.scene, cam)
+    assert st.n_pairs > 0
+    act = st.mask.active_pix.cpu().numpy().astype(np.int64)
+    pr = O.preprocess(wl.scene, cam)
+    rgb_o, T_o, nu_o, frag = O.render(wl.scene, cam, pr, act, **PT.BANDS)
+    PT.compare_render(st.rgb.cpu().numpy().astype(np.float64), st.T.cpu().numpy().astype(np.float64), rgb_o, T_o,
+                      frag)
+    assert float(T_o.min()) < 0.99   # the Gaussian covers some pixels
+
+
 def test_wide_footprints_every_k2_range(R):
     """Gaussians 20-70 degrees across at order 5: a large share of the pixels
     they reach lie 14.5-30 degrees from the centre (the twelve-term series
