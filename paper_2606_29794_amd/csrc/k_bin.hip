@@ -871,46 +871,13 @@ __global__ __launch_bounds__(256) void k_bin_cols(const uint32_t* __restrict__ c
   }
 }
 
-// Inclusive max over the 64 lanes (all active): the DPP pattern of the
-// sorting's wave scan with max in place of the sum (0, what lanes outside a
-// row read, is the identity of an unsigned max).
-__device__ __forceinline__ uint32_t wave_inclusive_max(uint32_t x) {
-  x = max(x, hpsort::dpp_u32<0x111, 0xf, true>(x));
-  x = max(x, hpsort::dpp_u32<0x112, 0xf, true>(x));
-  x = max(x, hpsort::dpp_u32<0x114, 0xf, true>(x));
-  x = max(x, hpsort::dpp_u32<0x118, 0xf, true>(x));
-  x = max(x, hpsort::dpp_u32<0x142, 0xa, false>(x));
-  x = max(x, hpsort::dpp_u32<0x143, 0xc, false>(x));
-  return x;
-}
-
-// index of the r-th set bit (from 0) of w; r < popcount(w)
-__device__ __forceinline__ uint32_t select_bit64(uint64_t w, uint32_t r) {
-  uint32_t pos = 0, v = (uint32_t)w, c = (uint32_t)__popc(v);
-  if (r >= c) {
-    r -= c;
-    v = (uint32_t)(w >> 32);
-    pos = 32;
-  }
-#pragma unroll
-  for (int h = 16; h >= 1; h >>= 1) {
-    c = (uint32_t)__popc(v & ((1u << h) - 1u));
-    if (r >= c) {
-      r -= c;
-      v >>= h;
-      pos += (uint32_t)h;
-    }
-  }
-  return pos;
-}
-
 // Per chunk: every hit of leaf b's column goes to its slot in tile (node, b).
-// The chunk's hits are numbered in (leaf, task) order and the wave writes 64
-// of them per store, lane k taking hit o + k: the column that holds it is
-// found by a running maximum over marks placed at every column's first
-// number, its rank in the column gives the slot and, through the column's
-// bits, the task.  So each store instruction is full (the slots of one
-// column are consecutive), where a store per column would carry ~10 lanes.
+// The chunk's hits are numbered in (leaf, task) order: column lane b lists
+// its hits (column and task, lowest task first) in LDS at their numbers,
+// and the wave then writes 64 of them per store, lane k taking hit o + k,
+// whose rank in its column gives the slot.  So each store instruction is
+// full (the slots of one column are consecutive), where a store per column
+// would carry ~10 lanes.
 constexpr int kMaxChunkHits = 64 * 64;
 
 __global__ __launch_bounds__(256) void k_bin_emit_sorted(const uint32_t* __restrict__ choff, uint32_t nn,
@@ -922,9 +889,9 @@ __global__ __launch_bounds__(256) void k_bin_emit_sorted(const uint32_t* __restr
                                                          const int64_t* __restrict__ n_pairs, int64_t capacity,
                                                          uint32_t* __restrict__ vals) {
   if (*n_pairs > capacity) return;
-  __shared__ uint64_t s_W[4][64], s_base[4][64];
+  __shared__ uint64_t s_base[4][64];
   __shared__ uint32_t s_g[4][64], s_off[4][64];
-  __shared__ uint8_t s_mark[4][kMaxChunkHits];
+  __shared__ uint16_t s_hit[4][kMaxChunkHits];  // column << 8 | task of every hit number
   const uint32_t nchunks = hp_uniform(((hp_cu32p)choff)[nn]);
   const int lane = hp_lane();
   const int wv = threadIdx.x >> 6;
@@ -954,27 +921,24 @@ __global__ __launch_bounds__(256) void k_bin_emit_sorted(const uint32_t* __restr
     const uint32_t incl = hpsort::wave_inclusive<uint32_t>(cnt);
     const uint32_t off = incl - cnt;
     const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
-    // the previous chunk's marks within [0, tot) go, then this chunk's
-    // columns mark their first number (distinct for non-empty columns)
-    for (uint32_t o = (uint32_t)lane; o < tot; o += 64) s_mark[wv][o] = 0;
-    __builtin_amdgcn_wave_barrier();
-    if (cnt) s_mark[wv][off] = (uint8_t)(lane + 1);
-    s_W[wv][lane] = W;
+    // column lane b: its hits at numbers off, off + 1, ... (every number
+    // below tot written once)
+    {
+      uint64_t w = W;
+      const uint32_t col = (uint32_t)lane << 8;
+      for (uint32_t r = off; w != 0; ++r) {
+        s_hit[wv][r] = (uint16_t)(col | (uint32_t)__builtin_ctzll(w));
+        w &= w - 1;
+      }
+    }
     s_base[wv][lane] = base;
     s_g[wv][lane] = g;
     s_off[wv][lane] = off;
     __builtin_amdgcn_wave_barrier();
-    uint32_t carry = 0;
-    for (uint32_t o = 0; o < tot; o += 64) {
-      const uint32_t k = o + (uint32_t)lane;
-      const uint32_t m = max(wave_inclusive_max(k < tot ? (uint32_t)s_mark[wv][k] : 0u), carry);
-      carry = (uint32_t)__builtin_amdgcn_readlane((int)m, 63);
-      if (k < tot) {
-        const uint32_t b = m - 1u;
-        const uint32_t r = k - s_off[wv][b];
-        const uint32_t j = select_bit64(s_W[wv][b], r);
-        vals[s_base[wv][b] + r] = s_g[wv][j];
-      }
+    for (uint32_t k = (uint32_t)lane; k < tot; k += 64) {
+      const uint32_t e = s_hit[wv][k];
+      const uint32_t b = e >> 8;
+      vals[s_base[wv][b] + (k - s_off[wv][b])] = s_g[wv][e & 0xffu];
     }
     __builtin_amdgcn_wave_barrier();  // this chunk's LDS reads are done
     if (!more) break;
