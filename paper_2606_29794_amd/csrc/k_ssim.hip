@@ -211,6 +211,7 @@ __global__ __launch_bounds__(256) void k_ssim_fwd(SsimArgs A, const float* __res
   };
   int32_t e[NG], en[NG];
   float v[NG][6], vn[NG][6];
+  float acc_s = 0.f, acc_l = 0.f;  // this thread's SSIM and L1 sums over the workgroup's tiles
   if ((int)blockIdx.x >= n_tiles) return;
   // one tile: the cells in e / v; with more, the next tile's (ln) are
   // fetched into en / vn during the passes
@@ -413,14 +414,8 @@ __global__ __launch_bounds__(256) void k_ssim_fwd(SsimArgs A, const float* __res
       float4* out = reinterpret_cast<float4*>(G + start * kSsG);
       for (int i = tid; i < 3 * cnt; i += 256) out[i] = stage[i];
     }
-    // block reduction of (ssum, lsum)
-    float red[2] = {ssum, lsum};
-    hp_wave_totals<2>(red);
-    if (hp_lane() == 0) { s_red[0][tid >> 6] = red[0]; s_red[1][tid >> 6] = red[1]; }
-    __syncthreads();
-    if (tid == 0)
-      part[ct] = make_float2(s_red[0][0] + s_red[0][1] + s_red[0][2] + s_red[0][3],
-                             s_red[1][0] + s_red[1][1] + s_red[1][2] + s_red[1][3]);
+    acc_s += ssum;
+    acc_l += lsum;
   };
   if constexpr (ZONES) {
     // with zone windows every workgroup has one tile (ssim_grid)
@@ -441,6 +436,14 @@ __global__ __launch_bounds__(256) void k_ssim_fwd(SsimArgs A, const float* __res
       }
     }
   }
+  // the workgroup's (sum of SSIM, sum of |img - ref|) over its tiles
+  float red[2] = {acc_s, acc_l};
+  hp_wave_totals<2>(red);
+  if (hp_lane() == 0) { s_red[0][tid >> 6] = red[0]; s_red[1][tid >> 6] = red[1]; }
+  __syncthreads();
+  if (tid == 0)
+    part[blockIdx.x] = make_float2(s_red[0][0] + s_red[0][1] + s_red[0][2] + s_red[0][3],
+                                   s_red[1][0] + s_red[1][1] + s_red[1][2] + s_red[1][3]);
 }
 
 // single block: mean SSIM, mean L1, loss
@@ -800,7 +803,9 @@ static hp_status ssim_fwd_launch(const SsimArgs& A, bool zones, const float* img
     case 1: HP_TRY(ssim_fwd_launch_b<2>(A, zones, img, ref, n_tiles, ssim_map, Gm, part, s)); break;
     default: HP_TRY(ssim_fwd_launch_b<1>(A, zones, img, ref, n_tiles, ssim_map, Gm, part, s)); break;
   }
-  hipLaunchKernelGGL(k_ssim_reduce, dim3(1), dim3(1024), 0, s, (const float2*)part, (int)n_tiles, A.n_active, lam, out);
+  // one partial per forward workgroup
+  hipLaunchKernelGGL(k_ssim_reduce, dim3(1), dim3(1024), 0, s, (const float2*)part, (int)ssim_grid(n_tiles, zones),
+                     A.n_active, lam, out);
   HP_CHECK_LAUNCH();
   return HP_OK;
 }
