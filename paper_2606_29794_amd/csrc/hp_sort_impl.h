@@ -132,7 +132,8 @@ __global__ __launch_bounds__(kThreads) void k_scan_reduce(const In* __restrict__
 // neighbouring threads start in different banks.
 template <class T, class In>
 __global__ __launch_bounds__(kThreads) void k_scan_down(const In* in, T* out, const uint64_t* __restrict__ cnt,
-                                                        int64_t cap, const T* __restrict__ sums, T* grand) {
+                                                        int64_t cap, const T* __restrict__ sums, T* grand,
+                                                        int64_t* count_out, const uint32_t* __restrict__ over) {
   __shared__ T s_w[4];
   __shared__ T s_x[kTile + kTile / kItems];
   const int64_t n = dev_count(cnt, cap);
@@ -148,7 +149,10 @@ __global__ __launch_bounds__(kThreads) void k_scan_down(const In* in, T* out, co
   T carry, tot_all;
   block_exclusive<T>(pre, &carry, s_w);
   block_exclusive<T>(all, &tot_all, s_w);
-  if (grand && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *grand = tot_all;
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
+    if (grand) *grand = tot_all;
+    if (count_out) *count_out = *over ? INT64_MAX : (int64_t)tot_all;
+  }
   const int run = (int)threadIdx.x * (kItems + 1);
   for (int64_t t = t0; t < t1; ++t) {
     const int64_t tb = t * kTile;
@@ -190,16 +194,19 @@ inline size_t scan_ws_bytes(int64_t cap) {
 
 // Exclusive scan of the first min(*cnt, cap) elements of `in` (converted to
 // T) into `out` (in place allowed); *grand (device, nullable) receives the
-// total.  cnt null: cap elements.
+// total.  cnt null: cap elements.  With count_out (device, nullable; then
+// `over` too) *count_out receives the total as int64, or INT64_MAX when *over
+// is set.
 template <class T, class In>
 inline hp_status scan_exclusive(const In* in, T* out, const uint64_t* cnt, int64_t cap, T* grand, void* ws,
-                                hipStream_t s) {
+                                hipStream_t s, int64_t* count_out = nullptr, const uint32_t* over = nullptr) {
   if (cap < 0) return HP_ERR_INVALID_ARG;
   const unsigned G = grid_for(cap);
   T* sums = (T*)ws;
   hipLaunchKernelGGL((k_scan_reduce<T, In>), dim3(G), dim3(kThreads), 0, s, in, cnt, cap, sums);
   HP_CHECK_LAUNCH();
-  hipLaunchKernelGGL((k_scan_down<T, In>), dim3(G), dim3(kThreads), 0, s, in, out, cnt, cap, (const T*)sums, grand);
+  hipLaunchKernelGGL((k_scan_down<T, In>), dim3(G), dim3(kThreads), 0, s, in, out, cnt, cap, (const T*)sums, grand,
+                     count_out, over);
   HP_CHECK_LAUNCH();
   return HP_OK;
 }

@@ -979,11 +979,6 @@ __global__ void k_col_count(const uint32_t* __restrict__ choff, uint32_t nn, int
   *ncol = (uint64_t)choff[nn] << (2 * depth);
 }
 
-// the pair total, or a count no buffer holds when the tasks overflowed: the
-// emission kernels then write nothing
-__global__ void k_store_total(const uint64_t* grand, const uint32_t* over, int64_t* n_pairs) {
-  *n_pairs = *over ? INT64_MAX : (int64_t)*grand;
-}
 __global__ void k_store_zero(int64_t* n_pairs) { *n_pairs = 0; }
 __global__ void k_store_unfinished(int64_t* n_pairs) { *n_pairs = INT64_MAX; }
 
@@ -1052,10 +1047,10 @@ extern "C" hp_status hp_bin(int32_t phase, const void* projected, int64_t P, con
     hipLaunchKernelGGL(k_bin_fine_count, dim3(fine_grid(w.cap_t)), dim3(256), 0, s, (const uint64_t*)w.nt, w.cap_t,
                        w.task_g, w.task_n, pv.disc, T, w.pmask, w.pcount);
     HP_CHECK_LAUNCH();
-    HP_TRY((hpsort::scan_exclusive<uint64_t, uint32_t>(w.pcount, w.poff, w.nt, w.cap_t, w.p_total, w.scan_ws, s)));
-    hipLaunchKernelGGL(k_store_total, dim3(1), dim3(1), 0, s, (const uint64_t*)w.p_total, (const uint32_t*)w.over,
-                       n_pairs);
-    HP_CHECK_LAUNCH();
+    // the pair total goes to *n_pairs with the scan (a count no buffer holds
+    // when the tasks overflowed: the emission kernels then write nothing)
+    HP_TRY((hpsort::scan_exclusive<uint64_t, uint32_t>(w.pcount, w.poff, w.nt, w.cap_t, w.p_total, w.scan_ws, s,
+                                                       n_pairs, (const uint32_t*)w.over)));
   }
   if ((phase & HP_BIN_EMIT) && P > 0) {
     // the task count is read on the device; the grid covers the capacity bound
@@ -1229,10 +1224,10 @@ hp_status hp_bin_sorted_widened(int32_t phase, const void* projected, int64_t P,
                        (const uint32_t*)sw.seg, (const uint32_t*)sw.cnode, (const uint32_t*)w.task_g, pv.disc, T,
                        sw.wcol, sw.cnt);
     HP_CHECK_LAUNCH();
-    HP_TRY((hpsort::scan_exclusive<uint64_t, uint32_t>(sw.cnt, sw.start, w.ncol, sw.L, w.p_total, sw.scan_ws, s)));
-    hipLaunchKernelGGL(k_store_total, dim3(1), dim3(1), 0, s, (const uint64_t*)w.p_total, (const uint32_t*)w.over,
-                       n_pairs);
-    HP_CHECK_LAUNCH();
+    // the pair total goes to *n_pairs with the scan (a count no buffer holds
+    // when the tasks overflowed: the emission kernels then write nothing)
+    HP_TRY((hpsort::scan_exclusive<uint64_t, uint32_t>(sw.cnt, sw.start, w.ncol, sw.L, w.p_total, sw.scan_ws, s,
+                                                       n_pairs, (const uint32_t*)w.over)));
   }
   if ((phase & HP_BIN_EMIT) && P > 0) {
     // the chunk count is read on the device: launch for the workspace's bound

@@ -133,7 +133,8 @@ class PairCapacityError(RuntimeError):
 
 class PairCount:
     """The pair count of one binning as the device wrote it (int64 [2]: the
-    entries the lists need, and the entries kept by a paper query), with the
+    entries the lists need, and the entries kept by a paper query, defined
+    for a query only), with the
     capacity of the list buffer it was emitted into.  Reading it waits for
     the binning; nothing on the render path reads it."""
 
@@ -419,7 +420,9 @@ class Rasterizer:
         nbytes = (A.lib().hp_bin_sorted_workspace_bytes(P, cam.order, self.prm.tile_log2) if query is None else
                   A.lib().hp_bin_query_workspace_bytes(P, cam.order, self.prm.tile_log2))
         ws = self.workspace(nbytes)
-        cnt = torch.zeros(2, dtype=torch.int64, device=self.device)
+        # the list count (written by every binning) and, for a paper query,
+        # the entries kept (zero until its emission writes it)
+        cnt = (torch.empty if query is None else torch.zeros)(2, dtype=torch.int64, device=self.device)
         ranges = torch.empty((max(m.n_tiles, 1), 2), dtype=torch.int32, device=self.device)
         cap = self.capacity_hint(P, cam, query, m.n_tiles)
         if cap is None:
