@@ -219,8 +219,9 @@ inline hp_status scan_exclusive(const In* in, T* out, const uint64_t* cnt, int64
 // within that digit)
 __global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t* __restrict__ keys,
                                                          const uint64_t* __restrict__ cnt, int64_t cap, int shift,
-                                                         int bits, uint32_t* __restrict__ hist) {
+                                                         int bits, uint32_t* __restrict__ hist, int64_t* mark) {
   __shared__ uint32_t s_h[256];
+  if (mark && blockIdx.x == 0 && threadIdx.x == 0) *mark = INT64_MAX;
   const int radix = 1 << bits;
   const uint32_t mask = (uint32_t)radix - 1;
   for (int d = threadIdx.x; d < radix; d += kThreads) s_h[d] = 0;
@@ -362,7 +363,8 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(const uint32_t* __re
 
 // keys[i] = src[i], vals[i] = i
 __global__ void k_keys_iota(const uint32_t* __restrict__ src, uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
-                            const uint64_t* __restrict__ cnt, int64_t cap) {
+                            const uint64_t* __restrict__ cnt, int64_t cap, int64_t* mark) {
+  if (mark && blockIdx.x == 0 && threadIdx.x == 0) *mark = INT64_MAX;
   const int64_t n = dev_count(cnt, cap);
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     keys[i] = src[i];
@@ -393,16 +395,19 @@ inline size_t radix_ws_bytes(int64_t cap) {
 // (keys, vals) and the workspace's second buffer the last pass wrote
 // (returned through them; no copy back).  With first_keys, the input keys are
 // read from there and each element's value is its index: keys and vals are
-// then outputs only.
+// then outputs only.  With mark (device, nullable), the sort's first kernel
+// also sets *mark = INT64_MAX (a caller's "not yet counted" flag, set by the
+// first kernel of its sequence); first_keys is required then.
 inline hp_status radix_sort(uint32_t* keys, uint32_t* vals, const uint64_t* cnt, int64_t cap, int nbits, void* ws,
                             hipStream_t s, uint32_t** out_keys = nullptr, uint32_t** out_vals = nullptr,
-                            const uint32_t* first_keys = nullptr) {
+                            const uint32_t* first_keys = nullptr, int64_t* mark = nullptr) {
   if (out_keys) *out_keys = keys;
   if (out_vals) *out_vals = vals;
+  if (mark && (!first_keys || cap <= 0)) return HP_ERR_INVALID_ARG;
   if (cap <= 0) return HP_OK;
   if (cap == 1 || nbits <= 0) {
     if (first_keys) {
-      hipLaunchKernelGGL(k_keys_iota, dim3(copy_grid(cap)), dim3(256), 0, s, first_keys, keys, vals, cnt, cap);
+      hipLaunchKernelGGL(k_keys_iota, dim3(copy_grid(cap)), dim3(256), 0, s, first_keys, keys, vals, cnt, cap, mark);
       HP_CHECK_LAUNCH();
     }
     return HP_OK;
@@ -421,7 +426,8 @@ inline hp_status radix_sort(uint32_t* keys, uint32_t* vals, const uint64_t* cnt,
     const int b = (shift + bits <= nbits) ? bits : nbits - shift;
     const uint32_t* src_k = (pass == 0 && first_keys) ? first_keys : ka;
     const uint32_t* src_v = (pass == 0 && first_keys) ? nullptr : va;
-    hipLaunchKernelGGL(k_radix_hist, dim3(G), dim3(kThreads), 0, s, src_k, cnt, cap, shift, b, hist);
+    hipLaunchKernelGGL(k_radix_hist, dim3(G), dim3(kThreads), 0, s, src_k, cnt, cap, shift, b, hist,
+                       pass == 0 ? mark : nullptr);
     HP_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_radix_digit_scan, dim3(1u << b), dim3(kThreads), 0, s, hist, (int)G, dtot);
     HP_CHECK_LAUNCH();

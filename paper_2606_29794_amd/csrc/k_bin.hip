@@ -980,7 +980,6 @@ __global__ void k_col_count(const uint32_t* __restrict__ choff, uint32_t nn, int
 }
 
 __global__ void k_store_zero(int64_t* n_pairs) { *n_pairs = 0; }
-__global__ void k_store_unfinished(int64_t* n_pairs) { *n_pairs = INT64_MAX; }
 
 // one wave per 64 tasks, at most 8192 blocks of 4 waves that loop over them
 static unsigned fine_grid(int64_t nt) {
@@ -991,16 +990,18 @@ static unsigned fine_grid(int64_t nt) {
 // Depth order, coarse walk and task list (shared by both emissions): tasks
 // (Gaussian, node at the split level) in order of radial depth; *w.nt holds
 // their number and *w.over whether they exceeded the workspace's capacity.
-static hp_status depth_order(const HpProjView& pv, int64_t P, BinWs& w, hipStream_t s) {
+// Its first kernel also sets *n_pairs = INT64_MAX: until the count completes,
+// the count says that nothing may be emitted.
+static hp_status depth_order(const HpProjView& pv, int64_t P, BinWs& w, int64_t* n_pairs, hipStream_t s) {
   // positive floats order as unsigned ints (+inf, a culled Gaussian, last):
   // the sort reads the depths' bits as its keys
   return hpsort::radix_sort(w.dkey, w.order, nullptr, P, 32, w.sort_ws, s, nullptr, nullptr,
-                            reinterpret_cast<const uint32_t*>(pv.depth));
+                            reinterpret_cast<const uint32_t*>(pv.depth), n_pairs);
 }
 
 static hp_status bin_tasks(const HpProjView& pv, int64_t P, const BinTables& T, float guard, BinWs& w, uint32_t* slots,
-                           hipStream_t s) {
-  HP_TRY(depth_order(pv, P, w, s));
+                           int64_t* n_pairs, hipStream_t s) {
+  HP_TRY(depth_order(pv, P, w, n_pairs, s));
   hipLaunchKernelGGL((k_bin_coarse<false>), dim3(hp_blocks(P, 256)), dim3(256), 0, s, P, w.order, pv.disc, pv.radius,
                      T, guard, w.tcount, (const uint64_t*)nullptr, w.cap_t, (uint32_t*)nullptr, (uint32_t*)nullptr,
                      slots);
@@ -1040,9 +1041,7 @@ extern "C" hp_status hp_bin(int32_t phase, const void* projected, int64_t P, con
       HP_CHECK_LAUNCH();
       return HP_OK;
     }
-    hipLaunchKernelGGL(k_store_unfinished, dim3(1), dim3(1), 0, s, n_pairs);
-    HP_CHECK_LAUNCH();
-    HP_TRY(bin_tasks(pv, P, T, prm->bin_guard, w, nullptr, s));
+    HP_TRY(bin_tasks(pv, P, T, prm->bin_guard, w, nullptr, n_pairs, s));
     // per task: its 64-bit hit mask and count; the counts scanned into offsets
     hipLaunchKernelGGL(k_bin_fine_count, dim3(fine_grid(w.cap_t)), dim3(256), 0, s, (const uint64_t*)w.nt, w.cap_t,
                        w.task_g, w.task_n, pv.disc, T, w.pmask, w.pcount);
@@ -1160,15 +1159,13 @@ hp_status hp_bin_sorted_widened(int32_t phase, const void* projected, int64_t P,
       return HP_OK;
     }
     // until the count below completes, *n_pairs says that nothing may be
-    // emitted
-    hipLaunchKernelGGL(k_store_unfinished, dim3(1), dim3(1), 0, s, n_pairs);
-    HP_CHECK_LAUNCH();
+    // emitted (set by the depth sort's first kernel)
     if (sw.nn <= kHistNodes) {
       // tasks written in node order straight from the walk (no task sort);
       // the histogram lives in task_n and its row scans, node counts and node
       // offsets in poff, which this path does not otherwise use
       // (nn x G + 2 nn <= 3 (P + 255) + 1536 <= task capacity)
-      HP_TRY(depth_order(pv, P, w, s));
+      HP_TRY(depth_order(pv, P, w, n_pairs, s));
       const unsigned G = hp_blocks(P, 256);
       const int nni = (int)sw.nn;
       uint32_t* hist = w.task_n;
@@ -1191,7 +1188,7 @@ hp_status hp_bin_sorted_widened(int32_t phase, const void* projected, int64_t P,
                          w.task_g);
       HP_CHECK_LAUNCH();
     } else {
-      HP_TRY(bin_tasks(pv, P, T, prm->bin_guard, w, sw.slots, s));
+      HP_TRY(bin_tasks(pv, P, T, prm->bin_guard, w, sw.slots, n_pairs, s));
       // stable sort of the tasks by node; segments and chunk offsets per node
       int nbits = 0;
       while (((int64_t)1 << nbits) < sw.nn) ++nbits;
