@@ -46,7 +46,16 @@ def _big_discs():
     return sc, SC.make_camera(rng, 9, SC.CAM_FULL)
 
 
-LIST_CASES = dict(CASES, big_discs=_big_discs)
+def _order10():
+    """3000 Gaussians at order 10, where the split level has 768 nodes: the
+    task list's count and scatter passes take one round of 256 Gaussians per
+    workgroup (two rounds below 384 nodes, as at order 9)."""
+    rng = np.random.default_rng(101)
+    sc = SC.make_scene(3000, 0, "volume", 2.0, 6.0, 101, log_scale_mu=-2.5, log_scale_sigma=0.6, rgb_dc=True, rng=rng)
+    return sc, SC.make_camera(rng, 10, SC.CAM_FULL)
+
+
+LIST_CASES = dict(CASES, big_discs=_big_discs, order10=_order10)
 
 
 @pytest.mark.parametrize("case", list(LIST_CASES))
