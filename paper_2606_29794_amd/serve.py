@@ -358,14 +358,27 @@ class Server:
                 keep_t.append((vals, ranges, nc))
                 counts.append(cnt)
                 nbytes += nproj + 4 * vals.numel() + 8 * m.n_tiles + 24 * m.n_active
-            for s0 in range(0, len(reqd), MAX_REQ_PER_RENDER):
-                chunk = reqd[s0:s0 + MAX_REQ_PER_RENDER]
-                arr = (A.hp_render_req * len(chunk))(*chunk)
-                A.call("hp_render_fwd_batch", len(chunk), arr, C.byref(prm), sptr)
+            if len(reqs) == 1:
+                # a lone request takes the single-view render (same kernel
+                # body, without the batch's request table)
+                r, m = reqs[0], R.mask(reqs[0].camera)
+                vals, ranges, nc = keep_t[0]
+                rgb, T = outs[0]
+                v = r.camera.view()
+                A.call("hp_render_fwd", _p(projs[0]), P, _p(vals), _p(ranges), m.n_tiles, C.byref(v), C.byref(prm),
+                       _p(m.buf), m.n_active, _p(rgb), _p(T), _p(nc), None, None, sptr)
+            else:
+                for s0 in range(0, len(reqd), MAX_REQ_PER_RENDER):
+                    chunk = reqd[s0:s0 + MAX_REQ_PER_RENDER]
+                    arr = (A.hp_render_req * len(chunk))(*chunk)
+                    A.call("hp_render_fwd_batch", len(chunk), arr, C.byref(prm), sptr)
             # the pair counts go to pinned host memory in the batch's stream
             # order, so they are readable once the batch's event completes
             host_counts = torch.empty(len(counts), dtype=torch.int64, pin_memory=True)
-            host_counts.copy_(torch.stack([c.dev[0] for c in counts]), non_blocking=True)
+            if len(counts) == 1:
+                host_counts.copy_(counts[0].dev[:1], non_blocking=True)
+            else:
+                host_counts.copy_(torch.stack([c.dev[0] for c in counts]), non_blocking=True)
             ev = torch.cuda.Event()
             ev.record(stream)
         b = _Batch(reqs, stream, ev, nbytes, outs=outs)
