@@ -665,7 +665,7 @@ class Rasterizer:
         img, ref = _dense(img), _dense(ref)
         m = self.mask(cam)
         sp = sp or A.default_ssim_params()
-        out = torch.zeros(3, dtype=torch.float32, device=self.device)
+        out = torch.empty(3, dtype=torch.float32, device=self.device)  # written whole by the call
         smap = torch.empty_like(img) if want_map else None
         dimg = torch.empty_like(img) if dL_dloss is not None else None
         ws_n = A.lib().hp_ssim_workspace_bytes(cam.order, self.prm.tile_log2, m.n_active)
@@ -682,7 +682,7 @@ class Rasterizer:
         img, ref = _dense(img), _dense(ref)
         m = self.mask(cam)
         sp = sp or A.default_ssim_params()
-        out = torch.zeros(3, dtype=torch.float32, device=self.device)
+        out = torch.empty(3, dtype=torch.float32, device=self.device)  # written whole by the call
         smap = torch.empty_like(img) if want_map else None
         ws_n = A.lib().hp_ssim_workspace_bytes(cam.order, self.prm.tile_log2, m.n_active)
         ws = _bytes(ws_n, self.device)
