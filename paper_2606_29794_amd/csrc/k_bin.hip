@@ -880,6 +880,38 @@ __global__ __launch_bounds__(256) void k_bin_cols(const uint32_t* __restrict__ c
 // would carry ~10 lanes.
 constexpr int kMaxChunkHits = 64 * 64;
 
+// (start, end) of every active tile from the scanned column counts; the end
+// of the last tile of the last node is the total.  When nothing is emitted
+// (the pairs exceed the capacity, or the count has not completed) every
+// range is empty, so that a render over them reads no list entry.  Written
+// by the emission kernel's threads, strided over its grid.
+struct TileRanges {
+  int32_t n_tiles;
+  const int32_t* active_tiles;
+  const uint64_t* ncol;   // (chunk, leaf) count entries
+  const uint64_t* total;  // pairs
+  uint32_t* ranges;
+};
+__device__ __forceinline__ void write_tile_ranges(const TileRanges& R, int depth, const uint32_t* __restrict__ choff,
+                                                  const uint64_t* __restrict__ start, bool none) {
+  const int nleaf = 1 << (2 * depth);
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < R.n_tiles;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    if (none) {
+      R.ranges[2 * k] = 0u;
+      R.ranges[2 * k + 1] = 0u;
+      continue;
+    }
+    const int t = R.active_tiles[k];
+    const uint32_t n = (uint32_t)t >> (2 * depth), b = (uint32_t)t & (uint32_t)(nleaf - 1);
+    const int64_t c0 = choff[n], nchn = (int64_t)choff[n + 1] - c0;
+    const uint64_t nc = *R.ncol;
+    const uint64_t i0 = (uint64_t)(c0 * nleaf + b * nchn), i1 = (uint64_t)(c0 * nleaf + (b + 1) * nchn);
+    R.ranges[2 * k] = (uint32_t)(i0 < nc ? start[i0] : *R.total);
+    R.ranges[2 * k + 1] = (uint32_t)(i1 < nc ? start[i1] : *R.total);
+  }
+}
+
 __global__ __launch_bounds__(256) void k_bin_emit_sorted(const uint32_t* __restrict__ choff, uint32_t nn,
                                                          const uint32_t* __restrict__ seg,
                                                          const uint32_t* __restrict__ cnode,
@@ -887,8 +919,10 @@ __global__ __launch_bounds__(256) void k_bin_emit_sorted(const uint32_t* __restr
                                                          const uint64_t* __restrict__ wcol,
                                                          const uint64_t* __restrict__ start,
                                                          const int64_t* __restrict__ n_pairs, int64_t capacity,
-                                                         uint32_t* __restrict__ vals) {
-  if (*n_pairs > capacity) return;
+                                                         uint32_t* __restrict__ vals, TileRanges tr) {
+  const bool none = *n_pairs > capacity;
+  write_tile_ranges(tr, depth, choff, start, none);
+  if (none) return;
   __shared__ uint64_t s_base[4][64];
   __shared__ uint32_t s_g[4][64], s_off[4][64];
   __shared__ uint16_t s_hit[4][kMaxChunkHits];  // column << 8 | task of every hit number
@@ -947,31 +981,6 @@ __global__ __launch_bounds__(256) void k_bin_emit_sorted(const uint32_t* __restr
     base = basen;
     g = gn;
   }
-}
-
-// (start, end) of every active tile from the scanned column counts; the end
-// of the last tile of the last node is the total.  When nothing was emitted
-// (the pairs exceed the capacity, or the count has not completed) every
-// range is empty, so that a render over them reads no list entry.
-__global__ void k_bin_ranges(int32_t n_tiles, const int32_t* __restrict__ active_tiles, int depth,
-                             const uint32_t* __restrict__ choff, const uint64_t* __restrict__ start,
-                             const uint64_t* __restrict__ ncol, const uint64_t* __restrict__ total,
-                             const int64_t* __restrict__ n_pairs, int64_t capacity, uint32_t* __restrict__ ranges) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= n_tiles) return;
-  if (*n_pairs > capacity) {
-    ranges[2 * k] = 0u;
-    ranges[2 * k + 1] = 0u;
-    return;
-  }
-  const int t = active_tiles[k];
-  const int nleaf = 1 << (2 * depth);
-  const uint32_t n = (uint32_t)t >> (2 * depth), b = (uint32_t)t & (uint32_t)(nleaf - 1);
-  const int64_t c0 = choff[n], nchn = (int64_t)choff[n + 1] - c0;
-  const uint64_t nc = *ncol;
-  const uint64_t i0 = (uint64_t)(c0 * nleaf + b * nchn), i1 = (uint64_t)(c0 * nleaf + (b + 1) * nchn);
-  ranges[2 * k] = (uint32_t)(i0 < nc ? start[i0] : *total);
-  ranges[2 * k + 1] = (uint32_t)(i1 < nc ? start[i1] : *total);
 }
 
 // number of (chunk, leaf) count entries: chunks x leaves per node
@@ -1228,16 +1237,12 @@ hp_status hp_bin_sorted_widened(int32_t phase, const void* projected, int64_t P,
   }
   if ((phase & HP_BIN_EMIT) && P > 0) {
     // the chunk count is read on the device: launch for the workspace's bound
+    // the emission also writes the tile ranges
+    const TileRanges tr{n_tiles, mv.active_tiles, (const uint64_t*)w.ncol, (const uint64_t*)w.p_total, tile_ranges};
     hipLaunchKernelGGL(k_bin_emit_sorted, dim3(chunk_grid(sw.nchunk_max)), dim3(256), 0, s, (const uint32_t*)sw.choff,
-                       nn, (const uint32_t*)sw.seg, (const uint32_t*)sw.cnode, (const uint32_t*)w.task_g, depth, (const uint64_t*)sw.wcol,
-                       (const uint64_t*)sw.start, (const int64_t*)n_pairs, capacity, vals);
+                       nn, (const uint32_t*)sw.seg, (const uint32_t*)sw.cnode, (const uint32_t*)w.task_g, depth,
+                       (const uint64_t*)sw.wcol, (const uint64_t*)sw.start, (const int64_t*)n_pairs, capacity, vals, tr);
     HP_CHECK_LAUNCH();
-    if (n_tiles > 0) {
-      hipLaunchKernelGGL(k_bin_ranges, dim3(hp_blocks(n_tiles, 256)), dim3(256), 0, s, n_tiles, mv.active_tiles, depth,
-                         (const uint32_t*)sw.choff, (const uint64_t*)sw.start, (const uint64_t*)w.ncol,
-                         (const uint64_t*)w.p_total, (const int64_t*)n_pairs, capacity, tile_ranges);
-      HP_CHECK_LAUNCH();
-    }
   } else if ((phase & HP_BIN_EMIT) && n_tiles > 0) {
     hipLaunchKernelGGL(k_fill_zero_u32, dim3(hp_blocks(2 * (int64_t)n_tiles, 256)), dim3(256), 0, s, tile_ranges,
                        2 * (int64_t)n_tiles);
