@@ -473,15 +473,17 @@ __global__ __launch_bounds__(1024) void k_ssim_reduce(const float2* __restrict__
 // ---------------------------------------------------------------------------
 // backward
 // ---------------------------------------------------------------------------
-template <int B>
+// The gathered patch; once the first pass has read it (the pass keeps its
+// outputs in registers until then), its output [9][P1S] and after that the
+// second pass's sums [9][B*B] overlay it.  The cells' directions and polar
+// flags are only needed with zone windows.
+template <int B, bool ZONES>
 struct SsBwdLds {
   static constexpr int H = B + 2 * SS_R, HP = (H + 3) & ~3, P1S = H * B + ((48 - (H * B) % 32) % 32);
+  static_assert(B < 8 || 9 * P1S + 9 * B * B <= 9 * H * HP, "first-pass output and sums fit over the patch");
   float in[9][H][HP];
-  union {
-    float p1[9][P1S];
-    double dir[H * H][3];
-  };
-  uint8_t polar[H * H];
+  double dir[ZONES ? H * H : 1][3];
+  uint8_t polar[ZONES ? H * H : 1];
 };
 
 // dL/dimg_p = dL/dloss * [ (1 - lam) sign(img - ref) / (3n)
@@ -492,10 +494,12 @@ __global__ __launch_bounds__(256) void k_ssim_bwd(SsimArgs A, const float* __res
                                                   const float* __restrict__ ref, const float* __restrict__ G,
                                                   const float* __restrict__ dL_dloss, float* __restrict__ dimg,
                                                   int n_tiles) {
-  using L = SsBwdLds<B>;
+  using L = SsBwdLds<B, ZONES>;
   constexpr int H = L::H;
   __shared__ L s;
-  float(*S)[B * B] = reinterpret_cast<float(*)[B * B]>(&s.in[0][0][0]);  // after pass 1
+  // over the patch: the first pass's output, then the second pass's sums
+  float(*P1)[L::P1S] = reinterpret_cast<float(*)[L::P1S]>(&s.in[0][0][0]);
+  float(*S)[B * B] = reinterpret_cast<float(*)[B * B]>(&s.in[0][0][0] + 9 * L::P1S);
   const int tid = threadIdx.x;
   constexpr int NG = (H * H + 255) / 256;
   // tiles l = blockIdx.x, + gridDim.x, ... as in the forward; the next
@@ -583,10 +587,11 @@ __global__ __launch_bounds__(256) void k_ssim_bwd(SsimArgs A, const float* __res
           kk[t] = k; rr[t] = r; cc[t] = c0;
         }
       }
+      __syncthreads();  // every read of the patch is done: the output goes over it
   #pragma unroll
       for (int t = 0; t < 4; ++t)
         if (kk[t] >= 0)
-          *reinterpret_cast<float4*>(&s.p1[kk[t]][rr[t] * B + cc[t]]) = make_float4(o[t][0], o[t][1], o[t][2], o[t][3]);
+          *reinterpret_cast<float4*>(&P1[kk[t]][rr[t] * B + cc[t]]) = make_float4(o[t][0], o[t][1], o[t][2], o[t][3]);
       if (more) load_cells(en, vn);
       __syncthreads();
       constexpr int RO = B / 2, NI2 = B * 9 * 2;
@@ -594,7 +599,7 @@ __global__ __launch_bounds__(256) void k_ssim_bwd(SsimArgs A, const float* __res
         const int c = it % B, k = (it / B) % 9, hh = it / (9 * B);
         float w[RO + 2 * SS_R];
   #pragma unroll
-        for (int j = 0; j < RO + 2 * SS_R; ++j) w[j] = s.p1[k][(hh * RO + j) * B + c];
+        for (int j = 0; j < RO + 2 * SS_R; ++j) w[j] = P1[k][(hh * RO + j) * B + c];
   #pragma unroll
         for (int u = 0; u < RO; ++u) {
           float acc = 0.f;
@@ -611,8 +616,7 @@ __global__ __launch_bounds__(256) void k_ssim_bwd(SsimArgs A, const float* __res
     }
     if (direct) {
       if (more) load_cells(en, vn);
-      // directions of the patch cells (over the first pass's place), for the
-      // polar windows
+      // directions of the patch cells, for the polar windows
       if (ZONES) {
         for (int i = tid; i < H * H; i += 256) {
           const int cx = i % H, cy = i / H;
@@ -628,14 +632,14 @@ __global__ __launch_bounds__(256) void k_ssim_bwd(SsimArgs A, const float* __res
   #pragma unroll
       for (int k = 0; k < 9; ++k) Sm[k] = 0.f;
       if (tid < B * B) {
-        const double* up = s.dir[(py + SS_R) * H + px + SS_R];
+        const double* up = ZONES ? s.dir[(py + SS_R) * H + px + SS_R] : nullptr;
         for (int b = 0; b < SS_W; ++b) {
           for (int a = 0; a < SS_W; ++a) {
             const int cy = py + b, cx = px + a;
             // q's own window at p: the great-circle Gaussian for a polar q,
             // the (symmetric) chart taps otherwise
             const float w = (ZONES && s.polar[cy * H + cx])
-                                ? __expf(-(float)(ss_dist2(up, s.dir[cy * H + cx]) * A.wscale))
+                                ? __expf(-(float)(ss_dist2(up, s.dir[ZONES ? cy * H + cx : 0]) * A.wscale))
                                 : A.g[a] * A.g[b];
   #pragma unroll
             for (int k = 0; k < 9; ++k) Sm[k] = fmaf(w, s.in[k][cy][cx], Sm[k]);
@@ -781,6 +785,12 @@ static unsigned ssim_grid(int32_t n_tiles, bool zones) {
   const int32_t g = 3 * 256;
   return (unsigned)(zones || n_tiles <= g ? n_tiles : g);
 }
+// the backward's patch and pass outputs share their LDS: four workgroups per
+// CU (what its registers allow)
+static unsigned ssim_bwd_grid(int32_t n_tiles, bool zones) {
+  const int32_t g = 4 * 256;
+  return (unsigned)(zones || n_tiles <= g ? n_tiles : g);
+}
 
 template <int B>
 static hp_status ssim_fwd_launch_b(const SsimArgs& A, bool zones, const float* img, const float* ref,
@@ -814,7 +824,7 @@ template <int B>
 static hp_status ssim_bwd_launch_b(const SsimArgs& A, bool zones, const float* img, const float* ref,
                                    int32_t n_tiles, const float* Gm, const float* dL_dloss, float* dL_dimg,
                                    hipStream_t s) {
-  const dim3 grid(ssim_grid(n_tiles, zones));
+  const dim3 grid(ssim_bwd_grid(n_tiles, zones));
   if (zones)
     hipLaunchKernelGGL((k_ssim_bwd<B, true>), grid, dim3(256), 0, s, A, img, ref, Gm, dL_dloss, dL_dimg, (int)n_tiles);
   else
